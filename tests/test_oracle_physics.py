@@ -1,0 +1,320 @@
+"""Pins of the oracle's energy, forces, virial and parameter gradients.
+
+The paper (Background section, DeePMD-kit subsection and Fig. 1(b)) fixes:
+the descriptor preserves translational, rotational and permutational
+invariance; E = sum_i E_i; forces are the gradient of the energy obtained by
+back-propagation.  Each test below checks the oracle against something other
+than its own formulas: closed forms of the switching function, special
+parameter choices that reduce the nets to known functions, invariances,
+extensivity, Newton's third law, and finite differences.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22867_amd import inputs as I
+
+
+@pytest.fixture(scope="module")
+def w192():
+    return I.workload("water192")
+
+
+def _desc_arrays_ok(desc):
+    assert oracle.n_params(desc) == desc.n_params
+
+
+def test_param_count_matches_layout():
+    _desc_arrays_ok(I.WATER)
+    _desc_arrays_ok(I.COPPER)
+    assert I.WATER.n_params == 1026124   # 25,800 embedding + 1,000,322 fitting + 2 e_bias
+
+
+# --------------------------------------------------------------------------- switch
+def test_switch_closed_forms():
+    rs, rc = 0.5, 6.0
+    # below rs: exactly 1/r, ds = -1/r^2
+    r = np.array([0.2, 0.3, 0.49])
+    s, ds = oracle.switch(r, rs, rc)
+    assert np.allclose(s, 1 / r, rtol=1e-15)
+    assert np.allclose(ds, -1 / r ** 2, rtol=1e-15)
+    # midpoint u = 1/2: polynomial factor u^3(-6u^2+15u-10)+1 = 1/2
+    rm = 0.5 * (rs + rc)
+    s, _ = oracle.switch(np.array([rm]), rs, rc)
+    assert abs(s[0] - 0.5 / rm) < 1e-15
+    # at and beyond rc: 0
+    s, ds = oracle.switch(np.array([rc, rc + 1.0]), rs, rc)
+    assert np.all(s == 0) and np.all(ds == 0)
+    # continuity of s, s', s'' at both knots (one-sided finite differences)
+    for knot in (rs, rc):
+        e = 1e-4
+        rl = np.array([knot - 2 * e, knot - e, knot - 1e-9])
+        rr = np.array([knot + 1e-9, knot + e, knot + 2 * e])
+        sl, dsl = oracle.switch(rl, rs, rc)
+        sr, dsr = oracle.switch(rr, rs, rc)
+        assert abs(sl[2] - sr[0]) < 1e-7
+        assert abs(dsl[2] - dsr[0]) < 1e-6
+        d2l = (dsl[2] - dsl[1]) / (rl[2] - rl[1])
+        d2r = (dsr[1] - dsr[0]) / (rr[1] - rr[0])
+        assert abs(d2l - d2r) < 1e-2 * max(1.0, abs(d2l))
+    # ds is the derivative of s
+    r = np.linspace(0.3, 5.9, 57)
+    h = 1e-6
+    sp, _ = oracle.switch(r + h, rs, rc)
+    sm, _ = oracle.switch(r - h, rs, rc)
+    _, ds = oracle.switch(r, rs, rc)
+    assert np.allclose((sp - sm) / (2 * h), ds, atol=1e-7)
+
+
+# --------------------------------------------------------------------------- env matrix
+def _two_atom_frame(dvec, L=20.0, types=(0, 0)):
+    x = np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0]]) + np.array([[0, 0, 0], dvec])
+    return x, np.array(types, dtype=np.int32), np.diag([L, L, L])
+
+
+def test_env_single_neighbour_along_axes():
+    desc = I.WATER
+    p = I.init_params(desc, 3)
+    for axis in range(3):
+        for sign in (1.0, -1.0):
+            dv = np.zeros(3)
+            dv[axis] = 2.0 * sign
+            x, t, box = _two_atom_frame(dv)
+            r = oracle.compute(x, t, box, desc, p, debug=True)
+            s, _ = oracle.switch(np.array([2.0]), desc.rcut_smth, desc.rcut)
+            want = np.zeros(4)
+            want[0] = s[0] / desc.std_s
+            want[1 + axis] = sign * s[0] / desc.std_v
+            assert np.allclose(r["R"][0, 0], want, rtol=1e-14, atol=1e-16)
+            assert np.all(r["R"][0, 1:] == 0)
+
+
+# --------------------------------------------------------------------------- embedding / descriptor
+def _zero_blocks(desc, p, names):
+    p = p.copy()
+    off = desc.param_offsets()
+    for nm in names:
+        o, shp = off[nm]
+        p[o:o + int(np.prod(shp))] = 0.0
+    return p
+
+
+def test_embedding_skip_concatenation():
+    """With W2 = W3 = 0 and b2 = b3 = 0 the embedding reduces to
+    G = [h1, h1, h1, h1] with h1 = tanh(s W1 + b1): checks the concatenated
+    identity skip of width-doubling layers.  Single neighbour: T[a,k] =
+    G[a] R[k] / nm."""
+    desc = I.WATER
+    p = I.init_params(desc, 9)
+    names = []
+    for ti in range(2):
+        for tj in range(2):
+            names += [f"emb{ti}{tj}.W2", f"emb{ti}{tj}.b2", f"emb{ti}{tj}.W3", f"emb{ti}{tj}.b3"]
+    p = _zero_blocks(desc, p, names)
+    x, t, box = _two_atom_frame(np.array([1.3, -0.7, 0.4]), types=(0, 1))
+    r = oracle.compute(x, t, box, desc, p, debug=True)
+    off = desc.param_offsets()
+    o1, _ = off["emb01.W1"]
+    ob, _ = off["emb01.b1"]
+    R = r["R"][0, 46]             # first H slot of atom 0 (type O)
+    h1 = np.tanh(R[0] * p[o1:o1 + 25] + p[ob:ob + 25])
+    G = np.concatenate([h1, h1, h1, h1])
+    assert np.allclose(r["T"][0], np.outer(G, R) / desc.nm, rtol=1e-13, atol=1e-16)
+
+
+def test_descriptor_constant_embedding():
+    """All embedding weights zero: G == c (constant per type pair), so
+    D[a, b] = c_a c_b |sum_j R_j|^2 / nm^2 when every neighbour has the same
+    type pair."""
+    desc = I.COPPER
+    p = I.init_params(desc, 4)
+    p = _zero_blocks(desc, p, ["emb00.W1", "emb00.W2", "emb00.W3"])
+    fr = I.copper_fcc(3, 3.634, 0.15, seed=1)
+    r = oracle.compute(fr.coords, fr.types, fr.box, desc, p, debug=True, rows=[0, 5])
+    off = desc.param_offsets()
+    b1 = p[off["emb00.b1"][0]:][:32]
+    b2 = p[off["emb00.b2"][0]:][:64]
+    b3 = p[off["emb00.b3"][0]:][:128]
+    h1 = np.tanh(b1)
+    h2 = np.concatenate([h1, h1]) + np.tanh(b2)
+    c = np.concatenate([h2, h2]) + np.tanh(b3)
+    for q in range(2):
+        Rsum = r["R"][q].sum(0)
+        D = np.outer(c, c[:16]) * (Rsum @ Rsum) / desc.nm ** 2
+        assert np.allclose(r["D"][q], D.reshape(-1), rtol=1e-12, atol=1e-18)
+
+
+def _rot(seed):
+    q = np.random.default_rng(seed).normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def _wrap_frac(x, h):
+    f = x @ np.linalg.inv(h)
+    f -= np.floor(f)
+    f = np.where(f >= 1.0, f - 1.0, f)
+    return f @ h
+
+
+def test_descriptor_rotation_invariant(w192):
+    fr, desc, p, _ = w192
+    Q = _rot(3)
+    r0 = oracle.compute(fr.coords, fr.types, fr.box, desc, p, debug=True, use_cells=False)
+    h = fr.box @ Q.T
+    x = _wrap_frac(fr.coords @ Q.T, h)
+    r1 = oracle.compute(x, fr.types, h, desc, p, debug=True, use_cells=False)
+    assert np.allclose(r0["D"], r1["D"], rtol=1e-10, atol=1e-14)
+
+
+# --------------------------------------------------------------------------- energy invariances
+def test_translation_invariance(w192):
+    fr, desc, p, _ = w192
+    r0 = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    x = _wrap_frac(fr.coords + np.array([1.234, -4.5, 7.77]), fr.box)
+    r1 = oracle.compute(x, fr.types, fr.box, desc, p)
+    assert abs(r0["E"] - r1["E"]) < 1e-12 * abs(r0["E"])
+    assert np.allclose(r0["F"], r1["F"], atol=1e-12)
+
+
+def test_rotation_covariance(w192):
+    fr, desc, p, _ = w192
+    Q = _rot(5)
+    r0 = oracle.compute(fr.coords, fr.types, fr.box, desc, p, use_cells=False)
+    h = fr.box @ Q.T
+    x = _wrap_frac(fr.coords @ Q.T, h)
+    r1 = oracle.compute(x, fr.types, h, desc, p, use_cells=False)
+    assert abs(r0["E"] - r1["E"]) < 1e-12 * abs(r0["E"])
+    assert np.allclose(r0["F"] @ Q.T, r1["F"], atol=1e-12)
+    assert np.allclose(Q @ r0["W"] @ Q.T, r1["W"], atol=1e-12)
+
+
+def test_same_type_permutation(w192):
+    fr, desc, p, _ = w192
+    rng = np.random.default_rng(0)
+    perm = np.arange(fr.n)
+    for t in range(desc.ntypes):
+        idx = np.nonzero(fr.types == t)[0]
+        perm[idx] = rng.permutation(idx)
+    r0 = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    r1 = oracle.compute(fr.coords[perm], fr.types[perm], fr.box, desc, p)
+    assert abs(r0["E"] - r1["E"]) < 1e-12 * abs(r0["E"])
+    assert np.allclose(r0["F"][perm], r1["F"], atol=1e-12)
+    assert np.allclose(r0["Ei"][perm], r1["Ei"], atol=1e-12)
+
+
+def test_supercell_extensive(w192):
+    fr, desc, p, _ = w192
+    L = np.diag(fr.box)
+    reps = [fr.coords + np.array([a, b, c]) * L for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+    x = np.concatenate(reps)
+    t = np.tile(fr.types, 8)
+    r0 = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    r1 = oracle.compute(x, t, fr.box * 2, desc, p)
+    assert abs(r1["E"] - 8 * r0["E"]) < 1e-11 * abs(r1["E"])
+    assert np.allclose(r1["F"], np.tile(r0["F"], (8, 1)), atol=1e-12)
+    assert np.allclose(r1["W"], 8 * r0["W"], atol=1e-11)
+
+
+def test_newton_third_law_and_virial_symmetry(w192):
+    fr, desc, p, _ = w192
+    r = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    assert np.abs(r["F"].sum(0)).max() < 1e-12 * fr.n
+    assert np.allclose(r["W"], r["W"].T, atol=1e-12)
+    assert np.isclose(r["E"], r["Ei"].sum(), rtol=1e-15)
+
+
+def test_isolated_cluster_virial_and_torque():
+    """A molecule cluster in a large box: no periodic images inside the cut-off,
+    so W = sum_i x_i (x) F_i (with the relative-vector definition) and the net
+    torque vanishes."""
+    fr = I.water_box(8, 7.0, seed=2)
+    L = 40.0
+    x = fr.coords + 10.0
+    r = oracle.compute(x, fr.types, np.diag([L, L, L]), I.WATER, I.init_params(I.WATER, 100))
+    W2 = x.T @ r["F"]
+    assert np.allclose(r["W"], W2, atol=1e-11)
+    torque = np.cross(x - x.mean(0), r["F"]).sum(0)
+    assert np.abs(torque).max() < 1e-11
+
+
+# --------------------------------------------------------------------------- finite differences
+def test_forces_central_fd(w192):
+    fr, desc, p, _ = w192
+    r = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    rng = np.random.default_rng(1)
+    h = 1e-3
+    comps = [(int(rng.integers(fr.n)), int(rng.integers(3))) for _ in range(30)]
+    for i, a in comps:
+        E = []
+        for k in (-2, -1, 1, 2):
+            x = fr.coords.copy()
+            x[i, a] += k * h
+            E.append(oracle.compute(x, fr.types, fr.box, desc, p, use_cells=False)["E"])
+        dE = (E[0] - 8 * E[1] + 8 * E[2] - E[3]) / (12 * h)
+        assert abs(-dE - r["F"][i, a]) < 1e-7, (i, a, -dE, r["F"][i, a])
+    assert np.sqrt((r["F"] ** 2).mean()) > 0.05   # the model is not trivially flat
+
+
+def test_virial_strain_fd(w192):
+    """W_ab = -dE/d eps_ab under x -> x (I + eps)^T, h -> h (I + eps)^T."""
+    fr, desc, p, _ = w192
+    r = oracle.compute(fr.coords, fr.types, fr.box, desc, p, use_cells=False)
+    h = 1e-5
+    Wfd = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            E = []
+            for k in (-2, -1, 1, 2):
+                eps = np.zeros((3, 3))
+                eps[a, b] = k * h
+                M = np.eye(3) + eps
+                E.append(oracle.compute(fr.coords @ M.T, fr.types, fr.box @ M.T, desc, p,
+                                        use_cells=False)["E"])
+            Wfd[a, b] = -(E[0] - 8 * E[1] + 8 * E[2] - E[3]) / (12 * h)
+    assert np.allclose(r["W"], Wfd, atol=1e-7), (r["W"], Wfd)
+
+
+def test_param_gradients_fd(w192):
+    fr, desc, p, _ = w192
+    g = oracle.compute(fr.coords, fr.types, fr.box, desc, p, grad_scale=1.0)["grad"]
+    off = desc.param_offsets()
+    rng = np.random.default_rng(2)
+    picks = []
+    for name, (o, shp) in off.items():
+        n = int(np.prod(shp))
+        for _ in range(2):
+            picks.append(o + int(rng.integers(n)))
+    h = 1e-5
+    for k in picks:
+        E = []
+        for s in (-1, 1):
+            q = p.copy()
+            q[k] += s * h
+            E.append(oracle.compute(fr.coords, fr.types, fr.box, desc, q)["E"])
+        fd = (E[1] - E[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+    # the gradient scales with the seed
+    g2 = oracle.compute(fr.coords, fr.types, fr.box, desc, p, grad_scale=-2.5)["grad"]
+    assert np.allclose(g2, -2.5 * g, rtol=1e-12, atol=1e-15)
+    # e_bias gradient equals the atom count per type
+    o, _ = off["e_bias"]
+    assert np.allclose(g[o:o + 2], [np.sum(fr.types == 0), np.sum(fr.types == 1)])
+
+
+def test_subset_rows_match_full(w192):
+    """Sampled evaluation (used at full workload sizes) agrees with the full
+    frame: E_i of a subset and the total force on one atom."""
+    fr, desc, p, _ = w192
+    full = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    rows = np.array([3, 17, 100, 191])
+    sub = oracle.compute(fr.coords, fr.types, fr.box, desc, p, rows=rows)
+    assert np.array_equal(sub["Ei"], full["Ei"][rows])
+    for k in (0, 77, 150):
+        f = oracle.force_on(fr.coords, fr.types, fr.box, desc, p, k)
+        assert np.allclose(f, full["F"][k], atol=1e-13)
