@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""DP se_a energy+force MD-step throughput on one MI355X.
+
+A step is one pass of the whole hot path over the frame: velocity-Verlet
+kick + drift (+ wrap), neighbour-list build, energy/forces/virial
+(environment matrix, embedding nets, descriptor, fitting net, backward,
+force/virial scatter), second kick.  Inputs are synthetic (seeded generators,
+random-weight model of the paper's water architecture) and resident in HBM
+before timing starts.
+
+Prints ONE JSON line.  `value` is the FP64 path's atom-steps/s; the mixed
+precision forms (BF16 / FP16 matrix-core GEMMs) are reported beside it with
+their speedup and their error against the FP64 oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TF = 78.6
+PEAK_BF16_TF = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(desc, real_rows, natoms):
+    """Flops per launch of the matrix stages (real neighbour rows only)."""
+    w1, fw, nd, m1 = desc.emb[0], desc.fit[0], desc.ndesc, desc.m1
+    gemm_row = 2 * (w1 + desc.emb[0] * desc.emb[1] + desc.emb[1] * desc.emb[2])
+    contr = 2 * m1 * 4
+    fit_fwd = 2 * (nd * fw + 2 * fw * fw) + 2 * fw
+    fit_bwd = 2 * (2 * fw * fw + fw * nd)
+    return {
+        "embed_fwd": real_rows * (gemm_row + contr),
+        "embed_bwd": real_rows * (2 * gemm_row + 2 * contr),
+        "fit_fwd": natoms * fit_fwd,
+        "fit_bwd": natoms * fit_bwd,
+        "descriptor": natoms * 2 * m1 * desc.m2 * 4,
+        "desc_bwd": natoms * 4 * m1 * desc.m2 * 4,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="water12k", choices=["water192", "water12k", "copper32k", "water98k"])
+    ap.add_argument("--modes", default="fp64,bf16,fp16")
+    ap.add_argument("--nve-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU spatial decomposition is designed, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_22867_amd import dpse, inputs as I
+
+    dev = torch.device("cuda:0")
+    fr, desc, params, dt = I.workload(args.workload)
+    wl_index = {"water192": 0, "water12k": 1, "copper32k": 2, "water98k": 3}[args.workload]
+    n = fr.n
+    model = dpse.Model(desc, params)
+    ctx = dpse.Context(model, n)
+    x0 = torch.tensor(fr.coords, device=dev)
+    v0 = torch.tensor(I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=200 + wl_index), device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    box = fr.box
+    nm = desc.nm
+    nl = torch.empty((n, nm), dtype=torch.int32, device=dev)
+    ov = torch.empty(1, dtype=torch.int32, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    W = torch.empty(9, dtype=torch.float64, device=dev)
+    ke = torch.empty(1, dtype=torch.float64, device=dev)
+    f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+
+    def step(x, v, mode):
+        ctx.kick_drift(x, v, f, t, box, dt)
+        ctx.build_nlist(x, t, box, out=nl, overflow=ov)
+        ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
+        ctx.kick(v, f, t, dt, ke)
+
+    def init_state(mode):
+        x = x0.clone()
+        v = v0.clone()
+        ctx.build_nlist(x, t, box, out=nl, overflow=ov)
+        ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
+        return x, v
+
+    # single-frame results on the initial configuration (accuracy)
+    first = {}
+    for mode in args.modes.split(","):
+        x, v = init_state(mode)
+        torch.cuda.synchronize()
+        first[mode] = dict(E=float(E.item()), F=f.cpu().numpy().copy(), W=W.cpu().numpy().copy())
+    real_rows = int((nl >= 0).sum().item())
+    if ctx.status() != 0:
+        raise RuntimeError(f"device status flags {ctx.status()}")
+
+    results = {}
+    for mode in args.modes.split(","):
+        x, v = init_state(mode)
+        for _ in range(args.warmup):
+            step(x, v, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(x, v, mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms = el / args.steps * 1e3
+        results[mode] = dict(ms_per_step=ms, atom_steps_per_s=n * args.steps / el,
+                             ns_per_day=(args.steps / el) * dt * 0.0864)
+        print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s", file=sys.stderr, flush=True)
+
+    # per-stage event timing (separate pass)
+    stages = {}
+    for mode in args.modes.split(","):
+        x, v = init_state(mode)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(args.profile_steps):
+            step(x, v, mode)
+        torch.cuda.synchronize()
+        st = ctx.stage_times()
+        ctx.profile(False)
+        stages[mode] = {k: (ms / c if c else 0.0, c) for k, (ms, c) in st.items()}
+    if ctx.status() != 0:
+        raise RuntimeError(f"device status flags {ctx.status()}")
+
+    # NVE energy drift (velocity Verlet, metal units)
+    drift = {}
+    for mode in args.modes.split(","):
+        if args.nve_steps <= 0:
+            break
+        x, v = init_state(mode)
+        hist = torch.empty((args.nve_steps + 1, 2), dtype=torch.float64, device=dev)
+        ctx.kick(v, torch.zeros_like(f), t, 0.0, ke)
+        hist[0, 0] = E[0]
+        hist[0, 1] = ke[0]
+        for k in range(args.nve_steps):
+            step(x, v, mode)
+            hist[k + 1, 0] = E[0]
+            hist[k + 1, 1] = ke[0]
+        h = hist.cpu().numpy()
+        etot = h[:, 0] + h[:, 1]
+        tps = np.arange(len(etot)) * dt * 1e-3
+        slope = np.polyfit(tps, (etot - etot[0]) / n * 1e3, 1)[0] if len(etot) > 2 else 0.0
+        drift[mode] = dict(max_dev_meV_per_atom=float(np.abs(etot - etot[0]).max() / n * 1e3),
+                           slope_meV_per_atom_per_ps=float(slope), steps=args.nve_steps,
+                           flags=ctx.status())
+
+    # roofline of the dominant FP64 kernel
+    flops = algorithmic_flops(desc, real_rows, n)
+    st64 = stages.get("fp64", {})
+    dom = max(st64, key=lambda k: st64[k][0]) if st64 else None
+    roof = None
+    if dom in flops:
+        avg_s = st64[dom][0] * 1e-3
+        ach = flops[dom] / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TF,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TF, 4), "traffic": None,
+                "avg_launch_ms": round(st64[dom][0], 4), "flops_per_launch": flops[dom]}
+
+    # oracle on the host cores (bounded sample: one full frame, twice)
+    cpu = None
+    o = None
+    if not args.no_cpu_baseline:
+        import oracle
+        times = []
+        for _ in range(2):
+            tc = time.perf_counter()
+            onl, _ = oracle.nlist(fr.coords, fr.types, fr.box, desc)
+            o = oracle.compute(fr.coords, fr.types, fr.box, desc, params, nl=onl)
+            times.append(time.perf_counter() - tc)
+        tf = float(np.median(times))
+        cpu = {"value": round(n / tf, 2), "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"one {args.workload} frame (neighbour list + E, F, W), {len(times)} runs, "
+                         f"median {tf:.2f} s"}
+    acc = {}
+    if o is not None:
+        for mode, r in first.items():
+            acc[mode] = dict(E_meV_per_atom=abs(r["E"] - o["E"]) / n * 1e3,
+                             F_rms_meV_per_A=float(np.sqrt(((r["F"] - o["F"]) ** 2).mean()) * 1e3),
+                             F_max_meV_per_A=float(np.abs(r["F"] - o["F"]).max() * 1e3),
+                             W_max_meV=float(np.abs(r["W"].reshape(3, 3) - o["W"]).max() * 1e3))
+        acc["force_rms_meV_per_A"] = float(np.sqrt((o["F"] ** 2).mean()) * 1e3)
+
+    base = results.get("fp64") or next(iter(results.values()))
+    line = {
+        "metric": "DP energy+force atom-steps/s & ns/day, 12k-atom water, FP64 vs mixed",
+        "value": round(base["atom_steps_per_s"], 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(base["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "natoms": n, "dt_fs": dt,
+                   "step": "kick+drift, neighbour list, E/F/W, kick", "real_neighbour_rows": real_rows},
+        "ns_per_day": round(base["ns_per_day"], 3),
+        "modes": {m: {k: round(vv, 4) for k, vv in r.items()} for m, r in results.items()},
+        "mixed_speedup": {m: round(results["fp64"]["ms_per_step"] / r["ms_per_step"], 3)
+                          for m, r in results.items() if m != "fp64" and "fp64" in results},
+        "accuracy_vs_oracle": acc,
+        "nve_drift": drift,
+        "stage_ms": {m: {k: round(vv[0], 4) for k, vv in s.items() if vv[1]} for m, s in stages.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,816 @@
+// Host side of libdpse: argument validation, model preparation (weight
+// fragments), context allocation and the launch sequences behind the C ABI
+// declared in include/dp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "dp_internal.h"
+
+using namespace dpse;
+
+namespace dpse {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return DP_ERR_HIP;
+}
+
+}  // namespace dpse
+
+#define HIPCHECK(x)                            \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #x); \
+  } while (0)
+
+namespace {
+
+// ------------------------------------------------------------ precision helpers
+uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t f32_to_f16(float f) {
+  uint32_t x;
+  memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  const uint32_t ax = x & 0x7fffffffu;
+  if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
+  if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);
+  if (ax < 0x38800000u) {
+    float v;
+    memcpy(&v, &ax, 4);
+    const uint32_t r = (uint32_t)std::nearbyint(v * 16777216.0f);
+    return (uint16_t)(sign | r);
+  }
+  uint32_t m = ax - 0x38000000u;
+  m += 0x0fffu + ((m >> 13) & 1u);
+  return (uint16_t)(sign | (m >> 13));
+}
+
+// ------------------------------------------------------------ descriptor
+int validate_desc(const dp_model_desc* d) {
+  if (!d) { set_error("desc is NULL"); return DP_ERR_BAD_ARG; }
+  if (d->ntypes < 1 || d->ntypes > DP_MAX_TYPES) { set_error("ntypes %d out of [1,%d]", d->ntypes, DP_MAX_TYPES); return DP_ERR_BAD_ARG; }
+  int nm = 0;
+  for (int t = 0; t < d->ntypes; ++t) {
+    if (d->sel[t] < 1) { set_error("sel[%d] = %d must be >= 1", t, d->sel[t]); return DP_ERR_BAD_ARG; }
+    nm += d->sel[t];
+  }
+  if (d->n_emb < 1 || d->n_emb > DP_MAX_LAYERS || d->n_fit < 1 || d->n_fit > DP_MAX_LAYERS) {
+    set_error("layer counts out of range"); return DP_ERR_BAD_ARG;
+  }
+  for (int l = 0; l < d->n_emb; ++l) if (d->emb[l] < 1) { set_error("emb width < 1"); return DP_ERR_BAD_ARG; }
+  for (int l = 0; l < d->n_fit; ++l) if (d->fit[l] < 1) { set_error("fit width < 1"); return DP_ERR_BAD_ARG; }
+  if (d->m2 < 1 || d->m2 > d->emb[d->n_emb - 1]) { set_error("m2 out of range"); return DP_ERR_BAD_ARG; }
+  if (!(d->rcut > 0) || !(d->rcut_smth >= 0) || !(d->rcut_smth < d->rcut)) { set_error("need 0 <= rcut_smth < rcut"); return DP_ERR_BAD_ARG; }
+  if (!(d->std_s > 0) || !(d->std_v > 0)) { set_error("std_s, std_v must be > 0"); return DP_ERR_BAD_ARG; }
+  // shapes the kernels implement
+  const int w = d->emb[0];
+  if (d->n_emb != 3 || !(w == 25 || w == 32) || d->emb[1] != 2 * w || d->emb[2] != 4 * w) {
+    set_error("embedding widths must be (w, 2w, 4w) with w in {25, 32}"); return DP_ERR_UNSUPPORTED;
+  }
+  if (d->m2 != 16) { set_error("m2 must be 16"); return DP_ERR_UNSUPPORTED; }
+  if (d->n_fit != 3 || d->fit[1] != d->fit[0] || d->fit[2] != d->fit[0] || d->fit[0] % 16 || d->fit[0] > 256) {
+    set_error("fitting widths must be three equal multiples of 16 <= 256"); return DP_ERR_UNSUPPORTED;
+  }
+  if (nm > kMaxNm) { set_error("sum(sel) = %d exceeds %d", nm, kMaxNm); return DP_ERR_UNSUPPORTED; }
+  for (int t = 0; t < d->ntypes; ++t)
+    if (!(d->masses[t] > 0)) { set_error("masses must be > 0"); return DP_ERR_BAD_ARG; }
+  return DP_OK;
+}
+
+struct ParamLayout {
+  int64_t embW[kMaxT][kMaxT][DP_MAX_LAYERS], embB[kMaxT][kMaxT][DP_MAX_LAYERS];
+  int64_t fitW[kMaxT][DP_MAX_LAYERS], fitB[kMaxT][DP_MAX_LAYERS], wo[kMaxT], bo[kMaxT], ebias;
+  int64_t total;
+};
+
+ParamLayout layout_of(const dp_model_desc* d) {
+  ParamLayout L;
+  memset(&L, 0, sizeof(L));
+  int64_t off = 0;
+  for (int a = 0; a < d->ntypes; ++a)
+    for (int b = 0; b < d->ntypes; ++b) {
+      int prev = 1;
+      for (int l = 0; l < d->n_emb; ++l) {
+        L.embW[a][b][l] = off; off += (int64_t)prev * d->emb[l];
+        L.embB[a][b][l] = off; off += d->emb[l];
+        prev = d->emb[l];
+      }
+    }
+  const int nd = d->emb[d->n_emb - 1] * d->m2;
+  for (int t = 0; t < d->ntypes; ++t) {
+    int prev = nd;
+    for (int l = 0; l < d->n_fit; ++l) {
+      L.fitW[t][l] = off; off += (int64_t)prev * d->fit[l];
+      L.fitB[t][l] = off; off += d->fit[l];
+      prev = d->fit[l];
+    }
+    L.wo[t] = off; off += prev;
+    L.bo[t] = off; off += 1;
+  }
+  L.ebias = off; off += d->ntypes;
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, what);
+  return DP_OK;
+}
+
+// Slot maps of the embedding activations (widths w, 2w, 4w).
+int feat1(int w, int p) { return p < w ? p : -1; }
+int feat2(int w, int p) { return (p & 31) < w ? (p >> 5) * w + (p & 31) : -1; }
+int feat3(int w, int p) {
+  const int f = feat2(w, p & 63);
+  return f < 0 ? -1 : (p >> 6) * 2 * w + f;
+}
+
+// Packed-index helpers of the two fragment kinds.
+//   f64 16x16x4 : element (t, v, lane) with k-feature 16t + 4(lane/16) + v when
+//                 the other operand is read from memory, 16t + 4v + lane/16
+//                 when it is a register tile produced by the previous MFMA.
+//   16x16x32    : element (t, lane, j) with k-feature 32t + 16(j/4) + 4(lane/16) + (j%4).
+inline int kfeat64(int t, int v, int lane) { return 16 * t + 4 * (lane >> 4) + v; }       // memory-fed
+inline int kfeat64c(int t, int v, int lane) { return 16 * t + 4 * v + (lane >> 4); }      // register-chained
+inline int kfeat32(int t, int lane, int j) { return 32 * t + 16 * (j >> 2) + 4 * (lane >> 4) + (j & 3); }
+
+// Builds one fragment block: out[mtile][ktile...] for a weight accessor
+// wfun(m_index, k_index) -> value (0 when padded).  For f64 the k tiles are
+// (t, v) pairs with ktiles16 = K/16; for lp they are t with ktiles32 = K/32.
+template <class F>
+void frag_block64(std::vector<double>& out, int64_t base, int mtiles, int ktiles16, F wfun, bool chained) {
+  for (int mt = 0; mt < mtiles; ++mt)
+    for (int t = 0; t < ktiles16; ++t)
+      for (int v = 0; v < 4; ++v)
+        for (int l = 0; l < 64; ++l)
+          out[base + (((int64_t)mt * ktiles16 + t) * 4 + v) * 64 + l] =
+              wfun(16 * mt + (l & 15), chained ? kfeat64c(t, v, l) : kfeat64(t, v, l));
+}
+template <class F>
+void frag_block32(std::vector<float>& out, int64_t base, int mtiles, int ktiles32, F wfun) {
+  for (int mt = 0; mt < mtiles; ++mt)
+    for (int t = 0; t < ktiles32; ++t)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j)
+          out[base + (((int64_t)mt * ktiles32 + t) * 64 + l) * 8 + j] = (float)wfun(16 * mt + (l & 15), kfeat32(t, l, j));
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(model)");
+  return DP_OK;
+}
+
+int upload_lp(uint16_t** bf, uint16_t** hf, const std::vector<float>& v) {
+  std::vector<uint16_t> b(v.size()), h(v.size());
+  for (size_t k = 0; k < v.size(); ++k) {
+    b[k] = f32_to_bf16(v[k]);
+    h[k] = f32_to_f16(v[k]);
+  }
+  int rc;
+  if ((rc = dev_alloc(bf, v.size(), "hipMalloc(frag bf16)"))) return rc;
+  if ((rc = dev_alloc(hf, v.size(), "hipMalloc(frag f16)"))) return rc;
+  if ((rc = upload(*bf, b.data(), b.size() * 2))) return rc;
+  return upload(*hf, h.data(), h.size() * 2);
+}
+
+void free_model(dp_model* m) {
+  if (!m) return;
+  void* ptrs[] = {m->params, m->emb_vec64, m->emb_vec32, m->emb_frag64, m->emb_frag_bf16, m->emb_frag_f16,
+                  m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_vec64, m->fit_vec32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+// Derives every device copy of the parameters.
+int prepare_model(dp_model* m, const double* P) {
+  const dp_model_desc& d = m->desc;
+  const ParamLayout L = layout_of(&d);
+  const int w = m->w1, nt = d.ntypes, fw = m->fw, nd = m->nd;
+  const int nnets = nt * nt;
+  int rc;
+  // ---- embedding vectors
+  m->emb_vec_per_net = 384;
+  std::vector<double> ev((size_t)nnets * 384, 0.0);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      double* v = &ev[(size_t)(a * nt + b) * 384];
+      for (int p = 0; p < 32; ++p) {
+        const int f = feat1(w, p);
+        if (f >= 0) { v[p] = P[L.embW[a][b][0] + f]; v[32 + p] = P[L.embB[a][b][0] + f]; }
+      }
+      for (int p = 0; p < 64; ++p) {
+        const int f = feat2(w, p);
+        if (f >= 0) v[64 + p] = P[L.embB[a][b][1] + f];
+      }
+      for (int p = 0; p < 128; ++p) {
+        const int f = feat3(w, p);
+        if (f >= 0) v[128 + p] = P[L.embB[a][b][2] + f];
+      }
+      for (int f = 0; f < 4 * w; ++f) v[256 + f] = P[L.embB[a][b][2] + f];
+    }
+  std::vector<float> ev32(ev.begin(), ev.end());
+  // ---- embedding fragments (same element counts for both kinds)
+  EmbFragOffsets& fo = m->efo;
+  fo.F2 = 0;
+  fo.F3n = fo.F2 + 2048;
+  fo.F3t = fo.F3n + (int64_t)m->n3 * 1024;
+  fo.B3 = fo.F3t + 8192;
+  fo.B2 = fo.B3 + 8192;
+  fo.per_net = fo.B2 + 2048;
+  std::vector<double> e64((size_t)nnets * fo.per_net, 0.0);
+  std::vector<float> e32((size_t)nnets * fo.per_net, 0.f);
+  const int m1 = 4 * w;
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      const double* W2 = P + L.embW[a][b][1];  // [w][2w]
+      const double* W3 = P + L.embW[a][b][2];  // [2w][4w]
+      const int64_t base = (int64_t)(a * nt + b) * fo.per_net;
+      auto w2 = [&](int in_slot, int out_slot) -> double {  // slots of layer 1 -> layer 2
+        const int fi = feat1(w, in_slot), fo2 = feat2(w, out_slot);
+        return (fi < 0 || fo2 < 0) ? 0.0 : W2[(int64_t)fi * 2 * w + fo2];
+      };
+      auto w3s = [&](int in_slot, int out_slot) -> double {  // layer-2 slot -> layer-3 slot
+        if (in_slot >= 64 || out_slot >= 128) return 0.0;
+        const int fi = feat2(w, in_slot), fo3 = feat3(w, out_slot);
+        return (fi < 0 || fo3 < 0) ? 0.0 : W3[(int64_t)fi * 4 * w + fo3];
+      };
+      auto w3f = [&](int in_slot, int out_feat) -> double {  // layer-2 slot -> layer-3 feature
+        const int fi = feat2(w, in_slot);
+        return (fi < 0 || out_feat >= m1) ? 0.0 : W3[(int64_t)fi * 4 * w + out_feat];
+      };
+      // forward (A operand W^T: m = out, k = in)
+      frag_block64(e64, base + fo.F2, 4, 2, [&](int mo, int ki) { return w2(ki, mo); }, true);
+      frag_block32(e32, base + fo.F2, 4, 1, [&](int mo, int ki) { return w2(ki, mo); });
+      frag_block64(e64, base + fo.F3n, m->n3, 4, [&](int mo, int ki) { return w3f(ki, mo); }, true);
+      frag_block32(e32, base + fo.F3n, m->n3, 2, [&](int mo, int ki) { return w3f(ki, mo); });
+      frag_block64(e64, base + fo.F3t, 8, 4, [&](int mo, int ki) { return w3s(ki, mo); }, true);
+      frag_block32(e32, base + fo.F3t, 8, 2, [&](int mo, int ki) { return w3s(ki, mo); });
+      // backward (A operand W: m = in, k = out)
+      frag_block64(e64, base + fo.B3, 4, 8, [&](int mi, int ko) { return w3s(mi, ko); }, true);
+      frag_block32(e32, base + fo.B3, 4, 4, [&](int mi, int ko) { return w3s(mi, ko); });
+      frag_block64(e64, base + fo.B2, 2, 4, [&](int mi, int ko) { return w2(mi, ko); }, true);
+      frag_block32(e32, base + fo.B2, 2, 2, [&](int mi, int ko) { return w2(mi, ko); });
+    }
+  // ---- fitting fragments
+  const int fwp = ((fw + 31) / 32) * 32;
+  FitFragOffsets& ff = m->ffo;
+  FitFragOffsets& fl = m->ffo_lp;
+  const int Kin[3] = {nd, fw, fw};
+  {
+    int64_t o = 0, ol = 0;
+    for (int l = 0; l < 3; ++l) {
+      ff.fwd[l] = o; o += (int64_t)fw * Kin[l];
+      fl.fwd[l] = ol; ol += (int64_t)fw * (((Kin[l] + 31) / 32) * 32);
+    }
+    for (int l = 0; l < 3; ++l) {
+      ff.bwd[l] = o; o += (int64_t)Kin[l] * fw;
+      fl.bwd[l] = ol; ol += (int64_t)Kin[l] * fwp;
+    }
+    ff.per_type = o;
+    fl.per_type = ol;
+  }
+  std::vector<double> f64v((size_t)nt * ff.per_type, 0.0);
+  std::vector<float> f32v((size_t)nt * fl.per_type, 0.f);
+  for (int t = 0; t < nt; ++t) {
+    for (int l = 0; l < 3; ++l) {
+      const double* W = P + L.fitW[t][l];  // [Kin][fw]
+      const int K = Kin[l];
+      auto wf = [&](int mo, int ki) -> double { return (ki < K && mo < fw) ? W[(int64_t)ki * fw + mo] : 0.0; };
+      auto wb = [&](int mi, int ko) -> double { return (mi < K && ko < fw) ? W[(int64_t)mi * fw + ko] : 0.0; };
+      frag_block64(f64v, t * ff.per_type + ff.fwd[l], fw / 16, K / 16, wf, false);
+      frag_block32(f32v, t * fl.per_type + fl.fwd[l], fw / 16, (K + 31) / 32, wf);
+      frag_block64(f64v, t * ff.per_type + ff.bwd[l], K / 16, fw / 16, wb, false);
+      frag_block32(f32v, t * fl.per_type + fl.bwd[l], K / 16, fwp / 32, wb);
+    }
+  }
+  // ---- fitting vectors: b1 b2 b3 wo | bo ebias
+  m->fit_vec_per_type = 4 * fw + 2;
+  std::vector<double> fv((size_t)nt * m->fit_vec_per_type, 0.0);
+  for (int t = 0; t < nt; ++t) {
+    double* v = &fv[(size_t)t * m->fit_vec_per_type];
+    for (int l = 0; l < 3; ++l)
+      for (int k = 0; k < fw; ++k) v[l * fw + k] = P[L.fitB[t][l] + k];
+    for (int k = 0; k < fw; ++k) v[3 * fw + k] = P[L.wo[t] + k];
+    v[4 * fw] = P[L.bo[t]];
+    v[4 * fw + 1] = P[L.ebias + t];
+  }
+  std::vector<float> fv32(fv.begin(), fv.end());
+  // ---- upload
+  if (!m->emb_vec64) {
+    if ((rc = dev_alloc(&m->params, (size_t)m->n_params, "hipMalloc(params)"))) return rc;
+    if ((rc = dev_alloc(&m->emb_vec64, ev.size(), "hipMalloc(emb vec)"))) return rc;
+    if ((rc = dev_alloc(&m->emb_vec32, ev32.size(), "hipMalloc(emb vec32)"))) return rc;
+    if ((rc = dev_alloc(&m->emb_frag64, e64.size(), "hipMalloc(emb frag)"))) return rc;
+    if ((rc = dev_alloc(&m->fit_frag64, f64v.size(), "hipMalloc(fit frag)"))) return rc;
+    if ((rc = dev_alloc(&m->fit_vec64, fv.size(), "hipMalloc(fit vec)"))) return rc;
+    if ((rc = dev_alloc(&m->fit_vec32, fv32.size(), "hipMalloc(fit vec32)"))) return rc;
+  } else {
+    (void)hipFree(m->emb_frag_bf16); (void)hipFree(m->emb_frag_f16);
+    (void)hipFree(m->fit_frag_bf16); (void)hipFree(m->fit_frag_f16);
+  }
+  if ((rc = upload(m->params, P, (size_t)m->n_params * 8))) return rc;
+  if ((rc = upload(m->emb_vec64, ev.data(), ev.size() * 8))) return rc;
+  if ((rc = upload(m->emb_vec32, ev32.data(), ev32.size() * 4))) return rc;
+  if ((rc = upload(m->emb_frag64, e64.data(), e64.size() * 8))) return rc;
+  if ((rc = upload(m->fit_frag64, f64v.data(), f64v.size() * 8))) return rc;
+  if ((rc = upload(m->fit_vec64, fv.data(), fv.size() * 8))) return rc;
+  if ((rc = upload(m->fit_vec32, fv32.data(), fv32.size() * 4))) return rc;
+  if ((rc = upload_lp(&m->emb_frag_bf16, &m->emb_frag_f16, e32))) return rc;
+  if ((rc = upload_lp(&m->fit_frag_bf16, &m->fit_frag_f16, f32v))) return rc;
+  return DP_OK;
+}
+
+// ------------------------------------------------------------ frames
+int check_box(const double* box, double rc, double L[3]) {
+  if (!box) { set_error("box is NULL"); return DP_ERR_BAD_ARG; }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      if (a != b && box[3 * a + b] != 0.0) {
+        set_error("box must be orthorhombic (diagonal) for the GPU path");
+        return DP_ERR_UNSUPPORTED;
+      }
+  for (int a = 0; a < 3; ++a) {
+    L[a] = box[4 * a];
+    if (!(L[a] > 0) || !std::isfinite(L[a])) { set_error("box edge %d not positive/finite", a); return DP_ERR_BAD_ARG; }
+    if (!(rc < L[a])) { set_error("cut-off %.6g must be below every box edge (edge %d = %.6g)", rc, a, L[a]); return DP_ERR_UNSUPPORTED; }
+  }
+  return DP_OK;
+}
+
+// Fills the pinned frame table and queues its upload.  Returns the total
+// number of cells in *ncells.
+int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nframes, hipStream_t s, int64_t* ncells) {
+  if (nframes < 1 || nframes > c->max_frames) {
+    set_error("nframes %d out of [1, %d]", nframes, c->max_frames);
+    return DP_ERR_CAPACITY;
+  }
+  if (c->frames_ev_pending) {
+    HIPCHECK(hipEventSynchronize(c->frames_ev));
+    c->frames_ev_pending = false;
+  }
+  const double rc = c->model->desc.rcut;
+  int64_t cells = 0;
+  for (int f = 0; f < nframes; ++f) {
+    double L[3];
+    int rcb = check_box(boxes + 9 * f, rc, L);
+    if (rcb) return rcb;
+    const int64_t a0 = off[f], a1 = off[f + 1];
+    if (a0 < 0 || a1 < a0) { set_error("frame offsets must be non-decreasing from 0"); return DP_ERR_BAD_ARG; }
+    FrameInfo& F = c->frames_host[f];
+    F.atom_off = (int32_t)a0;
+    F.natoms = (int32_t)(a1 - a0);
+    F.cell_off = (int32_t)cells;
+    int64_t nc = 1;
+    for (int a = 0; a < 3; ++a) {
+      int k = (int)std::floor(L[a] / (rc * (1.0 + 1e-10)));
+      if (k < 1) k = 1;
+      if (k > 1024) k = 1024;
+      F.ncell[a] = k;
+      F.L[a] = L[a];
+      nc *= k;
+    }
+    cells += nc;
+  }
+  if (off[0] != 0) { set_error("frame_off[0] must be 0"); return DP_ERR_BAD_ARG; }
+  if (off[nframes] > c->max_atoms) { set_error("%lld atoms exceed max_atoms %lld", (long long)off[nframes], (long long)c->max_atoms); return DP_ERR_CAPACITY; }
+  if (cells > c->max_cells) { set_error("%lld cells exceed the context capacity %lld", (long long)cells, (long long)c->max_cells); return DP_ERR_CAPACITY; }
+  HIPCHECK(hipMemcpyAsync(c->frames_dev, c->frames_host, sizeof(FrameInfo) * nframes, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipEventRecord(c->frames_ev, s));
+  c->frames_ev_pending = true;
+  c->nframes_last = nframes;
+  *ncells = cells;
+  return DP_OK;
+}
+
+// ------------------------------------------------------------ stage timing
+void prof_harvest(dp_ctx* c) {
+  for (int k = 0; k < c->prof_n; ++k) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(c->prof_ev[2 * k + 1]);
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]) == hipSuccess) {
+      c->prof_ms[c->prof_stage[k]] += ms;
+      c->prof_cnt[c->prof_stage[k]] += 1;
+    }
+  }
+  c->prof_n = 0;
+}
+
+struct StageScope {
+  dp_ctx* c;
+  int k;
+  hipStream_t s;
+  StageScope(dp_ctx* ctx, int stage, hipStream_t st) : c(ctx), k(-1), s(st) {
+    if (!c->prof_ev) return;
+    if (c->prof_n == c->prof_cap) prof_harvest(c);
+    k = c->prof_n++;
+    c->prof_stage[k] = stage;
+    (void)hipEventRecord(c->prof_ev[2 * k], s);
+  }
+  ~StageScope() {
+    if (k >= 0) (void)hipEventRecord(c->prof_ev[2 * k + 1], s);
+  }
+};
+
+int check_mode(int32_t mode) {
+  if (mode != DP_FP64 && mode != DP_MIX_BF16 && mode != DP_MIX_FP16) {
+    set_error("mode %d is not DP_FP64/DP_MIX_BF16/DP_MIX_FP16", mode);
+    return DP_ERR_BAD_ARG;
+  }
+  return DP_OK;
+}
+
+int set_device(int dev) {
+  HIPCHECK(hipSetDevice(dev));
+  return DP_OK;
+}
+
+int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double* boxes, const int64_t* off,
+                 int32_t nframes, const int32_t* nlist, int32_t mode, double* energies, double* atom_energy,
+                 double* forces, double* virials, hipStream_t s) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  int rc = check_mode(mode);
+  if (rc) return rc;
+  const int64_t n = off ? off[nframes] : 0;
+  if (n > 0 && (!x || !types || !nlist || !forces)) { set_error("coords/types/nlist/forces must be non-NULL"); return DP_ERR_BAD_ARG; }
+  if (!energies || !virials) { set_error("energy/virial outputs must be non-NULL"); return DP_ERR_BAD_ARG; }
+  if ((rc = set_device(c->device))) return rc;
+  int64_t ncells = 0;
+  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells))) return rc;
+  c->natoms_last = n;
+  c->types_last = types;
+  c->mode_last = mode;
+  c->last_stream = s;
+  const int32_t ntot = (int32_t)n;
+  { StageScope p(c, DP_STAGE_TYPESORT, s); launch_type_sort(c, types, ntot, nframes, s); }
+  { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, s); }
+  { StageScope p(c, DP_STAGE_EMBED_FWD, s); launch_embed_fwd(c, types, mode, s); }
+  { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
+  { StageScope p(c, DP_STAGE_FIT_FWD, s); launch_fit_forward(c, mode, s); }
+  { StageScope p(c, DP_STAGE_FIT_BWD, s); launch_fit_backward(c, mode, s); }
+  { StageScope p(c, DP_STAGE_DESC_BWD, s); launch_desc_bwd(c, mode, s); }
+  { StageScope p(c, DP_STAGE_EMBED_BWD, s); launch_embed_bwd(c, types, mode, s); }
+  { StageScope p(c, DP_STAGE_FORCE, s); launch_force(c, x, nlist, ntot, forces, s); }
+  { StageScope p(c, DP_STAGE_REDUCE, s); launch_frame_reduce(c, nframes, energies, atom_energy, virials, s); }
+  HIPCHECK(hipGetLastError());
+  c->have_state = true;
+  return DP_OK;
+}
+
+int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* boxes, const int64_t* off,
+               int32_t nframes, int32_t* nlist, int32_t* overflow, hipStream_t s) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  if (!overflow) { set_error("n_overflow_out must be non-NULL"); return DP_ERR_BAD_ARG; }
+  const int64_t n = off[nframes];
+  if (n > 0 && (!x || !types || !nlist)) { set_error("coords/types/nlist must be non-NULL"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  int64_t ncells = 0;
+  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells))) return rc;
+  c->last_stream = s;
+  const int32_t ntot = (int32_t)n;
+  StageScope p(c, DP_STAGE_NLIST, s);
+  launch_fill_i32(overflow, 0, 1, s);
+  launch_fill_i32(c->cell_count, 0, ncells, s);
+  launch_nl_bin(c, x, ntot, nframes, s);
+  launch_nl_scan(c, (int32_t)ncells, s);
+  launch_nl_scatter(c, ntot, s);
+  launch_nl_search(c, x, types, ntot, nframes, nlist, overflow, s);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+const char* dp_last_error(void) { return g_err; }
+
+int64_t dp_model_n_params(const dp_model_desc* desc) {
+  if (!desc || desc->ntypes < 1 || desc->ntypes > DP_MAX_TYPES || desc->n_emb < 1 || desc->n_emb > DP_MAX_LAYERS ||
+      desc->n_fit < 1 || desc->n_fit > DP_MAX_LAYERS) {
+    set_error("bad descriptor");
+    return DP_ERR_BAD_ARG;
+  }
+  return layout_of(desc).total;
+}
+
+int dp_model_create(const dp_model_desc* desc, const double* params_host, int64_t n_params, dp_model** out) {
+  if (!out) { set_error("out is NULL"); return DP_ERR_BAD_ARG; }
+  *out = nullptr;
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  const int64_t need = layout_of(desc).total;
+  if (!params_host || n_params != need) {
+    set_error("params: expected %lld values, got %lld", (long long)need, (long long)n_params);
+    return DP_ERR_BAD_ARG;
+  }
+  for (int64_t k = 0; k < n_params; ++k)
+    if (!std::isfinite(params_host[k])) { set_error("parameter %lld is not finite", (long long)k); return DP_ERR_BAD_ARG; }
+  dp_model* m = new dp_model;
+  memset(m, 0, sizeof(*m));
+  m->desc = *desc;
+  m->nm = 0;
+  m->sec[0] = 0;
+  for (int t = 0; t < desc->ntypes; ++t) {
+    m->sec[t + 1] = m->sec[t] + desc->sel[t];
+    m->nm += desc->sel[t];
+  }
+  for (int t = desc->ntypes + 1; t <= DP_MAX_TYPES; ++t) m->sec[t] = m->nm;
+  m->w1 = desc->emb[0];
+  m->m1 = desc->emb[2];
+  m->n3 = (m->m1 + 15) / 16;
+  m->nd = m->m1 * desc->m2;
+  m->fw = desc->fit[0];
+  m->n_params = n_params;
+  hipError_t e = hipGetDevice(&m->device);
+  if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
+  rc = prepare_model(m, params_host);
+  if (rc) { free_model(m); return rc; }
+  *out = m;
+  return DP_OK;
+}
+
+int dp_model_set_params(dp_model* m, const double* params_host, int64_t n_params) {
+  if (!m || !params_host || n_params != m->n_params) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(m->device))) return rc;
+  HIPCHECK(hipDeviceSynchronize());
+  return prepare_model(m, params_host);
+}
+
+int dp_model_destroy(dp_model* m) {
+  if (!m) return DP_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  free_model(m);
+  return DP_OK;
+}
+
+int dp_ctx_destroy(dp_ctx* c);
+
+int dp_ctx_profile(dp_ctx* c, int32_t enable) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  if (c->prof_ev) {
+    (void)hipDeviceSynchronize();
+    for (int k = 0; k < 2 * c->prof_cap; ++k) (void)hipEventDestroy(c->prof_ev[k]);
+    delete[] c->prof_ev;
+    delete[] c->prof_stage;
+    c->prof_ev = nullptr;
+    c->prof_stage = nullptr;
+    c->prof_cap = c->prof_n = 0;
+  }
+  for (int k = 0; k < DP_NSTAGES; ++k) { c->prof_ms[k] = 0; c->prof_cnt[k] = 0; }
+  if (!enable) return DP_OK;
+  const int cap = 4096;
+  c->prof_ev = new hipEvent_t[2 * cap];
+  c->prof_stage = new int32_t[cap];
+  for (int k = 0; k < 2 * cap; ++k) HIPCHECK(hipEventCreate(&c->prof_ev[k]));
+  c->prof_cap = cap;
+  return DP_OK;
+}
+
+int dp_ctx_stage_times(dp_ctx* c, double* total_ms, int64_t* counts) {
+  if (!c || !total_ms || !counts) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  prof_harvest(c);
+  for (int k = 0; k < DP_NSTAGES; ++k) {
+    total_ms[k] = c->prof_ms[k];
+    counts[k] = c->prof_cnt[k];
+    c->prof_ms[k] = 0;
+    c->prof_cnt[k] = 0;
+  }
+  return DP_OK;
+}
+
+int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int64_t workspace_budget_bytes,
+                  dp_ctx** out) {
+  if (!out) { set_error("out is NULL"); return DP_ERR_BAD_ARG; }
+  *out = nullptr;
+  if (!m) { set_error("model is NULL"); return DP_ERR_BAD_ARG; }
+  if (max_atoms < 1 || max_atoms > (int64_t)INT32_MAX / 27 - 1) { set_error("max_atoms out of range"); return DP_ERR_BAD_ARG; }
+  if (max_frames < 1 || max_frames > 1 << 20) { set_error("max_frames out of range"); return DP_ERR_BAD_ARG; }
+  if (workspace_budget_bytes < 0) { set_error("negative workspace budget"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(m->device))) return rc;
+  dp_ctx* c = new dp_ctx;
+  memset(c, 0, sizeof(*c));
+  c->model = m;
+  c->device = m->device;
+  c->max_atoms = max_atoms;
+  c->max_frames = max_frames;
+  c->max_cols = max_atoms + (int64_t)m->desc.ntypes * kColPad;
+  c->max_cells = max_atoms + 27LL * max_frames + 1024;
+  const int64_t N = max_atoms, C = c->max_cols;
+  const int nm = m->nm, m1 = m->m1, nd = m->nd;
+  const int fwp = ((m->fw + 31) / 32) * 32;
+  const int nchunks = (int)((N + 1023) / 1024);
+#define ALLOC(ptr, cnt)                                            \
+  if ((rc = dev_alloc(&(ptr), (size_t)(cnt), "hipMalloc(ctx)"))) { \
+    dp_ctx_destroy(c);                                             \
+    return rc;                                                     \
+  }
+  ALLOC(c->frames_dev, max_frames);
+  {
+    hipError_t e = hipHostMalloc((void**)&c->frames_host, sizeof(FrameInfo) * max_frames, hipHostMallocDefault);
+    if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "hipHostMalloc(frames)"); }
+    e = hipHostMalloc((void**)&c->flags_host, sizeof(int32_t), hipHostMallocDefault);
+    if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "hipHostMalloc(flags)"); }
+    e = hipEventCreateWithFlags(&c->frames_ev, hipEventDisableTiming);
+    if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "hipEventCreate"); }
+  }
+  ALLOC(c->flags_dev, 1);
+  ALLOC(c->cell_of, N);
+  ALLOC(c->cell_count, c->max_cells + 1);
+  ALLOC(c->cell_start, c->max_cells + 1);
+  ALLOC(c->cell_fill, c->max_cells + 1);
+  ALLOC(c->cell_atoms, N);
+  ALLOC(c->chunk_counts, (int64_t)nchunks * kMaxT + kMaxT);
+  ALLOC(c->type_meta, 2 * kMaxT);
+  ALLOC(c->col_of, N);
+  ALLOC(c->atom_at, C);
+  ALLOC(c->frame_of, N);
+  ALLOC(c->R, N * nm * 4);
+  ALLOC(c->nnei, N * kMaxT);
+  ALLOC(c->netd, N * nm * 4);
+  ALLOC(c->vatom, N * 9);
+  ALLOC(c->Ei_col, C);
+  ALLOC(c->Ei_atom, N);
+  ALLOC(c->gE_col, C);
+  ALLOC(c->grad_tmp, m->n_params);
+  double* tmp = nullptr;
+  ALLOC(tmp, C * m1 * 4); c->T = tmp;
+  ALLOC(tmp, C * nd); c->D = tmp;
+  ALLOC(tmp, C * nd); c->dD = tmp;
+  ALLOC(tmp, C * m1 * 4); c->gT = tmp;
+  for (int k = 0; k < 12; ++k) {
+    ALLOC(tmp, C * fwp);
+    c->fa[k] = tmp;
+  }
+#undef ALLOC
+  // zero-initialise every buffer once: padding columns of the mixed-precision
+  // activations (features fw..fwp) must hold finite zeros forever.
+  {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 12 && e == hipSuccess; ++k) e = hipMemset(c->fa[k], 0, (size_t)C * fwp * 8);
+    if (e == hipSuccess) e = hipMemset(c->D, 0, (size_t)C * nd * 8);
+    if (e == hipSuccess) e = hipMemset(c->flags_dev, 0, 4);
+    if (e == hipSuccess) e = hipMemset(c->netd, 0, (size_t)N * nm * 4 * 8);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "ctx init"); }
+  }
+  (void)workspace_budget_bytes;
+  *out = c;
+  return DP_OK;
+}
+
+int dp_ctx_destroy(dp_ctx* c) {
+  if (!c) return DP_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
+                  c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
+                  c->netd, c->vatom, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->T, c->D, c->dD, c->gT};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int k = 0; k < 12; ++k)
+    if (c->fa[k]) (void)hipFree(c->fa[k]);
+  dp_ctx_profile(c, 0);
+  if (c->frames_host) (void)hipHostFree(c->frames_host);
+  if (c->flags_host) (void)hipHostFree(c->flags_host);
+  if (c->frames_ev) (void)hipEventDestroy(c->frames_ev);
+  delete c;
+  return DP_OK;
+}
+
+int dp_build_nlist(dp_ctx* c, const double* coords, const int32_t* types, const double* box, int64_t n,
+                   int32_t* nlist_out, int32_t* n_overflow_out, hipStream_t stream) {
+  if (n < 0) { set_error("n < 0"); return DP_ERR_BAD_ARG; }
+  const int64_t off[2] = {0, n};
+  return nlist_impl(c, coords, types, box, off, 1, nlist_out, n_overflow_out, stream);
+}
+
+int dp_build_nlist_batch(dp_ctx* c, const double* coords, const int32_t* types, const double* boxes,
+                         const int64_t* frame_off, int32_t nframes, int32_t* nlist_out, int32_t* n_overflow_out,
+                         hipStream_t stream) {
+  if (!boxes || !frame_off) { set_error("boxes/frame_off are NULL"); return DP_ERR_BAD_ARG; }
+  return nlist_impl(c, coords, types, boxes, frame_off, nframes, nlist_out, n_overflow_out, stream);
+}
+
+int dp_compute(dp_ctx* c, const double* coords, const int32_t* types, const double* box, int64_t n,
+               const int32_t* nlist, int32_t mode, double* energy, double* atom_energy, double* forces,
+               double* virial, hipStream_t stream) {
+  if (n < 0) { set_error("n < 0"); return DP_ERR_BAD_ARG; }
+  const int64_t off[2] = {0, n};
+  return compute_impl(c, coords, types, box, off, 1, nlist, mode, energy, atom_energy, forces, virial, stream);
+}
+
+int dp_compute_batch(dp_ctx* c, const double* coords, const int32_t* types, const double* boxes,
+                     const int64_t* frame_off, int32_t nframes, const int32_t* nlist, int32_t mode,
+                     double* energies, double* forces, double* virials, hipStream_t stream) {
+  if (!boxes || !frame_off) { set_error("boxes/frame_off are NULL"); return DP_ERR_BAD_ARG; }
+  return compute_impl(c, coords, types, boxes, frame_off, nframes, nlist, mode, energies, nullptr, forces, virials,
+                      stream);
+}
+
+int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipStream_t stream) {
+  if (!c || !dL_dE || !grad_params) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
+  if (!c->have_state) { set_error("dp_backward_params needs a preceding dp_compute"); return DP_ERR_STATE; }
+  (void)stream;
+  set_error("parameter gradients are not implemented yet");
+  return DP_ERR_UNSUPPORTED;
+}
+
+int dp_md_kick_drift(dp_ctx* c, double* coords, double* vel, const double* forces, const int32_t* types,
+                     const double* box, int64_t n, double dt, int32_t* images, hipStream_t stream) {
+  if (!c || n < 0 || (n > 0 && (!coords || !vel || !forces || !types))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (n > c->max_atoms) { set_error("n exceeds max_atoms"); return DP_ERR_CAPACITY; }
+  if (!std::isfinite(dt)) { set_error("dt not finite"); return DP_ERR_BAD_ARG; }
+  double L[3];
+  int rc = check_box(box, c->model->desc.rcut, L);
+  if (rc) return rc;
+  if ((rc = set_device(c->device))) return rc;
+  StageScope p(c, DP_STAGE_MD, stream);
+  launch_kick_drift(c, coords, vel, forces, types, (int32_t)n, dt, L, images, stream);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+int dp_md_kick(dp_ctx* c, double* vel, const double* forces, const int32_t* types, int64_t n, double dt, double* ke,
+               hipStream_t stream) {
+  if (!c || n < 0 || !ke || (n > 0 && (!vel || !forces || !types))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (n > c->max_atoms) { set_error("n exceeds max_atoms"); return DP_ERR_CAPACITY; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  StageScope p(c, DP_STAGE_MD, stream);
+  launch_kick(c, vel, forces, types, (int32_t)n, dt, ke, stream);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+int dp_ctx_status(dp_ctx* c, int32_t* flags) {
+  if (!c || !flags) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  HIPCHECK(hipStreamSynchronize(c->last_stream));
+  HIPCHECK(hipMemcpy(c->flags_host, c->flags_dev, 4, hipMemcpyDeviceToHost));
+  *flags = *c->flags_host;
+  launch_fill_i32(c->flags_dev, 0, 1, c->last_stream);
+  HIPCHECK(hipStreamSynchronize(c->last_stream));
+  return DP_OK;
+}
+
+int dp_ctx_copy_buffer(dp_ctx* c, int32_t which, void* dst, int64_t* nbytes, hipStream_t stream) {
+  if (!c || !nbytes) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
+  const dp_model* m = c->model;
+  const int64_t n = c->natoms_last;
+  int64_t bytes;
+  switch (which) {
+    case 0: case 4: bytes = n * m->nm * 4 * 8; break;
+    case 1: bytes = n * m->m1 * 4 * 8; break;
+    case 2: case 3: bytes = n * m->nd * 8; break;
+    default: set_error("which %d out of range", which); return DP_ERR_BAD_ARG;
+  }
+  *nbytes = bytes;
+  if (!dst) return DP_OK;
+  if (!c->have_state) { set_error("no compute on this context yet"); return DP_ERR_STATE; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  if (which == 0) HIPCHECK(hipMemcpyAsync(dst, c->R, bytes, hipMemcpyDeviceToDevice, stream));
+  else if (which == 4) HIPCHECK(hipMemcpyAsync(dst, c->netd, bytes, hipMemcpyDeviceToDevice, stream));
+  else launch_gather_cols(c, which, c->mode_last, (int32_t)n, (double*)dst, stream);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+}  // extern "C"

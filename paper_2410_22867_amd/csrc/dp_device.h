@@ -1,0 +1,152 @@
+// Device-side helpers: matrix-core (MFMA) wrappers for gfx950, precision
+// traits, activation functions and wavefront utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpse {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// MFMA operand layouts on gfx950 (wave64; measured):
+//   f64 16x16x4 : A[m][k] at lane m + 16k;  B[k][n] at lane n + 16k;
+//                 D[m][n] at lane n + 16*(m%4), element m/4.
+//   16x16x32 bf16/f16 : A[m][k] at lane m + 16*(k/8), element k%8;
+//                 B[k][n] at lane n + 16*(k/8), element k%8;
+//                 D[m][n] (f32) at lane n + 16*(m/4), element m%4.
+// A D-layout tile (m = feature, n = row) therefore serves unchanged as the
+// B operand of the next product (k = feature, n = row) and as the A operand
+// of a product with rows as m, once the k index is permuted as below.
+//   f64 k-step (t, v)   : lane group g supplies feature 16t + 4v + g
+//   16x16x32 k-step t, element j : lane group g supplies
+//                         feature 32t + 16(j/4) + 4g + (j%4)
+// Operands read from memory may use any k order that A and B share; the
+// FP64 fitting GEMM uses 16t + 4g + v there (4 contiguous values per lane).
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct PrecBF16 {
+  typedef bf16x8 vec8;
+  static __device__ __forceinline__ f4 mfma(vec8 a, vec8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint16_t bits(float x) {
+    __bf16 h = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, h);
+  }
+  static __device__ __forceinline__ float tof(uint16_t b) {
+    return __builtin_bit_cast(float, ((uint32_t)b) << 16);
+  }
+};
+
+struct PrecF16 {
+  typedef h16x8 vec8;
+  static __device__ __forceinline__ f4 mfma(vec8 a, vec8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint16_t bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+  }
+  static __device__ __forceinline__ float tof(uint16_t b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+  }
+};
+
+// Packs 8 floats into the 8-element operand of a 16x16x32 MFMA.
+template <class P>
+__device__ __forceinline__ typename P::vec8 pack8(const float* x) {
+  u16x8 u;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) u[j] = P::bits(x[j]);
+  return __builtin_bit_cast(typename P::vec8, u);
+}
+
+template <class P>
+__device__ __forceinline__ typename P::vec8 load8(const uint16_t* p) {
+  u16x8 u = *reinterpret_cast<const u16x8*>(p);
+  return __builtin_bit_cast(typename P::vec8, u);
+}
+
+// ---------------------------------------------------------------------------
+// Activations.  FP32 (mixed forms): 1 - 2/(e^{2x}+1) with the hardware exp2
+// and reciprocal; saturates correctly at +-inf.
+// FP64 tanh(x) = 1 - 2 / (e^{2x} + 1).  e^{y} with Cody-Waite reduction
+// y = n ln2 + r (ln 2 split in a 32-bit head and a tail, so n*head is exact),
+// |r| <= ln2/2, and the Taylor series of e^r to degree 13 (truncation below
+// 1e-17 relative); the reciprocal is the hardware estimate refined by two
+// Newton steps.  Absolute error about 2e-16; relative accuracy is lost only
+// for |x| below ~1e-3, where the absolute error still is ~1e-16.
+__device__ __forceinline__ double tanh_d(double x) {
+  double y = 2.0 * x;
+  y = y > 40.0 ? 40.0 : (y < -40.0 ? -40.0 : y);
+  const double n = rint(y * 1.4426950408889634);
+  double r = fma(-n, 0.6931471803691238, y);
+  r = fma(-n, 1.9082149292705877e-10, r);
+  double p = 1.6059043836821613e-10;
+  p = fma(p, r, 2.08767569878681e-09);
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.7557319223985893e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 0.0001984126984126984);
+  p = fma(p, r, 0.001388888888888889);
+  p = fma(p, r, 0.008333333333333333);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const double e = __builtin_amdgcn_ldexp(p, (int)n);
+  const double d = e + 1.0;
+  double q = __builtin_amdgcn_rcp(d);
+  q = q * fma(-d, q, 2.0);
+  q = q * fma(-d, q, 2.0);
+  return fma(-2.0, q, 1.0);
+}
+
+__device__ __forceinline__ float tanh_f(float x) {
+  float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2/ln 2
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, 64); }
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Orders the LDS traffic of one wavefront (lanes exchange data through LDS
+// inside a wave-private region without a work-group barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hides a pointer's value from the optimiser for one loop iteration so that
+// loads through it are not hoisted out of the loop (the weight fragments are
+// loop-invariant across neighbour tiles; keeping all of them in registers
+// would exhaust the register file).
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
+__device__ __forceinline__ void set_flag(int32_t* flags, int32_t bit) { atomicOr(flags, bit); }
+
+}  // namespace dpse

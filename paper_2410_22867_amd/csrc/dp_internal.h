@@ -1,0 +1,177 @@
+// Internal structures of libdpse shared by the host driver and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dp.h"
+
+namespace dpse {
+
+constexpr int kMaxT = DP_MAX_TYPES;
+constexpr int kColPad = 128;     // fitting-GEMM column tile; type segments are padded to it
+constexpr int kCandCap = 512;    // neighbour candidates inside r_c per atom (LDS capacity)
+constexpr int kMaxNm = 1024;     // sum(sel)
+
+// Slot layout of the embedding activations (see k_embed.hip): widths
+// (w, 2w, 4w) with w <= 32 occupy 32, 64 and 128 slots.
+constexpr int kP1 = 32, kP2 = 64, kP3 = 128;
+
+// Per-frame table (device).
+struct FrameInfo {
+  int32_t atom_off;   // first atom
+  int32_t natoms;
+  int32_t cell_off;   // first cell of the frame's grid
+  int32_t ncell[3];
+  double L[3];        // orthorhombic edges
+};
+
+// Fragment-arranged weights of one embedding net in one precision.
+// Element counts (per net) for every precision:
+//   F2   : fwd layer 2 (T layout)        4 ot x 32 in-slots  x 16 = 2048
+//   F3n  : fwd layer 3, rows as M        n3 ot x 64 in-slots x 16 (n3 = m1/16 rounded up)
+//   F3t  : fwd layer 3 (T layout)        8 ot x 64 x 16 = 8192
+//   B3   : bwd dh2 = W3 dz3              4 it x 128 x 16 = 8192
+//   B2   : bwd dh1 = W2 dz2              2 it x 64 x 16 = 2048
+struct EmbFragOffsets {
+  int64_t F2, F3n, F3t, B3, B2, per_net;
+};
+
+// Fitting-net fragments per centre type: forward layer l uses W_l^T
+// (out x in), backward uses W_l (in x out).  Offsets in elements.
+struct FitFragOffsets {
+  int64_t fwd[3], bwd[3], per_type;
+};
+
+struct dp_model_impl;
+
+}  // namespace dpse
+
+struct dp_model {
+  dp_model_desc desc;
+  int nm;
+  int sec[DP_MAX_TYPES + 1];
+  int w1;          // first embedding width (25 or 32 ...)
+  int m1;          // last embedding width
+  int n3;          // m-tiles of m1
+  int nd;          // m1 * m2
+  int fw;          // fitting width
+  int64_t n_params;
+  // device buffers
+  double* params;            // flat FP64 copy
+  // embedding small vectors per net (FP64 and FP32 copies), slot/feature mapped:
+  //   W1s[32], b1s[32], b2s[64], b3s[128] (slot order), b3f[128] (feature order)
+  double* emb_vec64;
+  float* emb_vec32;
+  int64_t emb_vec_per_net;   // = 32+32+64+128+128
+  double* emb_frag64;
+  uint16_t* emb_frag_bf16;
+  uint16_t* emb_frag_f16;
+  dpse::EmbFragOffsets efo;
+  // fitting
+  double* fit_frag64;
+  uint16_t* fit_frag_bf16;
+  uint16_t* fit_frag_f16;
+  dpse::FitFragOffsets ffo;     // FP64 fragment offsets
+  dpse::FitFragOffsets ffo_lp;  // BF16/FP16 fragment offsets (K padded to 32)
+  double* fit_vec64;   // per type: b1, b2, b3, wo [fw each], bo, ebias  (4*fw + 2)
+  float* fit_vec32;
+  int64_t fit_vec_per_type;
+  int device;
+};
+
+struct dp_ctx {
+  const dp_model* model;
+  int64_t max_atoms;
+  int32_t max_frames;
+  int64_t max_cols;
+  int64_t max_cells;
+  int device;
+  // frame table
+  dpse::FrameInfo* frames_dev;
+  dpse::FrameInfo* frames_host;  // pinned staging
+  hipEvent_t frames_ev;
+  bool frames_ev_pending;
+  int32_t nframes_last;
+  int64_t natoms_last;
+  int32_t mode_last;
+  bool have_state;
+  const int32_t* types_last;
+  // status
+  int32_t* flags_dev;
+  int32_t* flags_host;  // pinned
+  hipStream_t last_stream;
+  // nlist scratch
+  int32_t* cell_of;
+  int32_t* cell_count;
+  int32_t* cell_start;
+  int32_t* cell_fill;
+  int32_t* cell_atoms;
+  // type sort
+  int32_t* chunk_counts;   // [nchunks * kMaxT]
+  int32_t* type_meta;      // [2*kMaxT]: n_t, cbase_t
+  int32_t* col_of;         // [max_atoms]
+  int32_t* atom_at;        // [max_cols]
+  int32_t* frame_of;       // [max_atoms]
+  // compute buffers
+  double* R;               // [N, nm, 4] f64
+  int32_t* nnei;           // [N, kMaxT]
+  void* T;                 // [cols, m1, 4]   f64 / f32
+  void* D;                 // [cols, nd]      f64 / lp
+  void* dD;                // [cols, nd]      f64 / f32
+  void* gT;                // [cols, m1, 4]   f64 / f32
+  // fitting activations [cols, fw]
+  void* fa[12];
+  double* Ei_col;          // [cols]
+  double* Ei_atom;         // [N]
+  double* netd;            // [N, nm, 4] f64
+  double* vatom;           // [N, 9]
+  // parameter-gradient scratch
+  double* gE_col;          // [cols]
+  double* grad_tmp;        // [n_params]
+  // opt-in stage timing
+  hipEvent_t* prof_ev;     // [2 * prof_cap]
+  int32_t* prof_stage;     // [prof_cap]
+  int32_t prof_cap, prof_n;
+  double prof_ms[DP_NSTAGES];
+  int64_t prof_cnt[DP_NSTAGES];
+};
+
+namespace dpse {
+
+// Error plumbing
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// ---------------------------------------------------------------- launchers
+// nlist
+void launch_nl_bin(dp_ctx* c, const double* x, int32_t ntot, int32_t nframes, hipStream_t s);
+void launch_nl_scan(dp_ctx* c, int32_t ncells, hipStream_t s);
+void launch_nl_scatter(dp_ctx* c, int32_t ntot, hipStream_t s);
+void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
+                      int32_t* nlist, int32_t* overflow, hipStream_t s);
+// small utilities
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void launch_type_sort(dp_ctx* c, const int32_t* types, int32_t ntot, int32_t nframes, hipStream_t s);
+// compute
+void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
+                hipStream_t s);
+void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
+void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
+void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot, double* forces, hipStream_t s);
+void launch_frame_reduce(dp_ctx* c, int32_t nframes, double* energies, double* atom_energy, double* virials,
+                         hipStream_t s);
+// md
+void launch_kick_drift(dp_ctx* c, double* x, double* v, const double* f, const int32_t* types, int32_t n,
+                       double dt, const double L[3], int32_t* images, hipStream_t s);
+void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, int32_t n, double dt, double* ke,
+                 hipStream_t s);
+// inspection
+void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, double* dst, hipStream_t s);
+
+}  // namespace dpse

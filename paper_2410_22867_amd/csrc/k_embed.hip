@@ -1,0 +1,675 @@
+// Embedding nets and the G^T R contraction (Background section: the smoothed
+// first column of R_i passes through the three-layer embedding net; the
+// descriptor preserves the symmetries), forward and backward.
+//
+// Work layout.  One wavefront owns one centre atom (one fitting column) and
+// walks its neighbour sections t_j = 0..ntypes-1 in tiles of 16 neighbour
+// rows (only the real rows of a section: sections are sorted and padded at
+// their end).  Inside a tile the activations live in registers in the MFMA
+// output layout with features along M and the 16 rows along N ("transposed"
+// layout): lane n + 16g holds features 16t + 4v + g (FP64) or 16t + 4g + v
+// (16x16x32 forms) of row n, element v.  That tile is
+// directly the B operand of the next layer (weights are the A operand, stored
+// pre-arranged per lane at model load), so layers chain without LDS traffic.
+//
+// Slot layout (widths w, 2w, 4w with w <= 32): layer 1 uses 32 slots
+// (feature f at slot f), layer 2 uses 64 (features [0, w) at slots [0, w),
+// [w, 2w) at [32, 32 + w)), layer 3 uses 128 (two copies of the layer-2
+// layout).  With that layout the identity skips of width-doubling layers,
+// h_l = [h_{l-1}, h_{l-1}] + tanh(z_l), stay inside a lane.
+//
+// Forward: layer 3 is evaluated with rows along M instead (the layer-2 tile
+// is a valid A operand as it is), so the contraction T = G^T R / nm reduces
+// over 4 rows inside a lane and over the 4 lane groups once per atom; the
+// layer-2 values needed by the layer-3 skip are exchanged through a
+// wave-private LDS tile.  Backward recomputes layers 1-3 in the transposed
+// layout, forms dE/dG = g_T R / nm and the direct term g_T^T G / nm, and
+// back-propagates with the transposed-weight fragments to dE/ds.
+#include "dp_internal.h"
+#include "dp_device.h"
+
+namespace dpse {
+
+struct EmbArgs {
+  const int32_t* atom_at;
+  const int32_t* types;
+  const double* R;
+  const int32_t* nnei;
+  const double* frag64;
+  const uint16_t* fraglp;
+  const double* vec64;
+  const float* vec32;
+  int64_t vec_per_net;
+  EmbFragOffsets fo;
+  void* T;
+  const void* gT;
+  double* netd;
+  int ncols, ntypes, nm;
+  int sec[kMaxT + 1];
+  double inv_nm;
+};
+
+// per-net vector block: W1s[32] | b1s[32] | b2s[64] | b3s[128] | b3f[128]
+constexpr int kV_W1 = 0, kV_B1 = 32, kV_B2 = 64, kV_B3S = 128, kV_B3F = 256;
+
+template <int W>
+__device__ __forceinline__ int slot2_of_feat(int f) {  // f in [0, 2W)
+  return (f / W) * 32 + (f % W);
+}
+template <int W>
+__device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
+  const int q = p & 63;
+  if ((q & 31) >= W) return -1;
+  return (p >> 6) * 2 * W + (q >> 5) * W + (q & 31);
+}
+
+// ============================================================== FP64 forward
+template <int W>
+__global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
+  constexpr int M1 = 4 * W;
+  constexpr int N3 = (M1 + 15) / 16;
+  __shared__ double h2s[4][16][kP2 + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 4 + wv;
+  if (col >= A.ncols) return;
+  const int i = A.atom_at[col];
+  if (i < 0) return;
+  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
+  const int r16 = lane & 15, g = lane >> 4;
+  double accT[N3][4];
+#pragma unroll
+  for (int o = 0; o < N3; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accT[o][k] = 0.0;
+
+  for (int tj = 0; tj < A.ntypes; ++tj) {
+    const int net = ti * A.ntypes + tj;
+    const double* vec = A.vec64 + net * A.vec_per_net;
+    const double* F2g = A.frag64 + net * A.fo.per_net + A.fo.F2;
+    const double* F3g = A.frag64 + net * A.fo.per_net + A.fo.F3n;
+    const int nn = A.nnei[i * kMaxT + tj];
+    const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    double w1s[2][4], b1s[2][4], b2s[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
+        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
+      }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * v + g];
+
+    for (int r0 = 0; r0 < nn; r0 += 16) {
+      const double* F2 = opaque(F2g);
+      const double* F3 = opaque(F3g);
+      const int row = r0 + r16;
+      const double s = row < nn ? Rs[row * 4] : 0.0;
+      double h1[2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
+      double h2[4][4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + b2s[ot][v]);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * v + g] = h2[ot][v];
+      wave_lds_sync();
+      // rows of this lane in the rows-along-M layout: r0 + 4g + v
+      double Rr[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * v + g;
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Rr[v][k] = x[k];
+      }
+#pragma unroll
+      for (int o = 0; o < N3; ++o) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(h2[mt][v], F3[((o * 4 + mt) * 4 + v) * 64 + lane], z);
+        const int feat = 16 * o + r16;
+        if (feat < M1) {
+          const double b3 = vec[kV_B3F + feat];
+          const int src = slot2_of_feat<W>(feat % (2 * W));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double G = h2s[wv][4 * v + g][src] + tanh_d(z[v] + b3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) accT[o][k] = fma(G, Rr[v][k], accT[o][k]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < N3; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double x = accT[o][k];
+      x += shfl_xor_d(x, 16);
+      x += shfl_xor_d(x, 32);
+      accT[o][k] = x * A.inv_nm;
+    }
+  if (g == 0) {
+    double* T = reinterpret_cast<double*>(A.T) + (int64_t)col * M1 * 4;
+#pragma unroll
+    for (int o = 0; o < N3; ++o) {
+      const int feat = 16 * o + r16;
+      if (feat < M1) {
+        d4 x = {accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+        *reinterpret_cast<d4*>(T + feat * 4) = x;
+      }
+    }
+  }
+}
+
+// ============================================================== FP64 backward
+template <int W>
+__global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
+  constexpr int M1 = 4 * W;
+  __shared__ d4 gts[4][kP3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 4 + wv;
+  if (col >= A.ncols) return;
+  const int i = A.atom_at[col];
+  if (i < 0) return;
+  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
+  const int r16 = lane & 15, g = lane >> 4;
+  {
+    const double* gT = reinterpret_cast<const double*>(A.gT) + (int64_t)col * M1 * 4;
+    for (int p = lane; p < kP3; p += 64) {
+      const int a = feat3_of_slot<W>(p);
+      d4 x = {0.0, 0.0, 0.0, 0.0};
+      if (a >= 0) {
+        x = *reinterpret_cast<const d4*>(gT + a * 4);
+        x = x * A.inv_nm;
+      }
+      gts[wv][p] = x;
+    }
+  }
+  wave_lds_sync();
+
+  for (int tj = 0; tj < A.ntypes; ++tj) {
+    const int net = ti * A.ntypes + tj;
+    const double* vec = A.vec64 + net * A.vec_per_net;
+    const double* baseg = A.frag64 + net * A.fo.per_net;
+    const int nn = A.nnei[i * kMaxT + tj];
+    const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
+    const double* Rs = A.R + rbase * 4;
+    double w1s[2][4], b1s[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
+        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
+      }
+
+    for (int r0 = 0; r0 < nn; r0 += 16) {
+      const double* base = opaque(baseg);
+      const double* F2 = base + A.fo.F2;
+      const double* F3 = base + A.fo.F3t;
+      const double* B3 = base + A.fo.B3;
+      const double* B2 = base + A.fo.B2;
+      const int row = r0 + r16;
+      const bool valid = row < nn;
+      d4 Rrow = {0.0, 0.0, 0.0, 0.0};
+      if (valid) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const double s = Rrow[0];
+      // ---- recompute forward (transposed layout)
+      double t1[2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
+      double t2[4][4], h2[4][4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t2[ot][v] = tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
+          h2[ot][v] = t1[ot & 1][v] + t2[ot][v];
+        }
+      }
+      // ---- layer 3 per output tile o, immediately folded into dh2 = W3 dz3
+      double skip2[4][4];
+      double dRd[4] = {0.0, 0.0, 0.0, 0.0};
+      d4 dh2a[4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        dh2a[ot] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.0;
+      }
+#pragma unroll 1
+      for (int oo = 0; oo < 2; ++oo) {
+      const double* F3o = opaque(F3 + oo * 4 * 16 * 64);
+      const double* B3o = opaque(B3 + oo * 4 * 4 * 64);
+#pragma unroll
+      for (int o4 = 0; o4 < 4; ++o4) {
+        const int o = 4 * oo + o4;
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(F3o[((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+        double dz3[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = 16 * o + 4 * v + g;
+          const double t3 = tanh_d(z[v] + vec[kV_B3S + p]);
+          const double G = h2[o4][v] + t3;
+          const d4 gt = gts[wv][p];
+          const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dRd[k] = fma(gt[k], G, dRd[k]);
+          dz3[v] = dG * (1.0 - t3 * t3);
+          skip2[o4][v] += dG;
+        }
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dh2a[it] = mfma_f64(B3o[((it * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[it]);
+      }
+      }
+      // ---- dz2 = (dh2 + skip) (1 - t2^2)
+      double dz2[4][4];
+      double skip1[2][4];
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip1[it][v] = 0.0;
+#pragma unroll
+      for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double dh2 = dh2a[it][v] + skip2[it][v];
+          dz2[it][v] = dh2 * (1.0 - t2[it][v] * t2[it][v]);
+          skip1[it & 1][v] += dh2;
+        }
+      // ---- dh1 = W2 dz2 + skip; dz1 = dh1 (1 - t1^2); ds = W1 . dz1
+      double dsp = 0.0;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((it * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double dh1 = z[v] + skip1[it][v];
+          dsp = fma(w1s[it][v], dh1 * (1.0 - t1[it][v] * t1[it][v]), dsp);
+        }
+      }
+      dsp += shfl_xor_d(dsp, 16);
+      dsp += shfl_xor_d(dsp, 32);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dRd[k] += shfl_xor_d(dRd[k], 16);
+        dRd[k] += shfl_xor_d(dRd[k], 32);
+      }
+      if (g == 0 && valid) {
+        d4 out = {dRd[0] + dsp, dRd[1], dRd[2], dRd[3]};
+        *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = out;
+      }
+    }
+  }
+}
+
+// ============================================================== mixed forward
+// Layer 1 in FP32 on the vector ALUs (K = 1), layers 2 and 3 on 16x16x32
+// MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32,
+// contraction in FP32.
+template <class P, int W>
+__global__ __launch_bounds__(256) void k_embed_fwd_lp(EmbArgs A) {
+  constexpr int M1 = 4 * W;
+  constexpr int N3 = (M1 + 15) / 16;
+  __shared__ float h2s[4][16][kP2 + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 4 + wv;
+  if (col >= A.ncols) return;
+  const int i = A.atom_at[col];
+  if (i < 0) return;
+  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
+  const int r16 = lane & 15, g = lane >> 4;
+  float accT[N3][4];
+#pragma unroll
+  for (int o = 0; o < N3; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
+
+  for (int tj = 0; tj < A.ntypes; ++tj) {
+    const int net = ti * A.ntypes + tj;
+    const float* vec = A.vec32 + net * A.vec_per_net;
+    const uint16_t* F2g = A.fraglp + net * A.fo.per_net + A.fo.F2;
+    const uint16_t* F3g = A.fraglp + net * A.fo.per_net + A.fo.F3n;
+    const int nn = A.nnei[i * kMaxT + tj];
+    const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    float w1s[2][4], b1s[2][4], b2s[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * g + v];
+        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * g + v];
+      }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
+
+    for (int r0 = 0; r0 < nn; r0 += 16) {
+      const uint16_t* F2 = opaque(F2g);
+      const uint16_t* F3 = opaque(F3g);
+      const int row = r0 + r16;
+      const float s = row < nn ? (float)Rs[row * 4] : 0.f;
+      float h1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j >> 2][j & 3], b1s[j >> 2][j & 3]));
+      const typename P::vec8 b1v = pack8<P>(h1);
+      float h2[8][4];  // [2*kt + j/4][j%4] for the two layer-3 k-steps
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+        z = P::mfma(load8<P>(F2 + (ot * 64 + lane) * 8), b1v, z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[4 * (ot & 1) + v] + tanh_f(z[v] + b2s[ot][v]);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * g + v] = h2[ot][v];
+      wave_lds_sync();
+      float Rr[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * g + v;
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
+      }
+      typename P::vec8 a3[2];
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        float tmp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tmp[j] = h2[2 * kt + (j >> 2)][j & 3];
+        a3[kt] = pack8<P>(tmp);
+      }
+#pragma unroll
+      for (int o = 0; o < N3; ++o) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(F3 + ((o * 2 + kt) * 64 + lane) * 8), z);
+        const int feat = 16 * o + r16;
+        if (feat < M1) {
+          const float b3 = vec[kV_B3F + feat];
+          const int src = slot2_of_feat<W>(feat % (2 * W));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float G = h2s[wv][4 * g + v][src] + tanh_f(z[v] + b3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) accT[o][k] = fmaf(G, Rr[v][k], accT[o][k]);
+          }
+        }
+      }
+    }
+  }
+  const float inv_nm = (float)A.inv_nm;
+#pragma unroll
+  for (int o = 0; o < N3; ++o)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float x = accT[o][k];
+      x += shfl_xor_f(x, 16);
+      x += shfl_xor_f(x, 32);
+      accT[o][k] = x * inv_nm;
+    }
+  if (g == 0) {
+    float* T = reinterpret_cast<float*>(A.T) + (int64_t)col * M1 * 4;
+#pragma unroll
+    for (int o = 0; o < N3; ++o) {
+      const int feat = 16 * o + r16;
+      if (feat < M1) {
+        f4 x = {accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+        *reinterpret_cast<f4*>(T + feat * 4) = x;
+      }
+    }
+  }
+}
+
+// ============================================================== mixed backward
+template <class P, int W>
+__global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
+  constexpr int M1 = 4 * W;
+  __shared__ f4 gts[4][kP3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 4 + wv;
+  if (col >= A.ncols) return;
+  const int i = A.atom_at[col];
+  if (i < 0) return;
+  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
+  const int r16 = lane & 15, g = lane >> 4;
+  {
+    const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
+    const float inv_nm = (float)A.inv_nm;
+    for (int p = lane; p < kP3; p += 64) {
+      const int a = feat3_of_slot<W>(p);
+      f4 x = {0.f, 0.f, 0.f, 0.f};
+      if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4) * inv_nm;
+      gts[wv][p] = x;
+    }
+  }
+  wave_lds_sync();
+
+  for (int tj = 0; tj < A.ntypes; ++tj) {
+    const int net = ti * A.ntypes + tj;
+    const float* vec = A.vec32 + net * A.vec_per_net;
+    const uint16_t* baseg = A.fraglp + net * A.fo.per_net;
+    const int nn = A.nnei[i * kMaxT + tj];
+    const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
+    const double* Rs = A.R + rbase * 4;
+    float w1s[8], b1s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+      b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+    }
+    for (int r0 = 0; r0 < nn; r0 += 16) {
+      const uint16_t* base = opaque(baseg);
+      const uint16_t* F2 = base + A.fo.F2;
+      const uint16_t* F3 = base + A.fo.F3t;
+      const uint16_t* B3 = base + A.fo.B3;
+      const uint16_t* B2 = base + A.fo.B2;
+      const int row = r0 + r16;
+      const bool valid = row < nn;
+      d4 Rd = {0.0, 0.0, 0.0, 0.0};
+      if (valid) Rd = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const float Rrow[4] = {(float)Rd[0], (float)Rd[1], (float)Rd[2], (float)Rd[3]};
+      const float s = Rrow[0];
+      float t1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
+      const typename P::vec8 b1v = pack8<P>(t1);
+      float t2[4][4], h2[4][4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+        z = P::mfma(load8<P>(F2 + (ot * 64 + lane) * 8), b1v, z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t2[ot][v] = tanh_f(z[v] + vec[kV_B2 + 16 * ot + 4 * g + v]);
+          h2[ot][v] = t1[4 * (ot & 1) + v] + t2[ot][v];
+        }
+      }
+      typename P::vec8 b2v[2];
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        float tmp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tmp[j] = h2[2 * kt + (j >> 2)][j & 3];
+        b2v[kt] = pack8<P>(tmp);
+      }
+      float dz3[8][4], skip2[4][4];
+      float dRd[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(F3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = 16 * o + 4 * g + v;
+          const float t3 = tanh_f(z[v] + vec[kV_B3S + p]);
+          const float G = h2[o & 3][v] + t3;
+          const f4 gt = gts[wv][p];
+          const float dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dRd[k] = fmaf(gt[k], G, dRd[k]);
+          dz3[o][v] = dG * (1.f - t3 * t3);
+          skip2[o & 3][v] += dG;
+        }
+      }
+      float dz2[4][4], skip1[2][4];
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip1[it][v] = 0.f;
+      typename P::vec8 bz3[4];
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        float tmp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tmp[j] = dz3[2 * kt + (j >> 2)][j & 3];
+        bz3[kt] = pack8<P>(tmp);
+      }
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) z = P::mfma(load8<P>(B3 + ((it * 4 + kt) * 64 + lane) * 8), bz3[kt], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float dh2 = z[v] + skip2[it][v];
+          dz2[it][v] = dh2 * (1.f - t2[it][v] * t2[it][v]);
+          skip1[it & 1][v] += dh2;
+        }
+      }
+      typename P::vec8 bz2[2];
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        float tmp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tmp[j] = dz2[2 * kt + (j >> 2)][j & 3];
+        bz2[kt] = pack8<P>(tmp);
+      }
+      float dsp = 0.f;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(B2 + ((it * 2 + kt) * 64 + lane) * 8), bz2[kt], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float dh1 = z[v] + skip1[it][v];
+          const float t = t1[4 * it + v];
+          dsp = fmaf(w1s[4 * it + v], dh1 * (1.f - t * t), dsp);
+        }
+      }
+      dsp += shfl_xor_f(dsp, 16);
+      dsp += shfl_xor_f(dsp, 32);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dRd[k] += shfl_xor_f(dRd[k], 16);
+        dRd[k] += shfl_xor_f(dRd[k], 32);
+      }
+      if (g == 0 && valid) {
+        d4 out = {(double)dRd[0] + (double)dsp, (double)dRd[1], (double)dRd[2], (double)dRd[3]};
+        *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = out;
+      }
+    }
+  }
+}
+
+// ============================================================== launchers
+static EmbArgs emb_args(dp_ctx* c, const int32_t* types, int32_t mode) {
+  const dp_model* m = c->model;
+  EmbArgs A;
+  A.atom_at = c->atom_at;
+  A.types = types;
+  A.R = c->R;
+  A.nnei = c->nnei;
+  A.frag64 = m->emb_frag64;
+  A.fraglp = mode == DP_MIX_FP16 ? m->emb_frag_f16 : m->emb_frag_bf16;
+  A.vec64 = m->emb_vec64;
+  A.vec32 = m->emb_vec32;
+  A.vec_per_net = m->emb_vec_per_net;
+  A.fo = m->efo;
+  A.T = c->T;
+  A.gT = c->gT;
+  A.netd = c->netd;
+  A.ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
+  A.ntypes = m->desc.ntypes;
+  A.nm = m->nm;
+  for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= m->desc.ntypes ? m->sec[t] : m->nm;
+  A.inv_nm = 1.0 / (double)m->nm;
+  return A;
+}
+
+#define DPSE_EMB_DISPATCH(KF64, KLP, W)                                                                  \
+  if (mode == DP_FP64) hipLaunchKernelGGL((KF64<W>), grid, block, 0, s, A);                             \
+  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((KLP<PrecBF16, W>), grid, block, 0, s, A);           \
+  else hipLaunchKernelGGL((KLP<PrecF16, W>), grid, block, 0, s, A);
+
+void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
+  EmbArgs A = emb_args(c, types, mode);
+  dim3 grid((A.ncols + 3) / 4), block(256);
+  if (c->model->w1 == 25) {
+    DPSE_EMB_DISPATCH(k_embed_fwd_f64, k_embed_fwd_lp, 25)
+  } else {
+    DPSE_EMB_DISPATCH(k_embed_fwd_f64, k_embed_fwd_lp, 32)
+  }
+}
+
+void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
+  EmbArgs A = emb_args(c, types, mode);
+  dim3 grid((A.ncols + 3) / 4), block(256);
+  if (c->model->w1 == 25) {
+    DPSE_EMB_DISPATCH(k_embed_bwd_f64, k_embed_bwd_lp, 25)
+  } else {
+    DPSE_EMB_DISPATCH(k_embed_bwd_f64, k_embed_bwd_lp, 32)
+  }
+}
+
+}  // namespace dpse

@@ -1,0 +1,514 @@
+// Descriptor D = T T<^T, the per-type fitting net (forward and backward) and
+// the descriptor backward (Background section: the fitting net maps D_i to
+// E_i; Computation Optimization section: the fitting GEMMs dominate, weights
+// are transposed once at start-up so every product is a plain one, mixed
+// precision runs the GEMMs in half precision).
+//
+// Fitting activations are stored atom-major, [column][feature], one column
+// per centre atom, columns bucketed by centre type into segments padded to
+// kColPad.  A GEMM computes out[col][m] = epi(sum_k X[col][k] W[k][m]) for
+// all columns of every type (blockIdx.z), with the weight operand stored in
+// per-lane fragment order (A operand, features along M) and X as the B
+// operand read straight from memory: for the k permutation used, lane
+// n + 16g reads 4 consecutive features of its column, so a wave loads 16
+// rows x 128 contiguous bytes.
+#include "dp_internal.h"
+#include "dp_device.h"
+
+namespace dpse {
+
+enum { EPI_TANH = 0, EPI_RES = 1, EPI_BWD = 2, EPI_PLAIN = 3 };
+
+struct GemmArgs {
+  const void* Afr;       // fragments of this layer for type 0
+  int64_t a_type_stride; // elements between types
+  const void* X;         // [cols][ldx]
+  int ldx;
+  int K;                 // reduction length (multiple of 16 for f64, padded to 32 for lp)
+  int Kreal;             // real reduction length (multiple of 16); lp columns beyond it are ignored
+  int M;                 // output features (multiple of 16)
+  const int32_t* meta;   // n_t, cbase_t
+  int epi;
+  const void* vec;       // per-type fitting vectors (b1 b2 b3 wo | bo ebias)
+  int64_t vec_type_stride;
+  int bias_off;          // offset of the bias of this layer inside the vector block
+  int wo_off;
+  // epilogue operands (f64 or f32)
+  const void* res;       // EPI_RES: skip input [cols][ldr]; EPI_BWD: dh of the layer above or null (= wo)
+  int ldr;
+  const void* tprev;     // EPI_BWD: tanh of the layer below [cols][ldt]
+  int ldt;
+  void* out0;            // EPI_TANH/RES: tanh t; EPI_BWD: dh; EPI_PLAIN: out
+  int ld0;
+  void* out1;            // EPI_RES: h = res + t; EPI_BWD: dz
+  int ld1;
+  void* outlp;           // lp copy for the next GEMM (mixed): EPI_TANH/RES: h; EPI_BWD: dz
+  int ldlp;
+};
+
+// ---------------------------------------------------------------- FP64 GEMM
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
+  const int t = blockIdx.z;
+  const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, gq = lane >> 4;
+  const int c0 = (blockIdx.x * 4 + wv) * NT * 16;
+  if (c0 >= n_t) return;
+  const int mtiles = g.M / 16;
+  const int mt0 = blockIdx.y * MT;
+  const int KS = g.K / 16;
+  const double* Afr = reinterpret_cast<const double*>(g.Afr) + t * g.a_type_stride;
+  const double* X = reinterpret_cast<const double*>(g.X);
+  d4 acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  const double* xrow[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) xrow[nt] = X + (int64_t)(cb + c0 + nt * 16 + r16) * g.ldx + 4 * gq;
+  int mtv[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) mtv[mt] = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
+  for (int S = 0; S < KS; ++S) {
+    d4 xb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) xb[nt] = *reinterpret_cast<const d4*>(xrow[nt] + 16 * S);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const double a = Afr[(((int64_t)mtv[mt] * KS + S) * 4 + v) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a, xb[nt][v], acc[mt][nt]);
+      }
+    }
+  }
+  const double* vec = reinterpret_cast<const double*>(g.vec) + t * g.vec_type_stride;
+  // D layout of the f64 MFMA: element v of lane n + 16g is row m = 16 mt + g + 4v.
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if (mt0 + mt >= mtiles) break;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t col = cb + c0 + nt * 16 + r16;
+      const d4 a = acc[mt][nt];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = (mt0 + mt) * 16 + gq + 4 * v;
+        if (g.epi == EPI_PLAIN) {
+          reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = a[v];
+        } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
+          const double tv = tanh_d(a[v] + vec[g.bias_off + m]);
+          reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = tv;
+          if (g.epi == EPI_RES)
+            reinterpret_cast<double*>(g.out1)[col * g.ld1 + m] =
+                reinterpret_cast<const double*>(g.res)[col * g.ldr + m] + tv;
+        } else {  // EPI_BWD: dh = acc + (res ? res : wo); dz = dh (1 - tprev^2)
+          const double r = g.res ? reinterpret_cast<const double*>(g.res)[col * g.ldr + m] : vec[g.wo_off + m];
+          const double tp = reinterpret_cast<const double*>(g.tprev)[col * g.ldt + m];
+          const double dh = a[v] + r;
+          if (g.out0) reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = dh;
+          reinterpret_cast<double*>(g.out1)[col * g.ld1 + m] = dh * (1.0 - tp * tp);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- mixed GEMM
+template <class P>
+__device__ __forceinline__ void store4lp(uint16_t* p, const float* v) {
+  u16x4 u = {P::bits(v[0]), P::bits(v[1]), P::bits(v[2]), P::bits(v[3])};
+  *reinterpret_cast<u16x4*>(p) = u;
+}
+
+template <class P, int MT, int NT>
+__global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
+  const int t = blockIdx.z;
+  const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, gq = lane >> 4;
+  const int c0 = (blockIdx.x * 4 + wv) * NT * 16;
+  if (c0 >= n_t) return;
+  const int mtiles = g.M / 16;
+  const int mt0 = blockIdx.y * MT;
+  const int KT = g.K / 32;
+  const uint16_t* Afr = reinterpret_cast<const uint16_t*>(g.Afr) + t * g.a_type_stride;
+  const uint16_t* X = reinterpret_cast<const uint16_t*>(g.X);
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* xrow[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) xrow[nt] = X + (int64_t)(cb + c0 + nt * 16 + r16) * g.ldx + 4 * gq;
+  int mtv[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) mtv[mt] = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
+  for (int kt = 0; kt < KT; ++kt) {
+    typename P::vec8 xb[NT];
+    // the padded upper half of the last k-step may hold stale bits: use zeros
+    const bool hi_ok = 32 * kt + 16 < g.Kreal;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const u16x4 lo = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt);
+      u16x4 hi = {0, 0, 0, 0};
+      if (hi_ok) hi = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt + 16);
+      u16x8 u = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      xb[nt] = __builtin_bit_cast(typename P::vec8, u);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const typename P::vec8 a = load8<P>(Afr + (((int64_t)mtv[mt] * KT + kt) * 64 + lane) * 8);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = P::mfma(a, xb[nt], acc[mt][nt]);
+    }
+  }
+  const float* vec = reinterpret_cast<const float*>(g.vec) + t * g.vec_type_stride;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if (mt0 + mt >= mtiles) break;
+    const int m0 = (mt0 + mt) * 16 + 4 * gq;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int64_t col = cb + c0 + nt * 16 + r16;
+      const f4 a = acc[mt][nt];
+      if (g.epi == EPI_PLAIN) {
+        *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = a;
+      } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
+        f4 r = {0.f, 0.f, 0.f, 0.f};
+        if (g.epi == EPI_RES) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
+        float tv[4], hv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          tv[v] = tanh_f(a[v] + vec[g.bias_off + m0 + v]);
+          hv[v] = r[v] + tv[v];
+        }
+        *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
+        if (g.out1)
+          *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out1) + col * g.ld1 + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+        if (g.outlp) store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, hv);
+      } else {
+        f4 r;
+        if (g.res) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
+        else
+#pragma unroll
+          for (int v = 0; v < 4; ++v) r[v] = vec[g.wo_off + m0 + v];
+        const f4 tp = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.tprev) + col * g.ldt + m0);
+        float dh[4], dz[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          dh[v] = a[v] + r[v];
+          dz[v] = dh[v] * (1.f - tp[v] * tp[v]);
+        }
+        if (g.out0) *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{dh[0], dh[1], dh[2], dh[3]};
+        store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, dz);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- descriptor
+// D[a*m2 + b] = sum_k T[a][k] T[b][k], a < m1, b < m2 (m2 = 16).  One
+// work-group per column, thread a writes 16 consecutive entries.
+template <typename TT, typename DT>
+__global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ atom_at, const TT* __restrict__ T,
+                                                    DT* __restrict__ D, int m1, int mode_lp_f16) {
+  __shared__ TT Ts[128][4];
+  const int col = blockIdx.x;
+  const bool real = atom_at[col] >= 0;
+  const int a = threadIdx.x;
+  if (a < m1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Ts[a][k] = real ? T[((int64_t)col * m1 + a) * 4 + k] : (TT)0;
+  __syncthreads();
+  if (a >= m1) return;
+  DT* out = D + ((int64_t)col * m1 + a) * 16;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    TT acc = Ts[a][0] * Ts[b][0] + Ts[a][1] * Ts[b][1] + Ts[a][2] * Ts[b][2] + Ts[a][3] * Ts[b][3];
+    if constexpr (sizeof(DT) == 2) {
+      out[b] = mode_lp_f16 ? PrecF16::bits((float)acc) : PrecBF16::bits((float)acc);
+    } else {
+      out[b] = (DT)acc;
+    }
+  }
+}
+
+// g_T[a][k] = sum_b dD[a][b] T[b][k] + [a < m2] sum_a' dD[a'][a] T[a'][k]
+template <typename TT>
+__global__ __launch_bounds__(128) void k_desc_bwd(const int32_t* __restrict__ atom_at, const TT* __restrict__ T,
+                                                  const TT* __restrict__ dD, TT* __restrict__ gT, int m1) {
+  __shared__ TT Ts[128][4];
+  __shared__ TT dDs[128 * 16 + 1];
+  const int col = blockIdx.x;
+  if (atom_at[col] < 0) return;
+  const int a = threadIdx.x;
+  if (a < m1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Ts[a][k] = T[((int64_t)col * m1 + a) * 4 + k];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) dDs[a * 16 + b] = dD[((int64_t)col * m1 + a) * 16 + b];
+  }
+  __syncthreads();
+  if (a >= m1) return;
+  TT acc[4] = {0, 0, 0, 0};
+  for (int b = 0; b < 16; ++b) {
+    const TT w = dDs[a * 16 + b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += w * Ts[b][k];
+  }
+  if (a < 16)
+    for (int a2 = 0; a2 < m1; ++a2) {
+      const TT w = dDs[a2 * 16 + a];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += w * Ts[a2][k];
+    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gT[((int64_t)col * m1 + a) * 4 + k] = acc[k];
+}
+
+// ---------------------------------------------------------------- fit output
+// E_i = h3 . w_out + b_out + e_bias[t]; dz3 = w_out (1 - t3^2).  One
+// wavefront per column.
+template <typename FT, class P>
+__global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ atom_at, const int32_t* __restrict__ types,
+                                                 const FT* __restrict__ h3, const FT* __restrict__ t3, int ld,
+                                                 const FT* __restrict__ vec, int64_t vstride, int wo_off, int fw,
+                                                 void* __restrict__ dz3, int lddz, double* __restrict__ Ei_col,
+                                                 double* __restrict__ Ei_atom, int ncols, int ntypes) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= ncols) return;
+  const int i = atom_at[col];
+  if (i < 0) return;
+  const int t = min(max(types[i], 0), ntypes - 1);
+  const FT* v = vec + t * vstride;
+  double acc = 0.0;
+  for (int m = lane; m < fw; m += 64) {
+    const FT wo = v[wo_off + m];
+    acc += (double)(h3[(int64_t)col * ld + m] * wo);
+    const FT tt = t3[(int64_t)col * ld + m];
+    const FT dz = wo * ((FT)1 - tt * tt);
+    if constexpr (sizeof(FT) == 8) reinterpret_cast<double*>(dz3)[(int64_t)col * lddz + m] = dz;
+    else reinterpret_cast<uint16_t*>(dz3)[(int64_t)col * lddz + m] = P::bits(dz);
+  }
+  acc = wave_sum_d(acc);
+  if (lane == 0) {
+    const double e = acc + (double)v[wo_off + fw] + (double)v[wo_off + fw + 1];
+    Ei_col[col] = e;
+    Ei_atom[i] = e;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+// Activation buffer slots in dp_ctx::fa (FP64 / mixed):
+//   FP64 : 0 t1(=h1) 1 t2 2 h2 3 t3 4 h3 5 dz3 6 dh2 7 dz2 8 dz1         [cols][fw]
+//   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
+//          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
+static int kMT = 5, kNT = 2;
+
+template <typename F>
+static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+  const int ntypes = c->model->desc.ntypes;
+  const int BN = 4 * kNT * 16;
+  const int mtiles = g.M / 16;
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + kMT - 1) / kMT), (unsigned)ntypes);
+  if (grid.x == 0) return;
+  if (mode == DP_FP64) hipLaunchKernelGGL((k_fit_gemm_f64<5, 2>), grid, dim3(256), 0, s, g);
+  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, 5, 2>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, 5, 2>), grid, dim3(256), 0, s, g);
+}
+
+static GemmArgs gemm_base(dp_ctx* c, int mode) {
+  const dp_model* m = c->model;
+  GemmArgs g = {};
+  g.meta = c->type_meta;
+  g.vec = mode == DP_FP64 ? (const void*)m->fit_vec64 : (const void*)m->fit_vec32;
+  g.vec_type_stride = m->fit_vec_per_type;
+  g.wo_off = 3 * m->fw;
+  return g;
+}
+
+void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) {
+  const dp_model* m = c->model;
+  const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
+  if (c->natoms_last <= 0) return;
+  if (mode == DP_FP64)
+    hipLaunchKernelGGL((k_descriptor<double, double>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const double*)c->T,
+                       (double*)c->D, m->m1, 0);
+  else
+    hipLaunchKernelGGL((k_descriptor<float, uint16_t>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const float*)c->T,
+                       (uint16_t*)c->D, m->m1, mode == DP_MIX_FP16 ? 1 : 0);
+}
+
+void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
+  const dp_model* m = c->model;
+  const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
+  if (c->natoms_last <= 0) return;
+  if (mode == DP_FP64)
+    hipLaunchKernelGGL((k_desc_bwd<double>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const double*)c->T,
+                       (const double*)c->dD, (double*)c->gT, m->m1);
+  else
+    hipLaunchKernelGGL((k_desc_bwd<float>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const float*)c->T,
+                       (const float*)c->dD, (float*)c->gT, m->m1);
+}
+
+void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
+  const dp_model* m = c->model;
+  if (c->natoms_last <= 0) return;
+  const int fw = m->fw;
+  const int fwp = ((fw + 31) / 32) * 32;
+  const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
+  GemmArgs g = gemm_base(c, mode);
+  const bool f64 = mode == DP_FP64;
+  const void* frag = f64 ? (const void*)m->fit_frag64
+                         : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
+  const int64_t* off_fwd = f64 ? m->ffo.fwd : m->ffo_lp.fwd;
+  const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
+  const int ld = f64 ? fw : fwp;
+  // layer 1: X = D [cols][nd]
+  g.a_type_stride = tstride;
+  g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[0]) : (const void*)((const uint16_t*)frag + off_fwd[0]);
+  g.X = c->D;
+  g.ldx = m->nd;
+  g.K = m->nd;
+  g.Kreal = m->nd;
+  g.M = fw;
+  g.epi = EPI_TANH;
+  g.bias_off = 0;
+  g.out0 = c->fa[0];
+  g.ld0 = ld;
+  g.out1 = nullptr;
+  g.outlp = f64 ? nullptr : c->fa[5];
+  g.ldlp = fwp;
+  gemm_launch<int>(c, g, mode, s);
+  // layers 2, 3
+  for (int l = 1; l < 3; ++l) {
+    g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[l]) : (const void*)((const uint16_t*)frag + off_fwd[l]);
+    if (f64) {
+      g.X = l == 1 ? c->fa[0] : c->fa[2];
+      g.ldx = fw;
+      g.K = fw;
+      g.Kreal = fw;
+      g.res = g.X;
+    } else {
+      g.X = l == 1 ? c->fa[5] : c->fa[6];
+      g.ldx = fwp;
+      g.K = fwp;
+      g.Kreal = fw;
+      g.res = l == 1 ? c->fa[0] : c->fa[2];
+    }
+    g.ldr = ld;
+    g.epi = EPI_RES;
+    g.bias_off = l * fw;
+    g.out0 = l == 1 ? c->fa[1] : c->fa[3];
+    g.out1 = l == 1 ? c->fa[2] : c->fa[4];
+    g.ld1 = ld;
+    g.outlp = f64 ? nullptr : (l == 1 ? c->fa[6] : nullptr);
+    gemm_launch<int>(c, g, mode, s);
+  }
+  // output
+  dim3 grid((ncols + 3) / 4);
+  if (f64)
+    hipLaunchKernelGGL((k_fit_out<double, PrecBF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
+                       (const double*)c->fa[4], (const double*)c->fa[3], ld, m->fit_vec64, m->fit_vec_per_type,
+                       3 * fw, fw, c->fa[5], ld, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
+  else if (mode == DP_MIX_BF16)
+    hipLaunchKernelGGL((k_fit_out<float, PrecBF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
+                       (const float*)c->fa[4], (const float*)c->fa[3], ld, m->fit_vec32, m->fit_vec_per_type, 3 * fw,
+                       fw, c->fa[7], fwp, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
+  else
+    hipLaunchKernelGGL((k_fit_out<float, PrecF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
+                       (const float*)c->fa[4], (const float*)c->fa[3], ld, m->fit_vec32, m->fit_vec_per_type, 3 * fw,
+                       fw, c->fa[7], fwp, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
+}
+
+void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
+  const dp_model* m = c->model;
+  if (c->natoms_last <= 0) return;
+  const int fw = m->fw;
+  const int fwp = ((fw + 31) / 32) * 32;
+  const bool f64 = mode == DP_FP64;
+  const void* frag = f64 ? (const void*)m->fit_frag64
+                         : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
+  const int64_t* off_bwd = f64 ? m->ffo.bwd : m->ffo_lp.bwd;
+  const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
+  const int ld = f64 ? fw : fwp;
+  GemmArgs g = gemm_base(c, mode);
+  g.a_type_stride = tstride;
+  auto fr = [&](int l) {
+    return f64 ? (const void*)((const double*)frag + off_bwd[l]) : (const void*)((const uint16_t*)frag + off_bwd[l]);
+  };
+  // layer 3: dh2 = w_out + W3 dz3 ; dz2 = dh2 (1 - t2^2)
+  g.Afr = fr(2);
+  g.X = f64 ? c->fa[5] : c->fa[7];
+  g.ldx = ld;
+  g.K = ld;
+  g.Kreal = fw;
+  g.M = fw;
+  g.epi = EPI_BWD;
+  g.res = nullptr;
+  g.tprev = c->fa[1];
+  g.ldt = ld;
+  g.out0 = f64 ? c->fa[6] : c->fa[10];
+  g.ld0 = ld;
+  g.out1 = f64 ? c->fa[7] : nullptr;
+  g.ld1 = ld;
+  g.outlp = f64 ? nullptr : c->fa[8];
+  g.ldlp = fwp;
+  gemm_launch<int>(c, g, mode, s);
+  // layer 2: dh1 = dh2 + W2 dz2 ; dz1 = dh1 (1 - t1^2)
+  g.Afr = fr(1);
+  g.X = f64 ? c->fa[7] : c->fa[8];
+  g.res = f64 ? c->fa[6] : c->fa[10];
+  g.ldr = ld;
+  g.tprev = c->fa[0];
+  g.out0 = nullptr;
+  g.out1 = f64 ? c->fa[8] : nullptr;
+  g.outlp = f64 ? nullptr : c->fa[9];
+  gemm_launch<int>(c, g, mode, s);
+  // layer 1: dD = W1 dz1
+  g.Afr = fr(0);
+  g.X = f64 ? c->fa[8] : c->fa[9];
+  g.M = m->nd;
+  g.epi = EPI_PLAIN;
+  g.out0 = c->dD;
+  g.ld0 = m->nd;
+  g.outlp = nullptr;
+  gemm_launch<int>(c, g, mode, s);
+}
+
+// ---------------------------------------------------------------- inspection
+// Copies a column-ordered per-atom buffer into atom order as f64.
+__global__ void k_gather_cols(const int32_t* __restrict__ col_of, const void* __restrict__ src, int kind_f32,
+                              int kind_lp, int width, double* __restrict__ dst, int ntot) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ntot * width) return;
+  const int i = (int)(idx / width), k = (int)(idx % width);
+  const int64_t s = (int64_t)col_of[i] * width + k;
+  double v;
+  if (kind_lp == 1) v = PrecBF16::tof(reinterpret_cast<const uint16_t*>(src)[s]);
+  else if (kind_lp == 2) v = PrecF16::tof(reinterpret_cast<const uint16_t*>(src)[s]);
+  else if (kind_f32) v = reinterpret_cast<const float*>(src)[s];
+  else v = reinterpret_cast<const double*>(src)[s];
+  dst[idx] = v;
+}
+
+void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, double* dst, hipStream_t s) {
+  const dp_model* m = c->model;
+  const void* src = which == 1 ? c->T : (which == 2 ? c->D : c->dD);
+  const int width = which == 1 ? m->m1 * 4 : m->nd;
+  const bool f64 = mode == DP_FP64;
+  int kind_lp = 0;
+  if (!f64 && which == 2) kind_lp = mode == DP_MIX_FP16 ? 2 : 1;
+  const int64_t tot = (int64_t)ntot * width;
+  if (tot > 0)
+    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, c->col_of, src,
+                       f64 ? 0 : 1, kind_lp, width, dst, ntot);
+}
+
+}  // namespace dpse
