@@ -664,11 +664,13 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->nnei, N * kMaxT);
   ALLOC(c->netd, N * nm * 4);
   ALLOC(c->vatom, N * 9);
+  ALLOC(c->ke_part, N / 256 + 2);
   ALLOC(c->Ei_col, C);
   ALLOC(c->Ei_atom, N);
   ALLOC(c->gE_col, C);
   ALLOC(c->grad_tmp, m->n_params);
   double* tmp = nullptr;
+  ALLOC(tmp, (int64_t)m->desc.ntypes * C * m1 * 4); c->Tpart = tmp;
   ALLOC(tmp, C * m1 * 4); c->T = tmp;
   ALLOC(tmp, C * nd); c->D = tmp;
   ALLOC(tmp, C * nd); c->dD = tmp;
@@ -700,7 +702,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
-                  c->netd, c->vatom, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->T, c->D, c->dD, c->gT};
+                  c->netd, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)

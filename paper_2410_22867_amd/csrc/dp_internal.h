@@ -116,6 +116,7 @@ struct dp_ctx {
   // compute buffers
   double* R;               // [N, nm, 4] f64
   int32_t* nnei;           // [N, kMaxT]
+  void* Tpart;             // [ntypes, cols, m1, 4] f64 / f32 (per neighbour section)
   void* T;                 // [cols, m1, 4]   f64 / f32
   void* D;                 // [cols, nd]      f64 / lp
   void* dD;                // [cols, nd]      f64 / f32
@@ -126,6 +127,7 @@ struct dp_ctx {
   double* Ei_atom;         // [N]
   double* netd;            // [N, nm, 4] f64
   double* vatom;           // [N, 9]
+  double* ke_part;         // [N/256 + 1] per-block kinetic energies
   // parameter-gradient scratch
   double* gE_col;          // [cols]
   double* grad_tmp;        // [n_params]

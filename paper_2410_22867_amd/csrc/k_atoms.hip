@@ -396,15 +396,18 @@ __global__ void k_kick_drift(MdArgs A) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_kick(MdArgs A) {
+// Second half-kick; each block writes its partial kinetic energy, a second
+// single-block kernel sums the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ part) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < A.n; i += 256) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < A.n) {
     const double m = A.mass[A.types[i]];
-    const double inv_m = kFtm2v / m;
+    const double h = 0.5 * A.dt * kFtm2v / m;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      double v = A.v[3 * i + a] + 0.5 * A.dt * A.f[3 * i + a] * inv_m;
+      const double v = A.v[3 * i + a] + h * A.f[3 * i + a];
       A.v[3 * i + a] = v;
       acc += 0.5 * m * v * v;
     }
@@ -415,7 +418,21 @@ __global__ __launch_bounds__(256) void k_kick(MdArgs A) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) A.ke[0] = red[0] / kFtm2v;
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int n, double scale,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) acc += part[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
 static MdArgs md_args(dp_ctx* c, double* x, double* v, const double* f, const int32_t* types, int32_t n, double dt) {
@@ -446,7 +463,9 @@ void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, in
                  hipStream_t s) {
   MdArgs A = md_args(c, nullptr, v, f, types, n, dt);
   A.ke = ke;
-  hipLaunchKernelGGL(k_kick, dim3(1), dim3(256), 0, s, A);
+  const int nb = (n + 255) / 256;
+  if (nb > 0) hipLaunchKernelGGL(k_kick, dim3(nb), dim3(256), 0, s, A, c->ke_part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, c->ke_part, nb, 1.0 / kFtm2v, ke);
 }
 
 }  // namespace dpse

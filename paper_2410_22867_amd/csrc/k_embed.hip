@@ -32,7 +32,7 @@ namespace dpse {
 
 struct EmbArgs {
   const int32_t* atom_at;
-  const int32_t* types;
+  const int32_t* meta;   // n_t, cbase_t per centre type
   const double* R;
   const int32_t* nnei;
   const double* frag64;
@@ -41,13 +41,22 @@ struct EmbArgs {
   const float* vec32;
   int64_t vec_per_net;
   EmbFragOffsets fo;
-  void* T;
-  const void* gT;
+  void* Tpart;           // forward: [ntypes][cols][m1][4] partial T per neighbour section
+  int64_t tpart_stride;  // elements between sections
+  const void* gT;        // backward: [cols][m1][4]
   double* netd;
-  int ncols, ntypes, nm;
+  int ntypes, nm, items;
   int sec[kMaxT + 1];
   double inv_nm;
 };
+
+// Returns 0 in a register the optimiser cannot see through; added to LDS
+// indices inside the neighbour-tile loop it keeps fragment loads in the loop.
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
 
 // per-net vector block: W1s[32] | b1s[32] | b2s[64] | b3s[128] | b3f[128]
 constexpr int kV_W1 = 0, kV_B1 = 32, kV_B2 = 64, kV_B3S = 128, kV_B3F = 256;
@@ -63,48 +72,62 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   return (p >> 6) * 2 * W + (q >> 5) * W + (q & 31);
 }
 
+// Common prologue of the per-net kernels: block (x = column chunk, y = net)
+// handles centre type ti = y / ntypes, neighbour section tj = y % ntypes,
+// columns [cb + x*WPB*items, ...) of the ti segment; wave w takes every
+// WPB-th column of the chunk.
+#define DPSE_NET_PROLOGUE(WPB)                                   \
+  const int net = blockIdx.y;                                    \
+  const int ti = net / A.ntypes, tj = net - ti * A.ntypes;       \
+  const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];       \
+  const int chunk0 = blockIdx.x * (WPB) * A.items;               \
+  if (chunk0 >= n_t) return;                                     \
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;     \
+  const int r16 = lane & 15, g = lane >> 4;
+
 // ============================================================== FP64 forward
-template <int W>
-__global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
+template <int W, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
-  __shared__ double h2s[4][16][kP2 + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int col = blockIdx.x * 4 + wv;
-  if (col >= A.ncols) return;
-  const int i = A.atom_at[col];
-  if (i < 0) return;
-  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
-  const int r16 = lane & 15, g = lane >> 4;
-  double accT[N3][4];
+  constexpr int NF2 = 2048, NF3 = N3 * 1024;
+  __shared__ double fr[NF2 + NF3];
+  __shared__ double h2s[WPB][16][kP2 + 1];
+  DPSE_NET_PROLOGUE(WPB)
+  {
+    const double* src = A.frag64 + net * A.fo.per_net;
+    for (int k = threadIdx.x; k < NF2; k += 64 * WPB) fr[k] = src[A.fo.F2 + k];
+    for (int k = threadIdx.x; k < NF3; k += 64 * WPB) fr[NF2 + k] = src[A.fo.F3n + k];
+  }
+  __syncthreads();
+  const double* vec = A.vec64 + net * A.vec_per_net;
+  double w1s[2][4], b1s[2][4], b2s[4][4];
 #pragma unroll
-  for (int o = 0; o < N3; ++o)
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) accT[o][k] = 0.0;
+    for (int v = 0; v < 4; ++v) {
+      w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
+      b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
+    }
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * v + g];
 
-  for (int tj = 0; tj < A.ntypes; ++tj) {
-    const int net = ti * A.ntypes + tj;
-    const double* vec = A.vec64 + net * A.vec_per_net;
-    const double* F2g = A.frag64 + net * A.fo.per_net + A.fo.F2;
-    const double* F3g = A.frag64 + net * A.fo.per_net + A.fo.F3n;
+  for (int it = 0; it < A.items; ++it) {
+    const int c = chunk0 + it * WPB + wv;
+    if (c >= n_t) break;
+    const int col = cb + c;
+    const int i = A.atom_at[col];
+    double accT[N3][4];
+#pragma unroll
+    for (int o = 0; o < N3; ++o)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) accT[o][k] = 0.0;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
-    double w1s[2][4], b1s[2][4], b2s[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
-        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
-      }
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * v + g];
-
     for (int r0 = 0; r0 < nn; r0 += 16) {
-      const double* F2 = opaque(F2g);
-      const double* F3 = opaque(F3g);
+      const int z0 = opaque_zero();
       const int row = r0 + r16;
       const double s = row < nn ? Rs[row * 4] : 0.0;
       double h1[2][4];
@@ -119,7 +142,7 @@ __global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
+          for (int v = 0; v < 4; ++v) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + b2s[ot][v]);
       }
@@ -129,7 +152,6 @@ __global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * v + g] = h2[ot][v];
       wave_lds_sync();
-      // rows of this lane in the rows-along-M layout: r0 + 4g + v
       double Rr[4][4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(h2[mt][v], F3[((o * 4 + mt) * 4 + v) * 64 + lane], z);
+          for (int v = 0; v < 4; ++v) z = mfma_f64(h2[mt][v], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
         const int feat = 16 * o + r16;
         if (feat < M1) {
           const double b3 = vec[kV_B3F + feat];
@@ -159,83 +181,76 @@ __global__ __launch_bounds__(256) void k_embed_fwd_f64(EmbArgs A) {
         }
       }
     }
-  }
 #pragma unroll
-  for (int o = 0; o < N3; ++o)
+    for (int o = 0; o < N3; ++o)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double x = accT[o][k];
-      x += shfl_xor_d(x, 16);
-      x += shfl_xor_d(x, 32);
-      accT[o][k] = x * A.inv_nm;
-    }
-  if (g == 0) {
-    double* T = reinterpret_cast<double*>(A.T) + (int64_t)col * M1 * 4;
+      for (int k = 0; k < 4; ++k) {
+        double x = accT[o][k];
+        x += shfl_xor_d(x, 16);
+        x += shfl_xor_d(x, 32);
+        accT[o][k] = x * A.inv_nm;
+      }
+    if (g == 0) {
+      double* T = reinterpret_cast<double*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
 #pragma unroll
-    for (int o = 0; o < N3; ++o) {
-      const int feat = 16 * o + r16;
-      if (feat < M1) {
-        d4 x = {accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
-        *reinterpret_cast<d4*>(T + feat * 4) = x;
+      for (int o = 0; o < N3; ++o) {
+        const int feat = 16 * o + r16;
+        if (feat < M1) *reinterpret_cast<d4*>(T + feat * 4) = d4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
       }
     }
   }
 }
 
 // ============================================================== FP64 backward
-template <int W>
-__global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
+template <int W, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
-  __shared__ d4 gts[4][kP3];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int col = blockIdx.x * 4 + wv;
-  if (col >= A.ncols) return;
-  const int i = A.atom_at[col];
-  if (i < 0) return;
-  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
-  const int r16 = lane & 15, g = lane >> 4;
-  {
-    const double* gT = reinterpret_cast<const double*>(A.gT) + (int64_t)col * M1 * 4;
-    for (int p = lane; p < kP3; p += 64) {
-      const int a = feat3_of_slot<W>(p);
-      d4 x = {0.0, 0.0, 0.0, 0.0};
-      if (a >= 0) {
-        x = *reinterpret_cast<const d4*>(gT + a * 4);
-        x = x * A.inv_nm;
-      }
-      gts[wv][p] = x;
-    }
+  __shared__ double fr[8192 + 8192];   // F3t | B3
+  __shared__ d4 gts[WPB][kP3];
+  DPSE_NET_PROLOGUE(WPB)
+  const double* gsrc = A.frag64 + net * A.fo.per_net;
+  for (int k = threadIdx.x; k < 8192; k += 64 * WPB) {
+    fr[k] = gsrc[A.fo.F3t + k];
+    fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
-  wave_lds_sync();
-
-  for (int tj = 0; tj < A.ntypes; ++tj) {
-    const int net = ti * A.ntypes + tj;
-    const double* vec = A.vec64 + net * A.vec_per_net;
-    const double* baseg = A.frag64 + net * A.fo.per_net;
+  __syncthreads();
+  const double* vec = A.vec64 + net * A.vec_per_net;
+  double w1s[2][4], b1s[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
+      b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
+    }
+  for (int it = 0; it < A.items; ++it) {
+    const int c = chunk0 + it * WPB + wv;
+    if (c >= n_t) break;
+    const int col = cb + c;
+    const int i = A.atom_at[col];
+    {
+      const double* gT = reinterpret_cast<const double*>(A.gT) + (int64_t)col * M1 * 4;
+      wave_lds_sync();
+      for (int p = lane; p < kP3; p += 64) {
+        const int a = feat3_of_slot<W>(p);
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (a >= 0) x = *reinterpret_cast<const d4*>(gT + a * 4) * A.inv_nm;
+        gts[wv][p] = x;
+      }
+      wave_lds_sync();
+    }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
-    double w1s[2][4], b1s[2][4];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
-        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
-      }
-
     for (int r0 = 0; r0 < nn; r0 += 16) {
-      const double* base = opaque(baseg);
-      const double* F2 = base + A.fo.F2;
-      const double* F3 = base + A.fo.F3t;
-      const double* B3 = base + A.fo.B3;
-      const double* B2 = base + A.fo.B2;
+      const int z0 = opaque_zero();
+      const double* F2 = opaque(gsrc + A.fo.F2);
+      const double* B2 = opaque(gsrc + A.fo.B2);
       const int row = r0 + r16;
       const bool valid = row < nn;
       d4 Rrow = {0.0, 0.0, 0.0, 0.0};
       if (valid) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
       const double s = Rrow[0];
-      // ---- recompute forward (transposed layout)
       double t1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
@@ -255,7 +270,7 @@ __global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
           h2[ot][v] = t1[ot & 1][v] + t2[ot][v];
         }
       }
-      // ---- layer 3 per output tile o, immediately folded into dh2 = W3 dz3
+      // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
       double dRd[4] = {0.0, 0.0, 0.0, 0.0};
       d4 dh2a[4];
@@ -267,63 +282,61 @@ __global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
       }
 #pragma unroll 1
       for (int oo = 0; oo < 2; ++oo) {
-      const double* F3o = opaque(F3 + oo * 4 * 16 * 64);
-      const double* B3o = opaque(B3 + oo * 4 * 4 * 64);
+        const int zo = opaque_zero() + oo;
 #pragma unroll
-      for (int o4 = 0; o4 < 4; ++o4) {
-        const int o = 4 * oo + o4;
-        d4 z = {0.0, 0.0, 0.0, 0.0};
+        for (int o4 = 0; o4 < 4; ++o4) {
+          d4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+          for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(F3o[((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
-        double dz3[4];
+            for (int v = 0; v < 4; ++v)
+              z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+          double dz3[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int p = 16 * o + 4 * v + g;
-          const double t3 = tanh_d(z[v] + vec[kV_B3S + p]);
-          const double G = h2[o4][v] + t3;
-          const d4 gt = gts[wv][p];
-          const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+          for (int v = 0; v < 4; ++v) {
+            const int p = 16 * (4 * zo + o4) + 4 * v + g;
+            const double t3 = tanh_d(z[v] + vec[kV_B3S + p]);
+            const double G = h2[o4][v] + t3;
+            const d4 gt = gts[wv][p];
+            const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) dRd[k] = fma(gt[k], G, dRd[k]);
-          dz3[v] = dG * (1.0 - t3 * t3);
-          skip2[o4][v] += dG;
+            for (int k = 0; k < 4; ++k) dRd[k] = fma(gt[k], G, dRd[k]);
+            dz3[v] = dG * (1.0 - t3 * t3);
+            skip2[o4][v] += dG;
+          }
+#pragma unroll
+          for (int i2 = 0; i2 < 4; ++i2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              dh2a[i2] = mfma_f64(fr[z0 + 8192 + zo * 1024 + ((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
         }
-#pragma unroll
-        for (int it = 0; it < 4; ++it)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) dh2a[it] = mfma_f64(B3o[((it * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[it]);
       }
-      }
-      // ---- dz2 = (dh2 + skip) (1 - t2^2)
       double dz2[4][4];
       double skip1[2][4];
 #pragma unroll
-      for (int it = 0; it < 2; ++it)
+      for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) skip1[it][v] = 0.0;
+        for (int v = 0; v < 4; ++v) skip1[i2][v] = 0.0;
 #pragma unroll
-      for (int it = 0; it < 4; ++it)
+      for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double dh2 = dh2a[it][v] + skip2[it][v];
-          dz2[it][v] = dh2 * (1.0 - t2[it][v] * t2[it][v]);
-          skip1[it & 1][v] += dh2;
+          const double dh2 = dh2a[i2][v] + skip2[i2][v];
+          dz2[i2][v] = dh2 * (1.0 - t2[i2][v] * t2[i2][v]);
+          skip1[i2 & 1][v] += dh2;
         }
-      // ---- dh1 = W2 dz2 + skip; dz1 = dh1 (1 - t1^2); ds = W1 . dz1
       double dsp = 0.0;
 #pragma unroll
-      for (int it = 0; it < 2; ++it) {
+      for (int i2 = 0; i2 < 2; ++i2) {
         d4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((it * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double dh1 = z[v] + skip1[it][v];
-          dsp = fma(w1s[it][v], dh1 * (1.0 - t1[it][v] * t1[it][v]), dsp);
+          const double dh1 = z[v] + skip1[i2][v];
+          dsp = fma(w1s[i2][v], dh1 * (1.0 - t1[i2][v] * t1[i2][v]), dsp);
         }
       }
       dsp += shfl_xor_d(dsp, 16);
@@ -333,10 +346,7 @@ __global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
         dRd[k] += shfl_xor_d(dRd[k], 16);
         dRd[k] += shfl_xor_d(dRd[k], 32);
       }
-      if (g == 0 && valid) {
-        d4 out = {dRd[0] + dsp, dRd[1], dRd[2], dRd[3]};
-        *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = out;
-      }
+      if (g == 0 && valid) *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = d4{dRd[0] + dsp, dRd[1], dRd[2], dRd[3]};
     }
   }
 }
@@ -345,58 +355,59 @@ __global__ __launch_bounds__(256) void k_embed_bwd_f64(EmbArgs A) {
 // Layer 1 in FP32 on the vector ALUs (K = 1), layers 2 and 3 on 16x16x32
 // MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32,
 // contraction in FP32.
-template <class P, int W>
-__global__ __launch_bounds__(256) void k_embed_fwd_lp(EmbArgs A) {
+template <class P, int W, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
-  __shared__ float h2s[4][16][kP2 + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int col = blockIdx.x * 4 + wv;
-  if (col >= A.ncols) return;
-  const int i = A.atom_at[col];
-  if (i < 0) return;
-  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
-  const int r16 = lane & 15, g = lane >> 4;
-  float accT[N3][4];
+  constexpr int NF2 = 2048, NF3 = N3 * 1024;
+  __shared__ __attribute__((aligned(16))) uint16_t fr[NF2 + NF3];
+  __shared__ float h2s[WPB][16][kP2 + 1];
+  DPSE_NET_PROLOGUE(WPB)
+  {
+    const uint16_t* src = A.fraglp + net * A.fo.per_net;
+    for (int k = threadIdx.x; k < NF2 / 8; k += 64 * WPB)
+      reinterpret_cast<u16x8*>(fr)[k] = reinterpret_cast<const u16x8*>(src + A.fo.F2)[k];
+    for (int k = threadIdx.x; k < NF3 / 8; k += 64 * WPB)
+      reinterpret_cast<u16x8*>(fr + NF2)[k] = reinterpret_cast<const u16x8*>(src + A.fo.F3n)[k];
+  }
+  __syncthreads();
+  const float* vec = A.vec32 + net * A.vec_per_net;
+  float w1s[8], b1s[8], b2s[4][4];
 #pragma unroll
-  for (int o = 0; o < N3; ++o)
+  for (int j = 0; j < 8; ++j) {
+    w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+    b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
+  for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
 
-  for (int tj = 0; tj < A.ntypes; ++tj) {
-    const int net = ti * A.ntypes + tj;
-    const float* vec = A.vec32 + net * A.vec_per_net;
-    const uint16_t* F2g = A.fraglp + net * A.fo.per_net + A.fo.F2;
-    const uint16_t* F3g = A.fraglp + net * A.fo.per_net + A.fo.F3n;
+  for (int it = 0; it < A.items; ++it) {
+    const int c = chunk0 + it * WPB + wv;
+    if (c >= n_t) break;
+    const int col = cb + c;
+    const int i = A.atom_at[col];
+    float accT[N3][4];
+#pragma unroll
+    for (int o = 0; o < N3; ++o)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
-    float w1s[2][4], b1s[2][4], b2s[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * g + v];
-        b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * g + v];
-      }
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
-
     for (int r0 = 0; r0 < nn; r0 += 16) {
-      const uint16_t* F2 = opaque(F2g);
-      const uint16_t* F3 = opaque(F3g);
+      const int z0 = opaque_zero();
       const int row = r0 + r16;
       const float s = row < nn ? (float)Rs[row * 4] : 0.f;
       float h1[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j >> 2][j & 3], b1s[j >> 2][j & 3]));
+      for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
       const typename P::vec8 b1v = pack8<P>(h1);
-      float h2[8][4];  // [2*kt + j/4][j%4] for the two layer-3 k-steps
+      float h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
-        z = P::mfma(load8<P>(F2 + (ot * 64 + lane) * 8), b1v, z);
+        z = P::mfma(load8<P>(fr + z0 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2[ot][v] = h1[4 * (ot & 1) + v] + tanh_f(z[v] + b2s[ot][v]);
       }
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(256) void k_embed_fwd_lp(EmbArgs A) {
       for (int o = 0; o < N3; ++o) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(F3 + ((o * 2 + kt) * 64 + lane) * 8), z);
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
         const int feat = 16 * o + r16;
         if (feat < M1) {
           const float b3 = vec[kV_B3F + feat];
@@ -441,73 +452,77 @@ __global__ __launch_bounds__(256) void k_embed_fwd_lp(EmbArgs A) {
         }
       }
     }
-  }
-  const float inv_nm = (float)A.inv_nm;
+    const float inv_nm = (float)A.inv_nm;
 #pragma unroll
-  for (int o = 0; o < N3; ++o)
+    for (int o = 0; o < N3; ++o)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      float x = accT[o][k];
-      x += shfl_xor_f(x, 16);
-      x += shfl_xor_f(x, 32);
-      accT[o][k] = x * inv_nm;
-    }
-  if (g == 0) {
-    float* T = reinterpret_cast<float*>(A.T) + (int64_t)col * M1 * 4;
+      for (int k = 0; k < 4; ++k) {
+        float x = accT[o][k];
+        x += shfl_xor_f(x, 16);
+        x += shfl_xor_f(x, 32);
+        accT[o][k] = x * inv_nm;
+      }
+    if (g == 0) {
+      float* T = reinterpret_cast<float*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
 #pragma unroll
-    for (int o = 0; o < N3; ++o) {
-      const int feat = 16 * o + r16;
-      if (feat < M1) {
-        f4 x = {accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
-        *reinterpret_cast<f4*>(T + feat * 4) = x;
+      for (int o = 0; o < N3; ++o) {
+        const int feat = 16 * o + r16;
+        if (feat < M1) *reinterpret_cast<f4*>(T + feat * 4) = f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
       }
     }
   }
 }
 
 // ============================================================== mixed backward
-template <class P, int W>
-__global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
+template <class P, int W, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
-  __shared__ f4 gts[4][kP3];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int col = blockIdx.x * 4 + wv;
-  if (col >= A.ncols) return;
-  const int i = A.atom_at[col];
-  if (i < 0) return;
-  const int ti = min(max(A.types[i], 0), A.ntypes - 1);
-  const int r16 = lane & 15, g = lane >> 4;
+  constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
+  __shared__ __attribute__((aligned(16))) uint16_t fr[NFR];
+  __shared__ f4 gts[WPB][kP3];
+  DPSE_NET_PROLOGUE(WPB)
   {
-    const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
-    const float inv_nm = (float)A.inv_nm;
-    for (int p = lane; p < kP3; p += 64) {
-      const int a = feat3_of_slot<W>(p);
-      f4 x = {0.f, 0.f, 0.f, 0.f};
-      if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4) * inv_nm;
-      gts[wv][p] = x;
+    const uint16_t* src = A.fraglp + net * A.fo.per_net;
+    const int64_t offs[4] = {A.fo.F2, A.fo.F3t, A.fo.B3, A.fo.B2};
+    const int lens[4] = {2048, 8192, 8192, 2048};
+    int dst = 0;
+    for (int b = 0; b < 4; ++b) {
+      for (int k = threadIdx.x; k < lens[b] / 8; k += 64 * WPB)
+        reinterpret_cast<u16x8*>(fr + dst)[k] = reinterpret_cast<const u16x8*>(src + offs[b])[k];
+      dst += lens[b];
     }
   }
-  wave_lds_sync();
-
-  for (int tj = 0; tj < A.ntypes; ++tj) {
-    const int net = ti * A.ntypes + tj;
-    const float* vec = A.vec32 + net * A.vec_per_net;
-    const uint16_t* baseg = A.fraglp + net * A.fo.per_net;
+  __syncthreads();
+  constexpr int oF2 = 0, oF3 = 2048, oB3 = 2048 + 8192, oB2 = 2048 + 8192 + 8192;
+  const float* vec = A.vec32 + net * A.vec_per_net;
+  float w1s[8], b1s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+    b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+  }
+  for (int it = 0; it < A.items; ++it) {
+    const int c = chunk0 + it * WPB + wv;
+    if (c >= n_t) break;
+    const int col = cb + c;
+    const int i = A.atom_at[col];
+    {
+      const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
+      const float inv_nm = (float)A.inv_nm;
+      wave_lds_sync();
+      for (int p = lane; p < kP3; p += 64) {
+        const int a = feat3_of_slot<W>(p);
+        f4 x = {0.f, 0.f, 0.f, 0.f};
+        if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4) * inv_nm;
+        gts[wv][p] = x;
+      }
+      wave_lds_sync();
+    }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
-    float w1s[8], b1s[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-      b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-    }
     for (int r0 = 0; r0 < nn; r0 += 16) {
-      const uint16_t* base = opaque(baseg);
-      const uint16_t* F2 = base + A.fo.F2;
-      const uint16_t* F3 = base + A.fo.F3t;
-      const uint16_t* B3 = base + A.fo.B3;
-      const uint16_t* B2 = base + A.fo.B2;
+      const int z0 = opaque_zero();
       const int row = r0 + r16;
       const bool valid = row < nn;
       d4 Rd = {0.0, 0.0, 0.0, 0.0};
@@ -522,7 +537,7 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
-        z = P::mfma(load8<P>(F2 + (ot * 64 + lane) * 8), b1v, z);
+        z = P::mfma(load8<P>(fr + z0 + oF2 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           t2[ot][v] = tanh_f(z[v] + vec[kV_B2 + 16 * ot + 4 * g + v]);
@@ -547,7 +562,7 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
       for (int o = 0; o < 8; ++o) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(F3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oF3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int p = 16 * o + 4 * g + v;
@@ -563,9 +578,9 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
       }
       float dz2[4][4], skip1[2][4];
 #pragma unroll
-      for (int it = 0; it < 2; ++it)
+      for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) skip1[it][v] = 0.f;
+        for (int v = 0; v < 4; ++v) skip1[i2][v] = 0.f;
       typename P::vec8 bz3[4];
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt) {
@@ -575,15 +590,15 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
         bz3[kt] = pack8<P>(tmp);
       }
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
+      for (int i2 = 0; i2 < 4; ++i2) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) z = P::mfma(load8<P>(B3 + ((it * 4 + kt) * 64 + lane) * 8), bz3[kt], z);
+        for (int kt = 0; kt < 4; ++kt) z = P::mfma(load8<P>(fr + z0 + oB3 + ((i2 * 4 + kt) * 64 + lane) * 8), bz3[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float dh2 = z[v] + skip2[it][v];
-          dz2[it][v] = dh2 * (1.f - t2[it][v] * t2[it][v]);
-          skip1[it & 1][v] += dh2;
+          const float dh2 = z[v] + skip2[i2][v];
+          dz2[i2][v] = dh2 * (1.f - t2[i2][v] * t2[i2][v]);
+          skip1[i2 & 1][v] += dh2;
         }
       }
       typename P::vec8 bz2[2];
@@ -596,15 +611,15 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
       }
       float dsp = 0.f;
 #pragma unroll
-      for (int it = 0; it < 2; ++it) {
+      for (int i2 = 0; i2 < 2; ++i2) {
         f4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(B2 + ((it * 2 + kt) * 64 + lane) * 8), bz2[kt], z);
+        for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oB2 + ((i2 * 2 + kt) * 64 + lane) * 8), bz2[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float dh1 = z[v] + skip1[it][v];
-          const float t = t1[4 * it + v];
-          dsp = fmaf(w1s[4 * it + v], dh1 * (1.f - t * t), dsp);
+          const float dh1 = z[v] + skip1[i2][v];
+          const float tt = t1[4 * i2 + v];
+          dsp = fmaf(w1s[4 * i2 + v], dh1 * (1.f - tt * tt), dsp);
         }
       }
       dsp += shfl_xor_f(dsp, 16);
@@ -614,20 +629,21 @@ __global__ __launch_bounds__(256) void k_embed_bwd_lp(EmbArgs A) {
         dRd[k] += shfl_xor_f(dRd[k], 16);
         dRd[k] += shfl_xor_f(dRd[k], 32);
       }
-      if (g == 0 && valid) {
-        d4 out = {(double)dRd[0] + (double)dsp, (double)dRd[1], (double)dRd[2], (double)dRd[3]};
-        *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = out;
-      }
+      if (g == 0 && valid)
+        *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) =
+            d4{(double)dRd[0] + (double)dsp, (double)dRd[1], (double)dRd[2], (double)dRd[3]};
     }
   }
 }
 
 // ============================================================== launchers
-static EmbArgs emb_args(dp_ctx* c, const int32_t* types, int32_t mode) {
+constexpr int kEmbWPB = 4;
+
+static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
   const dp_model* m = c->model;
   EmbArgs A;
   A.atom_at = c->atom_at;
-  A.types = types;
+  A.meta = c->type_meta;
   A.R = c->R;
   A.nnei = c->nnei;
   A.frag64 = m->emb_frag64;
@@ -636,25 +652,41 @@ static EmbArgs emb_args(dp_ctx* c, const int32_t* types, int32_t mode) {
   A.vec32 = m->emb_vec32;
   A.vec_per_net = m->emb_vec_per_net;
   A.fo = m->efo;
-  A.T = c->T;
+  A.Tpart = c->Tpart;
+  A.tpart_stride = c->max_cols * m->m1 * 4;
   A.gT = c->gT;
   A.netd = c->netd;
-  A.ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
   A.ntypes = m->desc.ntypes;
   A.nm = m->nm;
+  A.items = items;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= m->desc.ntypes ? m->sec[t] : m->nm;
   A.inv_nm = 1.0 / (double)m->nm;
   return A;
 }
 
-#define DPSE_EMB_DISPATCH(KF64, KLP, W)                                                                  \
-  if (mode == DP_FP64) hipLaunchKernelGGL((KF64<W>), grid, block, 0, s, A);                             \
-  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((KLP<PrecBF16, W>), grid, block, 0, s, A);           \
-  else hipLaunchKernelGGL((KLP<PrecF16, W>), grid, block, 0, s, A);
+// Columns per wave: about 1024 work-groups over all nets (4 per CU).
+static int emb_items(dp_ctx* c) {
+  const int64_t n = c->natoms_last;
+  const int nets = c->model->desc.ntypes * c->model->desc.ntypes;
+  int64_t items = (n * c->model->desc.ntypes) / (1024LL * kEmbWPB);
+  (void)nets;
+  if (items < 1) items = 1;
+  if (items > 16) items = 16;
+  return (int)items;
+}
+
+#define DPSE_EMB_DISPATCH(KF64, KLP, W)                                                                       \
+  if (mode == DP_FP64) hipLaunchKernelGGL((KF64<W, kEmbWPB>), grid, block, 0, s, A);                         \
+  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((KLP<PrecBF16, W, kEmbWPB>), grid, block, 0, s, A);       \
+  else hipLaunchKernelGGL((KLP<PrecF16, W, kEmbWPB>), grid, block, 0, s, A);
 
 void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
-  EmbArgs A = emb_args(c, types, mode);
-  dim3 grid((A.ncols + 3) / 4), block(256);
+  (void)types;
+  if (c->natoms_last <= 0) return;
+  const int items = emb_items(c);
+  EmbArgs A = emb_args(c, mode, items);
+  const int per_block = kEmbWPB * items;
+  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes)), block(64 * kEmbWPB);
   if (c->model->w1 == 25) {
     DPSE_EMB_DISPATCH(k_embed_fwd_f64, k_embed_fwd_lp, 25)
   } else {
@@ -663,8 +695,12 @@ void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t
 }
 
 void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
-  EmbArgs A = emb_args(c, types, mode);
-  dim3 grid((A.ncols + 3) / 4), block(256);
+  (void)types;
+  if (c->natoms_last <= 0) return;
+  const int items = emb_items(c);
+  EmbArgs A = emb_args(c, mode, items);
+  const int per_block = kEmbWPB * items;
+  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes)), block(64 * kEmbWPB);
   if (c->model->w1 == 25) {
     DPSE_EMB_DISPATCH(k_embed_bwd_f64, k_embed_bwd_lp, 25)
   } else {

@@ -215,15 +215,23 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
 // D[a*m2 + b] = sum_k T[a][k] T[b][k], a < m1, b < m2 (m2 = 16).  One
 // work-group per column, thread a writes 16 consecutive entries.
 template <typename TT, typename DT>
-__global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ atom_at, const TT* __restrict__ T,
+__global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ atom_at, const TT* __restrict__ Tpart,
+                                                    int64_t tstride, int ntypes, TT* __restrict__ T,
                                                     DT* __restrict__ D, int m1, int mode_lp_f16) {
   __shared__ TT Ts[128][4];
   const int col = blockIdx.x;
   const bool real = atom_at[col] >= 0;
   const int a = threadIdx.x;
-  if (a < m1)
+  if (a < m1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Ts[a][k] = real ? T[((int64_t)col * m1 + a) * 4 + k] : (TT)0;
+    for (int k = 0; k < 4; ++k) {
+      TT v = (TT)0;
+      if (real)
+        for (int t = 0; t < ntypes; ++t) v += Tpart[t * tstride + ((int64_t)col * m1 + a) * 4 + k];
+      Ts[a][k] = v;
+      if (real) T[((int64_t)col * m1 + a) * 4 + k] = v;
+    }
+  }
   __syncthreads();
   if (a >= m1) return;
   DT* out = D + ((int64_t)col * m1 + a) * 16;
@@ -337,12 +345,14 @@ void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) {
   const dp_model* m = c->model;
   const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
   if (c->natoms_last <= 0) return;
+  const int64_t ts = c->max_cols * m->m1 * 4;
   if (mode == DP_FP64)
-    hipLaunchKernelGGL((k_descriptor<double, double>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const double*)c->T,
-                       (double*)c->D, m->m1, 0);
+    hipLaunchKernelGGL((k_descriptor<double, double>), dim3(ncols), dim3(128), 0, s, c->atom_at,
+                       (const double*)c->Tpart, ts, m->desc.ntypes, (double*)c->T, (double*)c->D, m->m1, 0);
   else
-    hipLaunchKernelGGL((k_descriptor<float, uint16_t>), dim3(ncols), dim3(128), 0, s, c->atom_at, (const float*)c->T,
-                       (uint16_t*)c->D, m->m1, mode == DP_MIX_FP16 ? 1 : 0);
+    hipLaunchKernelGGL((k_descriptor<float, uint16_t>), dim3(ncols), dim3(128), 0, s, c->atom_at,
+                       (const float*)c->Tpart, ts, m->desc.ntypes, (float*)c->T, (uint16_t*)c->D, m->m1,
+                       mode == DP_MIX_FP16 ? 1 : 0);
 }
 
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
