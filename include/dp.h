@@ -172,8 +172,11 @@ int dp_compute_batch(dp_ctx* ctx, const double* coords, const int32_t* types, co
 
 /* Parameter gradient of a loss L through the energies of the last
  * dp_compute / dp_compute_batch on this context: grad_params [n_params]
- * device f64 receives sum_f dL/dE_f * dE_f/dtheta (overwritten), for
- * dL_dE [B] device f64.  Returns DP_ERR_STATE if no compute preceded. */
+ * device f64 receives sum_f dL/dE_f * dE_f/dtheta (overwritten, flat layout
+ * of dp_model_n_params), for dL_dE [B] device f64 (B = frames of that
+ * compute).  Needs the last compute in DP_FP64 (DP_ERR_UNSUPPORTED
+ * otherwise) and its inputs unchanged; DP_ERR_STATE if no compute preceded.
+ * Gradients are accumulated with atomics (summation order not fixed). */
 int dp_backward_params(dp_ctx* ctx, const double* dL_dE, double* grad_params, hipStream_t stream);
 
 /* Velocity-Verlet halves (FP64; Evaluation section time steps).

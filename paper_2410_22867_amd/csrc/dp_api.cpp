@@ -215,6 +215,21 @@ int prepare_model(dp_model* m, const double* P) {
   const int w = m->w1, nt = d.ntypes, fw = m->fw, nd = m->nd;
   const int nnets = nt * nt;
   int rc;
+  // ---- flat-parameter offsets for the gradient kernels
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b)
+      for (int l = 0; l < 3; ++l) {
+        m->emb_param_off[a * nt + b][2 * l] = L.embW[a][b][l];
+        m->emb_param_off[a * nt + b][2 * l + 1] = L.embB[a][b][l];
+      }
+  for (int l = 0; l < 3; ++l) {
+    m->fit_param_off[l] = L.fitW[0][l];
+    m->fit_param_off[3 + l] = L.fitB[0][l];
+  }
+  m->fit_param_off[6] = L.wo[0];
+  m->fit_param_off[7] = L.bo[0];
+  m->fit_param_stride = nt > 1 ? L.fitW[1][0] - L.fitW[0][0] : 0;
+  m->ebias_off = L.ebias;
   // ---- embedding vectors
   m->emb_vec_per_net = 384;
   std::vector<double> ev((size_t)nnets * 384, 0.0);
@@ -748,9 +763,15 @@ int dp_compute_batch(dp_ctx* c, const double* coords, const int32_t* types, cons
 int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipStream_t stream) {
   if (!c || !dL_dE || !grad_params) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
   if (!c->have_state) { set_error("dp_backward_params needs a preceding dp_compute"); return DP_ERR_STATE; }
-  (void)stream;
-  set_error("parameter gradients are not implemented yet");
-  return DP_ERR_UNSUPPORTED;
+  if (c->mode_last != DP_FP64) {
+    set_error("parameter gradients need a preceding DP_FP64 compute");
+    return DP_ERR_UNSUPPORTED;
+  }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  launch_param_grads(c, dL_dE, grad_params, stream);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
 }
 
 int dp_md_kick_drift(dp_ctx* c, double* coords, double* vel, const double* forces, const int32_t* types,

@@ -74,6 +74,11 @@ struct dp_model {
   uint16_t* fit_frag_f16;
   dpse::FitFragOffsets ffo;     // FP64 fragment offsets
   dpse::FitFragOffsets ffo_lp;  // BF16/FP16 fragment offsets (K padded to 32)
+  // flat-parameter offsets used by the gradient kernels
+  int64_t emb_param_off[DP_MAX_TYPES * DP_MAX_TYPES][6];  // W1 b1 W2 b2 W3 b3 per net
+  int64_t fit_param_off[8];   // type 0: W1 W2 W3 b1 b2 b3 w_out b_out
+  int64_t fit_param_stride;   // parameters per fitting net
+  int64_t ebias_off;
   double* fit_vec64;   // per type: b1, b2, b3, wo [fw each], bo, ebias  (4*fw + 2)
   float* fit_vec32;
   int64_t fit_vec_per_type;
@@ -173,6 +178,8 @@ void launch_kick_drift(dp_ctx* c, double* x, double* v, const double* f, const i
                        double dt, const double L[3], int32_t* images, hipStream_t s);
 void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, int32_t n, double dt, double* ke,
                  hipStream_t s);
+// parameter gradients (FP64 state of the last compute)
+void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t s);
 // inspection
 void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, double* dst, hipStream_t s);
 

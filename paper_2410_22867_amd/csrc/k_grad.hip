@@ -1,0 +1,466 @@
+// Parameter gradients of an energy loss, sum_f dL/dE_f dE_f/dtheta, from the
+// state of the last FP64 compute (energy-loss training of the model; the
+// paper's model is trained this way, its Background section cites the
+// training papers).  Everything downstream of E_f is linear in the seed, so
+// each centre-atom column is weighted by w_col = dL/dE of its frame and the
+// unit-seed deltas stored by the force backward are reused where they exist.
+//
+// Fitting weights:   dW_l = sum_col X_l[col]^T w_col dz_l[col]  (column
+//   reduction; MFMA with columns along K, split over column chunks,
+//   accumulated with global atomics).
+// Embedding weights: the backward of each neighbour row is recomputed (as in
+//   the force path, with g_T scaled by w_col); per 16-row tile the activations
+//   and deltas are transposed through LDS so that the reduction over rows is
+//   an MFMA product, accumulated in per-work-group LDS sums and added to the
+//   global gradient once per work-group.
+#include "dp_internal.h"
+#include "dp_device.h"
+
+namespace dpse {
+
+// ------------------------------------------------------------ column weights
+__global__ void k_col_weights(const int32_t* __restrict__ atom_at, const int32_t* __restrict__ frame_of,
+                              const double* __restrict__ dLdE, double* __restrict__ w, int ncols) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const int i = atom_at[c];
+  w[c] = i >= 0 ? dLdE[frame_of[i]] : 0.0;
+}
+
+// ------------------------------------------------------------ fitting grads
+// out[m][n] += sum_{col in chunk} X[col][m] w[col] Y[col][n]; m < M, n < N
+// (multiples of 16).  Block: 4 waves; wave w handles m-tile (blockIdx.y*4+w),
+// all n-tiles; blockIdx.x = column chunk; blockIdx.z = type.
+struct WGradArgs {
+  const double* X;  int ldx;
+  const double* Y;  int ldy;
+  const double* w;
+  const int32_t* meta;
+  int M, N, chunk;
+  double* out;      // gradient of type 0; type stride below
+  int64_t out_type_stride;
+  int64_t out_off;  // offset of this block inside the type's parameters
+};
+
+template <int NTMAX>
+__global__ __launch_bounds__(256) void k_wgrad_cols(WGradArgs a) {
+  const int t = blockIdx.z;
+  const int n_t = a.meta[2 * t], cb = a.meta[2 * t + 1];
+  const int c0 = blockIdx.x * a.chunk;
+  if (c0 >= n_t) return;
+  const int c1 = min(n_t, c0 + a.chunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int mt = blockIdx.y * 4 + wv;
+  if (mt * 16 >= a.M) return;
+  const int ntiles = a.N / 16;
+  d4 acc[NTMAX];
+#pragma unroll
+  for (int k = 0; k < NTMAX; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int c = c0; c < c1; c += 4) {
+    const int col = cb + c + g;
+    const bool ok = c + g < c1;
+    const double wc = ok ? a.w[col] : 0.0;
+    const double xa = ok ? a.X[(int64_t)col * a.ldx + mt * 16 + r16] * wc : 0.0;
+#pragma unroll
+    for (int nt = 0; nt < NTMAX; ++nt) {
+      if (nt < ntiles) {
+        const double yb = ok ? a.Y[(int64_t)col * a.ldy + nt * 16 + r16] : 0.0;
+        acc[nt] = mfma_f64(xa, yb, acc[nt]);
+      }
+    }
+  }
+  double* out = a.out + t * a.out_type_stride + a.out_off;
+#pragma unroll
+  for (int nt = 0; nt < NTMAX; ++nt) {
+    if (nt < ntiles)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = mt * 16 + 4 * v + g;
+        const int n = nt * 16 + r16;
+        atomicAdd(&out[(int64_t)m * a.N + n], acc[nt][v]);
+      }
+  }
+}
+
+// bias-type reductions: out[n] += sum_col w[col] Y[col][n] (Y == nullptr: 1)
+__global__ __launch_bounds__(256) void k_bgrad_cols(const double* __restrict__ Y, int ldy, const double* __restrict__ w,
+                                                    const int32_t* __restrict__ meta, int N, int chunk,
+                                                    double* __restrict__ out, int64_t out_type_stride,
+                                                    int64_t out_off) {
+  const int t = blockIdx.z;
+  const int n_t = meta[2 * t], cb = meta[2 * t + 1];
+  const int c0 = blockIdx.x * chunk;
+  if (c0 >= n_t) return;
+  const int c1 = min(n_t, c0 + chunk);
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) {
+      const int64_t col = cb + c;
+      acc += w[col] * (Y ? Y[col * ldy + n] : 1.0);
+    }
+    atomicAdd(&out[t * out_type_stride + out_off + n], acc);
+  }
+}
+
+// ------------------------------------------------------------ embedding grads
+struct EGradArgs {
+  const int32_t* atom_at;
+  const int32_t* meta;
+  const double* R;
+  const int32_t* nnei;
+  const double* frag64;
+  const double* vec64;
+  int64_t vec_per_net;
+  EmbFragOffsets fo;
+  const double* gT;
+  const double* wcol;
+  double* grad;
+  int64_t offW[kMaxT * kMaxT][3], offB[kMaxT * kMaxT][3];
+  int ntypes, nm, items;
+  int sec[kMaxT + 1];
+  double inv_nm;
+};
+
+template <int W>
+__device__ __forceinline__ int e_feat1(int p) { return p < W ? p : -1; }
+template <int W>
+__device__ __forceinline__ int e_feat2(int p) { return (p & 31) < W ? (p >> 5) * W + (p & 31) : -1; }
+template <int W>
+__device__ __forceinline__ int e_feat3(int p) {
+  const int f = e_feat2<W>(p & 63);
+  return f < 0 ? -1 : (p >> 6) * 2 * W + f;
+}
+
+constexpr int kGWPB = 2;
+
+template <int W>
+__global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
+  // per-block accumulators (slot-indexed)
+  __shared__ double aW3[64 * 128];
+  __shared__ double aW2[32 * 64];
+  __shared__ double aW1[32], aB1[32], aB2[64], aB3[128];
+  // per-wave transposition buffers: [row][slot]; buffer 0 holds h2 | dz3,
+  // then h1 | dz2 | dz1 | s
+  __shared__ double tb[kGWPB][16][65 + 129];
+  __shared__ d4 gts[kGWPB][128];
+  const int net = blockIdx.y;
+  const int ti = net / A.ntypes, tj = net - ti * A.ntypes;
+  const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];
+  const int chunk0 = blockIdx.x * kGWPB * A.items;
+  if (chunk0 >= n_t) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) aW3[k] = 0.0;
+  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) aW2[k] = 0.0;
+  for (int k = threadIdx.x; k < 128; k += 64 * kGWPB) {
+    aB3[k] = 0.0;
+    if (k < 64) aB2[k] = 0.0;
+    if (k < 32) { aB1[k] = 0.0; aW1[k] = 0.0; }
+  }
+  __syncthreads();
+  const double* base = A.frag64 + net * A.fo.per_net;
+  const double* vec = A.vec64 + net * A.vec_per_net;
+  double w1s[2][4], b1s[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      w1s[mt][v] = vec[16 * mt + 4 * v + g];
+      b1s[mt][v] = vec[32 + 16 * mt + 4 * v + g];
+    }
+  double (*T)[65 + 129] = tb[wv];
+  for (int it = 0; it < A.items; ++it) {
+    const int c = chunk0 + it * kGWPB + wv;
+    if (c >= n_t) break;
+    const int col = cb + c;
+    const int i = A.atom_at[col];
+    const double wc = A.wcol[col];
+    {
+      const double* gT = A.gT + (int64_t)col * (4 * W) * 4;
+      wave_lds_sync();
+      for (int p = lane; p < 128; p += 64) {
+        const int a = e_feat3<W>(p);
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (a >= 0) x = *reinterpret_cast<const d4*>(gT + a * 4) * (A.inv_nm * wc);
+        gts[wv][p] = x;
+      }
+      wave_lds_sync();
+    }
+    const int nn = A.nnei[i * kMaxT + tj];
+    const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    for (int r0 = 0; r0 < nn; r0 += 16) {
+      const double* F2 = opaque(base + A.fo.F2);
+      const double* F3 = opaque(base + A.fo.F3t);
+      const double* B3 = opaque(base + A.fo.B3);
+      const double* B2 = opaque(base + A.fo.B2);
+      const int row = r0 + r16;
+      d4 Rrow = {0.0, 0.0, 0.0, 0.0};
+      if (row < nn) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const double s = Rrow[0];
+      double t1[2][4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
+      double t2[4][4], h2[4][4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t2[ot][v] = tanh_d(z[v] + vec[64 + 16 * ot + 4 * v + g]);
+          h2[ot][v] = t1[ot & 1][v] + t2[ot][v];
+        }
+      }
+      wave_lds_sync();
+      // h2 -> T[row][0..64)
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[r16][16 * ot + 4 * v + g] = h2[ot][v];
+      double skip2[4][4];
+      d4 dh2a[4];
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot) {
+        dh2a[ot] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.0;
+      }
+#pragma unroll 1
+      for (int oo = 0; oo < 2; ++oo) {
+        const double* F3o = opaque(F3 + oo * 4 * 16 * 64);
+        const double* B3o = opaque(B3 + oo * 4 * 4 * 64);
+#pragma unroll
+        for (int o4 = 0; o4 < 4; ++o4) {
+          d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z = mfma_f64(F3o[((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+          double dz3[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int p = 16 * (4 * oo + o4) + 4 * v + g;
+            const double t3 = tanh_d(z[v] + vec[128 + p]);
+            const d4 gt = gts[wv][p];
+            const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+            dz3[v] = dG * (1.0 - t3 * t3);
+            skip2[o4][v] += dG;
+            T[r16][65 + p] = dz3[v];
+          }
+#pragma unroll
+          for (int i2 = 0; i2 < 4; ++i2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dh2a[i2] = mfma_f64(B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
+        }
+      }
+      wave_lds_sync();
+      // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]
+      {
+        const double one = 1.0;
+#pragma unroll 1
+        for (int qt = 0; qt < 8; ++qt) {
+          d4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+          d4 bacc = {0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int rr = 4 * ks + g;
+            const double bq = T[rr][65 + 16 * qt + r16];
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
+            bacc = mfma_f64(one, bq, bacc);
+          }
+#pragma unroll
+          for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) atomicAdd(&aW3[(16 * pt + 4 * v + g) * 128 + 16 * qt + r16], acc[pt][v]);
+          if (g == 0) atomicAdd(&aB3[16 * qt + r16], bacc[0]);
+        }
+      }
+      // dz2 = (dh2 + skip)(1 - t2^2); dh1 = W2 dz2 + skip; dz1 = dh1 (1 - t1^2)
+      double dz2[4][4], skip1[2][4];
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) skip1[i2][v] = 0.0;
+#pragma unroll
+      for (int i2 = 0; i2 < 4; ++i2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double dh2 = dh2a[i2][v] + skip2[i2][v];
+          dz2[i2][v] = dh2 * (1.0 - t2[i2][v] * t2[i2][v]);
+          skip1[i2 & 1][v] += dh2;
+        }
+      double dz1[2][4];
+#pragma unroll
+      for (int i2 = 0; i2 < 2; ++i2) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dz1[i2][v] = (z[v] + skip1[i2][v]) * (1.0 - t1[i2][v] * t1[i2][v]);
+      }
+      wave_lds_sync();
+      // buffer: h1 [0,32), dz2 [32,96), dz1 [96,128), s at 128
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          T[r16][16 * mt + 4 * v + g] = t1[mt][v];
+          T[r16][96 + 16 * mt + 4 * v + g] = dz1[mt][v];
+        }
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[r16][32 + 16 * ot + 4 * v + g] = dz2[ot][v];
+      if (g == 0) T[r16][128] = row < nn ? s : 0.0;
+      wave_lds_sync();
+      {
+        const double one = 1.0;
+#pragma unroll 1
+        for (int qt = 0; qt < 4; ++qt) {
+          d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+          d4 bacc = {0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int rr = 4 * ks + g;
+            const double bq = T[rr][32 + 16 * qt + r16];
+#pragma unroll
+            for (int pt = 0; pt < 2; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
+            bacc = mfma_f64(one, bq, bacc);
+          }
+#pragma unroll
+          for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) atomicAdd(&aW2[(16 * pt + 4 * v + g) * 64 + 16 * qt + r16], acc[pt][v]);
+          if (g == 0) atomicAdd(&aB2[16 * qt + r16], bacc[0]);
+        }
+        // dW1[q] = sum_row s dz1[q], db1[q] = sum_row dz1[q]
+#pragma unroll
+        for (int qt = 0; qt < 2; ++qt) {
+          d4 wacc = {0, 0, 0, 0}, bacc = {0, 0, 0, 0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int rr = 4 * ks + g;
+            const double bq = T[rr][96 + 16 * qt + r16];
+            wacc = mfma_f64(T[rr][128], bq, wacc);
+            bacc = mfma_f64(one, bq, bacc);
+          }
+          if (g == 0) {
+            atomicAdd(&aW1[16 * qt + r16], wacc[0]);
+            atomicAdd(&aB1[16 * qt + r16], bacc[0]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // slot-indexed block sums -> global gradient (feature-indexed)
+  double* gW3 = A.grad + A.offW[net][2];
+  double* gW2 = A.grad + A.offW[net][1];
+  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) {
+    const int fi = e_feat2<W>(k >> 7), fo = e_feat3<W>(k & 127);
+    if (fi >= 0 && fo >= 0) atomicAdd(&gW3[fi * 4 * W + fo], aW3[k]);
+  }
+  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) {
+    const int fi = e_feat1<W>(k >> 6), fo = e_feat2<W>(k & 63);
+    if (fi >= 0 && fo >= 0) atomicAdd(&gW2[fi * 2 * W + fo], aW2[k]);
+  }
+  for (int k = threadIdx.x; k < 128; k += 64 * kGWPB) {
+    const int f3 = e_feat3<W>(k);
+    if (f3 >= 0) atomicAdd(&A.grad[A.offB[net][2] + f3], aB3[k]);
+    if (k < 64) {
+      const int f2 = e_feat2<W>(k);
+      if (f2 >= 0) atomicAdd(&A.grad[A.offB[net][1] + f2], aB2[k]);
+    }
+    if (k < 32 && k < W) {
+      atomicAdd(&A.grad[A.offB[net][0] + k], aB1[k]);
+      atomicAdd(&A.grad[A.offW[net][0] + k], aW1[k]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ launcher
+void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t s) {
+  const dp_model* m = c->model;
+  const int n = (int)c->natoms_last;
+  const int nt = m->desc.ntypes;
+  const int ncols = (int)(c->natoms_last + nt * kColPad);
+  launch_fill_f64(grad, 0.0, m->n_params, s);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_col_weights, dim3((ncols + 255) / 256), dim3(256), 0, s, c->atom_at, c->frame_of, dLdE,
+                     c->gE_col, ncols);
+  // ---- fitting: per layer dW = X^T diag(w) dz, db = sum w dz; w_out, b_out, e_bias
+  const int fw = m->fw, nd = m->nd;
+  int chunk = n / 16 + 1;
+  chunk = chunk < 512 ? 512 : chunk;
+  const int nchunks = (n + chunk - 1) / chunk;
+  const double* X[3] = {(const double*)c->D, (const double*)c->fa[0], (const double*)c->fa[2]};
+  const int ldX[3] = {nd, fw, fw};
+  const int Kin[3] = {nd, fw, fw};
+  const double* DZ[3] = {(const double*)c->fa[8], (const double*)c->fa[7], (const double*)c->fa[5]};
+  for (int l = 0; l < 3; ++l) {
+    WGradArgs a = {};
+    a.X = X[l];
+    a.ldx = ldX[l];
+    a.Y = DZ[l];
+    a.ldy = fw;
+    a.w = c->gE_col;
+    a.meta = c->type_meta;
+    a.M = Kin[l];
+    a.N = fw;
+    a.chunk = chunk;
+    a.out = grad;
+    a.out_type_stride = m->fit_param_stride;
+    a.out_off = m->fit_param_off[l];
+    dim3 grid(nchunks, (Kin[l] / 16 + 3) / 4, nt);
+    hipLaunchKernelGGL((k_wgrad_cols<16>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, DZ[l], fw, c->gE_col, c->type_meta, fw,
+                       chunk, grad, m->fit_param_stride, m->fit_param_off[3 + l]);
+  }
+  // w_out: sum w h3; b_out and e_bias: sum w
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)c->fa[4], fw, c->gE_col,
+                     c->type_meta, fw, chunk, grad, m->fit_param_stride, m->fit_param_off[6]);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
+                     c->type_meta, 1, chunk, grad, m->fit_param_stride, m->fit_param_off[7]);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
+                     c->type_meta, 1, chunk, grad, 1, m->ebias_off);
+  // ---- embedding nets
+  EGradArgs A = {};
+  A.atom_at = c->atom_at;
+  A.meta = c->type_meta;
+  A.R = c->R;
+  A.nnei = c->nnei;
+  A.frag64 = m->emb_frag64;
+  A.vec64 = m->emb_vec64;
+  A.vec_per_net = m->emb_vec_per_net;
+  A.fo = m->efo;
+  A.gT = (const double*)c->gT;
+  A.wcol = c->gE_col;
+  A.grad = grad;
+  for (int k = 0; k < nt * nt; ++k)
+    for (int l = 0; l < 3; ++l) {
+      A.offW[k][l] = m->emb_param_off[k][2 * l];
+      A.offB[k][l] = m->emb_param_off[k][2 * l + 1];
+    }
+  A.ntypes = nt;
+  A.nm = m->nm;
+  int items = (int)((int64_t)n * nt / (1024LL * kGWPB));
+  items = items < 1 ? 1 : (items > 32 ? 32 : items);
+  A.items = items;
+  for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= nt ? m->sec[t] : m->nm;
+  A.inv_nm = 1.0 / (double)m->nm;
+  const int per_block = kGWPB * items;
+  dim3 grid((n + per_block - 1) / per_block, nt * nt);
+  if (m->w1 == 25) hipLaunchKernelGGL(k_embed_grad_f64<25>, grid, dim3(64 * kGWPB), 0, s, A);
+  else hipLaunchKernelGGL(k_embed_grad_f64<32>, grid, dim3(64 * kGWPB), 0, s, A);
+}
+
+}  // namespace dpse

@@ -289,3 +289,55 @@ class Context:
 
 def frame_offsets(sizes: Sequence[int]) -> np.ndarray:
     return np.concatenate([[0], np.cumsum(np.asarray(sizes, dtype=np.int64))]).astype(np.int64)
+
+
+def _autograd():
+    import torch
+
+    class DPEnergy(torch.autograd.Function):
+        """Frame energies E_f of a batch as a differentiable function of the
+        flat parameter vector and the coordinates.
+
+        forward(params, coords, types, boxes, frame_off, ctx, nlist) -> E [B]
+        backward(gE) -> (dL/dparams via dp_backward_params, dL/dcoords = -F gE_f)
+
+        The model of ``ctx`` is updated from ``params`` when they changed since
+        the last call.  Backward must run before another compute on ``ctx``.
+        """
+
+        @staticmethod
+        def forward(fctx, params, coords, types, boxes, frame_off, dctx, nlist):
+            model = dctx.model
+            p = params.detach()
+            key = (p.data_ptr(), p._version)
+            if getattr(model, "_param_key", None) != key:
+                model.set_params(p.cpu().numpy())
+                model._param_key = key
+            r = dctx.compute_batch(coords.detach(), types, boxes, frame_off, nlist, mode="fp64")
+            fctx.dctx = dctx
+            fctx.frame_off = np.asarray(frame_off, dtype=np.int64)
+            fctx.save_for_backward(r["F"])
+            return r["E"]
+
+        @staticmethod
+        def backward(fctx, gE):
+            (F,) = fctx.saved_tensors
+            gE = gE.contiguous().to(torch.float64)
+            gparams = fctx.dctx.backward_params(gE)
+            sizes = torch.as_tensor(np.diff(fctx.frame_off), device=gE.device)
+            gatom = torch.repeat_interleave(gE, sizes)
+            gcoords = -F * gatom[:, None]
+            return gparams, gcoords, None, None, None, None, None
+
+    return DPEnergy
+
+
+_DPEnergy = None
+
+
+def dp_energy(params, coords, types, boxes, frame_off, ctx: Context, nlist):
+    """Differentiable batch energies (see DPEnergy)."""
+    global _DPEnergy
+    if _DPEnergy is None:
+        _DPEnergy = _autograd()
+    return _DPEnergy.apply(params, coords, types, boxes, frame_off, ctx, nlist)
