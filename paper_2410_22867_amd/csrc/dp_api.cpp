@@ -484,6 +484,12 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   c->last_stream = s;
   const int32_t ntot = (int32_t)n;
   { StageScope p(c, DP_STAGE_TYPESORT, s); launch_type_sort(c, types, ntot, nframes, s); }
+  if (nlist != c->rev_list || n != c->natoms_rev) {
+    // list not built by this context: derive its reverse index now (slots
+    // whose reverse is not found fall back to atomics in the force pass)
+    StageScope p(c, DP_STAGE_NLIST, s);
+    launch_nl_reverse(c, x, types, nlist, ntot, s);
+  }
   { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, s); }
   { StageScope p(c, DP_STAGE_EMBED_FWD, s); launch_embed_fwd(c, types, mode, s); }
   { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
@@ -517,6 +523,10 @@ int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* b
   launch_nl_scan(c, (int32_t)ncells, s);
   launch_nl_scatter(c, ntot, s);
   launch_nl_search(c, x, types, ntot, nframes, nlist, overflow, s);
+  launch_type_sort(c, types, ntot, nframes, s);  // frame_of for the reverse index
+  launch_nl_reverse(c, x, types, nlist, ntot, s);
+  c->rev_list = nlist;
+  c->natoms_rev = n;
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }
@@ -678,6 +688,8 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->R, N * nm * 4);
   ALLOC(c->nnei, N * kMaxT);
   ALLOC(c->netd, N * nm * 4);
+  ALLOC(c->g3, N * nm * 4);
+  ALLOC(c->rev, N * nm);
   ALLOC(c->vatom, N * 9);
   ALLOC(c->ke_part, N / 256 + 2);
   ALLOC(c->Ei_col, C);
@@ -717,7 +729,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
-                  c->netd, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
+                  c->netd, c->g3, c->rev, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)

@@ -131,6 +131,10 @@ struct dp_ctx {
   double* Ei_col;          // [cols]
   double* Ei_atom;         // [N]
   double* netd;            // [N, nm, 4] f64
+  double* g3;              // [N, nm, 4] f64 pair force terms
+  int32_t* rev;            // [N, nm] reverse-entry index of the list in use
+  const int32_t* rev_list; // neighbour list rev was built for (by dp_build_nlist on this ctx)
+  int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]
   double* ke_part;         // [N/256 + 1] per-block kinetic energies
   // parameter-gradient scratch
@@ -157,6 +161,8 @@ void launch_nl_scan(dp_ctx* c, int32_t ncells, hipStream_t s);
 void launch_nl_scatter(dp_ctx* c, int32_t ntot, hipStream_t s);
 void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
                       int32_t* nlist, int32_t* overflow, hipStream_t s);
+void launch_nl_reverse(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
+                       hipStream_t s);
 // small utilities
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);

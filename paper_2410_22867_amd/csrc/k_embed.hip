@@ -87,7 +87,7 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
 
 // ============================================================== FP64 forward
 template <int W, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_fwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
@@ -100,19 +100,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
     for (int k = threadIdx.x; k < NF3; k += 64 * WPB) fr[NF2 + k] = src[A.fo.F3n + k];
   }
   __syncthreads();
-  const double* vec = A.vec64 + net * A.vec_per_net;
-  double w1s[2][4], b1s[2][4], b2s[4][4];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
-      b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
-    }
-#pragma unroll
-  for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * v + g];
+  const double* vecg = A.vec64 + net * A.vec_per_net;
 
   for (int it = 0; it < A.items; ++it) {
     const int c = chunk0 + it * WPB + wv;
@@ -128,13 +116,15 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
+      const double* vec = opaque(vecg);  // per-tile L1 reads instead of hoisted registers
       const int row = r0 + r16;
       const double s = row < nn ? Rs[row * 4] : 0.0;
       double h1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
+        for (int v = 0; v < 4; ++v)
+          h1[mt][v] = tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
       double h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -144,7 +134,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + b2s[ot][v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
       wave_lds_sync();
 #pragma unroll
@@ -167,7 +157,8 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(h2[mt][v], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
+          for (int v = 0; v < 4; ++v)
+            z = mfma_f64(h2s[wv][r16][z0 + 16 * mt + 4 * v + g], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
         const int feat = 16 * o + r16;
         if (feat < M1) {
           const double b3 = vec[kV_B3F + feat];
@@ -203,7 +194,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_f64(EmbArgs A) {
 
 // ============================================================== FP64 backward
 template <int W, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_bwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   __shared__ double fr[8192 + 8192];   // F3t | B3
   __shared__ d4 gts[WPB][kP3];
@@ -214,15 +205,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
-  const double* vec = A.vec64 + net * A.vec_per_net;
-  double w1s[2][4], b1s[2][4];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      w1s[mt][v] = vec[kV_W1 + 16 * mt + 4 * v + g];
-      b1s[mt][v] = vec[kV_B1 + 16 * mt + 4 * v + g];
-    }
+  const double* vecg = A.vec64 + net * A.vec_per_net;
   for (int it = 0; it < A.items; ++it) {
     const int c = chunk0 + it * WPB + wv;
     if (c >= n_t) break;
@@ -246,6 +229,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
       const int z0 = opaque_zero();
       const double* F2 = opaque(gsrc + A.fo.F2);
       const double* B2 = opaque(gsrc + A.fo.B2);
+      const double* vec = opaque(vecg);
       const int row = r0 + r16;
       const bool valid = row < nn;
       d4 Rrow = {0.0, 0.0, 0.0, 0.0};
@@ -255,8 +239,9 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) t1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
-      double t2[4][4], h2[4][4];
+        for (int v = 0; v < 4; ++v)
+          t1[mt][v] = tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
+      double h2[4][4];  // t2 = h2 - t1 is re-derived where needed
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
         d4 z = {0.0, 0.0, 0.0, 0.0};
@@ -265,10 +250,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          t2[ot][v] = tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
-          h2[ot][v] = t1[ot & 1][v] + t2[ot][v];
-        }
+        for (int v = 0; v < 4; ++v) h2[ot][v] = t1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
       // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
@@ -322,7 +304,8 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double dh2 = dh2a[i2][v] + skip2[i2][v];
-          dz2[i2][v] = dh2 * (1.0 - t2[i2][v] * t2[i2][v]);
+          const double t2 = h2[i2][v] - t1[i2 & 1][v];
+          dz2[i2][v] = dh2 * (1.0 - t2 * t2);
           skip1[i2 & 1][v] += dh2;
         }
       double dsp = 0.0;
@@ -336,7 +319,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_f64(EmbArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double dh1 = z[v] + skip1[i2][v];
-          dsp = fma(w1s[i2][v], dh1 * (1.0 - t1[i2][v] * t1[i2][v]), dsp);
+          dsp = fma(vec[kV_W1 + 16 * i2 + 4 * v + g], dh1 * (1.0 - t1[i2][v] * t1[i2][v]), dsp);
         }
       }
       dsp += shfl_xor_d(dsp, 16);
@@ -637,7 +620,9 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
 }
 
 // ============================================================== launchers
-constexpr int kEmbWPB = 4;
+// FP64 kernels run 2 waves per SIMD: 8-wave work-groups share one LDS copy
+// of the net's fragments.  The mixed kernels fit 3 work-groups of 4 waves.
+constexpr int kWPB64 = 8, kWPBlp = 4;
 
 static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
   const dp_model* m = c->model;
@@ -665,47 +650,46 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
 }
 
 // Columns per wave: about 1024 work-groups over all nets (4 per CU).
-static int emb_items(dp_ctx* c) {
+static int emb_items(dp_ctx* c, int wpb) {
   const int64_t n = c->natoms_last;
-  const int nets = c->model->desc.ntypes * c->model->desc.ntypes;
-  int64_t items = (n * c->model->desc.ntypes) / (1024LL * kEmbWPB);
-  (void)nets;
+  int64_t items = (n * c->model->desc.ntypes) / (1024LL * wpb);
   if (items < 1) items = 1;
   if (items > 16) items = 16;
   return (int)items;
 }
 
-#define DPSE_EMB_DISPATCH(KF64, KLP, W)                                                                       \
-  if (mode == DP_FP64) hipLaunchKernelGGL((KF64<W, kEmbWPB>), grid, block, 0, s, A);                         \
-  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((KLP<PrecBF16, W, kEmbWPB>), grid, block, 0, s, A);       \
-  else hipLaunchKernelGGL((KLP<PrecF16, W, kEmbWPB>), grid, block, 0, s, A);
+template <int W>
+static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
+  const int wpb = mode == DP_FP64 ? kWPB64 : kWPBlp;
+  const int items = emb_items(c, wpb);
+  EmbArgs A = emb_args(c, mode, items);
+  const int per_block = wpb * items;
+  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes));
+  dim3 block(64 * wpb);
+  if (mode == DP_FP64) {
+    if (bwd) hipLaunchKernelGGL((k_embed_bwd_f64<W, kWPB64>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64>), grid, block, 0, s, A);
+  } else if (mode == DP_MIX_BF16) {
+    if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_embed_fwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);
+  } else {
+    if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<PrecF16, W, kWPBlp>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_embed_fwd_lp<PrecF16, W, kWPBlp>), grid, block, 0, s, A);
+  }
+}
 
 void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
   (void)types;
   if (c->natoms_last <= 0) return;
-  const int items = emb_items(c);
-  EmbArgs A = emb_args(c, mode, items);
-  const int per_block = kEmbWPB * items;
-  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes)), block(64 * kEmbWPB);
-  if (c->model->w1 == 25) {
-    DPSE_EMB_DISPATCH(k_embed_fwd_f64, k_embed_fwd_lp, 25)
-  } else {
-    DPSE_EMB_DISPATCH(k_embed_fwd_f64, k_embed_fwd_lp, 32)
-  }
+  if (c->model->w1 == 25) launch_embed<25>(c, mode, false, s);
+  else launch_embed<32>(c, mode, false, s);
 }
 
 void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s) {
   (void)types;
   if (c->natoms_last <= 0) return;
-  const int items = emb_items(c);
-  EmbArgs A = emb_args(c, mode, items);
-  const int per_block = kEmbWPB * items;
-  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes)), block(64 * kEmbWPB);
-  if (c->model->w1 == 25) {
-    DPSE_EMB_DISPATCH(k_embed_bwd_f64, k_embed_bwd_lp, 25)
-  } else {
-    DPSE_EMB_DISPATCH(k_embed_bwd_f64, k_embed_bwd_lp, 32)
-  }
+  if (c->model->w1 == 25) launch_embed<25>(c, mode, true, s);
+  else launch_embed<32>(c, mode, true, s);
 }
 
 }  // namespace dpse

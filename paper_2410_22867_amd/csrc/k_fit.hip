@@ -223,25 +223,29 @@ __global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ 
   const bool real = atom_at[col] >= 0;
   const int a = threadIdx.x;
   if (a < m1) {
+    TT v[4] = {(TT)0, (TT)0, (TT)0, (TT)0};
+    if (real)
+      for (int t = 0; t < ntypes; ++t) {
+        const TT* p = Tpart + t * tstride + ((int64_t)col * m1 + a) * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += p[k];
+      }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      TT v = (TT)0;
-      if (real)
-        for (int t = 0; t < ntypes; ++t) v += Tpart[t * tstride + ((int64_t)col * m1 + a) * 4 + k];
-      Ts[a][k] = v;
-      if (real) T[((int64_t)col * m1 + a) * 4 + k] = v;
+      Ts[a][k] = v[k];
+      if (real) T[((int64_t)col * m1 + a) * 4 + k] = v[k];
     }
   }
   __syncthreads();
-  if (a >= m1) return;
-  DT* out = D + ((int64_t)col * m1 + a) * 16;
-#pragma unroll
-  for (int b = 0; b < 16; ++b) {
-    TT acc = Ts[a][0] * Ts[b][0] + Ts[a][1] * Ts[b][1] + Ts[a][2] * Ts[b][2] + Ts[a][3] * Ts[b][3];
+  // consecutive threads write consecutive entries e = a*16 + b
+  DT* out = D + (int64_t)col * m1 * 16;
+  for (int e = threadIdx.x; e < m1 * 16; e += 128) {
+    const int aa = e >> 4, b = e & 15;
+    const TT acc = Ts[aa][0] * Ts[b][0] + Ts[aa][1] * Ts[b][1] + Ts[aa][2] * Ts[b][2] + Ts[aa][3] * Ts[b][3];
     if constexpr (sizeof(DT) == 2) {
-      out[b] = mode_lp_f16 ? PrecF16::bits((float)acc) : PrecBF16::bits((float)acc);
+      out[e] = mode_lp_f16 ? PrecF16::bits((float)acc) : PrecBF16::bits((float)acc);
     } else {
-      out[b] = (DT)acc;
+      out[e] = (DT)acc;
     }
   }
 }

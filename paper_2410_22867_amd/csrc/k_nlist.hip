@@ -127,56 +127,78 @@ __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
                      cell_coord(zi, F.L[2], F.ncell[2])};
   int ncand = 0;
   bool capacity = false;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cc[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
-        int s[3];
+  // Lane c < 27 describes stencil cell c (dx, dy, dz in {-1,0,1}): first
+  // atom, atom count and image code; a wave prefix sum over the counts turns
+  // the 27 cell loops into one flat loop over all candidates.
+  int c_start = 0, c_cnt = 0, c_code = 13;
+  if (lane < 27) {
+    const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+    int cc[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+    int sh[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          s[a] = 0;
-          if (cc[a] < 0) { cc[a] += F.ncell[a]; s[a] = -1; }
-          else if (cc[a] >= F.ncell[a]) { cc[a] -= F.ncell[a]; s[a] = 1; }
-        }
-        const int cid = F.cell_off + cc[0] + F.ncell[0] * (cc[1] + F.ncell[1] * cc[2]);
-        const int b = A.cell_start[cid], e = A.cell_start[cid + 1];
-        const double shx = (double)s[0] * F.L[0], shy = (double)s[1] * F.L[1], shz = (double)s[2] * F.L[2];
-        const int scode = (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1);
-        const bool self_img = (s[0] == 0 && s[1] == 0 && s[2] == 0);
-        for (int q0 = b; q0 < e; q0 += 64) {
-          const int q = q0 + lane;
-          bool keep = false;
-          double r2 = 0.0;
-          int j = -1;
-          if (q < e) {
-            j = A.cell_atoms[q];
-            if (!(self_img && j == i)) {
-              const double ddx = (A.x[3 * j] - xi) + shx;
-              const double ddy = (A.x[3 * j + 1] - yi) + shy;
-              const double ddz = (A.x[3 * j + 2] - zi) + shz;
-              r2 = r2_nofma(ddx, ddy, ddz);
-              keep = r2 < A.rc2;
-            }
-          }
-          const uint64_t mask = __ballot(keep);
-          const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-          const int slot = ncand + before;
-          if (keep) {
-            if (slot < kCandCap) {
-              cr2[w][slot] = r2;
-              cpk[w][slot] = 27 * j + scode;
-              int tj = A.types[j];
-              if (tj < 0 || tj >= A.ntypes) {
-                set_flag(A.flags, DP_FLAG_BAD_INPUT);
-                tj = tj < 0 ? 0 : A.ntypes - 1;
-              }
-              ctp[w][slot] = (int8_t)tj;
-            }
-          }
-          ncand += __popcll(mask);
-        }
+    for (int a = 0; a < 3; ++a) {
+      sh[a] = 0;
+      if (cc[a] < 0) { cc[a] += F.ncell[a]; sh[a] = -1; }
+      else if (cc[a] >= F.ncell[a]) { cc[a] -= F.ncell[a]; sh[a] = 1; }
+    }
+    const int cid = F.cell_off + cc[0] + F.ncell[0] * (cc[1] + F.ncell[1] * cc[2]);
+    c_start = A.cell_start[cid];
+    c_cnt = A.cell_start[cid + 1] - c_start;
+    c_code = (sh[0] + 1) + 3 * (sh[1] + 1) + 9 * (sh[2] + 1);
+  }
+  int c_end = c_cnt;  // inclusive prefix sum
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    const int y = __shfl_up(c_end, off, 64);
+    if (lane >= off) c_end += y;
+  }
+  const int total = __shfl(c_end, 26, 64);
+  for (int t0 = 0; t0 < total; t0 += 64) {
+    const int t = t0 + lane;
+    // cell holding flat index t (all lanes run the lookup and the shuffles)
+    const int tt = t < total ? t : total - 1;
+    int c = 0;
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1) {
+      const int probe = c + step - 1;
+      const int e = __shfl(c_end, probe < 27 ? probe : 26, 64);
+      if (probe < 27 && e <= tt) c += step;
+    }
+    const int cstart = __shfl(c_start, c, 64);
+    const int cbeg = __shfl(c_end - c_cnt, c, 64);
+    const int scode = __shfl(c_code, c, 64);
+    bool keep = false;
+    double r2 = 0.0;
+    int j = -1;
+    if (t < total) {
+      j = A.cell_atoms[cstart + (t - cbeg)];
+      if (!(scode == 13 && j == i)) {
+        const double shx = (double)(scode % 3 - 1) * F.L[0];
+        const double shy = (double)((scode / 3) % 3 - 1) * F.L[1];
+        const double shz = (double)(scode / 9 - 1) * F.L[2];
+        const double ddx = (A.x[3 * j] - xi) + shx;
+        const double ddy = (A.x[3 * j + 1] - yi) + shy;
+        const double ddz = (A.x[3 * j + 2] - zi) + shz;
+        r2 = r2_nofma(ddx, ddy, ddz);
+        keep = r2 < A.rc2;
       }
+    }
+    const uint64_t mask = __ballot(keep);
+    const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+    const int slot = ncand + before;
+    if (keep && slot < kCandCap) {
+      cr2[w][slot] = r2;
+      cpk[w][slot] = 27 * j + scode;
+      int tj = A.types[j];
+      if (tj < 0 || tj >= A.ntypes) {
+        set_flag(A.flags, DP_FLAG_BAD_INPUT);
+        tj = tj < 0 ? 0 : A.ntypes - 1;
+      }
+      ctp[w][slot] = (int8_t)tj;
+    }
+    ncand += __popcll(mask);
+  }
   if (ncand > kCandCap) {
     capacity = true;
     ncand = kCandCap;
@@ -215,6 +237,84 @@ __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
     }
     if (capacity) set_flag(A.flags, DP_FLAG_CAND_CAPACITY);
   }
+}
+
+// Reverse index of a symmetric list: for entry q' of atom i pointing to
+// (j, s), the slot q of j's list holding (i, -s), stored as j*nm + q
+// (-1 when j's section was truncated before i).  The key (r^2, packed) of
+// the reverse entry is bit-identical (fl(a - b) = -fl(b - a) and the shift
+// changes sign exactly), so a binary search over j's sorted section finds
+// it; a pair missing from j's list is never matched to a wrong slot.
+struct RevArgs {
+  const double* x;
+  const int32_t* types;
+  const int32_t* nlist;
+  const int32_t* frame_of;
+  const FrameInfo* fr;
+  int32_t* rev;
+  int ntot, nm, ntypes;
+  int sel[kMaxT];
+  int sec[kMaxT + 1];
+};
+
+__device__ __forceinline__ double pair_r2(const double* x, int a, int e, const double* L) {
+  const int b = e / 27, sc = e - 27 * (e / 27);
+  const double dx = (x[3 * b] - x[3 * a]) + (double)(sc % 3 - 1) * L[0];
+  const double dy = (x[3 * b + 1] - x[3 * a + 1]) + (double)((sc / 3) % 3 - 1) * L[1];
+  const double dz = (x[3 * b + 2] - x[3 * a + 2]) + (double)(sc / 9 - 1) * L[2];
+  return r2_nofma(dx, dy, dz);
+}
+
+__global__ __launch_bounds__(256) void k_nl_reverse(RevArgs A) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= A.ntot) return;
+  int ti = A.types[i];
+  ti = ti < 0 ? 0 : (ti >= A.ntypes ? A.ntypes - 1 : ti);
+  const double* L = A.fr[A.frame_of[i]].L;
+  for (int q = lane; q < A.nm; q += 64) {
+    const int e = A.nlist[(int64_t)i * A.nm + q];
+    int out = -1;
+    if (e >= 0 && e / 27 < A.ntot) {
+      const int j = e / 27;
+      const int target = 27 * i + (26 - (e - 27 * j));
+      const double r2 = pair_r2(A.x, i, e, L);
+      const int32_t* row = A.nlist + (int64_t)j * A.nm + A.sec[ti];
+      int lo = 0, hi = A.sel[ti];  // first position with key >= (r2, target)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int em = row[mid];
+        bool less;
+        if (em < 0 || em / 27 >= A.ntot) less = false;  // padding sorts last
+        else {
+          const double rm = pair_r2(A.x, j, em, L);
+          less = rm < r2 || (rm == r2 && em < target);
+        }
+        if (less) lo = mid + 1; else hi = mid;
+      }
+      if (lo < A.sel[ti] && row[lo] == target) out = j * A.nm + A.sec[ti] + lo;
+    }
+    A.rev[(int64_t)i * A.nm + q] = out;
+  }
+}
+
+void launch_nl_reverse(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
+                       hipStream_t s) {
+  if (ntot <= 0) return;
+  const dp_model* m = c->model;
+  RevArgs A;
+  A.x = x;
+  A.types = types;
+  A.nlist = nlist;
+  A.frame_of = c->frame_of;
+  A.fr = c->frames_dev;
+  A.rev = c->rev;
+  A.ntot = ntot;
+  A.nm = m->nm;
+  A.ntypes = m->desc.ntypes;
+  for (int t = 0; t < kMaxT; ++t) A.sel[t] = t < m->desc.ntypes ? m->desc.sel[t] : 0;
+  for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= m->desc.ntypes ? m->sec[t] : m->nm;
+  hipLaunchKernelGGL(k_nl_reverse, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
 }
 
 void launch_nl_bin(dp_ctx* c, const double* x, int32_t ntot, int32_t nframes, hipStream_t s) {
