@@ -391,7 +391,7 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
     c->frames_ev_pending = false;
   }
   const double rc = c->model->desc.rcut;
-  int64_t cells = 0;
+  int64_t cells = 0, chunks = 0;
   for (int f = 0; f < nframes; ++f) {
     double L[3];
     int rcb = check_box(boxes + 9 * f, rc, L);
@@ -402,6 +402,8 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
     F.atom_off = (int32_t)a0;
     F.natoms = (int32_t)(a1 - a0);
     F.cell_off = (int32_t)cells;
+    F.chunk_off = (int32_t)chunks;
+    chunks += (F.natoms + kRedChunk - 1) / kRedChunk;
     int64_t nc = 1;
     for (int a = 0; a < 3; ++a) {
       int k = (int)std::floor(L[a] / (rc * (1.0 + 1e-10)));
@@ -420,6 +422,7 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
   HIPCHECK(hipEventRecord(c->frames_ev, s));
   c->frames_ev_pending = true;
   c->nframes_last = nframes;
+  c->nchunks_last = (int32_t)chunks;
   *ncells = cells;
   return DP_OK;
 }
@@ -690,6 +693,7 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->netd, N * nm * 4);
   ALLOC(c->g3, N * nm * 4);
   ALLOC(c->rev, N * nm);
+  ALLOC(c->red_part, 10 * (N / kRedChunk + (int64_t)max_frames + 1));
   ALLOC(c->vatom, N * 9);
   ALLOC(c->ke_part, N / 256 + 2);
   ALLOC(c->Ei_col, C);
@@ -729,7 +733,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)
@@ -781,6 +785,7 @@ int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipS
   }
   int rc;
   if ((rc = set_device(c->device))) return rc;
+  launch_descriptor_ex(c, DP_FP64, true, stream);  // D is only formed inside the GEMM on the force path
   launch_param_grads(c, dL_dE, grad_params, stream);
   HIPCHECK(hipGetLastError());
   return DP_OK;
@@ -843,7 +848,10 @@ int dp_ctx_copy_buffer(dp_ctx* c, int32_t which, void* dst, int64_t* nbytes, hip
   if ((rc = set_device(c->device))) return rc;
   if (which == 0) HIPCHECK(hipMemcpyAsync(dst, c->R, bytes, hipMemcpyDeviceToDevice, stream));
   else if (which == 4) HIPCHECK(hipMemcpyAsync(dst, c->netd, bytes, hipMemcpyDeviceToDevice, stream));
-  else launch_gather_cols(c, which, c->mode_last, (int32_t)n, (double*)dst, stream);
+  else {
+    if (which == 2 && c->mode_last == DP_FP64) launch_descriptor_ex(c, DP_FP64, true, stream);
+    launch_gather_cols(c, which, c->mode_last, (int32_t)n, (double*)dst, stream);
+  }
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }

@@ -12,6 +12,7 @@ constexpr int kMaxT = DP_MAX_TYPES;
 constexpr int kColPad = 128;     // fitting-GEMM column tile; type segments are padded to it
 constexpr int kCandCap = 512;    // neighbour candidates inside r_c per atom (LDS capacity)
 constexpr int kMaxNm = 1024;     // sum(sel)
+constexpr int kRedChunk = 1024;  // atoms per partial sum of the per-frame reductions
 
 // Slot layout of the embedding activations (see k_embed.hip): widths
 // (w, 2w, 4w) with w <= 32 occupy 32, 64 and 128 slots.
@@ -22,6 +23,7 @@ struct FrameInfo {
   int32_t atom_off;   // first atom
   int32_t natoms;
   int32_t cell_off;   // first cell of the frame's grid
+  int32_t chunk_off;  // first reduction chunk of the frame (chunks of kRedChunk atoms)
   int32_t ncell[3];
   double L[3];        // orthorhombic edges
 };
@@ -137,6 +139,8 @@ struct dp_ctx {
   int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]
   double* ke_part;         // [N/256 + 1] per-block kinetic energies
+  double* red_part;        // [chunks, 10] per-chunk energy + virial partial sums
+  int32_t nchunks_last;
   // parameter-gradient scratch
   double* gE_col;          // [cols]
   double* grad_tmp;        // [n_params]
@@ -172,6 +176,7 @@ void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t*
                 hipStream_t s);
 void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
 void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s);
 void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s);

@@ -348,19 +348,27 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
 }
 
 // ---------------------------------------------------------------- reductions
-// One work-group per frame: E_f = sum of E_i and W_f = sum of per-atom virial
-// rows over the frame's atoms, in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_frame_reduce(const FrameInfo* __restrict__ fr, const double* __restrict__ Ei,
-                                                      const double* __restrict__ vatom, double* __restrict__ E,
-                                                      double* __restrict__ W, int32_t* flags) {
+// Per-frame E_f = sum of E_i and W_f = sum of per-atom virial rows in two
+// fixed-order stages: one block per chunk of kRedChunk atoms of a frame,
+// then one block per frame over its chunks (deterministic).
+__global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restrict__ fr, int nframes,
+                                                      const double* __restrict__ Ei, const double* __restrict__ vatom,
+                                                      double* __restrict__ part) {
   __shared__ double red[10][256];
-  const int f = blockIdx.x;
-  const int a0 = fr[f].atom_off, n = fr[f].natoms;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nframes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fr[mid].chunk_off <= b) lo = mid; else hi = mid - 1;
+  }
+  const FrameInfo F = fr[lo];
+  const int a0 = F.atom_off + (b - F.chunk_off) * kRedChunk;
+  const int a1 = min(F.atom_off + F.natoms, a0 + kRedChunk);
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = threadIdx.x; k < n; k += 256) {
-    acc[0] += Ei[a0 + k];
+  for (int k = a0 + (int)threadIdx.x; k < a1; k += 256) {
+    acc[0] += Ei[k];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[1 + c] += vatom[(int64_t)(a0 + k) * 9 + c];
+    for (int c = 0; c < 9; ++c) acc[1 + c] += vatom[(int64_t)k * 9 + c];
   }
 #pragma unroll
   for (int c = 0; c < 10; ++c) red[c][threadIdx.x] = acc[c];
@@ -371,10 +379,22 @@ __global__ __launch_bounds__(256) void k_frame_reduce(const FrameInfo* __restric
       for (int c = 0; c < 10; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    E[f] = red[0][0];
-    if (!isfinite(red[0][0])) set_flag(flags, DP_FLAG_NONFINITE);
-    for (int c = 0; c < 9; ++c) W[9 * f + c] = red[1 + c][0];
+  if (threadIdx.x < 10) part[(int64_t)b * 10 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_frame_reduce(const FrameInfo* __restrict__ fr, const double* __restrict__ part,
+                                                     double* __restrict__ E, double* __restrict__ W, int32_t* flags) {
+  const int f = blockIdx.x;
+  const int c0 = fr[f].chunk_off, nc = (fr[f].natoms + kRedChunk - 1) / kRedChunk;
+  if (threadIdx.x < 10) {
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[(int64_t)(c0 + c) * 10 + threadIdx.x];
+    if (threadIdx.x == 0) {
+      E[f] = acc;
+      if (!isfinite(acc)) set_flag(flags, DP_FLAG_NONFINITE);
+    } else {
+      W[9 * f + threadIdx.x - 1] = acc;
+    }
   }
 }
 
@@ -385,8 +405,11 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
 
 void launch_frame_reduce(dp_ctx* c, int32_t nframes, double* energies, double* atom_energy, double* virials,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(256), 0, s, c->frames_dev, c->Ei_atom, c->vatom, energies,
-                     virials, c->flags_dev);
+  if (c->nchunks_last > 0)
+    hipLaunchKernelGGL(k_chunk_reduce, dim3(c->nchunks_last), dim3(256), 0, s, c->frames_dev, nframes, c->Ei_atom,
+                       c->vatom, c->red_part);
+  hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(64), 0, s, c->frames_dev, c->red_part, energies, virials,
+                     c->flags_dev);
   if (atom_energy && c->natoms_last > 0)
     hipLaunchKernelGGL(k_copy_f64, dim3((c->natoms_last + 255) / 256), dim3(256), 0, s, c->Ei_atom, atom_energy,
                        (int)c->natoms_last);

@@ -85,6 +85,13 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;     \
   const int r16 = lane & 15, g = lane >> 4;
 
+// FP64 k-step (t, v) covers slots 16t + 4v + {0..3}; with w = 25 the slot
+// groups 28..31 (mod 32) hold only padding, so those k-steps are skipped.
+template <int W>
+__device__ __forceinline__ constexpr bool kpad(int t, int v) {
+  return W <= 28 && (t & 1) && v == 3;
+}
+
 // ============================================================== FP64 forward
 template <int W, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_fwd_f64(EmbArgs A) {
@@ -132,7 +139,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
+          for (int v = 0; v < 4; ++v)
+            if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
@@ -158,7 +166,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            z = mfma_f64(h2s[wv][r16][z0 + 16 * mt + 4 * v + g], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
+            if (!kpad<W>(mt, v))
+              z = mfma_f64(h2s[wv][r16][z0 + 16 * mt + 4 * v + g], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
         const int feat = 16 * o + r16;
         if (feat < M1) {
           const double b3 = vec[kV_B3F + feat];
@@ -248,7 +257,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
+          for (int v = 0; v < 4; ++v)
+            if (!kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2[ot][v] = t1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+              if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
           double dz3[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -290,7 +300,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              dh2a[i2] = mfma_f64(fr[z0 + 8192 + zo * 1024 + ((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
+              if (!kpad<W>(o4, v))
+                dh2a[i2] = mfma_f64(fr[z0 + 8192 + zo * 1024 + ((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
         }
       }
       double dz2[4][4];
@@ -315,7 +326,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+          for (int v = 0; v < 4; ++v)
+            if (!kpad<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double dh1 = z[v] + skip1[i2][v];

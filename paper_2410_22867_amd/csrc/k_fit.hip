@@ -44,10 +44,12 @@ struct GemmArgs {
   int ld1;
   void* outlp;           // lp copy for the next GEMM (mixed): EPI_TANH/RES: h; EPI_BWD: dz
   int ldlp;
+  const double* T;       // FP64 layer 1: X[col][a*16 + b] = sum_k T[col][a][k] T[col][b][k] built on the fly
+  int m1;
 };
 
 // ---------------------------------------------------------------- FP64 GEMM
-template <int MT, int NT>
+template <int MT, int NT, bool XT>
 __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
@@ -71,10 +73,31 @@ __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
   int mtv[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) mtv[mt] = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
+  // descriptor from T: lane group g needs D[a = S][b = 4g + v], v = 0..3
+  d4 Tb[NT][4];
+  const double* trow[NT];
+  if constexpr (XT) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      trow[nt] = g.T + (int64_t)(cb + c0 + nt * 16 + r16) * g.m1 * 4;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tb[nt][v] = *reinterpret_cast<const d4*>(trow[nt] + (4 * gq + v) * 4);
+    }
+  }
   for (int S = 0; S < KS; ++S) {
     d4 xb[NT];
+    if constexpr (XT) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) xb[nt] = *reinterpret_cast<const d4*>(xrow[nt] + 16 * S);
+      for (int nt = 0; nt < NT; ++nt) {
+        const d4 ta = *reinterpret_cast<const d4*>(trow[nt] + S * 4);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          xb[nt][v] = ta[0] * Tb[nt][v][0] + ta[1] * Tb[nt][v][1] + ta[2] * Tb[nt][v][2] + ta[3] * Tb[nt][v][3];
+      }
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) xb[nt] = *reinterpret_cast<const d4*>(xrow[nt] + 16 * S);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
 #pragma unroll
@@ -218,6 +241,8 @@ template <typename TT, typename DT>
 __global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ atom_at, const TT* __restrict__ Tpart,
                                                     int64_t tstride, int ntypes, TT* __restrict__ T,
                                                     DT* __restrict__ D, int m1, int mode_lp_f16) {
+  // D == nullptr: only the section sum T is formed (FP64 builds D inside the
+  // fitting GEMM)
   __shared__ TT Ts[128][4];
   const int col = blockIdx.x;
   const bool real = atom_at[col] >= 0;
@@ -233,9 +258,10 @@ __global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       Ts[a][k] = v[k];
-      if (real) T[((int64_t)col * m1 + a) * 4 + k] = v[k];
+      T[((int64_t)col * m1 + a) * 4 + k] = v[k];  // zeros on padding columns
     }
   }
+  if (D == nullptr) return;
   __syncthreads();
   // consecutive threads write consecutive entries e = a*16 + b
   DT* out = D + (int64_t)col * m1 * 16;
@@ -330,7 +356,10 @@ static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
   const int mtiles = g.M / 16;
   dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + kMT - 1) / kMT), (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (mode == DP_FP64) hipLaunchKernelGGL((k_fit_gemm_f64<5, 2>), grid, dim3(256), 0, s, g);
+  if (mode == DP_FP64) {
+    if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<5, 2, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_fit_gemm_f64<5, 2, false>), grid, dim3(256), 0, s, g);
+  }
   else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, 5, 2>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, 5, 2>), grid, dim3(256), 0, s, g);
 }
@@ -345,14 +374,17 @@ static GemmArgs gemm_base(dp_ctx* c, int mode) {
   return g;
 }
 
-void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) {
+void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) { launch_descriptor_ex(c, mode, mode != DP_FP64, s); }
+
+void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s) {
   const dp_model* m = c->model;
   const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
   if (c->natoms_last <= 0) return;
   const int64_t ts = c->max_cols * m->m1 * 4;
   if (mode == DP_FP64)
     hipLaunchKernelGGL((k_descriptor<double, double>), dim3(ncols), dim3(128), 0, s, c->atom_at,
-                       (const double*)c->Tpart, ts, m->desc.ntypes, (double*)c->T, (double*)c->D, m->m1, 0);
+                       (const double*)c->Tpart, ts, m->desc.ntypes, (double*)c->T,
+                       write_d ? (double*)c->D : (double*)nullptr, m->m1, 0);
   else
     hipLaunchKernelGGL((k_descriptor<float, uint16_t>), dim3(ncols), dim3(128), 0, s, c->atom_at,
                        (const float*)c->Tpart, ts, m->desc.ntypes, (float*)c->T, (uint16_t*)c->D, m->m1,
@@ -391,6 +423,8 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.ldx = m->nd;
   g.K = m->nd;
   g.Kreal = m->nd;
+  g.T = f64 ? (const double*)c->T : nullptr;  // FP64: descriptor built inside the GEMM
+  g.m1 = m->m1;
   g.M = fw;
   g.epi = EPI_TANH;
   g.bias_off = 0;
@@ -400,6 +434,7 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.outlp = f64 ? nullptr : c->fa[5];
   g.ldlp = fwp;
   gemm_launch<int>(c, g, mode, s);
+  g.T = nullptr;
   // layers 2, 3
   for (int l = 1; l < 3; ++l) {
     g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[l]) : (const void*)((const uint16_t*)frag + off_fwd[l]);
