@@ -168,11 +168,15 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   const uint16_t* xrow[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) xrow[nt] = X + (int64_t)(cb + c0 + nt * 16 + r16) * g.ldx + 4 * gq;
-  int mtv[MT];
+  const uint16_t* arow[MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) mtv[mt] = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
-  for (int kt = 0; kt < KT; ++kt) {
-    typename P::vec8 xb[NT];
+  for (int mt = 0; mt < MT; ++mt) {
+    const int m = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
+    arow[mt] = Afr + ((int64_t)m * KT * 64 + lane) * 8;
+  }
+  // register double buffer: operands of k-step kt+1 load while kt computes
+  u16x8 xa[NT], aa[MT];
+  auto load = [&](int kt, u16x8* xv, u16x8* av) {
     // the padded upper half of the last k-step may hold stale bits: use zeros
     const bool hi_ok = 32 * kt + 16 < g.Kreal;
 #pragma unroll
@@ -180,14 +184,26 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
       const u16x4 lo = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt);
       u16x4 hi = {0, 0, 0, 0};
       if (hi_ok) hi = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt + 16);
-      u16x8 u = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      xb[nt] = __builtin_bit_cast(typename P::vec8, u);
+      xv[nt] = u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const typename P::vec8 a = load8<P>(Afr + (((int64_t)mtv[mt] * KT + kt) * 64 + lane) * 8);
+    for (int mt = 0; mt < MT; ++mt) av[mt] = *reinterpret_cast<const u16x8*>(arow[mt] + (int64_t)kt * 512);
+  };
+  load(0, xa, aa);
+  for (int kt = 0; kt < KT; ++kt) {
+    u16x8 xn[NT], an[MT];
+    if (kt + 1 < KT) load(kt + 1, xn, an);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = P::mfma(a, xb[nt], acc[mt][nt]);
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]), __builtin_bit_cast(typename P::vec8, xa[nt]),
+                              acc[mt][nt]);
+    if (kt + 1 < KT) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) xa[nt] = xn[nt];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) aa[mt] = an[mt];
     }
   }
   const float* vec = reinterpret_cast<const float*>(g.vec) + t * g.vec_type_stride;
@@ -347,21 +363,30 @@ __global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ ato
 //   FP64 : 0 t1(=h1) 1 t2 2 h2 3 t3 4 h3 5 dz3 6 dh2 7 dz2 8 dz1         [cols][fw]
 //   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
 //          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
-static int kMT = 5, kNT = 2;
-
-template <typename F>
-static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+// Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
+template <int MT, int NT>
+static void gemm_launch_cfg(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
-  const int BN = 4 * kNT * 16;
+  const int BN = 4 * NT * 16;
   const int mtiles = g.M / 16;
-  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + kMT - 1) / kMT), (unsigned)ntypes);
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + MT - 1) / MT), (unsigned)ntypes);
   if (grid.x == 0) return;
   if (mode == DP_FP64) {
-    if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<5, 2, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fit_gemm_f64<5, 2, false>), grid, dim3(256), 0, s, g);
+    if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
+  } else if (mode == DP_MIX_BF16) {
+    hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MT, NT>), grid, dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MT, NT>), grid, dim3(256), 0, s, g);
   }
-  else if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, 5, 2>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, 5, 2>), grid, dim3(256), 0, s, g);
+}
+
+// Tile shapes picked by a sweep on the 12,288-atom water model: FP64 MFMA
+// (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the 16x16x32
+// half-precision MFMA does best with more waves resident (4x1).
+static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+  if (mode == DP_FP64) gemm_launch_cfg<3, 2>(c, g, mode, s);
+  else gemm_launch_cfg<4, 1>(c, g, mode, s);
 }
 
 static GemmArgs gemm_base(dp_ctx* c, int mode) {
@@ -433,7 +458,7 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.out1 = nullptr;
   g.outlp = f64 ? nullptr : c->fa[5];
   g.ldlp = fwp;
-  gemm_launch<int>(c, g, mode, s);
+  gemm_launch(c, g, mode, s);
   g.T = nullptr;
   // layers 2, 3
   for (int l = 1; l < 3; ++l) {
@@ -458,7 +483,7 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
     g.out1 = l == 1 ? c->fa[2] : c->fa[4];
     g.ld1 = ld;
     g.outlp = f64 ? nullptr : (l == 1 ? c->fa[6] : nullptr);
-    gemm_launch<int>(c, g, mode, s);
+    gemm_launch(c, g, mode, s);
   }
   // output
   dim3 grid((ncols + 3) / 4);
@@ -509,7 +534,7 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.ld1 = ld;
   g.outlp = f64 ? nullptr : c->fa[8];
   g.ldlp = fwp;
-  gemm_launch<int>(c, g, mode, s);
+  gemm_launch(c, g, mode, s);
   // layer 2: dh1 = dh2 + W2 dz2 ; dz1 = dh1 (1 - t1^2)
   g.Afr = fr(1);
   g.X = f64 ? c->fa[7] : c->fa[8];
@@ -519,7 +544,7 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.out0 = nullptr;
   g.out1 = f64 ? c->fa[8] : nullptr;
   g.outlp = f64 ? nullptr : c->fa[9];
-  gemm_launch<int>(c, g, mode, s);
+  gemm_launch(c, g, mode, s);
   // layer 1: dD = W1 dz1
   g.Afr = fr(0);
   g.X = f64 ? c->fa[8] : c->fa[9];
@@ -528,7 +553,7 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.out0 = c->dD;
   g.ld0 = m->nd;
   g.outlp = nullptr;
-  gemm_launch<int>(c, g, mode, s);
+  gemm_launch(c, g, mode, s);
 }
 
 // ---------------------------------------------------------------- inspection
