@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--nve-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--workspace-gib", type=float, default=64.0,
+                    help="embedding-activation store budget; 0 recomputes the activations in the backward pass")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -91,7 +93,8 @@ def main():
     wl_index = {"water192": 0, "water12k": 1, "copper32k": 2, "water98k": 3}[args.workload]
     n = fr.n
     model = dpse.Model(desc, params)
-    ctx = dpse.Context(model, n)
+    ctx = dpse.Context(model, n, budget_bytes=int(args.workspace_gib * 2 ** 30))
+    activations = {}
     x0 = torch.tensor(fr.coords, device=dev)
     v0 = torch.tensor(I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=200 + wl_index), device=dev)
     t = torch.tensor(fr.types, device=dev)
@@ -115,6 +118,7 @@ def main():
         v = v0.clone()
         ctx.build_nlist(x, t, box, out=nl, overflow=ov)
         ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
+        activations[mode] = "stored" if ctx.store_info()[1] else "recomputed"
         return x, v
 
     if args.calib_copy:
@@ -251,7 +255,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "natoms": n, "dt_fs": dt,
-                   "step": "kick+drift, neighbour list, E/F/W, kick", "real_neighbour_rows": real_rows},
+                   "step": "kick+drift, neighbour list, E/F/W, kick", "real_neighbour_rows": real_rows,
+                   "embedding_activations": activations},
         "ns_per_day": round(base["ns_per_day"], 3),
         "modes": {m: {k: round(vv, 4) for k, vv in r.items()} for m, r in results.items()},
         "mixed_speedup": {m: round(results["fp64"]["ms_per_step"] / r["ms_per_step"], 3)

@@ -127,9 +127,13 @@ int dp_model_destroy(dp_model* model);
 
 /* Allocates every work buffer for up to max_atoms atoms in up to max_frames
  * frames (Computation Optimization section: all memory is allocated in the
- * initial phase).  workspace_budget_bytes caps the embedding-activation store:
- * when n * nm * m1 * 8 bytes exceed it (or it is 0), the backward pass
- * recomputes the embedding activations instead of reading stored ones. */
+ * initial phase).  workspace_budget_bytes caps the embedding-activation store
+ * (at most max_atoms * T * 16 * m1 * 8 bytes are taken, with T = sum over
+ * neighbour types of ceil(sel_t / 16) row tiles per atom): a DP_FP64 compute
+ * on n atoms keeps the last embedding layer's tanh output there when
+ * n * T * 16 * m1 * 8 bytes fit, and otherwise (or with a budget of 0) the
+ * backward pass recomputes it.  The mixed modes always recompute (their
+ * half-precision layer costs less than the store's memory traffic). */
 int dp_ctx_create(const dp_model* model, int64_t max_atoms, int32_t max_frames, int64_t workspace_budget_bytes,
                   dp_ctx** out);
 int dp_ctx_destroy(dp_ctx* ctx);
@@ -192,6 +196,13 @@ int dp_md_kick(dp_ctx* ctx, double* vel, const double* forces, const int32_t* ty
 /* Device status word accumulated since the last call (DP_FLAG_*); waits for
  * the context's last stream, then clears the word. */
 int dp_ctx_status(dp_ctx* ctx, int32_t* flags);
+
+/* Embedding-activation store of the context (the budget given to
+ * dp_ctx_create): *capacity_bytes receives its size (0 when the budget was 0),
+ * *last_used 1 when the last dp_compute / dp_compute_batch kept the last
+ * embedding layer's activations there instead of recomputing them in the
+ * backward pass, else 0.  Either pointer may be NULL.  Host-only; no wait. */
+int dp_ctx_store_info(dp_ctx* ctx, int64_t* capacity_bytes, int32_t* last_used);
 
 /* Inspection of intermediate buffers of the last compute (tests, debugging).
  * which: 0 = environment matrix [n, nm, 4] f64 (atom order);

@@ -494,6 +494,7 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
     launch_nl_reverse(c, x, types, nlist, ntot, s);
   }
   { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, s); }
+  c->act_used_last = c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
   { StageScope p(c, DP_STAGE_EMBED_FWD, s); launch_embed_fwd(c, types, mode, s); }
   { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
   { StageScope p(c, DP_STAGE_FIT_FWD, s); launch_fit_forward(c, mode, s); }
@@ -572,6 +573,11 @@ int dp_model_create(const dp_model_desc* desc, const double* params_host, int64_
     m->nm += desc->sel[t];
   }
   for (int t = desc->ntypes + 1; t <= DP_MAX_TYPES; ++t) m->sec[t] = m->nm;
+  m->tpa = 0;
+  for (int t = 0; t <= DP_MAX_TYPES; ++t) {
+    m->toff[t] = m->tpa;
+    if (t < desc->ntypes) m->tpa += (desc->sel[t] + 15) / 16;
+  }
   m->w1 = desc->emb[0];
   m->m1 = desc->emb[2];
   m->n3 = (m->m1 + 15) / 16;
@@ -710,6 +716,19 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
     ALLOC(tmp, C * fwp);
     c->fa[k] = tmp;
   }
+  {
+    // activation store: as much of the full [max_atoms, tpa, m1, 16] f64
+    // store as the budget allows; each compute uses it when its atoms fit
+    // (plus one record of slack: padding slots of the last record may be
+    // read, and discarded, past its end)
+    const int64_t full = N * m->tpa * (int64_t)m1 * 16 * 8;
+    const int64_t bytes = workspace_budget_bytes < full ? workspace_budget_bytes : full;
+    if (bytes >= (int64_t)m->tpa * m1 * 16 * 8) {
+      ALLOC(tmp, bytes / 8 + (int64_t)m1 * 16);
+      c->act = tmp;
+      c->act_bytes = bytes;
+    }
+  }
 #undef ALLOC
   // zero-initialise every buffer once: padding columns of the mixed-precision
   // activations (features fw..fwp) must hold finite zeros forever.
@@ -722,7 +741,6 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "ctx init"); }
   }
-  (void)workspace_budget_bytes;
   *out = c;
   return DP_OK;
 }
@@ -733,7 +751,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT};
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)
@@ -827,6 +845,13 @@ int dp_ctx_status(dp_ctx* c, int32_t* flags) {
   *flags = *c->flags_host;
   launch_fill_i32(c->flags_dev, 0, 1, c->last_stream);
   HIPCHECK(hipStreamSynchronize(c->last_stream));
+  return DP_OK;
+}
+
+int dp_ctx_store_info(dp_ctx* c, int64_t* capacity_bytes, int32_t* last_used) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  if (capacity_bytes) *capacity_bytes = c->act_bytes;
+  if (last_used) *last_used = c->act_used_last ? 1 : 0;
   return DP_OK;
 }
 

@@ -56,6 +56,8 @@ struct dp_model {
   int w1;          // first embedding width (25 or 32 ...)
   int m1;          // last embedding width
   int n3;          // m-tiles of m1
+  int tpa;         // 16-row neighbour tiles per atom: sum_t ceil(sel_t / 16)
+  int toff[DP_MAX_TYPES + 1];  // first tile of each neighbour section
   int nd;          // m1 * m2
   int fw;          // fitting width
   int64_t n_params;
@@ -135,6 +137,11 @@ struct dp_ctx {
   double* netd;            // [N, nm, 4] f64
   double* g3;              // [N, nm, 4] f64 pair force terms
   int32_t* rev;            // [N, nm] reverse-entry index of the list in use
+  // last embedding layer's tanh output per 16-row neighbour tile, [N, tpa,
+  // m1, 16] f64 (FP64) or f32 (mixed), when it fits the workspace budget
+  void* act;
+  int64_t act_bytes;
+  bool act_used_last;
   const int32_t* rev_list; // neighbour list rev was built for (by dp_build_nlist on this ctx)
   int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]

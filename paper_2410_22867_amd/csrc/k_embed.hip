@@ -25,6 +25,14 @@
 // wave-private LDS tile.  Backward recomputes layers 1-3 in the transposed
 // layout, forms dE/dG = g_T R / nm and the direct term g_T^T G / nm, and
 // back-propagates with the transposed-weight fragments to dE/ds.
+//
+// Activation store (ST, FP64 only): when the context's workspace budget holds
+// it, the forward also writes the last layer's tanh output t3 = G - [h2, h2]
+// of every 16-row tile as a [m1][16] record, and the backward reads it back
+// instead of recomputing layer 3 (the widest layer: 4/5 of the net's
+// products).  Layers 1 and 2 are always recomputed.  The mixed forms always
+// recompute: their half-precision layer 3 costs less than the store's HBM
+// round trip.
 #include "dp_internal.h"
 #include "dp_device.h"
 
@@ -45,6 +53,9 @@ struct EmbArgs {
   int64_t tpart_stride;  // elements between sections
   const void* gT;        // backward: [cols][m1][4]
   double* netd;
+  void* act;             // last-layer tanh store [N][tpa][m1][16] (f64 / f32), or NULL
+  int tpa;
+  int toff[kMaxT];
   int ntypes, nm, items;
   int sec[kMaxT + 1];
   double inv_nm;
@@ -93,7 +104,7 @@ __device__ __forceinline__ constexpr bool kpad(int t, int v) {
 }
 
 // ============================================================== FP64 forward
-template <int W, int WPB>
+template <int W, int WPB, bool ST>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_fwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
@@ -126,6 +137,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const double* vec = opaque(vecg);  // per-tile L1 reads instead of hoisted registers
       const int row = r0 + r16;
       const double s = row < nn ? Rs[row * 4] : 0.0;
+      double* rec =
+          ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + r16 * 16 + g
+             : nullptr;
       double h1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
@@ -174,7 +188,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           const int src = slot2_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double G = h2s[wv][4 * v + g][src] + tanh_d(z[v] + b3);
+            const double t3 = tanh_d(z[v] + b3);
+            if constexpr (ST) rec[o * 256 + 4 * v] = t3;
+            const double G = h2s[wv][4 * v + g][src] + t3;
 #pragma unroll
             for (int k = 0; k < 4; ++k) accT[o][k] = fma(G, Rr[v][k], accT[o][k]);
           }
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 }
 
 // ============================================================== FP64 backward
-template <int W, int WPB>
+template <int W, int WPB, bool ST>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_bwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   __shared__ double fr[8192 + 8192];   // F3t | B3
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   DPSE_NET_PROLOGUE(WPB)
   const double* gsrc = A.frag64 + net * A.fo.per_net;
   for (int k = threadIdx.x; k < 8192; k += 64 * WPB) {
-    fr[k] = gsrc[A.fo.F3t + k];
+    if constexpr (!ST) fr[k] = gsrc[A.fo.F3t + k];
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
@@ -244,6 +260,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       d4 Rrow = {0.0, 0.0, 0.0, 0.0};
       if (valid) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
       const double s = Rrow[0];
+      const double* rec =
+          ST ? static_cast<const double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + g * 16 + r16
+             : nullptr;
       double t1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
@@ -278,16 +297,29 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int o4 = 0; o4 < 4; ++o4) {
           d4 z = {0.0, 0.0, 0.0, 0.0};
+          if constexpr (!ST) {
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+              for (int v = 0; v < 4; ++v)
+                if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+          }
           double dz3[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int p = 16 * (4 * zo + o4) + 4 * v + g;
-            const double t3 = tanh_d(z[v] + vec[kV_B3S + p]);
+            double t3;
+            if constexpr (ST) {
+              // slot p = 64 zo + 16 o4 + 4 v + g holds feature
+              // 2W zo + W (o4 / 2) + 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g < W
+              const int lo = 16 * (o4 & 1) + 4 * v;
+              // (a padding slot may read past its record: the store has one
+              // record of slack at its end, and the value is discarded)
+              const double x = rec[(zo * 2 * W + (o4 >> 1) * W + lo) * 16];
+              t3 = lo + g < W ? x : 0.0;
+            } else {
+              t3 = tanh_d(z[v] + vec[kV_B3S + p]);
+            }
             const double G = h2[o4][v] + t3;
             const d4 gt = gts[wv][p];
             const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
@@ -653,6 +685,9 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
   A.tpart_stride = c->max_cols * m->m1 * 4;
   A.gT = c->gT;
   A.netd = c->netd;
+  A.act = c->act_used_last ? c->act : nullptr;
+  A.tpa = m->tpa;
+  for (int t = 0; t < kMaxT; ++t) A.toff[t] = m->toff[t];
   A.ntypes = m->desc.ntypes;
   A.nm = m->nm;
   A.items = items;
@@ -670,6 +705,12 @@ static int emb_items(dp_ctx* c, int wpb) {
   return (int)items;
 }
 
+template <int W, bool ST>
+static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, hipStream_t s) {
+  if (bwd) hipLaunchKernelGGL((k_embed_bwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
+}
+
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int wpb = mode == DP_FP64 ? kWPB64 : kWPBlp;
@@ -679,8 +720,8 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes));
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
-    if (bwd) hipLaunchKernelGGL((k_embed_bwd_f64<W, kWPB64>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64>), grid, block, 0, s, A);
+    if (A.act) launch_embed_f64<W, true>(bwd, grid, block, A, s);
+    else launch_embed_f64<W, false>(bwd, grid, block, A, s);
   } else if (mode == DP_MIX_BF16) {
     if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);
     else hipLaunchKernelGGL((k_embed_fwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);

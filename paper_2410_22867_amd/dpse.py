@@ -26,8 +26,8 @@ BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 # Symbols declared in include/dp.h (checked by the CPU tests).
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_destroy", "dp_ctx_create",
            "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_compute", "dp_compute_batch",
-           "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_copy_buffer",
-           "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
+           "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_store_info",
+           "dp_ctx_copy_buffer", "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
 
 STAGES = ("nlist", "typesort", "env", "embed_fwd", "descriptor", "fit_fwd", "fit_bwd", "desc_bwd", "embed_bwd",
           "force", "reduce", "md")
@@ -93,6 +93,7 @@ def lib():
             "dp_md_kick_drift": (ctypes.c_int, [P, P, P, P, P, P, i64, dbl, P, P]),
             "dp_md_kick": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_ctx_status": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
+            "dp_ctx_store_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
             "dp_ctx_copy_buffer": (ctypes.c_int, [P, i32, P, ctypes.POINTER(i64), P]),
             "dp_ctx_profile": (ctypes.c_int, [P, i32]),
             "dp_ctx_stage_times": (ctypes.c_int, [P, P, P]),
@@ -268,6 +269,12 @@ class Context:
         f = ctypes.c_int32(0)
         _check(lib().dp_ctx_status(self.handle, ctypes.byref(f)))
         return int(f.value)
+
+    def store_info(self) -> tuple:
+        """(capacity in bytes, whether the last compute used the activation store)."""
+        cap, used = ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(lib().dp_ctx_store_info(self.handle, ctypes.byref(cap), ctypes.byref(used)))
+        return int(cap.value), bool(used.value)
 
     def profile(self, enable: bool) -> None:
         _check(lib().dp_ctx_profile(self.handle, int(bool(enable))))

@@ -68,3 +68,5 @@ def test_null_arguments_rejected():
     assert L.dp_build_nlist(None, None, None, None, -1, None, None, None) == -1
     f = ctypes.c_int32(0)
     assert L.dp_ctx_status(None, ctypes.byref(f)) == -1
+    cap, used = ctypes.c_int64(0), ctypes.c_int32(0)
+    assert L.dp_ctx_store_info(None, ctypes.byref(cap), ctypes.byref(used)) == -1
