@@ -75,6 +75,11 @@ def main():
     ap.add_argument("--nve-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--nlist", default="verlet", choices=["verlet", "rebuild"],
+                    help="verlet: Verlet list rebuilt every --rebuild-every steps with --skin, formatted every "
+                         "step; rebuild: cell-list build from scratch every step")
+    ap.add_argument("--skin", type=float, default=2.0)
+    ap.add_argument("--rebuild-every", type=int, default=50)
     ap.add_argument("--workspace-gib", type=float, default=64.0,
                     help="embedding-activation store budget; 0 recomputes the activations in the backward pass")
     ap.add_argument("--calib-copy", action="store_true",
@@ -107,16 +112,37 @@ def main():
     ke = torch.empty(1, dtype=torch.float64, device=dev)
     f = torch.empty((n, 3), dtype=torch.float64, device=dev)
 
-    def step(x, v, mode):
-        ctx.kick_drift(x, v, f, t, box, dt)
-        ctx.build_nlist(x, t, box, out=nl, overflow=ov)
+    verlet = args.nlist == "verlet"
+    counter = [0]
+
+    def neighbours(x):
+        if verlet:
+            if counter[0] % args.rebuild_every == 0:
+                ctx.skin_build(x, t, box, args.skin)
+            ctx.skin_format(x, t, out=nl, overflow=ov)
+        else:
+            ctx.build_nlist(x, t, box, out=nl, overflow=ov)
+
+    rebuilds = [0]
+
+    def step(x, v, mode, exact=False):
+        """One MD step.  exact: also rebuild the Verlet list whenever an atom
+        has moved beyond half the skin (checked on the host, with a sync)."""
+        counter[0] += 1
+        ctx.kick_drift(x, v, f, t, box, dt, wrap=not verlet)
+        neighbours(x)
+        if exact and verlet and ctx.status() & dpse.FLAG_SKIN_EXCEEDED:
+            ctx.skin_build(x, t, box, args.skin)
+            ctx.skin_format(x, t, out=nl, overflow=ov)
+            rebuilds[0] += 1
         ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
         ctx.kick(v, f, t, dt, ke)
 
     def init_state(mode):
         x = x0.clone()
         v = v0.clone()
-        ctx.build_nlist(x, t, box, out=nl, overflow=ov)
+        counter[0] = 0
+        neighbours(x)
         ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
         activations[mode] = "stored" if ctx.store_info()[1] else "recomputed"
         return x, v
@@ -170,12 +196,14 @@ def main():
         ctx.profile(False)
         stages[mode] = {k: (ms / c if c else 0.0, c) for k, (ms, c) in st.items()}
     fl = ctx.status()
-    if fl & ~dpse.FLAG_SEL_OVERFLOW:
+    if fl & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED):
         raise RuntimeError(f"device status flags {fl}")
     status_flags = fl
 
-    # NVE energy drift (velocity Verlet, metal units).  The drift is measured
-    # up to the first step whose neighbour list was truncated (sel overflow),
+    # NVE energy drift (velocity Verlet, metal units).  The Verlet list is
+    # rebuilt on schedule and, in addition, whenever an atom has moved beyond
+    # half the skin, so every step sees the complete list.  The drift is
+    # measured up to the first step whose list was truncated (sel overflow),
     # after which the random-weight model's energy is no longer smooth.
     drift = {}
     for mode in args.modes.split(","):
@@ -187,8 +215,10 @@ def main():
         hist[0, 0] = E[0]
         hist[0, 1] = ke[0]
         hist[0, 2] = 0.0
+        ctx.status()
+        rebuilds[0] = 0
         for k in range(args.nve_steps):
-            step(x, v, mode)
+            step(x, v, mode, exact=True)
             hist[k + 1, 0] = E[0]
             hist[k + 1, 1] = ke[0]
             hist[k + 1, 2] = ov[0]
@@ -199,6 +229,7 @@ def main():
         tps = np.arange(len(etot)) * dt * 1e-3
         slope = float(np.polyfit(tps, (etot - etot[0]) / n * 1e3, 1)[0]) if len(etot) > 2 else 0.0
         drift[mode] = dict(steps_before_sel_overflow=clean - 1, steps=args.nve_steps,
+                           extra_verlet_rebuilds=rebuilds[0],
                            max_dev_meV_per_atom=float(np.abs(etot - etot[0]).max() / n * 1e3),
                            slope_meV_per_atom_per_ps=slope,
                            flags=ctx.status())
@@ -255,7 +286,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "natoms": n, "dt_fs": dt,
-                   "step": "kick+drift, neighbour list, E/F/W, kick", "real_neighbour_rows": real_rows,
+                   "step": ("kick+drift, Verlet list (format every step, rebuild every "
+                            f"{args.rebuild_every} steps, skin {args.skin} A), E/F/W, kick" if verlet else
+                            "kick+drift, cell-list neighbour build, E/F/W, kick"),
+                   "real_neighbour_rows": real_rows,
                    "embedding_activations": activations},
         "ns_per_day": round(base["ns_per_day"], 3),
         "modes": {m: {k: round(vv, 4) for k, vv in r.items()} for m, r in results.items()},

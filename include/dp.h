@@ -71,6 +71,7 @@ extern "C" {
 #define DP_FLAG_CAND_CAPACITY 8 /* more than the per-atom candidate capacity inside r_c */
 #define DP_FLAG_SEL_OVERFLOW 16 /* some section had more neighbours than sel (truncated) */
 #define DP_FLAG_BAD_INPUT 32    /* a type outside [0, ntypes) or a neighbour index >= n (ignored) */
+#define DP_FLAG_SKIN_EXCEEDED 64 /* an atom moved more than skin/2 since the Verlet build (list may miss pairs) */
 
 /* Precision modes (Computation Optimization section, mixed precision) */
 #define DP_FP64 0     /* everything in FP64 */
@@ -148,6 +149,26 @@ int dp_ctx_destroy(dp_ctx* ctx);
 int dp_build_nlist(dp_ctx* ctx, const double* coords, const int32_t* types, const double* box, int64_t n,
                    int32_t* nlist_out, int32_t* n_overflow_out, hipStream_t stream);
 
+/* Verlet (skin) list for MD (Evaluation section: the neighbour list is
+ * rebuilt every 50 steps with a 2 A skin).
+ * dp_nlist_skin_build first wraps coords [n, 3] (device f64, in place) into
+ * [0, L) by whole box lengths, adding the lengths moved to images [n, 3]
+ * (device int32, may be NULL), then keeps in the context every pair image
+ * (j, s) with r^2 < (r_c + skin)^2 and the positions of the build.  Needs
+ * r_c + skin below every box edge (DP_ERR_UNSUPPORTED).
+ * dp_nlist_skin_format writes, from the current coords (not wrapped since
+ * the build: r_ij keeps the image of the build), the list dp_build_nlist
+ * defines: same cut-off test, order, truncation, padding and n_overflow_out
+ * (device int32, written) -- exactly the list of all pairs within r_c while
+ * no atom has moved more than skin/2 since the build; beyond that
+ * DP_FLAG_SKIN_EXCEEDED is raised and pairs may be missing.  It also
+ * prepares the reverse-entry index that dp_compute uses with this list.
+ * DP_ERR_STATE when no build with the same n preceded on this context. */
+int dp_nlist_skin_build(dp_ctx* ctx, double* coords, const int32_t* types, const double* box, int64_t n, double skin,
+                        int32_t* images, hipStream_t stream);
+int dp_nlist_skin_format(dp_ctx* ctx, const double* coords, const int32_t* types, int64_t n, int32_t* nlist_out,
+                         int32_t* n_overflow_out, hipStream_t stream);
+
 /* Batched form: frames f = 0..B-1 hold atoms [frame_off[f], frame_off[f+1])
  * of coords/types; boxes [B, 9] and frame_off [B+1] are HOST arrays.  Entries
  * use global atom indices; atoms of different frames never neighbour. */
@@ -184,12 +205,14 @@ int dp_compute_batch(dp_ctx* ctx, const double* coords, const int32_t* types, co
 int dp_backward_params(dp_ctx* ctx, const double* dL_dE, double* grad_params, hipStream_t stream);
 
 /* Velocity-Verlet halves (FP64; Evaluation section time steps).
- *   dp_md_kick_drift: v += dt/2 * F/m; x += dt * v; x wrapped into [0, L)
- *                     (image counters [n,3] int32 updated when non-NULL).
+ *   dp_md_kick_drift: v += dt/2 * F/m; x += dt * v; with wrap != 0, x is
+ *                     wrapped into [0, L) (image counters [n,3] int32
+ *                     updated when non-NULL); with wrap = 0 (between Verlet
+ *                     builds) positions are left unwrapped and box may be NULL.
  *   dp_md_kick:       v += dt/2 * F/m; ke [1] device f64 = sum 1/2 m v^2 (eV).
  * dt in fs, v in Angstrom/fs, masses from the model descriptor. */
 int dp_md_kick_drift(dp_ctx* ctx, double* coords, double* vel, const double* forces, const int32_t* types,
-                     const double* box, int64_t n, double dt, int32_t* images, hipStream_t stream);
+                     const double* box, int64_t n, double dt, int32_t wrap, int32_t* images, hipStream_t stream);
 int dp_md_kick(dp_ctx* ctx, double* vel, const double* forces, const int32_t* types, int64_t n, double dt,
                double* ke, hipStream_t stream);
 

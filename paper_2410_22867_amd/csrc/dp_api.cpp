@@ -381,7 +381,9 @@ int check_box(const double* box, double rc, double L[3]) {
 
 // Fills the pinned frame table and queues its upload.  Returns the total
 // number of cells in *ncells.
-int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nframes, hipStream_t s, int64_t* ncells) {
+// Cells have edge >= rlist (the cut-off, or cut-off + skin for a Verlet list).
+int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nframes, hipStream_t s, int64_t* ncells,
+                 double rlist) {
   if (nframes < 1 || nframes > c->max_frames) {
     set_error("nframes %d out of [1, %d]", nframes, c->max_frames);
     return DP_ERR_CAPACITY;
@@ -390,7 +392,7 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
     HIPCHECK(hipEventSynchronize(c->frames_ev));
     c->frames_ev_pending = false;
   }
-  const double rc = c->model->desc.rcut;
+  const double rc = rlist;
   int64_t cells = 0, chunks = 0;
   for (int f = 0; f < nframes; ++f) {
     double L[3];
@@ -480,7 +482,7 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   if (!energies || !virials) { set_error("energy/virial outputs must be non-NULL"); return DP_ERR_BAD_ARG; }
   if ((rc = set_device(c->device))) return rc;
   int64_t ncells = 0;
-  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells))) return rc;
+  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells, c->model->desc.rcut))) return rc;
   c->natoms_last = n;
   c->types_last = types;
   c->mode_last = mode;
@@ -517,7 +519,7 @@ int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* b
   int rc;
   if ((rc = set_device(c->device))) return rc;
   int64_t ncells = 0;
-  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells))) return rc;
+  if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells, c->model->desc.rcut))) return rc;
   c->last_stream = s;
   const int32_t ntot = (int32_t)n;
   StageScope p(c, DP_STAGE_NLIST, s);
@@ -529,6 +531,56 @@ int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* b
   launch_nl_search(c, x, types, ntot, nframes, nlist, overflow, s);
   launch_type_sort(c, types, ntot, nframes, s);  // frame_of for the reverse index
   launch_nl_reverse(c, x, types, nlist, ntot, s);
+  c->rev_list = nlist;
+  c->natoms_rev = n;
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+int skin_build_impl(dp_ctx* c, double* x, const int32_t* types, const double* box, int64_t n, double skin,
+                    int32_t* images, hipStream_t s) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  if (n < 0 || (n > 0 && (!x || !types))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (!(skin >= 0.0) || !std::isfinite(skin)) { set_error("skin must be finite and >= 0"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  const double rlist = c->model->desc.rcut + skin;
+  double L[3];
+  if ((rc = check_box(box, rlist, L))) return rc;
+  int64_t ncells = 0;
+  const int64_t off[2] = {0, n};
+  if ((rc = stage_frames(c, box, off, 1, s, &ncells, rlist))) return rc;
+  c->last_stream = s;
+  c->skin = skin;
+  for (int a = 0; a < 3; ++a) c->skin_L[a] = L[a];
+  const int32_t ntot = (int32_t)n;
+  StageScope p(c, DP_STAGE_NLIST, s);
+  launch_wrap(c, x, ntot, L, images, s);
+  launch_fill_i32(c->cell_count, 0, ncells, s);
+  launch_nl_bin(c, x, ntot, 1, s);
+  launch_nl_scan(c, (int32_t)ncells, s);
+  launch_nl_scatter(c, ntot, s);
+  launch_nl_skin_build(c, x, types, ntot, s);
+  c->skin_n = n;
+  c->rev_list = nullptr;
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+int skin_format_impl(dp_ctx* c, const double* x, const int32_t* types, int64_t n, int32_t* nlist, int32_t* overflow,
+                     hipStream_t s) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  if (!overflow || n < 0 || (n > 0 && (!x || !types || !nlist))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (c->skin_n < 0 || n != c->skin_n) {
+    set_error("no Verlet list built for %lld atoms on this context", (long long)n);
+    return DP_ERR_STATE;
+  }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  c->last_stream = s;
+  StageScope p(c, DP_STAGE_NLIST, s);
+  launch_fill_i32(overflow, 0, 1, s);
+  launch_nl_skin_format(c, x, types, (int32_t)n, nlist, overflow, s);
   c->rev_list = nlist;
   c->natoms_rev = n;
   HIPCHECK(hipGetLastError());
@@ -699,6 +751,13 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->netd, N * nm * 4);
   ALLOC(c->g3, N * nm * 4);
   ALLOC(c->rev, N * nm);
+  ALLOC(c->skin_cand, N * kCandCap);
+  ALLOC(c->skin_ncand, N);
+  ALLOC(c->skin_crev, N * kCandCap);
+  ALLOC(c->skin_slot, N * kCandCap);
+  ALLOC(c->skin_cof, N * nm);
+  ALLOC(c->skin_xref, N * 3);
+  c->skin_n = -1;
   ALLOC(c->red_part, 10 * (N / kRedChunk + (int64_t)max_frames + 1));
   ALLOC(c->vatom, N * 9);
   ALLOC(c->ke_part, N / 256 + 2);
@@ -751,7 +810,8 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act};
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
+                  c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)
@@ -769,6 +829,16 @@ int dp_build_nlist(dp_ctx* c, const double* coords, const int32_t* types, const 
   if (n < 0) { set_error("n < 0"); return DP_ERR_BAD_ARG; }
   const int64_t off[2] = {0, n};
   return nlist_impl(c, coords, types, box, off, 1, nlist_out, n_overflow_out, stream);
+}
+
+int dp_nlist_skin_build(dp_ctx* c, double* coords, const int32_t* types, const double* box, int64_t n, double skin,
+                        int32_t* images, hipStream_t stream) {
+  return skin_build_impl(c, coords, types, box, n, skin, images, stream);
+}
+
+int dp_nlist_skin_format(dp_ctx* c, const double* coords, const int32_t* types, int64_t n, int32_t* nlist_out,
+                         int32_t* n_overflow_out, hipStream_t stream) {
+  return skin_format_impl(c, coords, types, n, nlist_out, n_overflow_out, stream);
 }
 
 int dp_build_nlist_batch(dp_ctx* c, const double* coords, const int32_t* types, const double* boxes,
@@ -810,16 +880,16 @@ int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipS
 }
 
 int dp_md_kick_drift(dp_ctx* c, double* coords, double* vel, const double* forces, const int32_t* types,
-                     const double* box, int64_t n, double dt, int32_t* images, hipStream_t stream) {
+                     const double* box, int64_t n, double dt, int32_t wrap, int32_t* images, hipStream_t stream) {
   if (!c || n < 0 || (n > 0 && (!coords || !vel || !forces || !types))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
   if (n > c->max_atoms) { set_error("n exceeds max_atoms"); return DP_ERR_CAPACITY; }
   if (!std::isfinite(dt)) { set_error("dt not finite"); return DP_ERR_BAD_ARG; }
   double L[3];
-  int rc = check_box(box, c->model->desc.rcut, L);
-  if (rc) return rc;
+  int rc;
+  if (wrap && (rc = check_box(box, c->model->desc.rcut, L))) return rc;
   if ((rc = set_device(c->device))) return rc;
   StageScope p(c, DP_STAGE_MD, stream);
-  launch_kick_drift(c, coords, vel, forces, types, (int32_t)n, dt, L, images, stream);
+  launch_kick_drift(c, coords, vel, forces, types, (int32_t)n, dt, wrap ? L : nullptr, images, stream);
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }

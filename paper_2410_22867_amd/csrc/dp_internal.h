@@ -137,6 +137,16 @@ struct dp_ctx {
   double* netd;            // [N, nm, 4] f64
   double* g3;              // [N, nm, 4] f64 pair force terms
   int32_t* rev;            // [N, nm] reverse-entry index of the list in use
+  // Verlet (skin) list of the last dp_nlist_skin_build
+  int32_t* skin_cand;      // [N, kCandCap] packed candidates, sorted by packed value
+  int32_t* skin_ncand;     // [N]
+  int32_t* skin_crev;      // [N, kCandCap] position of the reverse pair in j's candidates (-1: absent)
+  int32_t* skin_slot;      // [N, kCandCap] list entry i*nm + q of the candidate after the last format (-1)
+  int32_t* skin_cof;       // [N, nm] candidate behind each list slot
+  double* skin_xref;       // [N, 3] positions at the build
+  double skin_L[3];
+  double skin;
+  int64_t skin_n;          // atoms of the build (-1: no build)
   // last embedding layer's tanh output per 16-row neighbour tile, [N, tpa,
   // m1, 16] f64 (FP64) or f32 (mixed), when it fits the workspace budget
   void* act;
@@ -174,6 +184,9 @@ void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t 
                       int32_t* nlist, int32_t* overflow, hipStream_t s);
 void launch_nl_reverse(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
                        hipStream_t s);
+void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, hipStream_t s);
+void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* nlist,
+                           int32_t* overflow, hipStream_t s);
 // small utilities
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
@@ -193,7 +206,8 @@ void launch_frame_reduce(dp_ctx* c, int32_t nframes, double* energies, double* a
                          hipStream_t s);
 // md
 void launch_kick_drift(dp_ctx* c, double* x, double* v, const double* f, const int32_t* types, int32_t n,
-                       double dt, const double L[3], int32_t* images, hipStream_t s);
+                       double dt, const double* L, int32_t* images, hipStream_t s);
+void launch_wrap(dp_ctx* c, double* x, int32_t n, const double L[3], int32_t* images, hipStream_t s);
 void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, int32_t n, double dt, double* ke,
                  hipStream_t s);
 // parameter gradients (FP64 state of the last compute)

@@ -427,6 +427,7 @@ struct MdArgs {
   int32_t* images;
   double* ke;
   int n;
+  int wrap;
   double dt;
   double L[3];
   double mass[kMaxT];
@@ -441,12 +442,34 @@ __global__ void k_kick_drift(MdArgs A) {
     double v = A.v[3 * i + a] + 0.5 * A.dt * A.f[3 * i + a] * inv_m;
     A.v[3 * i + a] = v;
     double x = A.x[3 * i + a] + A.dt * v;
-    const double L = A.L[a];
-    int im = 0;
-    if (x >= L) { x -= L; im = 1; }
-    else if (x < 0.0) { x += L; im = -1; if (x >= L) x -= L; }
+    if (A.wrap) {
+      const double L = A.L[a];
+      int im = 0;
+      if (x >= L) { x -= L; im = 1; }
+      else if (x < 0.0) { x += L; im = -1; if (x >= L) x -= L; }
+      if (A.images) A.images[3 * i + a] += im;
+    }
     A.x[3 * i + a] = x;
-    if (A.images) A.images[3 * i + a] += im;
+  }
+}
+
+// Wraps positions into [0, L) by whole box lengths (any distance), counting
+// the lengths moved in the image counters.
+__global__ void k_wrap(MdArgs A) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double x = A.x[3 * i + a];
+    const double L = A.L[a];
+    if (x >= 0.0 && x < L) continue;
+    const double k = floor(x / L);
+    x -= k * L;
+    if (x >= L) x -= L;  // rounding of x - k L
+    if (x < 0.0) x += L;
+    if (x >= L) x = 0.0;
+    A.x[3 * i + a] = x;
+    if (A.images) A.images[3 * i + a] += (int32_t)k;
   }
 }
 
@@ -498,6 +521,7 @@ static MdArgs md_args(dp_ctx* c, double* x, double* v, const double* f, const in
   A.images = nullptr;
   A.ke = nullptr;
   A.n = n;
+  A.wrap = 0;
   A.dt = dt;
   for (int a = 0; a < 3; ++a) A.L[a] = 0;
   for (int t = 0; t < kMaxT; ++t) A.mass[t] = t < c->model->desc.ntypes ? c->model->desc.masses[t] : 1.0;
@@ -505,12 +529,22 @@ static MdArgs md_args(dp_ctx* c, double* x, double* v, const double* f, const in
 }
 
 void launch_kick_drift(dp_ctx* c, double* x, double* v, const double* f, const int32_t* types, int32_t n, double dt,
-                       const double L[3], int32_t* images, hipStream_t s) {
+                       const double* L, int32_t* images, hipStream_t s) {
   if (n <= 0) return;
   MdArgs A = md_args(c, x, v, f, types, n, dt);
-  for (int a = 0; a < 3; ++a) A.L[a] = L[a];
+  A.wrap = L != nullptr;
+  if (L)
+    for (int a = 0; a < 3; ++a) A.L[a] = L[a];
   A.images = images;
   hipLaunchKernelGGL(k_kick_drift, dim3((n + 255) / 256), dim3(256), 0, s, A);
+}
+
+void launch_wrap(dp_ctx* c, double* x, int32_t n, const double L[3], int32_t* images, hipStream_t s) {
+  if (n <= 0) return;
+  MdArgs A = md_args(c, x, nullptr, nullptr, nullptr, n, 0.0);
+  for (int a = 0; a < 3; ++a) A.L[a] = L[a];
+  A.images = images;
+  hipLaunchKernelGGL(k_wrap, dim3((n + 255) / 256), dim3(256), 0, s, A);
 }
 
 void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, int32_t n, double dt, double* ke,

@@ -112,21 +112,36 @@ struct SearchArgs {
 
 constexpr int kSearchWaves = 4;
 
-__global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
-  __shared__ double cr2[kSearchWaves][kCandCap];
-  __shared__ int32_t cpk[kSearchWaves][kCandCap];
-  __shared__ int8_t ctp[kSearchWaves][kCandCap];
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int i = blockIdx.x * kSearchWaves + w;
-  if (i >= A.ntot) return;
-  const int f = find_frame(A.fr, A.nframes, i);
-  const FrameInfo F = A.fr[f];
+// Wave-private candidate buffers in LDS: one 16-byte record per candidate.
+struct CandRec {
+  double r2;
+  int32_t pk;
+  int16_t k;  // position in the Verlet candidate list (format only)
+  int8_t t;
+  int8_t pad;
+};
+struct CandLds {
+  CandRec r[kSearchWaves][kCandCap];
+};
+
+__device__ __forceinline__ int clamp_type(const int32_t* types, int j, int ntypes, int32_t* flags) {
+  int tj = types[j];
+  if (tj < 0 || tj >= ntypes) {
+    set_flag(flags, DP_FLAG_BAD_INPUT);
+    tj = tj < 0 ? 0 : ntypes - 1;
+  }
+  return tj;
+}
+
+// Walks the 27 stencil cells of atom i (one wavefront) and appends every
+// (j, s) with r^2 < rad2 to the LDS buffers of wave w, in a fixed order.
+// Returns the candidate count (capped at kCandCap; *capacity set beyond).
+__device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds& L, int w, int lane, int i, const FrameInfo& F, double rad2,
+                            bool* capacity) {
   const double xi = A.x[3 * i], yi = A.x[3 * i + 1], zi = A.x[3 * i + 2];
   const int ci[3] = {cell_coord(xi, F.L[0], F.ncell[0]), cell_coord(yi, F.L[1], F.ncell[1]),
                      cell_coord(zi, F.L[2], F.ncell[2])};
   int ncand = 0;
-  bool capacity = false;
   // Lane c < 27 describes stencil cell c (dx, dy, dz in {-1,0,1}): first
   // atom, atom count and image code; a wave prefix sum over the counts turns
   // the 27 cell loops into one flat loop over all candidates.
@@ -180,7 +195,7 @@ __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
         const double ddy = (A.x[3 * j + 1] - yi) + shy;
         const double ddz = (A.x[3 * j + 2] - zi) + shz;
         r2 = r2_nofma(ddx, ddy, ddz);
-        keep = r2 < A.rc2;
+        keep = r2 < rad2;
       }
     }
     const uint64_t mask = __ballot(keep);
@@ -188,47 +203,107 @@ __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
     const int slot = ncand + before;
     if (keep && slot < kCandCap) {
-      cr2[w][slot] = r2;
-      cpk[w][slot] = 27 * j + scode;
-      int tj = A.types[j];
-      if (tj < 0 || tj >= A.ntypes) {
-        set_flag(A.flags, DP_FLAG_BAD_INPUT);
-        tj = tj < 0 ? 0 : A.ntypes - 1;
-      }
-      ctp[w][slot] = (int8_t)tj;
+      CandRec rec;
+      rec.r2 = r2;
+      rec.pk = 27 * j + scode;
+      rec.k = 0;
+      rec.t = (int8_t)clamp_type(A.types, j, A.ntypes, A.flags);
+      rec.pad = 0;
+      L.r[w][slot] = rec;
     }
     ncand += __popcll(mask);
   }
   if (ncand > kCandCap) {
-    capacity = true;
+    *capacity = true;
     ncand = kCandCap;
   }
-  wave_lds_sync();
-  // rank of each candidate inside its type section
+  return ncand;
+}
+
+// Ranks the ncand LDS candidates of wave w inside their type sections by
+// (r^2, packed) -- a total order, so the result does not depend on the order
+// of the buffer -- writes the first sel[t] of each section to row i of the
+// list, pads with -1 and counts what was dropped.  The buffer is first
+// regrouped by type (through registers), so each candidate is compared only
+// with its own section.  With cof != NULL (Verlet format) it also records,
+// per written slot, the candidate it came from and, per kept candidate, its
+// slot (-1 when truncated).
+__device__ __forceinline__ void rank_and_write(const SearchArgs& A, CandLds& L, int w, int lane, int i, int ncand, bool capacity,
+                               int32_t* cof, int32_t* slot_of) {
+  constexpr int kPer = kCandCap / 64;
+  // records move as 16-byte vectors (r^2 bits | packed | k, type)
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4* R = reinterpret_cast<u32x4*>(&L.r[w][0]);
+  u32x4 mine[kPer];
+  int pos[kPer], mt[kPer];
   int cnt[kMaxT] = {0, 0, 0, 0};
-  int32_t* row = A.nlist + (int64_t)i * A.nm;
-  for (int c = lane; c < ncand; c += 64) {
-    const double r2 = cr2[w][c];
-    const int pk = cpk[w][c];
-    const int t = ctp[w][c];
-    int rank = 0;
-    for (int o = 0; o < ncand; ++o) {
-      const double r2o = cr2[w][o];
-      const int pko = cpk[w][o];
-      rank += (ctp[w][o] == t) && (r2o < r2 || (r2o == r2 && pko < pk));
+#pragma clang loop unroll(full)
+  for (int m = 0; m < kPer; ++m) {
+    pos[m] = -1;
+    mt[m] = -1;
+    if (m * 64 < ncand) {
+      const int c = m * 64 + lane;
+      if (c < ncand) {
+        mine[m] = R[c];
+        mt[m] = (int)((mine[m][3] >> 16) & 0xff);
+      }
+#pragma unroll
+      for (int u = 0; u < kMaxT; ++u) {
+        if (u < A.ntypes) {
+          const uint64_t bal = __ballot(mt[m] == u);
+          const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+          if (mt[m] == u) pos[m] = cnt[u] + before;
+          cnt[u] += __popcll(bal);
+        }
+      }
     }
-    if (rank < A.sel[t]) row[A.sec[t] + rank] = pk;
-#pragma unroll
-    for (int u = 0; u < kMaxT; ++u) cnt[u] += (t == u);
   }
-  int ovf = 0;
-  for (int t = 0; t < A.ntypes; ++t) {
-    int n_t = cnt[t];
+  int off[kMaxT];
+  {
+    int acc = 0;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) n_t += __shfl_xor(n_t, m, 64);
-    const int kept = n_t < A.sel[t] ? n_t : A.sel[t];
-    for (int q = kept + lane; q < A.sel[t]; q += 64) row[A.sec[t] + q] = -1;
-    ovf += n_t - kept;
+    for (int u = 0; u < kMaxT; ++u) {
+      off[u] = acc;
+      acc += cnt[u];
+    }
+  }
+  wave_lds_sync();
+#pragma clang loop unroll(full)
+  for (int m = 0; m < kPer; ++m)
+    if (pos[m] >= 0) {
+      int base = 0;  // off[t] without a dynamically indexed register array
+#pragma unroll
+      for (int u = 1; u < kMaxT; ++u) base = mt[m] == u ? off[u] : base;
+      R[base + pos[m]] = mine[m];
+    }
+  wave_lds_sync();
+  int32_t* row = A.nlist + (int64_t)i * A.nm;
+  int ovf = 0;
+#pragma unroll
+  for (int u = 0; u < kMaxT; ++u) {
+    if (u >= A.ntypes) break;
+    const CandRec* sec = &L.r[w][off[u]];
+    const int n_u = cnt[u];
+    const int sel = A.sel[u];
+    for (int c = lane; c < n_u; c += 64) {
+      const CandRec me = sec[c];
+      int rank = 0;
+#pragma unroll 4
+      for (int o = 0; o < n_u; ++o) {
+        const CandRec ot = sec[o];
+        rank += (ot.r2 < me.r2 || (ot.r2 == me.r2 && ot.pk < me.pk));
+      }
+      const bool kept = rank < sel;
+      if (kept) row[A.sec[u] + rank] = me.pk;
+      if (cof) {
+        if (kept) cof[(int64_t)i * A.nm + A.sec[u] + rank] = me.k;
+        slot_of[(int64_t)i * kCandCap + me.k] = kept ? i * A.nm + A.sec[u] + rank : -1;
+      }
+    }
+    const int kept = n_u < sel ? n_u : sel;
+    for (int q = kept + lane; q < sel; q += 64) row[A.sec[u] + q] = -1;
+    ovf += n_u - kept;
   }
   if (lane == 0) {
     if (ovf) {
@@ -237,6 +312,155 @@ __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
     }
     if (capacity) set_flag(A.flags, DP_FLAG_CAND_CAPACITY);
   }
+}
+
+__global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
+  __shared__ CandLds L;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kSearchWaves + w;
+  if (i >= A.ntot) return;
+  const FrameInfo F = A.fr[find_frame(A.fr, A.nframes, i)];
+  bool capacity = false;
+  const int ncand = gather_cells(A, L, w, lane, i, F, A.rc2, &capacity);
+  wave_lds_sync();
+  rank_and_write(A, L, w, lane, i, ncand, capacity, nullptr, nullptr);
+}
+
+// ------------------------------------------------------------ Verlet list
+// Build: every (j, s) with r^2 < (r_c + skin)^2 on the wrapped positions,
+// stored per atom sorted by packed value (so a pair's reverse entry is found
+// by binary search), with the positions of the build.
+struct SkinArgs {
+  int32_t* cand;    // [n, kCandCap]
+  int32_t* ncand;   // [n]
+  int32_t* crev;    // [n, kCandCap]
+  int32_t* slot_of; // [n, kCandCap]
+  int32_t* cof;     // [n, nm]
+  double* xref;     // [n, 3]
+  double L[3];
+  double half_skin2;
+};
+
+__global__ __launch_bounds__(256) void k_nl_skin_build(SearchArgs A, SkinArgs S, double rl2) {
+  __shared__ CandLds L;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kSearchWaves + w;
+  if (i >= A.ntot) return;
+  const FrameInfo F = A.fr[find_frame(A.fr, A.nframes, i)];
+  bool capacity = false;
+  const int ncand = gather_cells(A, L, w, lane, i, F, rl2, &capacity);
+  wave_lds_sync();
+  for (int c = lane; c < ncand; c += 64) {
+    const int pk = L.r[w][c].pk;
+    int rank = 0;
+    for (int o = 0; o < ncand; ++o) rank += L.r[w][o].pk < pk;
+    S.cand[(int64_t)i * kCandCap + rank] = pk;
+  }
+  if (lane < 3) S.xref[3 * i + lane] = A.x[3 * i + lane];
+  if (lane == 0) {
+    S.ncand[i] = ncand;
+    if (capacity) set_flag(A.flags, DP_FLAG_CAND_CAPACITY);
+  }
+}
+
+// Position of each candidate's reverse pair (i, -s) in j's candidate list.
+__global__ void k_nl_skin_crev(SkinArgs S, int ntot) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(q / kCandCap), k = (int)(q - (int64_t)i * kCandCap);
+  if (i >= ntot) return;
+  if (k >= S.ncand[i]) return;
+  const int e = S.cand[q];
+  const int j = e / 27;
+  const int target = 27 * i + (26 - (e - 27 * j));
+  const int32_t* cj = S.cand + (int64_t)j * kCandCap;
+  int lo = 0, hi = S.ncand[j];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cj[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  S.crev[q] = (lo < S.ncand[j] && cj[lo] == target) ? lo : -1;
+}
+
+// Format: the sorted, truncated list on the current positions from the
+// candidates of the last build (same test and order as the cell search).
+__global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S) {
+  __shared__ CandLds L;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kSearchWaves + w;
+  if (i >= A.ntot) return;
+  const double xi = A.x[3 * i], yi = A.x[3 * i + 1], zi = A.x[3 * i + 2];
+  if (lane == 0) {
+    const double ex = xi - S.xref[3 * i], ey = yi - S.xref[3 * i + 1], ez = zi - S.xref[3 * i + 2];
+    if (!((ex * ex + ey * ey) + ez * ez <= S.half_skin2)) set_flag(A.flags, DP_FLAG_SKIN_EXCEEDED);
+  }
+  const int nc = S.ncand[i];
+  const int32_t* ci = S.cand + (int64_t)i * kCandCap;
+  // all loads of a lane's candidates are issued before any is used
+  constexpr int kPer = kCandCap / 64;
+  int e[kPer], tj[kPer];
+  double r2[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) e[m] = (64 * m < nc && 64 * m + lane < nc) ? ci[64 * m + lane] : -1;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    r2[m] = 0.0;
+    tj[m] = 0;
+    if (e[m] >= 0) {
+      const int j = e[m] / 27, sc = e[m] - 27 * j;
+      const double ddx = (A.x[3 * j] - xi) + (double)(sc % 3 - 1) * S.L[0];
+      const double ddy = (A.x[3 * j + 1] - yi) + (double)((sc / 3) % 3 - 1) * S.L[1];
+      const double ddz = (A.x[3 * j + 2] - zi) + (double)(sc / 9 - 1) * S.L[2];
+      r2[m] = r2_nofma(ddx, ddy, ddz);
+      tj[m] = A.types[j];
+    }
+  }
+  int ncand = 0;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    if (64 * m >= nc) break;
+    const int k = 64 * m + lane;
+    const bool keep = e[m] >= 0 && r2[m] < A.rc2;
+    if (e[m] >= 0 && !keep) S.slot_of[(int64_t)i * kCandCap + k] = -1;
+    const uint64_t mask = __ballot(keep);
+    const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+    if (keep) {
+      int t = tj[m];
+      if (t < 0 || t >= A.ntypes) {
+        set_flag(A.flags, DP_FLAG_BAD_INPUT);
+        t = t < 0 ? 0 : A.ntypes - 1;
+      }
+      CandRec rec;
+      rec.r2 = r2[m];
+      rec.pk = e[m];
+      rec.k = (int16_t)k;
+      rec.t = (int8_t)t;
+      rec.pad = 0;
+      L.r[w][ncand + before] = rec;  // < nc <= kCandCap
+    }
+    ncand += __popcll(mask);
+  }
+  wave_lds_sync();
+  rank_and_write(A, L, w, lane, i, ncand, false, S.cof, S.slot_of);
+}
+
+// Reverse index from the candidate bookkeeping of the format (same meaning
+// as the index built by binary search below).
+__global__ void k_nl_skin_revmap(const int32_t* __restrict__ nlist, SkinArgs S, int32_t* __restrict__ rev, int ntot,
+                                 int nm) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)ntot * nm) return;
+  const int e = nlist[q];
+  int out = -1;
+  if (e >= 0) {
+    const int i = (int)(q / nm);
+    const int kr = S.crev[(int64_t)i * kCandCap + S.cof[q]];
+    if (kr >= 0) out = S.slot_of[(int64_t)(e / 27) * kCandCap + kr];
+  }
+  rev[q] = out;
 }
 
 // Reverse index of a symmetric list: for entry q' of atom i pointing to
@@ -333,9 +557,8 @@ void launch_nl_scatter(dp_ctx* c, int32_t ntot, hipStream_t s) {
                      c->cell_fill, c->cell_atoms, ntot);
 }
 
-void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
-                      int32_t* nlist, int32_t* overflow, hipStream_t s) {
-  if (ntot <= 0) return;
+static SearchArgs search_args(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
+                              int32_t* nlist, int32_t* overflow) {
   const dp_model* m = c->model;
   SearchArgs A;
   A.x = x;
@@ -353,7 +576,50 @@ void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t 
   for (int t = 0; t < kMaxT; ++t) A.sel[t] = t < m->desc.ntypes ? m->desc.sel[t] : 0;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= m->desc.ntypes ? m->sec[t] : m->nm;
   A.rc2 = m->desc.rcut * m->desc.rcut;
+  return A;
+}
+
+static SkinArgs skin_args(dp_ctx* c) {
+  SkinArgs S;
+  S.cand = c->skin_cand;
+  S.ncand = c->skin_ncand;
+  S.crev = c->skin_crev;
+  S.slot_of = c->skin_slot;
+  S.cof = c->skin_cof;
+  S.xref = c->skin_xref;
+  for (int a = 0; a < 3; ++a) S.L[a] = c->skin_L[a];
+  S.half_skin2 = 0.25 * c->skin * c->skin;
+  return S;
+}
+
+void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
+                      int32_t* nlist, int32_t* overflow, hipStream_t s) {
+  if (ntot <= 0) return;
+  SearchArgs A = search_args(c, x, types, ntot, nframes, nlist, overflow);
   hipLaunchKernelGGL(k_nl_search, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s, A);
+}
+
+void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, hipStream_t s) {
+  if (ntot <= 0) return;
+  SearchArgs A = search_args(c, x, types, ntot, 1, nullptr, nullptr);
+  SkinArgs S = skin_args(c);
+  const double rl = c->model->desc.rcut + c->skin;
+  hipLaunchKernelGGL(k_nl_skin_build, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s,
+                     A, S, rl * rl);
+  const int64_t q = (int64_t)ntot * kCandCap;
+  hipLaunchKernelGGL(k_nl_skin_crev, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, S, ntot);
+}
+
+void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* nlist,
+                           int32_t* overflow, hipStream_t s) {
+  if (ntot <= 0) return;
+  SearchArgs A = search_args(c, x, types, ntot, 1, nlist, overflow);
+  SkinArgs S = skin_args(c);
+  hipLaunchKernelGGL(k_nl_skin_format, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s,
+                     A, S);
+  const int64_t q = (int64_t)ntot * A.nm;
+  hipLaunchKernelGGL(k_nl_skin_revmap, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, nlist, S, c->rev, ntot,
+                     A.nm);
 }
 
 }  // namespace dpse

@@ -20,12 +20,14 @@ DP_FP64, DP_MIX_BF16, DP_MIX_FP16 = 0, 1, 2
 MODES = {"fp64": DP_FP64, "bf16": DP_MIX_BF16, "fp16": DP_MIX_FP16}
 
 FLAG_NOT_WRAPPED, FLAG_OVERLAP, FLAG_NONFINITE, FLAG_CAND_CAPACITY, FLAG_SEL_OVERFLOW = 1, 2, 4, 8, 16
+FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED = 32, 64
 
 BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 
 # Symbols declared in include/dp.h (checked by the CPU tests).
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_destroy", "dp_ctx_create",
-           "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_compute", "dp_compute_batch",
+           "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_nlist_skin_build", "dp_nlist_skin_format",
+           "dp_compute", "dp_compute_batch",
            "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_store_info",
            "dp_ctx_copy_buffer", "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
 
@@ -90,7 +92,9 @@ def lib():
             "dp_compute": (ctypes.c_int, [P, P, P, P, i64, P, i32, P, P, P, P, P]),
             "dp_compute_batch": (ctypes.c_int, [P, P, P, P, P, i32, P, i32, P, P, P, P]),
             "dp_backward_params": (ctypes.c_int, [P, P, P, P]),
-            "dp_md_kick_drift": (ctypes.c_int, [P, P, P, P, P, P, i64, dbl, P, P]),
+            "dp_md_kick_drift": (ctypes.c_int, [P, P, P, P, P, P, i64, dbl, i32, P, P]),
+            "dp_nlist_skin_build": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
+            "dp_nlist_skin_format": (ctypes.c_int, [P, P, P, i64, P, P, P]),
             "dp_md_kick": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_ctx_status": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
             "dp_ctx_store_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -194,6 +198,25 @@ class Context:
                                     _ptr(overflow), _stream()))
         return out, overflow
 
+    def skin_build(self, coords, types, box, skin, images=None):
+        """Verlet build: wraps coords in place (images updated when given) and
+        keeps every pair image within r_c + skin."""
+        _check(lib().dp_nlist_skin_build(self.handle, _ptr(coords), _ptr(types), _box9(box).ctypes.data,
+                                         int(types.shape[0]), float(skin), _ptr(images), _stream()))
+
+    def skin_format(self, coords, types, out=None, overflow=None):
+        """Sorted, truncated list on the current positions from the last Verlet build."""
+        import torch
+        n = int(types.shape[0])
+        nm = int(sum(self.model.desc.sel))
+        if out is None:
+            out = torch.empty((n, nm), dtype=torch.int32, device=coords.device)
+        if overflow is None:
+            overflow = torch.empty(1, dtype=torch.int32, device=coords.device)
+        _check(lib().dp_nlist_skin_format(self.handle, _ptr(coords), _ptr(types), n, _ptr(out), _ptr(overflow),
+                                          _stream()))
+        return out, overflow
+
     def build_nlist_batch(self, coords, types, boxes, frame_off, out=None, overflow=None):
         import torch
         n = int(types.shape[0])
@@ -255,10 +278,11 @@ class Context:
         return grad
 
     # ------------------------------------------------------------ md
-    def kick_drift(self, coords, vel, forces, types, box, dt, images=None):
+    def kick_drift(self, coords, vel, forces, types, box, dt, images=None, wrap=True):
+        b = _box9(box) if wrap else None
         _check(lib().dp_md_kick_drift(self.handle, _ptr(coords), _ptr(vel), _ptr(forces), _ptr(types),
-                                      _box9(box).ctypes.data, int(types.shape[0]), float(dt), _ptr(images),
-                                      _stream()))
+                                      None if b is None else b.ctypes.data, int(types.shape[0]), float(dt),
+                                      int(bool(wrap)), _ptr(images), _stream()))
 
     def kick(self, vel, forces, types, dt, ke):
         _check(lib().dp_md_kick(self.handle, _ptr(vel), _ptr(forces), _ptr(types), int(types.shape[0]), float(dt),

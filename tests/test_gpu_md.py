@@ -1,7 +1,7 @@
 """GPU velocity-Verlet NVE (FP64) against the oracle's integrator driven by
 the oracle's forces, on the 192-atom water frame: 10 steps at dt = 0.5 fs
-from Maxwell-Boltzmann velocities at 300 K (neighbour list rebuilt every
-step)."""
+from Maxwell-Boltzmann velocities at 300 K, with the neighbour list rebuilt
+every step, and with a Verlet list (2 A skin) rebuilt every 4 steps."""
 import numpy as np
 import pytest
 
@@ -45,6 +45,52 @@ def test_nve_trajectory_matches_oracle():
         E.append((r["E"].item(), ke.item()))
     torch.cuda.synchronize()
     assert np.abs(x.cpu().numpy() - xo).max() < 1e-10
+    assert np.abs(v.cpu().numpy() - vo).max() < 1e-12
+    assert abs(E[-1][0] - hist[-1][0]) < 1e-9 * abs(hist[-1][0])
+    assert abs(E[-1][1] - hist[-1][1]) < 1e-9 * max(1.0, abs(hist[-1][1]))
+    assert ctx.status() == 0
+
+
+def test_nve_verlet_list_matches_oracle():
+    """Positions stay unwrapped between Verlet builds; each build wraps them
+    in place and counts the box lengths in image counters, so x + img * L is
+    the oracle's unwrapped trajectory."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_22867_amd import dpse
+    fr, desc, p, dt = I.workload("water192")
+    v0 = I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=201)
+    m = np.asarray(desc.masses)[fr.types]
+    L = np.diag(fr.box)
+
+    def force_fn(x):
+        o = oracle.compute(x, fr.types, fr.box, desc, p, use_cells=False)
+        return o["E"], o["F"]
+
+    xo, vo, hist = oracle.nve(fr.coords, v0, m, force_fn, dt, 10)
+    dev = torch.device("cuda:0")
+    ctx = dpse.Context(dpse.Model(desc, p), fr.n)
+    x = torch.tensor(fr.coords, device=dev)
+    v = torch.tensor(v0, device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    img = torch.zeros((fr.n, 3), dtype=torch.int32, device=dev)
+    ctx.skin_build(x, t, fr.box, 2.0, images=img)
+    nl, ov = ctx.skin_format(x, t)
+    r = ctx.compute(x, t, fr.box, nl)
+    f = r["F"]
+    ke = torch.zeros(1, dtype=torch.float64, device=dev)
+    E = []
+    for k in range(1, 11):
+        ctx.kick_drift(x, v, f, t, fr.box, dt, wrap=False)
+        if k % 4 == 0:
+            ctx.skin_build(x, t, fr.box, 2.0, images=img)
+        ctx.skin_format(x, t, out=nl, overflow=ov)
+        r = ctx.compute(x, t, fr.box, nl, forces=f)
+        ctx.kick(v, f, t, dt, ke)
+        E.append((r["E"].item(), ke.item()))
+    torch.cuda.synchronize()
+    xu = x.cpu().numpy() + img.cpu().numpy() * L
+    assert np.abs(xu - xo).max() < 1e-10
     assert np.abs(v.cpu().numpy() - vo).max() < 1e-12
     assert abs(E[-1][0] - hist[-1][0]) < 1e-9 * abs(hist[-1][0])
     assert abs(E[-1][1] - hist[-1][1]) < 1e-9 * max(1.0, abs(hist[-1][1]))
