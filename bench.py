@@ -30,16 +30,20 @@ PEAK_BF16_TF = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_flops(desc, real_rows, natoms):
-    """Flops per launch of the matrix stages (real neighbour rows only)."""
+def algorithmic_flops(desc, real_rows, natoms, stored=False):
+    """Flops per launch of the matrix stages (real neighbour rows only).  The
+    embedding backward recomputes layers 1-2 (and layer 3 unless its output
+    was stored by the forward), then back-propagates through all three."""
     w1, fw, nd, m1 = desc.emb[0], desc.fit[0], desc.ndesc, desc.m1
-    gemm_row = 2 * (w1 + desc.emb[0] * desc.emb[1] + desc.emb[1] * desc.emb[2])
+    l12 = 2 * (w1 + desc.emb[0] * desc.emb[1])
+    l3 = 2 * desc.emb[1] * desc.emb[2]
+    gemm_row = l12 + l3
     contr = 2 * m1 * 4
     fit_fwd = 2 * (nd * fw + 2 * fw * fw) + 2 * fw
     fit_bwd = 2 * (2 * fw * fw + fw * nd)
     return {
         "embed_fwd": real_rows * (gemm_row + contr),
-        "embed_bwd": real_rows * (2 * gemm_row + 2 * contr),
+        "embed_bwd": real_rows * ((l12 if stored else gemm_row) + gemm_row + 2 * contr),
         "fit_fwd": natoms * fit_fwd,
         "fit_bwd": natoms * fit_bwd,
         "descriptor": natoms * 2 * m1 * desc.m2 * 4,
@@ -167,23 +171,7 @@ def main():
         raise RuntimeError(f"device status flags {fl}")
     status_flags = fl
 
-    results = {}
-    for mode in args.modes.split(","):
-        x, v = init_state(mode)
-        for _ in range(args.warmup):
-            step(x, v, mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step(x, v, mode)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ms = el / args.steps * 1e3
-        results[mode] = dict(ms_per_step=ms, atom_steps_per_s=n * args.steps / el,
-                             ns_per_day=(args.steps / el) * dt * 0.0864)
-        print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s", file=sys.stderr, flush=True)
-
-    # per-stage event timing (separate pass)
+    # per-stage event timing (separate pass over all stages)
     stages = {}
     for mode in args.modes.split(","):
         x, v = init_state(mode)
@@ -195,6 +183,34 @@ def main():
         st = ctx.stage_times()
         ctx.profile(False)
         stages[mode] = {k: (ms / c if c else 0.0, c) for k, (ms, c) in st.items()}
+    st64 = stages.get("fp64", {})
+    dom = max(st64, key=lambda k: st64[k][0]) if st64 else None
+
+    # timed region; in FP64 the dominant stage is also timed with HIP events
+    # recorded on its own stream inside the same region (roofline below)
+    results = {}
+    dom_live = None
+    for mode in args.modes.split(","):
+        x, v = init_state(mode)
+        for _ in range(args.warmup):
+            step(x, v, mode)
+        live = mode == "fp64" and dom is not None
+        if live:
+            ctx.profile(True, stages=[dom])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(x, v, mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if live:
+            ms_dom, cnt = ctx.stage_times()[dom]
+            ctx.profile(False)
+            dom_live = (ms_dom / cnt, cnt) if cnt else None
+        ms = el / args.steps * 1e3
+        results[mode] = dict(ms_per_step=ms, atom_steps_per_s=n * args.steps / el,
+                             ns_per_day=(args.steps / el) * dt * 0.0864)
+        print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s", file=sys.stderr, flush=True)
     fl = ctx.status()
     if fl & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED):
         raise RuntimeError(f"device status flags {fl}")
@@ -234,17 +250,16 @@ def main():
                            slope_meV_per_atom_per_ps=slope,
                            flags=ctx.status())
 
-    # roofline of the dominant FP64 kernel
-    flops = algorithmic_flops(desc, real_rows, n)
-    st64 = stages.get("fp64", {})
-    dom = max(st64, key=lambda k: st64[k][0]) if st64 else None
+    # roofline of the dominant FP64 kernel, timed inside the timed region
+    flops = algorithmic_flops(desc, real_rows, n, stored=activations.get("fp64") == "stored")
     roof = None
-    if dom in flops:
-        avg_s = st64[dom][0] * 1e-3
+    if dom in flops and dom_live is not None:
+        avg_s = dom_live[0] * 1e-3
         ach = flops[dom] / avg_s / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TF,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TF, 4), "traffic": measured_traffic(dom, args.workload),
-                "avg_launch_ms": round(st64[dom][0], 4), "flops_per_launch": flops[dom]}
+                "avg_launch_ms": round(dom_live[0], 4), "launches_timed": dom_live[1],
+                "flops_per_launch": flops[dom]}
 
     # oracle on the host cores (bounded sample: one full frame, twice)
     cpu = None

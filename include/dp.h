@@ -238,11 +238,13 @@ int dp_ctx_store_info(dp_ctx* ctx, int64_t* capacity_bytes, int32_t* last_used);
 int dp_ctx_copy_buffer(dp_ctx* ctx, int32_t which, void* dst, int64_t* nbytes, hipStream_t stream);
 
 /* Opt-in per-stage timing with HIP events recorded on the call's stream
- * around every stage of dp_build_nlist / dp_compute / the integrator.
- * enable != 0 allocates an event pool (setup call, not for timed loops that
- * forbid allocation); enable == 0 releases it.  dp_ctx_stage_times waits for
- * the recorded events, adds their durations into total_ms[s] and counts[s]
- * (arrays of DP_NSTAGES, caller-owned, host) and clears the record. */
+ * around the stages of dp_build_nlist / dp_nlist_skin_* / dp_compute / the
+ * integrator.  stage_mask selects the stages timed (bit s for stage s, -1
+ * for all); a non-zero mask allocates an event pool (setup call, not for
+ * loops that forbid allocation), 0 releases it.  dp_ctx_stage_times waits
+ * for the recorded events, adds their durations into total_ms[s] and
+ * counts[s] (arrays of DP_NSTAGES, caller-owned, host) and clears the
+ * record. */
 #define DP_NSTAGES 12
 #define DP_STAGE_NLIST 0
 #define DP_STAGE_TYPESORT 1
@@ -256,7 +258,7 @@ int dp_ctx_copy_buffer(dp_ctx* ctx, int32_t which, void* dst, int64_t* nbytes, h
 #define DP_STAGE_FORCE 9
 #define DP_STAGE_REDUCE 10
 #define DP_STAGE_MD 11
-int dp_ctx_profile(dp_ctx* ctx, int32_t enable);
+int dp_ctx_profile(dp_ctx* ctx, int32_t stage_mask);
 int dp_ctx_stage_times(dp_ctx* ctx, double* total_ms, int64_t* counts);
 
 /* Message of the last error on this thread ("" if none). */

@@ -447,7 +447,7 @@ struct StageScope {
   int k;
   hipStream_t s;
   StageScope(dp_ctx* ctx, int stage, hipStream_t st) : c(ctx), k(-1), s(st) {
-    if (!c->prof_ev) return;
+    if (!c->prof_ev || !((c->prof_mask >> stage) & 1)) return;
     if (c->prof_n == c->prof_cap) prof_harvest(c);
     k = c->prof_n++;
     c->prof_stage[k] = stage;
@@ -676,6 +676,7 @@ int dp_ctx_profile(dp_ctx* c, int32_t enable) {
     c->prof_cap = c->prof_n = 0;
   }
   for (int k = 0; k < DP_NSTAGES; ++k) { c->prof_ms[k] = 0; c->prof_cnt[k] = 0; }
+  c->prof_mask = enable;
   if (!enable) return DP_OK;
   const int cap = 4096;
   c->prof_ev = new hipEvent_t[2 * cap];

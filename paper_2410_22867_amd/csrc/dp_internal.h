@@ -165,6 +165,7 @@ struct dp_ctx {
   hipEvent_t* prof_ev;     // [2 * prof_cap]
   int32_t* prof_stage;     // [prof_cap]
   int32_t prof_cap, prof_n;
+  int32_t prof_mask;       // stages timed (bit s = stage s)
   double prof_ms[DP_NSTAGES];
   int64_t prof_cnt[DP_NSTAGES];
 };

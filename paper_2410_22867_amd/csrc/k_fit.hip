@@ -9,9 +9,9 @@
 // kColPad.  A GEMM computes out[col][m] = epi(sum_k X[col][k] W[k][m]) for
 // all columns of every type (blockIdx.z), with the weight operand stored in
 // per-lane fragment order (A operand, features along M) and X as the B
-// operand read straight from memory: for the k permutation used, lane
-// n + 16g reads 4 consecutive features of its column, so a wave loads 16
-// rows x 128 contiguous bytes.
+// operand: FP64 reads it straight from memory (lane n + 16g reads 4
+// consecutive features of its column); the half-precision GEMM stages it
+// through LDS in fragment order.
 #include "dp_internal.h"
 #include "dp_device.h"
 
@@ -147,106 +147,135 @@ __device__ __forceinline__ void store4lp(uint16_t* p, const float* v) {
   *reinterpret_cast<u16x4*>(p) = u;
 }
 
-template <class P, int MT, int NT>
+// Epilogue of one 16x16 output tile row group: lane holds features m0..m0+3
+// of column col.
+template <class P>
+__device__ __forceinline__ void epi_lp(const GemmArgs& g, const float* vec, int64_t col, int m0, const f4 a) {
+  if (g.epi == EPI_PLAIN) {
+    *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = a;
+  } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
+    f4 r = {0.f, 0.f, 0.f, 0.f};
+    if (g.epi == EPI_RES) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
+    float tv[4], hv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      tv[v] = tanh_f(a[v] + vec[g.bias_off + m0 + v]);
+      hv[v] = r[v] + tv[v];
+    }
+    *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
+    if (g.out1)
+      *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out1) + col * g.ld1 + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+    if (g.outlp) store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, hv);
+  } else {
+    f4 r;
+    if (g.res) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
+    else
+#pragma unroll
+      for (int v = 0; v < 4; ++v) r[v] = vec[g.wo_off + m0 + v];
+    const f4 tp = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.tprev) + col * g.ldt + m0);
+    float dh[4], dz[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      dh[v] = a[v] + r[v];
+      dz[v] = dh[v] * (1.f - tp[v] * tp[v]);
+    }
+    if (g.out0) *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{dh[0], dh[1], dh[2], dh[3]};
+    store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, dz);
+  }
+}
+
+// Half-precision GEMM.  A work-group of 4 waves covers 16 m-tiles (wave w:
+// tiles 16 by + 4w .. +3) and 16 NTW columns; the X tile of each 32-wide
+// k-step is loaded once per work-group into LDS (double-buffered), already
+// in B-fragment order, and shared by the 4 waves; each wave streams its own
+// weight fragments from memory (one 16-byte load per lane and m-tile).
+template <class P, int MTW, int NTW>
 __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
+  constexpr int BN = 16 * NTW;
+  __shared__ __attribute__((aligned(16))) uint16_t xs[2][NTW * 64 * 8];
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
+  const int c0 = blockIdx.x * BN;
+  if (c0 >= n_t) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, gq = lane >> 4;
-  const int c0 = (blockIdx.x * 4 + wv) * NT * 16;
-  if (c0 >= n_t) return;
   const int mtiles = g.M / 16;
-  const int mt0 = blockIdx.y * MT;
+  const int mt0 = (blockIdx.y * 4 + wv) * MTW;
   const int KT = g.K / 32;
   const uint16_t* Afr = reinterpret_cast<const uint16_t*>(g.Afr) + t * g.a_type_stride;
-  const uint16_t* X = reinterpret_cast<const uint16_t*>(g.X);
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int a = 0; a < MT; ++a)
-#pragma unroll
-    for (int b = 0; b < NT; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t* xrow[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) xrow[nt] = X + (int64_t)(cb + c0 + nt * 16 + r16) * g.ldx + 4 * gq;
-  const uint16_t* arow[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int m = (mt0 + mt) < mtiles ? (mt0 + mt) : (mtiles - 1);
-    arow[mt] = Afr + ((int64_t)m * KT * 64 + lane) * 8;
-  }
-  // register double buffer: operands of k-step kt+1 load while kt computes
-  u16x8 xa[NT], aa[MT];
-  auto load = [&](int kt, u16x8* xv, u16x8* av) {
-    // the padded upper half of the last k-step may hold stale bits: use zeros
-    const bool hi_ok = 32 * kt + 16 < g.Kreal;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const u16x4 lo = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt);
-      u16x4 hi = {0, 0, 0, 0};
-      if (hi_ok) hi = *reinterpret_cast<const u16x4*>(xrow[nt] + 32 * kt + 16);
-      xv[nt] = u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) av[mt] = *reinterpret_cast<const u16x8*>(arow[mt] + (int64_t)kt * 512);
+  // copy role: thread (col, q) moves X[col][32 kt + 8q .. +7]; its two
+  // 4-value halves h land in lane (col % 16) + 16 (2 (q % 2) + h), elements
+  // 4 (q / 2) .. +3, of n-tile col / 16 (the k order of the fragments)
+  const int ccol = threadIdx.x >> 2, q = threadIdx.x & 3;
+  const bool copier = ccol < BN;
+  const uint16_t* xsrc = reinterpret_cast<const uint16_t*>(g.X) + (int64_t)(cb + c0 + ccol) * g.ldx + 8 * q;
+  const int d0 = (((ccol >> 4) * 64 + 32 * (q & 1) + (ccol & 15)) * 8) + 4 * (q >> 1);
+  const int d1 = d0 + 16 * 8;
+  auto gload = [&](int kt) {
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    // the padded upper half of the last k-step may hold stale bits: zeros
+    if (copier && (q < 2 || 32 * kt + 16 < g.Kreal)) v = *reinterpret_cast<const u16x8*>(xsrc + 32 * kt);
+    return v;
   };
-  load(0, xa, aa);
-  for (int kt = 0; kt < KT; ++kt) {
-    u16x8 xn[NT], an[MT];
-    if (kt + 1 < KT) load(kt + 1, xn, an);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]), __builtin_bit_cast(typename P::vec8, xa[nt]),
-                              acc[mt][nt]);
-    if (kt + 1 < KT) {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) xa[nt] = xn[nt];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) aa[mt] = an[mt];
+  auto lstore = [&](int buf, const u16x8 v) {
+    if (copier) {
+      *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<u16x4*>(&xs[buf][d1]) = u16x4{v[4], v[5], v[6], v[7]};
     }
+  };
+  bool mval[MTW];
+  const uint16_t* arow[MTW];
+#pragma unroll
+  for (int mt = 0; mt < MTW; ++mt) {
+    mval[mt] = mt0 + mt < mtiles;
+    arow[mt] = Afr + ((int64_t)(mval[mt] ? mt0 + mt : 0) * KT * 64 + lane) * 8;
+  }
+  auto aload = [&](int kt, u16x8* av) {
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+      if (mval[mt]) av[mt] = *reinterpret_cast<const u16x8*>(arow[mt] + (int64_t)kt * 512);
+  };
+  f4 acc[MTW][NTW];
+#pragma unroll
+  for (int a = 0; a < MTW; ++a)
+#pragma unroll
+    for (int b = 0; b < NTW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  u16x8 xr = gload(0);
+  u16x8 aa[MTW] = {};
+  aload(0, aa);
+  lstore(0, xr);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    u16x8 an[MTW] = {};
+    if (kt + 1 < KT) {
+      xr = gload(kt + 1);
+      aload(kt + 1, an);
+    }
+    u16x8 bb[NTW];
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) bb[nt] = *reinterpret_cast<const u16x8*>(&xs[buf][(nt * 64 + lane) * 8]);
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+      if (mval[mt])
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt)
+          acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]),
+                                __builtin_bit_cast(typename P::vec8, bb[nt]), acc[mt][nt]);
+    if (kt + 1 < KT) {
+      lstore(buf ^ 1, xr);
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) aa[mt] = an[mt];
+    }
+    __syncthreads();
   }
   const float* vec = reinterpret_cast<const float*>(g.vec) + t * g.vec_type_stride;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    if (mt0 + mt >= mtiles) break;
+  for (int mt = 0; mt < MTW; ++mt) {
+    if (!mval[mt]) break;
     const int m0 = (mt0 + mt) * 16 + 4 * gq;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int64_t col = cb + c0 + nt * 16 + r16;
-      const f4 a = acc[mt][nt];
-      if (g.epi == EPI_PLAIN) {
-        *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = a;
-      } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
-        f4 r = {0.f, 0.f, 0.f, 0.f};
-        if (g.epi == EPI_RES) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
-        float tv[4], hv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          tv[v] = tanh_f(a[v] + vec[g.bias_off + m0 + v]);
-          hv[v] = r[v] + tv[v];
-        }
-        *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
-        if (g.out1)
-          *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out1) + col * g.ld1 + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
-        if (g.outlp) store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, hv);
-      } else {
-        f4 r;
-        if (g.res) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
-        else
-#pragma unroll
-          for (int v = 0; v < 4; ++v) r[v] = vec[g.wo_off + m0 + v];
-        const f4 tp = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.tprev) + col * g.ldt + m0);
-        float dh[4], dz[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          dh[v] = a[v] + r[v];
-          dz[v] = dh[v] * (1.f - tp[v] * tp[v]);
-        }
-        if (g.out0) *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{dh[0], dh[1], dh[2], dh[3]};
-        store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, dz);
-      }
-    }
+    for (int nt = 0; nt < NTW; ++nt) epi_lp<P>(g, vec, (int64_t)(cb + c0 + nt * 16 + r16), m0, acc[mt][nt]);
   }
 }
 
@@ -365,28 +394,35 @@ __global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ ato
 //          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
 template <int MT, int NT>
-static void gemm_launch_cfg(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 4 * NT * 16;
   const int mtiles = g.M / 16;
   dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + MT - 1) / MT), (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (mode == DP_FP64) {
-    if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
-  } else if (mode == DP_MIX_BF16) {
-    hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MT, NT>), grid, dim3(256), 0, s, g);
-  } else {
-    hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MT, NT>), grid, dim3(256), 0, s, g);
-  }
+  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
 }
 
-// Tile shapes picked by a sweep on the 12,288-atom water model: FP64 MFMA
-// (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the 16x16x32
-// half-precision MFMA does best with more waves resident (4x1).
+template <int MTW, int NTW>
+static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+  const int ntypes = c->model->desc.ntypes;
+  const int BN = 16 * NTW;
+  const int mtiles = g.M / 16;
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + 4 * MTW - 1) / (4 * MTW)),
+            (unsigned)ntypes);
+  if (grid.x == 0) return;
+  if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW>), grid, dim3(256), 0, s, g);
+}
+
+// Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
+// (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the half-precision
+// GEMM does best with small 2x2 wave tiles (more work-groups in flight),
+// 4 waves sharing a 32-column X tile.
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
-  if (mode == DP_FP64) gemm_launch_cfg<3, 2>(c, g, mode, s);
-  else gemm_launch_cfg<4, 1>(c, g, mode, s);
+  if (mode == DP_FP64) gemm_launch_f64<3, 2>(c, g, s);
+  else gemm_launch_lp<2, 2>(c, g, mode, s);
 }
 
 static GemmArgs gemm_base(dp_ctx* c, int mode) {

@@ -300,8 +300,13 @@ class Context:
         _check(lib().dp_ctx_store_info(self.handle, ctypes.byref(cap), ctypes.byref(used)))
         return int(cap.value), bool(used.value)
 
-    def profile(self, enable: bool) -> None:
-        _check(lib().dp_ctx_profile(self.handle, int(bool(enable))))
+    def profile(self, enable, stages=None) -> None:
+        """Per-stage event timing: enable=False releases it; stages (names from
+        STAGES) restricts it to those stages."""
+        mask = 0
+        if enable:
+            mask = -1 if stages is None else sum(1 << STAGES.index(n) for n in stages)
+        _check(lib().dp_ctx_profile(self.handle, int(mask)))
 
     def stage_times(self) -> dict:
         ms = np.zeros(len(STAGES), dtype=np.float64)
