@@ -59,8 +59,10 @@ def measured_traffic(stage, workload):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"] or rec["workload"] != workload:
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"] or rec["workload"] != workload:
         return None
     key = "k_" + stage + "_f64"
     for name, v in rec["kernels"].items():

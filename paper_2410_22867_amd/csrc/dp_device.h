@@ -141,10 +141,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // loads through it are not hoisted out of the loop (the weight fragments are
 // loop-invariant across neighbour tiles; keeping all of them in registers
 // would exhaust the register file).
+// The pointer itself is not passed through the asm (that would turn it into
+// a generic pointer and its loads into flat loads, which also count against
+// the LDS wait counter): an opaque zero offset is added instead, so loads
+// stay global.
 template <typename T>
 __device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+v"(p));
-  return p;
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return p + z;
 }
 
 __device__ __forceinline__ void set_flag(int32_t* flags, int32_t bit) { atomicOr(flags, bit); }
