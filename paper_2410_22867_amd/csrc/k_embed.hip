@@ -181,7 +181,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v))
-              z = mfma_f64(h2s[wv][r16][z0 + 16 * mt + 4 * v + g], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
+              z = mfma_f64(h2[mt][v], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
         const int feat = 16 * o + r16;
         if (feat < M1) {
           const double b3 = vec[kV_B3F + feat];

@@ -49,7 +49,7 @@ struct GemmArgs {
 };
 
 // ---------------------------------------------------------------- FP64 GEMM
-template <int MT, int NT, bool XT>
+template <int MT, int NT, bool XT, bool PF>
 __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
@@ -84,27 +84,52 @@ __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
       for (int v = 0; v < 4; ++v) Tb[nt][v] = *reinterpret_cast<const d4*>(trow[nt] + (4 * gq + v) * 4);
     }
   }
-  for (int S = 0; S < KS; ++S) {
-    d4 xb[NT];
-    if constexpr (XT) {
+  // PF: operands of k-step S + 1 are loaded while S computes (register
+  // double buffer: X rows or T rows, and the weight fragments).  It pays for
+  // the short (K = 240, M = 240) products; for the long ones the extra
+  // registers cost more occupancy than the prefetch gains.
+  d4 xr[NT], xn[NT];
+  double ar[MT][4], an[MT][4];
+  auto load = [&](int S, d4* xv, double (*av)[4]) {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const d4 ta = *reinterpret_cast<const d4*>(trow[nt] + S * 4);
+    for (int nt = 0; nt < NT; ++nt)
+      xv[nt] = *reinterpret_cast<const d4*>(XT ? trow[nt] + S * 4 : xrow[nt] + 16 * S);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) av[mt][v] = Afr[(((int64_t)mtv[mt] * KS + S) * 4 + v) * 64 + lane];
+  };
+  load(0, xr, ar);
+  for (int S = 0; S < KS; ++S) {
+    if (PF && S + 1 < KS) load(S + 1, xn, an);
+    d4 xb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if constexpr (XT) {
+        const d4 ta = xr[nt];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           xb[nt][v] = ta[0] * Tb[nt][v][0] + ta[1] * Tb[nt][v][1] + ta[2] * Tb[nt][v][2] + ta[3] * Tb[nt][v][3];
+      } else {
+        xb[nt] = xr[nt];
       }
-    } else {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) xb[nt] = *reinterpret_cast<const d4*>(xrow[nt] + 16 * S);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const double a = Afr[(((int64_t)mtv[mt] * KS + S) * 4 + v) * 64 + lane];
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a, xb[nt][v], acc[mt][nt]);
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(ar[mt][v], xb[nt][v], acc[mt][nt]);
+    if (S + 1 < KS) {
+      if constexpr (PF) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) xr[nt] = xn[nt];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ar[mt][v] = an[mt][v];
+      } else {
+        load(S + 1, xr, ar);
       }
     }
   }
@@ -393,15 +418,15 @@ __global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ ato
 //   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
 //          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
-template <int MT, int NT>
+template <int MT, int NT, bool PF>
 static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 4 * NT * 16;
   const int mtiles = g.M / 16;
   dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + MT - 1) / MT), (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
+  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true, PF>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false, PF>), grid, dim3(256), 0, s, g);
 }
 
 template <int MTW, int NTW>
@@ -421,8 +446,9 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
 // GEMM does best with small 2x2 wave tiles (more work-groups in flight),
 // 4 waves sharing a 32-column X tile.
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
-  if (mode == DP_FP64) gemm_launch_f64<3, 2>(c, g, s);
-  else gemm_launch_lp<2, 2>(c, g, mode, s);
+  if (mode != DP_FP64) gemm_launch_lp<2, 2>(c, g, mode, s);
+  else if (g.T || g.M > 256 || g.K > 256) gemm_launch_f64<3, 2, false>(c, g, s);
+  else gemm_launch_f64<3, 2, true>(c, g, s);
 }
 
 static GemmArgs gemm_base(dp_ctx* c, int mode) {
