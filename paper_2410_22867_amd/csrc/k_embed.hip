@@ -70,7 +70,7 @@ __device__ __forceinline__ int opaque_zero() {
 }
 
 // per-net vector block: W1s[32] | b1s[32] | b2s[64] | b3s[128] | b3f[128]
-constexpr int kV_W1 = 0, kV_B1 = 32, kV_B2 = 64, kV_B3S = 128, kV_B3F = 256;
+constexpr int kV_W1 = 0, kV_B1 = 32, kV_B2 = 64, kV_B3S = 128, kV_B3F = 256, kVecPerNet = 384;
 
 template <int W>
 __device__ __forceinline__ int slot2_of_feat(int f) {  // f in [0, 2W)
@@ -111,14 +111,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
   __shared__ double fr[NF2 + NF3];
   __shared__ double h2s[WPB][16][kP2 + 1];
+  __shared__ double vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
     const double* src = A.frag64 + net * A.fo.per_net;
     for (int k = threadIdx.x; k < NF2; k += 64 * WPB) fr[k] = src[A.fo.F2 + k];
     for (int k = threadIdx.x; k < NF3; k += 64 * WPB) fr[NF2 + k] = src[A.fo.F3n + k];
+    const double* vsrc = A.vec64 + net * A.vec_per_net;
+    for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
   }
   __syncthreads();
-  const double* vecg = A.vec64 + net * A.vec_per_net;
 
   for (int it = 0; it < A.items; ++it) {
     const int c = chunk0 + it * WPB + wv;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
-      const double* vec = opaque(vecg);  // per-tile L1 reads instead of hoisted registers
+      const double* vec = vs + z0;  // per-tile LDS reads instead of hoisted registers
       const int row = r0 + r16;
       const double s = row < nn ? Rs[row * 4] : 0.0;
       double* rec =
@@ -221,16 +223,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <int W, int WPB, bool ST>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_bwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
-  __shared__ double fr[8192 + 8192];   // F3t | B3
+  // F3t | B3; with the activation store F3t is not needed and its space
+  // holds F2 | B2 | the vector block instead (no global operand loads)
+  __shared__ double fr[8192 + 8192];
   __shared__ d4 gts[WPB][kP3];
   DPSE_NET_PROLOGUE(WPB)
   const double* gsrc = A.frag64 + net * A.fo.per_net;
+  const double* vecg = A.vec64 + net * A.vec_per_net;
   for (int k = threadIdx.x; k < 8192; k += 64 * WPB) {
-    if constexpr (!ST) fr[k] = gsrc[A.fo.F3t + k];
+    if constexpr (!ST) {
+      fr[k] = gsrc[A.fo.F3t + k];
+    } else {
+      if (k < 2048) fr[k] = gsrc[A.fo.F2 + k];
+      else if (k < 4096) fr[k] = gsrc[A.fo.B2 + k - 2048];
+      else if (k < 4096 + kVecPerNet) fr[k] = vecg[k - 4096];
+    }
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
-  const double* vecg = A.vec64 + net * A.vec_per_net;
   for (int it = 0; it < A.items; ++it) {
     const int c = chunk0 + it * WPB + wv;
     if (c >= n_t) break;
@@ -252,9 +262,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     const double* Rs = A.R + rbase * 4;
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
-      const double* F2 = opaque(gsrc + A.fo.F2);
-      const double* B2 = opaque(gsrc + A.fo.B2);
-      const double* vec = opaque(vecg);
+      const double* F2 = ST ? fr + z0 : opaque(gsrc + A.fo.F2);
+      const double* B2 = ST ? fr + 2048 + z0 : opaque(gsrc + A.fo.B2);
+      const double* vec = ST ? fr + 4096 + z0 : opaque(vecg);
       const int row = r0 + r16;
       const bool valid = row < nn;
       d4 Rrow = {0.0, 0.0, 0.0, 0.0};
