@@ -97,7 +97,8 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   const int r16 = lane & 15, g = lane >> 4;
 
 // FP64 k-step (t, v) covers slots 16t + 4v + {0..3}; with w = 25 the slot
-// groups 28..31 (mod 32) hold only padding, so those k-steps are skipped.
+// groups 28..31 (mod 32) hold only padding, so those k-steps are skipped and
+// the activations of those slots (tanh(0) = 0) are not evaluated.
 template <int W>
 __device__ __forceinline__ constexpr bool kpad(int t, int v) {
   return W <= 28 && (t & 1) && v == 3;
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          h1[mt][v] = tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
+          h1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
       double h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
       wave_lds_sync();
 #pragma unroll
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          t1[mt][v] = tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
+          t1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
       double h2[4][4];  // t2 = h2 - t1 is re-derived where needed
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = t1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
       }
       // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
