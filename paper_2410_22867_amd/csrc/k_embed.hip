@@ -274,6 +274,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const double* rec =
           ST ? static_cast<const double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + g * 16 + r16
              : nullptr;
+      // stored t3 of the whole tile, requested before layers 1-2 are
+      // recomputed so that the loads are in flight meanwhile.  Slot
+      // p = 64 zo + 16 o4 + 4 v + g holds feature 2W zo + W (o4 / 2) +
+      // 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g < W; a padding slot
+      // may read past its record (the store has one record of slack at its
+      // end) and its value is discarded.
+      double t3v[2][16];
+      if constexpr (ST) {
+#pragma unroll
+        for (int oo = 0; oo < 2; ++oo)
+#pragma unroll
+          for (int o4 = 0; o4 < 4; ++o4)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lo = 16 * (o4 & 1) + 4 * v;
+              t3v[oo][o4 * 4 + v] = (lo < W) ? rec[(oo * 2 * W + (o4 >> 1) * W + lo) * 16] : 0.0;
+            }
+      }
       double t1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
@@ -321,13 +339,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
             const int p = 16 * (4 * zo + o4) + 4 * v + g;
             double t3;
             if constexpr (ST) {
-              // slot p = 64 zo + 16 o4 + 4 v + g holds feature
-              // 2W zo + W (o4 / 2) + 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g < W
-              const int lo = 16 * (o4 & 1) + 4 * v;
-              // (a padding slot may read past its record: the store has one
-              // record of slack at its end, and the value is discarded)
-              const double x = rec[(zo * 2 * W + (o4 >> 1) * W + lo) * 16];
-              t3 = lo + g < W ? x : 0.0;
+              const double x = oo == 0 ? t3v[0][o4 * 4 + v] : t3v[1][o4 * 4 + v];
+              t3 = 16 * (o4 & 1) + 4 * v + g < W ? x : 0.0;
             } else {
               t3 = tanh_d(z[v] + vec[kV_B3S + p]);
             }
