@@ -135,11 +135,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int k = 0; k < 4; ++k) accT[o][k] = 0.0;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
       const double* vec = vs + z0;  // per-tile LDS reads instead of hoisted registers
       const int row = r0 + r16;
-      const double s = row < nn ? Rs[row * 4] : 0.0;
+      const double s = s_next;
+      s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
       double* rec =
           ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + r16 * 16 + g
              : nullptr;
@@ -261,6 +263,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
+    d4 R_next = {0.0, 0.0, 0.0, 0.0};  // row of the next tile is always in flight
+    if (r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + r16 * 4);
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
       const double* F2 = ST ? fr + z0 : opaque(gsrc + A.fo.F2);
@@ -268,8 +272,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const double* vec = ST ? fr + 4096 + z0 : opaque(vecg);
       const int row = r0 + r16;
       const bool valid = row < nn;
-      d4 Rrow = {0.0, 0.0, 0.0, 0.0};
-      if (valid) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const d4 Rrow = R_next;
+      R_next = d4{0.0, 0.0, 0.0, 0.0};
+      if (row + 16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + 16) * 4);
       const double s = Rrow[0];
       const double* rec =
           ST ? static_cast<const double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + g * 16 + r16
@@ -446,10 +451,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
       for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
-      const float s = row < nn ? (float)Rs[row * 4] : 0.f;
+      const float s = (float)s_next;
+      s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
       float h1[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
@@ -572,12 +579,15 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
+    d4 R_next = {0.0, 0.0, 0.0, 0.0};  // row of the next tile is always in flight
+    if (r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + r16 * 4);
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
       const bool valid = row < nn;
-      d4 Rd = {0.0, 0.0, 0.0, 0.0};
-      if (valid) Rd = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const d4 Rd = R_next;
+      R_next = d4{0.0, 0.0, 0.0, 0.0};
+      if (row + 16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + 16) * 4);
       const float Rrow[4] = {(float)Rd[0], (float)Rd[1], (float)Rd[2], (float)Rd[3]};
       const float s = Rrow[0];
       float t1[8];
