@@ -145,6 +145,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       double* rec =
           ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + r16 * 16 + g
              : nullptr;
+      // rows of the contraction, requested before layers 1-2 run
+      double Rr[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * v + g;
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Rr[v][k] = x[k];
+      }
       double h1[2][4];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
@@ -169,15 +179,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * v + g] = h2[ot][v];
       wave_lds_sync();
-      double Rr[4][4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = r0 + 4 * v + g;
-        d4 x = {0.0, 0.0, 0.0, 0.0};
-        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Rr[v][k] = x[k];
-      }
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
         d4 z = {0.0, 0.0, 0.0, 0.0};
@@ -418,6 +419,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
   __shared__ __attribute__((aligned(16))) uint16_t fr[NF2 + NF3];
   __shared__ float h2s[WPB][16][kP2 + 1];
+  __shared__ float vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
     const uint16_t* src = A.fraglp + net * A.fo.per_net;
@@ -427,7 +429,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
       reinterpret_cast<u16x8*>(fr + NF2)[k] = reinterpret_cast<const u16x8*>(src + A.fo.F3n)[k];
   }
   __syncthreads();
-  const float* vec = A.vec32 + net * A.vec_per_net;
+  {
+    const float* vsrc = A.vec32 + net * A.vec_per_net;
+    for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
+  }
+  __syncthreads();
+  const float* vec = vs;
   float w1s[8], b1s[8], b2s[4][4];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -457,6 +464,17 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
       const int row = r0 + r16;
       const float s = (float)s_next;
       s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
+      // rows of the contraction, requested before layers 1-2 run
+      float Rr[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * g + v;
+        d4 x = {0.0, 0.0, 0.0, 0.0};
+        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
+      }
+
       float h1[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
@@ -475,15 +493,6 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * g + v] = h2[ot][v];
       wave_lds_sync();
-      float Rr[4][4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = r0 + 4 * g + v;
-        d4 x = {0.0, 0.0, 0.0, 0.0};
-        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
-      }
       typename P::vec8 a3[2];
 #pragma unroll
       for (int kt = 0; kt < 2; ++kt) {
@@ -538,6 +547,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
   __shared__ __attribute__((aligned(16))) uint16_t fr[NFR];
   __shared__ f4 gts[WPB][kP3];
+  __shared__ float vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
     const uint16_t* src = A.fraglp + net * A.fo.per_net;
@@ -552,7 +562,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
   }
   __syncthreads();
   constexpr int oF2 = 0, oF3 = 2048, oB3 = 2048 + 8192, oB2 = 2048 + 8192 + 8192;
-  const float* vec = A.vec32 + net * A.vec_per_net;
+  {
+    const float* vsrc = A.vec32 + net * A.vec_per_net;
+    for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
+  }
+  __syncthreads();
+  const float* vec = vs;
   float w1s[8], b1s[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
