@@ -209,98 +209,109 @@ __device__ __forceinline__ void epi_lp(const GemmArgs& g, const float* vec, int6
   }
 }
 
-// Half-precision GEMM.  A work-group of 4 waves covers 16 m-tiles (wave w:
-// tiles 16 by + 4w .. +3) and 16 NTW columns; the X tile of each 32-wide
-// k-step is loaded once per work-group into LDS (double-buffered), already
-// in B-fragment order, and shared by the 4 waves; each wave streams its own
-// weight fragments from memory (one 16-byte load per lane and m-tile).
+// Half-precision GEMM, 2D-tiled through LDS.  A work-group of 4 waves
+// (2 along M x 2 along N) computes a (32 MTW) x (32 NTW) output tile: wave
+// (wm, wn) owns MTW m-tiles x NTW n-tiles.  Each 32-wide k-step of the
+// weight tile (pre-arranged fragments, copied as they are) and of the X tile
+// (rearranged into B-fragment order on the way) is loaded once per
+// work-group into double-buffered LDS, so a weight fragment serves 2 NTW
+// n-tiles and an X fragment 2 MTW m-tiles.
 template <class P, int MTW, int NTW>
 __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
-  constexpr int BN = 16 * NTW;
-  __shared__ __attribute__((aligned(16))) uint16_t xs[2][NTW * 64 * 8];
+  constexpr int MB = 2 * MTW, NB = 2 * NTW;  // m-tiles, n-tiles per work-group
+  constexpr int BN = 16 * NB;
+  __shared__ __attribute__((aligned(16))) uint16_t as[2][MB * 512];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[2][NB * 512];
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
   const int c0 = blockIdx.x * BN;
   if (c0 >= n_t) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
   const int r16 = lane & 15, gq = lane >> 4;
   const int mtiles = g.M / 16;
-  const int mt0 = (blockIdx.y * 4 + wv) * MTW;
+  const int mb0 = blockIdx.y * MB;
   const int KT = g.K / 32;
   const uint16_t* Afr = reinterpret_cast<const uint16_t*>(g.Afr) + t * g.a_type_stride;
-  // copy role: thread (col, q) moves X[col][32 kt + 8q .. +7]; its two
-  // 4-value halves h land in lane (col % 16) + 16 (2 (q % 2) + h), elements
-  // 4 (q / 2) .. +3, of n-tile col / 16 (the k order of the fragments)
-  const int ccol = threadIdx.x >> 2, q = threadIdx.x & 3;
-  const bool copier = ccol < BN;
-  const uint16_t* xsrc = reinterpret_cast<const uint16_t*>(g.X) + (int64_t)(cb + c0 + ccol) * g.ldx + 8 * q;
-  const int d0 = (((ccol >> 4) * 64 + 32 * (q & 1) + (ccol & 15)) * 8) + 4 * (q >> 1);
-  const int d1 = d0 + 16 * 8;
-  auto gload = [&](int kt) {
-    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-    // the padded upper half of the last k-step may hold stale bits: zeros
-    if (copier && (q < 2 || 32 * kt + 16 < g.Kreal)) v = *reinterpret_cast<const u16x8*>(xsrc + 32 * kt);
-    return v;
-  };
-  auto lstore = [&](int buf, const u16x8 v) {
-    if (copier) {
-      *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{v[0], v[1], v[2], v[3]};
-      *reinterpret_cast<u16x4*>(&xs[buf][d1]) = u16x4{v[4], v[5], v[6], v[7]};
+  const uint16_t* X = reinterpret_cast<const uint16_t*>(g.X);
+  // weight copy: MB fragments of 64 lanes x 16 B per k-step; thread tid
+  // moves lane tid % 64 of fragments tid / 64 + 4u
+  constexpr int AU = (MB + 3) / 4;
+  // X copy: thread (col, q) moves X[col][32 kt + 8q .. +7] into lane
+  // (col % 16) + 16 (2 (q % 2) + h), elements 4 (q / 2) .. +3, of n-tile
+  // col / 16 (the k order of the fragments); BN * 4 / 256 columns each
+  constexpr int XU = (BN * 4 + 255) / 256;
+  auto load = [&](int kt, u16x8* av, u16x8* xv) {
+#pragma unroll
+    for (int u = 0; u < AU; ++u) {
+      const int f = (tid >> 6) + 4 * u;
+      av[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (f < MB && mb0 + f < mtiles)
+        av[u] = *reinterpret_cast<const u16x8*>(Afr + (((int64_t)(mb0 + f) * KT + kt) * 64 + lane) * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < XU; ++u) {
+      const int e = tid + 256 * u, col = e >> 2, q = e & 3;
+      xv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      // the padded upper half of the last k-step may hold stale bits: zeros
+      if (col < BN && (q < 2 || 32 * kt + 16 < g.Kreal))
+        xv[u] = *reinterpret_cast<const u16x8*>(X + (int64_t)(cb + c0 + col) * g.ldx + 32 * kt + 8 * q);
     }
   };
-  bool mval[MTW];
-  const uint16_t* arow[MTW];
+  auto store = [&](int buf, const u16x8* av, const u16x8* xv) {
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-    mval[mt] = mt0 + mt < mtiles;
-    arow[mt] = Afr + ((int64_t)(mval[mt] ? mt0 + mt : 0) * KT * 64 + lane) * 8;
-  }
-  auto aload = [&](int kt, u16x8* av) {
+    for (int u = 0; u < AU; ++u) {
+      const int f = (tid >> 6) + 4 * u;
+      if (f < MB) *reinterpret_cast<u16x8*>(&as[buf][(f * 64 + lane) * 8]) = av[u];
+    }
 #pragma unroll
-    for (int mt = 0; mt < MTW; ++mt)
-      if (mval[mt]) av[mt] = *reinterpret_cast<const u16x8*>(arow[mt] + (int64_t)kt * 512);
+    for (int u = 0; u < XU; ++u) {
+      const int e = tid + 256 * u, col = e >> 2, q = e & 3;
+      if (col < BN) {
+        const int d0 = (((col >> 4) * 64 + 32 * (q & 1) + (col & 15)) * 8) + 4 * (q >> 1);
+        *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{xv[u][0], xv[u][1], xv[u][2], xv[u][3]};
+        *reinterpret_cast<u16x4*>(&xs[buf][d0 + 128]) = u16x4{xv[u][4], xv[u][5], xv[u][6], xv[u][7]};
+      }
+    }
   };
   f4 acc[MTW][NTW];
 #pragma unroll
   for (int a = 0; a < MTW; ++a)
 #pragma unroll
     for (int b = 0; b < NTW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  u16x8 xr = gload(0);
-  u16x8 aa[MTW] = {};
-  aload(0, aa);
-  lstore(0, xr);
+  u16x8 ar[AU], xr[XU];
+  load(0, ar, xr);
+  store(0, ar, xr);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int buf = kt & 1;
-    u16x8 an[MTW] = {};
-    if (kt + 1 < KT) {
-      xr = gload(kt + 1);
-      aload(kt + 1, an);
-    }
-    u16x8 bb[NTW];
+    if (kt + 1 < KT) load(kt + 1, ar, xr);
+    u16x8 aa[MTW], bb[NTW];
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) bb[nt] = *reinterpret_cast<const u16x8*>(&xs[buf][(nt * 64 + lane) * 8]);
+    for (int mt = 0; mt < MTW; ++mt) aa[mt] = *reinterpret_cast<const u16x8*>(&as[buf][((wm * MTW + mt) * 64 + lane) * 8]);
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) bb[nt] = *reinterpret_cast<const u16x8*>(&xs[buf][((wn * NTW + nt) * 64 + lane) * 8]);
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
-      if (mval[mt])
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt)
-          acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]),
-                                __builtin_bit_cast(typename P::vec8, bb[nt]), acc[mt][nt]);
-    if (kt + 1 < KT) {
-      lstore(buf ^ 1, xr);
-#pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) aa[mt] = an[mt];
-    }
+      for (int nt = 0; nt < NTW; ++nt)
+        acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]), __builtin_bit_cast(typename P::vec8, bb[nt]),
+                              acc[mt][nt]);
+    if (kt + 1 < KT) store(buf ^ 1, ar, xr);
     __syncthreads();
   }
   const float* vec = reinterpret_cast<const float*>(g.vec) + t * g.vec_type_stride;
 #pragma unroll
   for (int mt = 0; mt < MTW; ++mt) {
-    if (!mval[mt]) break;
-    const int m0 = (mt0 + mt) * 16 + 4 * gq;
+    const int m = mb0 + wm * MTW + mt;
+    if (m >= mtiles) break;
+    const int m0 = m * 16 + 4 * gq;
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) epi_lp<P>(g, vec, (int64_t)(cb + c0 + nt * 16 + r16), m0, acc[mt][nt]);
+    for (int nt = 0; nt < NTW; ++nt) {
+      const int cl = c0 + (wn * NTW + nt) * 16;
+      if (cl < n_t) epi_lp<P>(g, vec, (int64_t)(cb + cl + r16), m0, acc[mt][nt]);
+    }
   }
 }
 
@@ -432,9 +443,9 @@ static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
 template <int MTW, int NTW>
 static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
-  const int BN = 16 * NTW;
+  const int BN = 32 * NTW;
   const int mtiles = g.M / 16;
-  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + 4 * MTW - 1) / (4 * MTW)),
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + 2 * MTW - 1) / (2 * MTW)),
             (unsigned)ntypes);
   if (grid.x == 0) return;
   if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW>), grid, dim3(256), 0, s, g);
@@ -443,12 +454,16 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
 
 // Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
 // (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the half-precision
-// GEMM does best with small 2x2 wave tiles (more work-groups in flight),
-// 4 waves sharing a 32-column X tile.
+// GEMM 2x2 per wave (64 x 64 per work-group; larger tiles leave too few
+// work-groups at these sizes).
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
-  if (mode != DP_FP64) gemm_launch_lp<2, 2>(c, g, mode, s);
-  else if (g.T || g.M > 256 || g.K > 256) gemm_launch_f64<3, 2, false>(c, g, s);
-  else gemm_launch_f64<3, 2, true>(c, g, s);
+  if (mode != DP_FP64) {
+    gemm_launch_lp<2, 2>(c, g, mode, s);
+  } else if (g.T || g.M > 256 || g.K > 256) {
+    gemm_launch_f64<3, 2, false>(c, g, s);
+  } else {
+    gemm_launch_f64<3, 2, true>(c, g, s);
+  }
 }
 
 static GemmArgs gemm_base(dp_ctx* c, int mode) {
