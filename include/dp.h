@@ -199,8 +199,11 @@ int dp_compute_batch(dp_ctx* ctx, const double* coords, const int32_t* types, co
  * dp_compute / dp_compute_batch on this context: grad_params [n_params]
  * device f64 receives sum_f dL/dE_f * dE_f/dtheta (overwritten, flat layout
  * of dp_model_n_params), for dL_dE [B] device f64 (B = frames of that
- * compute).  Needs the last compute in DP_FP64 (DP_ERR_UNSUPPORTED
- * otherwise) and its inputs unchanged; DP_ERR_STATE if no compute preceded.
+ * compute), with the compute's inputs unchanged; DP_ERR_STATE if no compute
+ * preceded.  After a mixed-precision compute the layer inputs, deltas and
+ * g_T of its half-precision passes are used (widened to FP64 for the
+ * weight-gradient reductions; the embedding nets are re-evaluated in FP64),
+ * so the result is the mixed model's gradient to mixed-precision accuracy.
  * Gradients are accumulated with atomics (summation order not fixed). */
 int dp_backward_params(dp_ctx* ctx, const double* dL_dE, double* grad_params, hipStream_t stream);
 

@@ -388,19 +388,17 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
     set_error("nframes %d out of [1, %d]", nframes, c->max_frames);
     return DP_ERR_CAPACITY;
   }
-  if (c->frames_ev_pending) {
-    HIPCHECK(hipEventSynchronize(c->frames_ev));
-    c->frames_ev_pending = false;
-  }
   const double rc = rlist;
   int64_t cells = 0, chunks = 0;
+  FrameInfo* F_new = c->frames_prev + c->max_frames;  // scratch half of the host copy
   for (int f = 0; f < nframes; ++f) {
     double L[3];
     int rcb = check_box(boxes + 9 * f, rc, L);
     if (rcb) return rcb;
     const int64_t a0 = off[f], a1 = off[f + 1];
     if (a0 < 0 || a1 < a0) { set_error("frame offsets must be non-decreasing from 0"); return DP_ERR_BAD_ARG; }
-    FrameInfo& F = c->frames_host[f];
+    FrameInfo& F = F_new[f];
+    memset(&F, 0, sizeof(F));
     F.atom_off = (int32_t)a0;
     F.natoms = (int32_t)(a1 - a0);
     F.cell_off = (int32_t)cells;
@@ -420,9 +418,19 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
   if (off[0] != 0) { set_error("frame_off[0] must be 0"); return DP_ERR_BAD_ARG; }
   if (off[nframes] > c->max_atoms) { set_error("%lld atoms exceed max_atoms %lld", (long long)off[nframes], (long long)c->max_atoms); return DP_ERR_CAPACITY; }
   if (cells > c->max_cells) { set_error("%lld cells exceed the context capacity %lld", (long long)cells, (long long)c->max_cells); return DP_ERR_CAPACITY; }
-  HIPCHECK(hipMemcpyAsync(c->frames_dev, c->frames_host, sizeof(FrameInfo) * nframes, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipEventRecord(c->frames_ev, s));
-  c->frames_ev_pending = true;
+  // upload only when the table differs from the one already on the device
+  if (nframes != c->nframes_dev || memcmp(F_new, c->frames_prev, sizeof(FrameInfo) * nframes) != 0) {
+    if (c->frames_ev_pending) {
+      HIPCHECK(hipEventSynchronize(c->frames_ev));
+      c->frames_ev_pending = false;
+    }
+    memcpy(c->frames_host, F_new, sizeof(FrameInfo) * nframes);
+    memcpy(c->frames_prev, F_new, sizeof(FrameInfo) * nframes);
+    c->nframes_dev = nframes;
+    HIPCHECK(hipMemcpyAsync(c->frames_dev, c->frames_host, sizeof(FrameInfo) * nframes, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipEventRecord(c->frames_ev, s));
+    c->frames_ev_pending = true;
+  }
   c->nframes_last = nframes;
   c->nchunks_last = (int32_t)chunks;
   *ncells = cells;
@@ -731,6 +739,8 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   {
     hipError_t e = hipHostMalloc((void**)&c->frames_host, sizeof(FrameInfo) * max_frames, hipHostMallocDefault);
     if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "hipHostMalloc(frames)"); }
+    c->frames_prev = new FrameInfo[2 * (size_t)max_frames];
+    c->nframes_dev = -1;
     e = hipHostMalloc((void**)&c->flags_host, sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) { dp_ctx_destroy(c); return hip_fail(e, "hipHostMalloc(flags)"); }
     e = hipEventCreateWithFlags(&c->frames_ev, hipEventDisableTiming);
@@ -819,6 +829,7 @@ int dp_ctx_destroy(dp_ctx* c) {
     if (c->fa[k]) (void)hipFree(c->fa[k]);
   dp_ctx_profile(c, 0);
   if (c->frames_host) (void)hipHostFree(c->frames_host);
+  delete[] c->frames_prev;
   if (c->flags_host) (void)hipHostFree(c->flags_host);
   if (c->frames_ev) (void)hipEventDestroy(c->frames_ev);
   delete c;
@@ -868,14 +879,53 @@ int dp_compute_batch(dp_ctx* c, const double* coords, const int32_t* types, cons
 int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipStream_t stream) {
   if (!c || !dL_dE || !grad_params) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
   if (!c->have_state) { set_error("dp_backward_params needs a preceding dp_compute"); return DP_ERR_STATE; }
-  if (c->mode_last != DP_FP64) {
-    set_error("parameter gradients need a preceding DP_FP64 compute");
-    return DP_ERR_UNSUPPORTED;
-  }
   int rc;
   if ((rc = set_device(c->device))) return rc;
-  launch_descriptor_ex(c, DP_FP64, true, stream);  // D is only formed inside the GEMM on the force path
-  launch_param_grads(c, dL_dE, grad_params, stream);
+  const dp_model* m = c->model;
+  const int fw = m->fw, nd = m->nd, fwp = ((fw + 31) / 32) * 32;
+  ParamGradInputs in;
+  in.ldz = fw;
+  if (c->mode_last == DP_FP64) {
+    launch_descriptor_ex(c, DP_FP64, true, stream);  // D is only formed inside the GEMM on the force path
+    in.X[0] = (const double*)c->D;
+    in.X[1] = (const double*)c->fa[0];
+    in.X[2] = (const double*)c->fa[2];
+    in.dz[0] = (const double*)c->fa[8];
+    in.dz[1] = (const double*)c->fa[7];
+    in.dz[2] = (const double*)c->fa[5];
+    in.h3 = (const double*)c->fa[4];
+    in.gT = (const double*)c->gT;
+  } else {
+    // mixed: the layer inputs, deltas and g_T of the mixed-precision passes,
+    // widened to FP64 into buffers the force path no longer needs; the
+    // weight-gradient reductions then run in FP64
+    const int lp = c->mode_last == DP_MIX_BF16 ? 1 : 2;
+    const int64_t cols = c->natoms_last + (int64_t)m->desc.ntypes * kColPad;
+    double* D64 = (double*)c->dD;
+    double* f64[6] = {(double*)c->fa[1], (double*)c->fa[3], (double*)c->fa[10],
+                      (double*)c->fa[11], (double*)c->fa[5], (double*)c->fa[6]};
+    launch_widen(c->D, lp, nd, D64, nd, nd, cols, stream);
+    launch_widen(c->fa[0], 0, fwp, f64[0], fw, fw, cols, stream);  // h1
+    launch_widen(c->fa[2], 0, fwp, f64[1], fw, fw, cols, stream);  // h2
+    launch_widen(c->fa[4], 0, fwp, f64[2], fw, fw, cols, stream);  // h3
+    launch_widen(c->fa[9], lp, fwp, f64[3], fw, fw, cols, stream);  // dz1
+    launch_widen(c->fa[8], lp, fwp, f64[4], fw, fw, cols, stream);  // dz2
+    launch_widen(c->fa[7], lp, fwp, f64[5], fw, fw, cols, stream);  // dz3
+    double* gT64 = (double*)c->Tpart;
+    launch_widen(c->gT, 0, m->m1 * 4, gT64, m->m1 * 4, m->m1 * 4, cols, stream);
+    in.X[0] = D64;
+    in.X[1] = f64[0];
+    in.X[2] = f64[1];
+    in.h3 = f64[2];
+    in.dz[0] = f64[3];
+    in.dz[1] = f64[4];
+    in.dz[2] = f64[5];
+    in.gT = gT64;
+  }
+  in.ldx[0] = nd;
+  in.ldx[1] = fw;
+  in.ldx[2] = fw;
+  launch_param_grads(c, in, dL_dE, grad_params, stream);
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }

@@ -99,6 +99,8 @@ struct dp_ctx {
   // frame table
   dpse::FrameInfo* frames_dev;
   dpse::FrameInfo* frames_host;  // pinned staging
+  dpse::FrameInfo* frames_prev;  // host copy of the table on the device
+  int32_t nframes_dev;           // entries of that table (-1: none)
   hipEvent_t frames_ev;
   bool frames_ev_pending;
   int32_t nframes_last;
@@ -211,8 +213,21 @@ void launch_kick_drift(dp_ctx* c, double* x, double* v, const double* f, const i
 void launch_wrap(dp_ctx* c, double* x, int32_t n, const double L[3], int32_t* images, hipStream_t s);
 void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, int32_t n, double dt, double* ke,
                  hipStream_t s);
-// parameter gradients (FP64 state of the last compute)
-void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t s);
+// parameter gradients from the state of the last compute, in FP64: the layer
+// inputs X_l and deltas dz_l of the fitting net (columns, leading dims ldx/ldz)
+// and g_T; FP64 computes pass their own buffers, mixed ones widened copies
+struct ParamGradInputs {
+  const double* X[3];
+  int ldx[3];
+  const double* dz[3];
+  const double* h3;
+  int ldz;
+  const double* gT;
+};
+void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE, double* grad, hipStream_t s);
+// widens a [rows][width] block of FP32 (kind 0), BF16 (1) or FP16 (2) values
+void launch_widen(const void* src, int kind, int ld_src, double* dst, int ld_dst, int width, int64_t rows,
+                  hipStream_t s);
 // inspection
 void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, double* dst, hipStream_t s);
 

@@ -388,7 +388,29 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
 }
 
 // ------------------------------------------------------------ launcher
-void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t s) {
+__global__ void k_widen(const void* __restrict__ src, int kind, int ld_src, double* __restrict__ dst, int ld_dst,
+                        int width, int64_t rows) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rows * width) return;
+  const int64_t r = q / width;
+  const int k = (int)(q - r * width);
+  const int64_t si = r * ld_src + k;
+  double v;
+  if (kind == 0) v = (double)static_cast<const float*>(src)[si];
+  else if (kind == 1) v = (double)PrecBF16::tof(static_cast<const uint16_t*>(src)[si]);
+  else v = (double)PrecF16::tof(static_cast<const uint16_t*>(src)[si]);
+  dst[r * ld_dst + k] = v;
+}
+
+void launch_widen(const void* src, int kind, int ld_src, double* dst, int ld_dst, int width, int64_t rows,
+                  hipStream_t s) {
+  const int64_t n = rows * width;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, kind, ld_src, dst, ld_dst, width,
+                     rows);
+}
+
+void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE, double* grad, hipStream_t s) {
   const dp_model* m = c->model;
   const int n = (int)c->natoms_last;
   const int nt = m->desc.ntypes;
@@ -402,16 +424,13 @@ void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t
   int chunk = n / 16 + 1;
   chunk = chunk < 512 ? 512 : chunk;
   const int nchunks = (n + chunk - 1) / chunk;
-  const double* X[3] = {(const double*)c->D, (const double*)c->fa[0], (const double*)c->fa[2]};
-  const int ldX[3] = {nd, fw, fw};
   const int Kin[3] = {nd, fw, fw};
-  const double* DZ[3] = {(const double*)c->fa[8], (const double*)c->fa[7], (const double*)c->fa[5]};
   for (int l = 0; l < 3; ++l) {
     WGradArgs a = {};
-    a.X = X[l];
-    a.ldx = ldX[l];
-    a.Y = DZ[l];
-    a.ldy = fw;
+    a.X = in.X[l];
+    a.ldx = in.ldx[l];
+    a.Y = in.dz[l];
+    a.ldy = in.ldz;
     a.w = c->gE_col;
     a.meta = c->type_meta;
     a.M = Kin[l];
@@ -422,12 +441,12 @@ void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t
     a.out_off = m->fit_param_off[l];
     dim3 grid(nchunks, (Kin[l] / 16 + 3) / 4, nt);
     hipLaunchKernelGGL((k_wgrad_cols<16>), grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, DZ[l], fw, c->gE_col, c->type_meta, fw,
-                       chunk, grad, m->fit_param_stride, m->fit_param_off[3 + l]);
+    hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, in.dz[l], in.ldz, c->gE_col, c->type_meta,
+                       fw, chunk, grad, m->fit_param_stride, m->fit_param_off[3 + l]);
   }
   // w_out: sum w h3; b_out and e_bias: sum w
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)c->fa[4], fw, c->gE_col,
-                     c->type_meta, fw, chunk, grad, m->fit_param_stride, m->fit_param_off[6]);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, in.h3, in.ldz, c->gE_col, c->type_meta, fw,
+                     chunk, grad, m->fit_param_stride, m->fit_param_off[6]);
   hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
                      c->type_meta, 1, chunk, grad, m->fit_param_stride, m->fit_param_off[7]);
   hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
@@ -442,7 +461,7 @@ void launch_param_grads(dp_ctx* c, const double* dLdE, double* grad, hipStream_t
   A.vec64 = m->emb_vec64;
   A.vec_per_net = m->emb_vec_per_net;
   A.fo = m->efo;
-  A.gT = (const double*)c->gT;
+  A.gT = in.gT;
   A.wcol = c->gE_col;
   A.grad = grad;
   for (int k = 0; k < nt * nt; ++k)

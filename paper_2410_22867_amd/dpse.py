@@ -334,22 +334,25 @@ def _autograd():
         """Frame energies E_f of a batch as a differentiable function of the
         flat parameter vector and the coordinates.
 
-        forward(params, coords, types, boxes, frame_off, ctx, nlist) -> E [B]
+        forward(params, coords, types, boxes, frame_off, ctx, nlist, mode) -> E [B]
         backward(gE) -> (dL/dparams via dp_backward_params, dL/dcoords = -F gE_f)
+
+        mode is "fp64", "bf16" or "fp16" (the mixed forms give the mixed
+        model's energies, forces and parameter gradients).
 
         The model of ``ctx`` is updated from ``params`` when they changed since
         the last call.  Backward must run before another compute on ``ctx``.
         """
 
         @staticmethod
-        def forward(fctx, params, coords, types, boxes, frame_off, dctx, nlist):
+        def forward(fctx, params, coords, types, boxes, frame_off, dctx, nlist, mode="fp64"):
             model = dctx.model
             p = params.detach()
             key = (p.data_ptr(), p._version)
             if getattr(model, "_param_key", None) != key:
                 model.set_params(p.cpu().numpy())
                 model._param_key = key
-            r = dctx.compute_batch(coords.detach(), types, boxes, frame_off, nlist, mode="fp64")
+            r = dctx.compute_batch(coords.detach(), types, boxes, frame_off, nlist, mode=mode)
             fctx.dctx = dctx
             fctx.frame_off = np.asarray(frame_off, dtype=np.int64)
             fctx.save_for_backward(r["F"])
@@ -363,7 +366,7 @@ def _autograd():
             sizes = torch.as_tensor(np.diff(fctx.frame_off), device=gE.device)
             gatom = torch.repeat_interleave(gE, sizes)
             gcoords = -F * gatom[:, None]
-            return gparams, gcoords, None, None, None, None, None
+            return gparams, gcoords, None, None, None, None, None, None
 
     return DPEnergy
 
@@ -371,9 +374,9 @@ def _autograd():
 _DPEnergy = None
 
 
-def dp_energy(params, coords, types, boxes, frame_off, ctx: Context, nlist):
+def dp_energy(params, coords, types, boxes, frame_off, ctx: Context, nlist, mode: str = "fp64"):
     """Differentiable batch energies (see DPEnergy)."""
     global _DPEnergy
     if _DPEnergy is None:
         _DPEnergy = _autograd()
-    return _DPEnergy.apply(params, coords, types, boxes, frame_off, ctx, nlist)
+    return _DPEnergy.apply(params, coords, types, boxes, frame_off, ctx, nlist, mode)

@@ -121,3 +121,38 @@ def test_param_grads_finite_differences(batch):
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
     b["model"].set_params(b["p"])
+
+
+@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01)])
+def test_mixed_param_grads_close_to_oracle(batch, mode, tol):
+    """Mixed-precision form of the training step: energies, forces and
+    parameter gradients of the mixed model, compared with the FP64 oracle
+    (error stated; bounded by tol of the largest gradient entry)."""
+    b = batch
+    from paper_2410_22867_amd import dpse
+    params = torch.tensor(b["p"], device=b["dev"], requires_grad=True)
+    coords = b["x"].clone().requires_grad_(True)
+    E = dpse.dp_energy(params, coords, b["t"], b["boxes"], b["off"], b["ctx"], b["nl"], mode)
+    tgt = torch.tensor(b["targets"], device=b["dev"])
+    L = ((E - tgt) ** 2).mean()
+    L.backward()
+    torch.cuda.synchronize()
+    g = params.grad.cpu().numpy()
+    Em = E.detach().cpu().numpy()
+    B = len(b["frames"])
+    want = np.zeros_like(g)
+    for f, fr in enumerate(b["frames"]):
+        o = oracle.compute(fr.coords, fr.types, fr.box, b["desc"], b["p"], grad_scale=2.0 * (Em[f] - b["targets"][f]) / B)
+        want += o["grad"]
+    scale = np.abs(want).max()
+    rel = np.abs(g - want).max() / scale
+    _say(mode, "param grad max error / max |grad|", rel)
+    assert np.isfinite(g).all()
+    assert rel <= tol
+    # the coordinate gradient is -F of the mixed model times dL/dE_f
+    r = b["ctx"].compute_batch(b["x"], b["t"], b["boxes"], b["off"], b["nl"], mode=mode)
+    F = r["F"].cpu().numpy()
+    gx = coords.grad.cpu().numpy()
+    for f in range(B):
+        a0, a1 = b["off"][f], b["off"][f + 1]
+        assert np.allclose(gx[a0:a1], -F[a0:a1] * 2.0 * (Em[f] - b["targets"][f]) / B, atol=1e-12)
