@@ -76,7 +76,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="water12k", choices=["water192", "water12k", "copper32k", "water98k"])
+    ap.add_argument("--workload", default="water12k",
+                    choices=["water192", "water12k", "copper32k", "water98k", "waterbatch64"])
     ap.add_argument("--modes", default="fp64,bf16,fp16")
     ap.add_argument("--nve-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -100,6 +101,9 @@ def main():
     from paper_2410_22867_amd import dpse, inputs as I
 
     dev = torch.device("cuda:0")
+    if args.workload == "waterbatch64":
+        bench_batch(args, torch, dpse, I, dev)
+        return
     fr, desc, params, dt = I.workload(args.workload)
     wl_index = {"water192": 0, "water12k": 1, "copper32k": 2, "water98k": 3}[args.workload]
     n = fr.n
@@ -318,6 +322,78 @@ def main():
         "status_flags": status_flags,
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, torch, dpse, I, dev):
+    """Training step on a batch of 64 water frames of uneven size: energies,
+    forces and the parameter gradient of L = (1/B) sum_f (E_f - Ehat_f)^2,
+    per mode.  The neighbour lists are built once (static frames)."""
+    (frames, targets), desc, params, _ = I.workload("waterbatch64")
+    sizes = [f.n for f in frames]
+    off = dpse.frame_offsets(sizes)
+    n = int(off[-1])
+    B = len(frames)
+    x = torch.tensor(np.concatenate([f.coords for f in frames]), device=dev)
+    t = torch.tensor(np.concatenate([f.types for f in frames]), device=dev)
+    boxes = np.stack([f.box for f in frames])
+    tgt = torch.tensor(targets, device=dev)
+    model = dpse.Model(desc, params)
+    ctx = dpse.Context(model, n, max_frames=B, budget_bytes=int(args.workspace_gib * 2 ** 30))
+    nl, ov = ctx.build_nlist_batch(x, t, boxes, off)
+    grad = torch.empty(model.n_params, dtype=torch.float64, device=dev)
+
+    def step(mode, gE=None):
+        r = ctx.compute_batch(x, t, boxes, off, nl, mode=mode)
+        g = gE if gE is not None else 2.0 * (r["E"] - tgt) / B
+        ctx.backward_params(g, grad)
+        return r
+
+    results, grads, ener = {}, {}, {}
+    gE_ref = None
+    for mode in args.modes.split(","):
+        for _ in range(args.warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        results[mode] = dict(ms_per_step=el / args.steps * 1e3, atom_steps_per_s=n * args.steps / el,
+                             frames_per_s=B * args.steps / el)
+        print(f"# {mode}: {el / args.steps * 1e3:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s",
+              file=sys.stderr, flush=True)
+        r = step(mode)
+        if gE_ref is None:
+            gE_ref = (2.0 * (r["E"] - tgt) / B).clone()
+        r = step(mode, gE_ref)  # the same dL/dE for every mode: gradients compare like for like
+        torch.cuda.synchronize()
+        grads[mode] = grad.cpu().numpy().copy()
+        ener[mode] = (r["E"].cpu().numpy().copy(), r["F"].cpu().numpy().copy())
+    acc = {}
+    if "fp64" in grads:
+        gref = grads["fp64"]
+        E64, F64 = ener["fp64"]
+        for mode in grads:
+            if mode == "fp64":
+                continue
+            Em, Fm = ener[mode]
+            acc[mode] = dict(grad_max_err_rel=float(np.abs(grads[mode] - gref).max() / np.abs(gref).max()),
+                             E_meV_per_atom=float((np.abs(Em - E64) / np.asarray(sizes)).max() * 1e3),
+                             F_rms_meV_per_A=float(np.sqrt(((Fm - F64) ** 2).mean()) * 1e3))
+    line = {
+        "metric": "DP training step (E, F, dL/dtheta) atom-steps/s, 64-frame water batch",
+        "value": round(results[next(iter(results))]["atom_steps_per_s"], 1),
+        "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(results[next(iter(results))]["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "waterbatch64", "frames": B, "natoms": n, "min_atoms": min(sizes),
+                   "max_atoms": max(sizes), "step": "batched E/F/W + parameter gradient of the energy MSE loss"},
+        "modes": {m: {k: round(v, 4) for k, v in r.items()} for m, r in results.items()},
+        "mixed_vs_fp64": acc,
+        "status_flags": ctx.status(),
     }
     print(json.dumps(line), flush=True)
 

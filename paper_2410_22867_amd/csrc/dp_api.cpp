@@ -776,6 +776,17 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->Ei_atom, N);
   ALLOC(c->gE_col, C);
   ALLOC(c->grad_tmp, m->n_params);
+  {
+    // parameter-gradient workspace: per-chunk partials of the fitting
+    // reductions, per-work-group records of the embedding reductions
+    int64_t fch = N / 1024, slots = N / 128;
+    c->grad_chunks = (int32_t)(fch < 1 ? 1 : (fch > 16 ? 16 : fch));
+    c->grad_slots = (int32_t)(slots < 1 ? 1 : (slots > 256 ? 256 : slots));
+    const int64_t nt = m->desc.ntypes;
+    const int64_t fit = nt * c->grad_chunks * (int64_t)nd * m->fw;
+    const int64_t emb = nt * nt * c->grad_slots * 10496LL;
+    ALLOC(c->gpart, fit > emb ? fit : emb);
+  }
   double* tmp = nullptr;
   ALLOC(tmp, (int64_t)m->desc.ntypes * C * m1 * 4); c->Tpart = tmp;
   ALLOC(tmp, C * m1 * 4); c->T = tmp;
@@ -822,7 +833,8 @@ int dp_ctx_destroy(dp_ctx* c) {
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
                   c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
-                  c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref};
+                  c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
+                  c->gpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)

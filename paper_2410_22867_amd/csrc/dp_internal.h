@@ -163,6 +163,9 @@ struct dp_ctx {
   // parameter-gradient scratch
   double* gE_col;          // [cols]
   double* grad_tmp;        // [n_params]
+  double* gpart;           // partial sums of the parameter-gradient reductions
+  int32_t grad_chunks;     // column chunks per type of the fitting reductions
+  int32_t grad_slots;      // work-group records per net of the embedding reductions
   // opt-in stage timing
   hipEvent_t* prof_ev;     // [2 * prof_cap]
   int32_t* prof_stage;     // [prof_cap]

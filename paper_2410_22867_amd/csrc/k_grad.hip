@@ -6,13 +6,14 @@
 // unit-seed deltas stored by the force backward are reused where they exist.
 //
 // Fitting weights:   dW_l = sum_col X_l[col]^T w_col dz_l[col]  (column
-//   reduction; MFMA with columns along K, split over column chunks,
-//   accumulated with global atomics).
+//   reduction; MFMA with columns along K, split over column chunks whose
+//   partial sums are written to a workspace and summed in chunk order).
 // Embedding weights: the backward of each neighbour row is recomputed (as in
 //   the force path, with g_T scaled by w_col); per 16-row tile the activations
 //   and deltas are transposed through LDS so that the reduction over rows is
-//   an MFMA product, accumulated in per-work-group LDS sums and added to the
-//   global gradient once per work-group.
+//   an MFMA product, accumulated in per-work-group LDS sums that are written
+//   to the workspace and summed in work-group order.  No global atomics: the
+//   gradient is deterministic.
 #include "dp_internal.h"
 #include "dp_device.h"
 
@@ -36,10 +37,8 @@ struct WGradArgs {
   const double* Y;  int ldy;
   const double* w;
   const int32_t* meta;
-  int M, N, chunk;
-  double* out;      // gradient of type 0; type stride below
-  int64_t out_type_stride;
-  int64_t out_off;  // offset of this block inside the type's parameters
+  int M, N, chunk, nchunks;
+  double* part;     // [type][chunk][M][N] partial sums
 };
 
 template <int NTMAX>
@@ -57,20 +56,25 @@ __global__ __launch_bounds__(256) void k_wgrad_cols(WGradArgs a) {
   d4 acc[NTMAX];
 #pragma unroll
   for (int k = 0; k < NTMAX; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int c = c0; c < c1; c += 4) {
-    const int col = cb + c + g;
-    const bool ok = c + g < c1;
-    const double wc = ok ? a.w[col] : 0.0;
-    const double xa = ok ? a.X[(int64_t)col * a.ldx + mt * 16 + r16] * wc : 0.0;
+  for (int c = c0; c < c1; c += 8) {  // two k-steps of 4 columns per trip, loads first
+    double xa[2], yb[2][NTMAX];
 #pragma unroll
-    for (int nt = 0; nt < NTMAX; ++nt) {
-      if (nt < ntiles) {
-        const double yb = ok ? a.Y[(int64_t)col * a.ldy + nt * 16 + r16] : 0.0;
-        acc[nt] = mfma_f64(xa, yb, acc[nt]);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int col = cb + c + 4 * h + g;
+      const bool ok = c + 4 * h + g < c1;
+      const double wc = ok ? a.w[col] : 0.0;
+      xa[h] = ok ? a.X[(int64_t)col * a.ldx + mt * 16 + r16] * wc : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < NTMAX; ++nt)
+        yb[h][nt] = (ok && nt < ntiles) ? a.Y[(int64_t)col * a.ldy + nt * 16 + r16] : 0.0;
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nt = 0; nt < NTMAX; ++nt)
+        if (nt < ntiles) acc[nt] = mfma_f64(xa[h], yb[h][nt], acc[nt]);
   }
-  double* out = a.out + t * a.out_type_stride + a.out_off;
+  double* out = a.part + ((int64_t)t * a.nchunks + blockIdx.x) * a.M * a.N;
 #pragma unroll
   for (int nt = 0; nt < NTMAX; ++nt) {
     if (nt < ntiles)
@@ -78,28 +82,51 @@ __global__ __launch_bounds__(256) void k_wgrad_cols(WGradArgs a) {
       for (int v = 0; v < 4; ++v) {
         const int m = mt * 16 + 4 * v + g;
         const int n = nt * 16 + r16;
-        atomicAdd(&out[(int64_t)m * a.N + n], acc[nt][v]);
+        out[(int64_t)m * a.N + n] = acc[nt][v];
       }
   }
 }
 
+// out[t][e] = sum over the chunks that hold columns of type t of part[t][c][e]
+__global__ void k_sum_chunks(const double* __restrict__ part, const int32_t* __restrict__ meta, int chunk,
+                             int nchunks, int E, double* __restrict__ out, int64_t out_type_stride, int64_t out_off) {
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int used = (meta[2 * t] + chunk - 1) / chunk;
+  const double* p = part + (int64_t)t * nchunks * E + e;
+  double acc = 0.0;
+  for (int c = 0; c < used; ++c) acc += p[(int64_t)c * E];
+  out[t * out_type_stride + out_off + e] = acc;
+}
+
 // bias-type reductions: out[n] += sum_col w[col] Y[col][n] (Y == nullptr: 1)
+// bias-type partial sums: part[t][chunk][n] = sum_col w[col] Y[col][n]
+// (Y == nullptr: 1); a work-group of 4 waves splits the chunk's columns
+// four ways and adds the quarters in LDS in a fixed order
 __global__ __launch_bounds__(256) void k_bgrad_cols(const double* __restrict__ Y, int ldy, const double* __restrict__ w,
-                                                    const int32_t* __restrict__ meta, int N, int chunk,
-                                                    double* __restrict__ out, int64_t out_type_stride,
-                                                    int64_t out_off) {
+                                                    const int32_t* __restrict__ meta, int N, int chunk, int nchunks,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4][256];
   const int t = blockIdx.z;
   const int n_t = meta[2 * t], cb = meta[2 * t + 1];
   const int c0 = blockIdx.x * chunk;
   if (c0 >= n_t) return;
   const int c1 = min(n_t, c0 + chunk);
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+  const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+  double* out = part + ((int64_t)t * nchunks + blockIdx.x) * N;
+  for (int n0 = 0; n0 < N; n0 += 64) {
+    const int n = n0 + l;
     double acc = 0.0;
-    for (int c = c0; c < c1; ++c) {
-      const int64_t col = cb + c;
-      acc += w[col] * (Y ? Y[col * ldy + n] : 1.0);
-    }
-    atomicAdd(&out[t * out_type_stride + out_off + n], acc);
+    if (n < N)
+      for (int c = c0 + q; c < c1; c += 4) {
+        const int64_t col = cb + c;
+        acc += w[col] * (Y ? Y[col * ldy + n] : 1.0);
+      }
+    red[q][l] = acc;
+    __syncthreads();
+    if (q == 0 && n < N) out[n] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+    __syncthreads();
   }
 }
 
@@ -116,6 +143,8 @@ struct EGradArgs {
   const double* gT;
   const double* wcol;
   double* grad;
+  double* part;     // [net][slot][kEgRec] partial records
+  int nslots;
   int64_t offW[kMaxT * kMaxT][3], offB[kMaxT * kMaxT][3];
   int ntypes, nm, items;
   int sec[kMaxT + 1];
@@ -133,6 +162,9 @@ __device__ __forceinline__ int e_feat3(int p) {
 }
 
 constexpr int kGWPB = 2;
+// partial record of one work-group (slot-indexed): W3 | W2 | b3 | b2 | b1 | W1
+constexpr int kEgW3 = 0, kEgW2 = 64 * 128, kEgB3 = kEgW2 + 32 * 64, kEgB2 = kEgB3 + 128, kEgB1 = kEgB2 + 64,
+              kEgW1 = kEgB1 + 32, kEgRec = kEgW1 + 32;
 
 template <int W>
 __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
@@ -362,29 +394,52 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
     }
   }
   __syncthreads();
-  // slot-indexed block sums -> global gradient (feature-indexed)
-  double* gW3 = A.grad + A.offW[net][2];
-  double* gW2 = A.grad + A.offW[net][1];
-  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) {
-    const int fi = e_feat2<W>(k >> 7), fo = e_feat3<W>(k & 127);
-    if (fi >= 0 && fo >= 0) atomicAdd(&gW3[fi * 4 * W + fo], aW3[k]);
-  }
-  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) {
-    const int fi = e_feat1<W>(k >> 6), fo = e_feat2<W>(k & 63);
-    if (fi >= 0 && fo >= 0) atomicAdd(&gW2[fi * 2 * W + fo], aW2[k]);
-  }
+  // slot-indexed block sums -> this work-group's partial record
+  double* pr = A.part + ((int64_t)net * A.nslots + blockIdx.x) * kEgRec;
+  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) pr[kEgW3 + k] = aW3[k];
+  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) pr[kEgW2 + k] = aW2[k];
   for (int k = threadIdx.x; k < 128; k += 64 * kGWPB) {
-    const int f3 = e_feat3<W>(k);
-    if (f3 >= 0) atomicAdd(&A.grad[A.offB[net][2] + f3], aB3[k]);
-    if (k < 64) {
-      const int f2 = e_feat2<W>(k);
-      if (f2 >= 0) atomicAdd(&A.grad[A.offB[net][1] + f2], aB2[k]);
-    }
-    if (k < 32 && k < W) {
-      atomicAdd(&A.grad[A.offB[net][0] + k], aB1[k]);
-      atomicAdd(&A.grad[A.offW[net][0] + k], aW1[k]);
+    pr[kEgB3 + k] = aB3[k];
+    if (k < 64) pr[kEgB2 + k] = aB2[k];
+    if (k < 32) {
+      pr[kEgB1 + k] = aB1[k];
+      pr[kEgW1 + k] = aW1[k];
     }
   }
+}
+
+// sums the partial records of the work-groups that held columns, in
+// work-group order, and maps slots to the flat parameter layout
+template <int W>
+__global__ void k_egrad_reduce(EGradArgs A) {
+  const int net = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kEgRec) return;
+  const int ti = net / A.ntypes;
+  const int used = (A.meta[2 * ti] + kGWPB * A.items - 1) / (kGWPB * A.items);
+  int dst = -1;
+  if (k < kEgW2) {
+    const int fi = e_feat2<W>(k >> 7), fo = e_feat3<W>(k & 127);
+    if (fi >= 0 && fo >= 0) dst = (int)A.offW[net][2] + fi * 4 * W + fo;
+  } else if (k < kEgB3) {
+    const int kk = k - kEgW2, fi = e_feat1<W>(kk >> 6), fo = e_feat2<W>(kk & 63);
+    if (fi >= 0 && fo >= 0) dst = (int)A.offW[net][1] + fi * 2 * W + fo;
+  } else if (k < kEgB2) {
+    const int f3 = e_feat3<W>(k - kEgB3);
+    if (f3 >= 0) dst = (int)A.offB[net][2] + f3;
+  } else if (k < kEgB1) {
+    const int f2 = e_feat2<W>(k - kEgB2);
+    if (f2 >= 0) dst = (int)A.offB[net][1] + f2;
+  } else if (k < kEgW1) {
+    if (k - kEgB1 < W) dst = (int)A.offB[net][0] + (k - kEgB1);
+  } else {
+    if (k - kEgW1 < W) dst = (int)A.offW[net][0] + (k - kEgW1);
+  }
+  if (dst < 0) return;
+  const double* p = A.part + (int64_t)net * A.nslots * kEgRec + k;
+  double acc = 0.0;
+  for (int c = 0; c < used; ++c) acc += p[(int64_t)c * kEgRec];
+  A.grad[dst] = acc;
 }
 
 // ------------------------------------------------------------ launcher
@@ -420,11 +475,17 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
   hipLaunchKernelGGL(k_col_weights, dim3((ncols + 255) / 256), dim3(256), 0, s, c->atom_at, c->frame_of, dLdE,
                      c->gE_col, ncols);
   // ---- fitting: per layer dW = X^T diag(w) dz, db = sum w dz; w_out, b_out, e_bias
+  // Column chunks of a type write partial sums into the workspace, which the
+  // next kernel sums in chunk order; launches on one stream reuse it in turn.
   const int fw = m->fw, nd = m->nd;
-  int chunk = n / 16 + 1;
-  chunk = chunk < 512 ? 512 : chunk;
-  const int nchunks = (n + chunk - 1) / chunk;
+  const int nch = c->grad_chunks;
+  int chunk = (n + nch - 1) / nch;
+  chunk = chunk < 64 ? 64 : chunk;
   const int Kin[3] = {nd, fw, fw};
+  auto sum_chunks = [&](int E, int64_t stride, int64_t off) {
+    hipLaunchKernelGGL(k_sum_chunks, dim3((E + 255) / 256, nt), dim3(256), 0, s, c->gpart, c->type_meta, chunk, nch,
+                       E, grad, stride, off);
+  };
   for (int l = 0; l < 3; ++l) {
     WGradArgs a = {};
     a.X = in.X[l];
@@ -436,21 +497,25 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     a.M = Kin[l];
     a.N = fw;
     a.chunk = chunk;
-    a.out = grad;
-    a.out_type_stride = m->fit_param_stride;
-    a.out_off = m->fit_param_off[l];
-    dim3 grid(nchunks, (Kin[l] / 16 + 3) / 4, nt);
+    a.nchunks = nch;
+    a.part = c->gpart;
+    dim3 grid(nch, (Kin[l] / 16 + 3) / 4, nt);
     hipLaunchKernelGGL((k_wgrad_cols<16>), grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, in.dz[l], in.ldz, c->gE_col, c->type_meta,
-                       fw, chunk, grad, m->fit_param_stride, m->fit_param_off[3 + l]);
+    sum_chunks(Kin[l] * fw, m->fit_param_stride, m->fit_param_off[l]);
+    hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, in.dz[l], in.ldz, c->gE_col, c->type_meta, fw,
+                       chunk, nch, c->gpart);
+    sum_chunks(fw, m->fit_param_stride, m->fit_param_off[3 + l]);
   }
   // w_out: sum w h3; b_out and e_bias: sum w
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, in.h3, in.ldz, c->gE_col, c->type_meta, fw,
-                     chunk, grad, m->fit_param_stride, m->fit_param_off[6]);
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
-                     c->type_meta, 1, chunk, grad, m->fit_param_stride, m->fit_param_off[7]);
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nchunks, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
-                     c->type_meta, 1, chunk, grad, 1, m->ebias_off);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, in.h3, in.ldz, c->gE_col, c->type_meta, fw, chunk,
+                     nch, c->gpart);
+  sum_chunks(fw, m->fit_param_stride, m->fit_param_off[6]);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
+                     c->type_meta, 1, chunk, nch, c->gpart);
+  sum_chunks(1, m->fit_param_stride, m->fit_param_off[7]);
+  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
+                     c->type_meta, 1, chunk, nch, c->gpart);
+  sum_chunks(1, 1, m->ebias_off);
   // ---- embedding nets
   EGradArgs A = {};
   A.atom_at = c->atom_at;
@@ -464,6 +529,8 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
   A.gT = in.gT;
   A.wcol = c->gE_col;
   A.grad = grad;
+  A.part = c->gpart;
+  A.nslots = c->grad_slots;
   for (int k = 0; k < nt * nt; ++k)
     for (int l = 0; l < 3; ++l) {
       A.offW[k][l] = m->emb_param_off[k][2 * l];
@@ -471,15 +538,21 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     }
   A.ntypes = nt;
   A.nm = m->nm;
-  int items = (int)((int64_t)n * nt / (1024LL * kGWPB));
-  items = items < 1 ? 1 : (items > 32 ? 32 : items);
-  A.items = items;
+  // columns per wave such that a type's columns need at most nslots work-groups
+  int items = (n + kGWPB * A.nslots - 1) / (kGWPB * A.nslots);
+  A.items = items < 1 ? 1 : items;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= nt ? m->sec[t] : m->nm;
   A.inv_nm = 1.0 / (double)m->nm;
-  const int per_block = kGWPB * items;
+  const int per_block = kGWPB * A.items;
   dim3 grid((n + per_block - 1) / per_block, nt * nt);
-  if (m->w1 == 25) hipLaunchKernelGGL(k_embed_grad_f64<25>, grid, dim3(64 * kGWPB), 0, s, A);
-  else hipLaunchKernelGGL(k_embed_grad_f64<32>, grid, dim3(64 * kGWPB), 0, s, A);
+  dim3 rgrid((kEgRec + 255) / 256, nt * nt);
+  if (m->w1 == 25) {
+    hipLaunchKernelGGL(k_embed_grad_f64<25>, grid, dim3(64 * kGWPB), 0, s, A);
+    hipLaunchKernelGGL(k_egrad_reduce<25>, rgrid, dim3(256), 0, s, A);
+  } else {
+    hipLaunchKernelGGL(k_embed_grad_f64<32>, grid, dim3(64 * kGWPB), 0, s, A);
+    hipLaunchKernelGGL(k_egrad_reduce<32>, rgrid, dim3(256), 0, s, A);
+  }
 }
 
 }  // namespace dpse
