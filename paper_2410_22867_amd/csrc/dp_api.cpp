@@ -779,11 +779,13 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   {
     // parameter-gradient workspace: per-chunk partials of the fitting
     // reductions, per-work-group records of the embedding reductions
-    int64_t fch = N / 1024, slots = N / 128;
+    int64_t fch = N / 1024, slots = N / 64;
     c->grad_chunks = (int32_t)(fch < 1 ? 1 : (fch > 16 ? 16 : fch));
-    c->grad_slots = (int32_t)(slots < 1 ? 1 : (slots > 256 ? 256 : slots));
+    c->grad_slots = (int32_t)(slots < 1 ? 1 : (slots > 1024 ? 1024 : slots));
     const int64_t nt = m->desc.ntypes;
-    const int64_t fit = nt * c->grad_chunks * (int64_t)nd * m->fw;
+    const int64_t fit_w = nt * c->grad_chunks * (int64_t)nd * m->fw;
+    const int64_t fit_b = nt * ((N + 255) / 256) * (int64_t)m->fw;  // bias sums: 256-column chunks
+    const int64_t fit = fit_w > fit_b ? fit_w : fit_b;
     const int64_t emb = nt * nt * c->grad_slots * 10496LL;
     ALLOC(c->gpart, fit > emb ? fit : emb);
   }

@@ -486,6 +486,15 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     hipLaunchKernelGGL(k_sum_chunks, dim3((E + 255) / 256, nt), dim3(256), 0, s, c->gpart, c->type_meta, chunk, nch,
                        E, grad, stride, off);
   };
+  // bias-type sums have tiny partials: short chunks, many work-groups
+  const int bchunk = 256;
+  const int bnch = (n + bchunk - 1) / bchunk;
+  auto bgrad = [&](const double* Y, int N, int64_t stride, int64_t off) {
+    hipLaunchKernelGGL(k_bgrad_cols, dim3(bnch, 1, nt), dim3(256), 0, s, Y, in.ldz, c->gE_col, c->type_meta, N, bchunk,
+                       bnch, c->gpart);
+    hipLaunchKernelGGL(k_sum_chunks, dim3((N + 255) / 256, nt), dim3(256), 0, s, c->gpart, c->type_meta, bchunk, bnch,
+                       N, grad, stride, off);
+  };
   for (int l = 0; l < 3; ++l) {
     WGradArgs a = {};
     a.X = in.X[l];
@@ -502,20 +511,12 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     dim3 grid(nch, (Kin[l] / 16 + 3) / 4, nt);
     hipLaunchKernelGGL((k_wgrad_cols<16>), grid, dim3(256), 0, s, a);
     sum_chunks(Kin[l] * fw, m->fit_param_stride, m->fit_param_off[l]);
-    hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, in.dz[l], in.ldz, c->gE_col, c->type_meta, fw,
-                       chunk, nch, c->gpart);
-    sum_chunks(fw, m->fit_param_stride, m->fit_param_off[3 + l]);
+    bgrad(in.dz[l], fw, m->fit_param_stride, m->fit_param_off[3 + l]);
   }
   // w_out: sum w h3; b_out and e_bias: sum w
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, in.h3, in.ldz, c->gE_col, c->type_meta, fw, chunk,
-                     nch, c->gpart);
-  sum_chunks(fw, m->fit_param_stride, m->fit_param_off[6]);
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
-                     c->type_meta, 1, chunk, nch, c->gpart);
-  sum_chunks(1, m->fit_param_stride, m->fit_param_off[7]);
-  hipLaunchKernelGGL(k_bgrad_cols, dim3(nch, 1, nt), dim3(256), 0, s, (const double*)nullptr, 0, c->gE_col,
-                     c->type_meta, 1, chunk, nch, c->gpart);
-  sum_chunks(1, 1, m->ebias_off);
+  bgrad(in.h3, fw, m->fit_param_stride, m->fit_param_off[6]);
+  bgrad(nullptr, 1, m->fit_param_stride, m->fit_param_off[7]);
+  bgrad(nullptr, 1, 1, m->ebias_off);
   // ---- embedding nets
   EGradArgs A = {};
   A.atom_at = c->atom_at;
