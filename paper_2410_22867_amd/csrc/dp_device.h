@@ -79,38 +79,42 @@ __device__ __forceinline__ typename P::vec8 load8(const uint16_t* p) {
 // ---------------------------------------------------------------------------
 // Activations.  FP32 (mixed forms): 1 - 2/(e^{2x}+1) with the hardware exp2
 // and reciprocal; saturates correctly at +-inf.
-// FP64 tanh(x) = 1 - 2 / (e^{2x} + 1).  e^{y} with Cody-Waite reduction
-// y = n ln2 + r (ln 2 split in a 32-bit head and a tail, so n*head is exact),
-// |r| <= ln2/2, and the Taylor series of e^r to degree 13 (truncation below
-// 1e-17 relative); the reciprocal is the hardware estimate refined by two
-// Newton steps.  Absolute error about 2e-16; relative accuracy is lost only
-// for |x| below ~1e-3, where the absolute error still is ~1e-16.
+// FP64 tanh.  With t = |x| and e = exp(-2t) in (0, 1], tanh(t) = 2/(1 + e) - 1;
+// the sign of x is copied onto the result.  t is carried as u = t/32 clamped
+// to [0, 1] (one scaled, clamped instruction; tanh(32) rounds to 1).  Range
+// reduction -2t = n ln2 + 2w, |w| <= ln2/4, with ln 2 split in a 32-bit head
+// (n*head/64 is exact) and a tail; exp(2w) is a degree-11 polynomial fitted
+// to it in the Chebyshev (near-minimax) sense, fit error 3e-18 relative,
+// evaluated in w/32 with the coefficients scaled by 32^k (exact, so the
+// roundings are those of the unscaled form).  The reciprocal is the hardware
+// estimate refined by two Newton steps.  Absolute error below 5e-16 (about
+// 2 ulp of 1); relative accuracy is lost only for |x| below ~1e-3, where the
+// absolute error still is ~1e-16.  A NaN argument gives +-0: every caller's
+// arguments derive from coordinates checked by the wrap test and parameters
+// checked finite when the model is created.
 __device__ __forceinline__ double tanh_d(double x) {
-  double y = 2.0 * x;
-  y = y > 40.0 ? 40.0 : (y < -40.0 ? -40.0 : y);
-  const double n = rint(y * 1.4426950408889634);
-  double r = fma(-n, 0.6931471803691238, y);
-  r = fma(-n, 1.9082149292705877e-10, r);
-  double p = 1.6059043836821613e-10;
-  p = fma(p, r, 2.08767569878681e-09);
-  p = fma(p, r, 2.505210838544172e-08);
-  p = fma(p, r, 2.755731922398589e-07);
-  p = fma(p, r, 2.7557319223985893e-06);
-  p = fma(p, r, 2.48015873015873e-05);
-  p = fma(p, r, 0.0001984126984126984);
-  p = fma(p, r, 0.001388888888888889);
-  p = fma(p, r, 0.008333333333333333);
-  p = fma(p, r, 0.041666666666666664);
-  p = fma(p, r, 0.16666666666666666);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
+  const double u = __builtin_fmin(__builtin_fmax(__builtin_fabs(x) * 0.03125, 0.0), 1.0);
+  const double n = rint(u * -92.33248261689366);  // -64/ln2
+  double w = fma(-n, 0.01083042469326756, -u);    // head(ln2)/64
+  w = fma(-n, 2.9815858269852933e-12, w);         // tail(ln2)/64
+  double p = 1852793749593.745;
+  p = fma(p, w, 318582644689.01984);
+  p = fma(p, w, 49642711972.90849);
+  p = fma(p, w, 6980997548.528086);
+  p = fma(p, w, 872628278.1579455);
+  p = fma(p, w, 95443718.12474826);
+  p = fma(p, w, 8947848.533318589);
+  p = fma(p, w, 699050.6666636708);
+  p = fma(p, w, 43690.6666666667);
+  p = fma(p, w, 2048.0000000000077);
+  p = fma(p, w, 64.0);
+  p = fma(p, w, 1.0);
   const double e = __builtin_amdgcn_ldexp(p, (int)n);
-  const double d = e + 1.0;
+  const double d = 1.0 + e;
   double q = __builtin_amdgcn_rcp(d);
   q = q * fma(-d, q, 2.0);
   q = q * fma(-d, q, 2.0);
-  return fma(-2.0, q, 1.0);
+  return __builtin_copysign(fma(2.0, q, -1.0), x);
 }
 
 __device__ __forceinline__ float tanh_f(float x) {

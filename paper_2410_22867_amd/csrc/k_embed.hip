@@ -164,14 +164,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       double h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
-        d4 z = {0.0, 0.0, 0.0, 0.0};
+        const double* b2 = vec + kV_B2 + 16 * ot + g;
+        d4 z = {b2[0], b2[4], b2[8], b2[12]};
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v]);
       }
       wave_lds_sync();
 #pragma unroll
@@ -181,20 +182,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       wave_lds_sync();
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
-        d4 z = {0.0, 0.0, 0.0, 0.0};
+        const int feat = 16 * o + r16;
+        const double b3 = vec[kV_B3F + feat];  // the table spans kP3 features
+        d4 z = {b3, b3, b3, b3};
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v))
               z = mfma_f64(h2[mt][v], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
-        const int feat = 16 * o + r16;
         if (feat < M1) {
-          const double b3 = vec[kV_B3F + feat];
           const int src = slot2_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double t3 = tanh_d(z[v] + b3);
+            const double t3 = tanh_d(z[v]);
             if constexpr (ST) rec[o * 256 + 4 * v] = t3;
             const double G = h2s[wv][4 * v + g][src] + t3;
 #pragma unroll
@@ -307,14 +308,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       double h2[4][4];  // t2 = h2 - t1 is re-derived where needed
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
-        d4 z = {0.0, 0.0, 0.0, 0.0};
+        const double* b2 = vec + kV_B2 + 16 * ot + g;
+        d4 z = {b2[0], b2[4], b2[8], b2[12]};
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v] + vec[kV_B2 + 16 * ot + 4 * v + g]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v]);
       }
       // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
@@ -333,6 +335,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int o4 = 0; o4 < 4; ++o4) {
           d4 z = {0.0, 0.0, 0.0, 0.0};
           if constexpr (!ST) {
+            const double* b3 = vec + kV_B3S + 16 * (4 * zo + o4) + g;
+            z = d4{b3[0], b3[4], b3[8], b3[12]};
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -348,7 +352,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
               const double x = oo == 0 ? t3v[0][o4 * 4 + v] : t3v[1][o4 * 4 + v];
               t3 = 16 * (o4 & 1) + 4 * v + g < W ? x : 0.0;
             } else {
-              t3 = tanh_d(z[v] + vec[kV_B3S + p]);
+              t3 = tanh_d(z[v]);
             }
             const double G = h2[o4][v] + t3;
             const d4 gt = gts[wv][p];
@@ -384,7 +388,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       double dsp = 0.0;
 #pragma unroll
       for (int i2 = 0; i2 < 2; ++i2) {
-        d4 z = {0.0, 0.0, 0.0, 0.0};
+        d4 z = {skip1[i2][0], skip1[i2][1], skip1[i2][2], skip1[i2][3]};
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
             if (!kpad<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double dh1 = z[v] + skip1[i2][v];
+          const double dh1 = z[v];
           dsp = fma(vec[kV_W1 + 16 * i2 + 4 * v + g], dh1 * (1.0 - t1[i2][v] * t1[i2][v]), dsp);
         }
       }
@@ -482,10 +486,10 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
       float h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        f4 z = {b2s[ot][0], b2s[ot][1], b2s[ot][2], b2s[ot][3]};
         z = P::mfma(load8<P>(fr + z0 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[4 * (ot & 1) + v] + tanh_f(z[v] + b2s[ot][v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[4 * (ot & 1) + v] + tanh_f(z[v]);
       }
       wave_lds_sync();
 #pragma unroll
@@ -503,16 +507,16 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
       }
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        const int feat = 16 * o + r16;
+        const float b3 = vec[kV_B3F + feat];  // the table spans kP3 features
+        f4 z = {b3, b3, b3, b3};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
-        const int feat = 16 * o + r16;
         if (feat < M1) {
-          const float b3 = vec[kV_B3F + feat];
           const int src = slot2_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float G = h2s[wv][4 * g + v][src] + tanh_f(z[v] + b3);
+            const float G = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) accT[o][k] = fmaf(G, Rr[v][k], accT[o][k]);
           }
@@ -612,11 +616,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
       float t2[4][4], h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        const float* b2 = vec + kV_B2 + 16 * ot + 4 * g;
+        f4 z = {b2[0], b2[1], b2[2], b2[3]};
         z = P::mfma(load8<P>(fr + z0 + oF2 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          t2[ot][v] = tanh_f(z[v] + vec[kV_B2 + 16 * ot + 4 * g + v]);
+          t2[ot][v] = tanh_f(z[v]);
           h2[ot][v] = t1[4 * (ot & 1) + v] + t2[ot][v];
         }
       }
@@ -636,13 +641,14 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
         for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.f;
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        const float* b3 = vec + kV_B3S + 16 * o + 4 * g;
+        f4 z = {b3[0], b3[1], b3[2], b3[3]};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oF3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int p = 16 * o + 4 * g + v;
-          const float t3 = tanh_f(z[v] + vec[kV_B3S + p]);
+          const float t3 = tanh_f(z[v]);
           const float G = h2[o & 3][v] + t3;
           const f4 gt = gts[wv][p];
           const float dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
@@ -667,12 +673,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
       }
 #pragma unroll
       for (int i2 = 0; i2 < 4; ++i2) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        f4 z = {skip2[i2][0], skip2[i2][1], skip2[i2][2], skip2[i2][3]};
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) z = P::mfma(load8<P>(fr + z0 + oB3 + ((i2 * 4 + kt) * 64 + lane) * 8), bz3[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float dh2 = z[v] + skip2[i2][v];
+          const float dh2 = z[v];
           dz2[i2][v] = dh2 * (1.f - t2[i2][v] * t2[i2][v]);
           skip1[i2 & 1][v] += dh2;
         }
@@ -688,12 +694,12 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
       float dsp = 0.f;
 #pragma unroll
       for (int i2 = 0; i2 < 2; ++i2) {
-        f4 z = {0.f, 0.f, 0.f, 0.f};
+        f4 z = {skip1[i2][0], skip1[i2][1], skip1[i2][2], skip1[i2][3]};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oB2 + ((i2 * 2 + kt) * 64 + lane) * 8), bz2[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float dh1 = z[v] + skip1[i2][v];
+          const float dh1 = z[v];
           const float tt = t1[4 * i2 + v];
           dsp = fmaf(w1s[4 * i2 + v], dh1 * (1.f - tt * tt), dsp);
         }
