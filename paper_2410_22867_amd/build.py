@@ -20,9 +20,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+# Per-file additions.  The embedding kernels keep matrix-core results in
+# ordinary VGPRs (no copies between accumulation and arithmetic registers,
+# measured faster for the half-precision forms); the fitting GEMMs and the
+# gradient reductions measured slower that way and keep the default.
+FILE_FLAGS = {"k_embed.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+    cmd = ["hipcc", *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

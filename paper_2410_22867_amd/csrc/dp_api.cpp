@@ -162,14 +162,19 @@ inline int kfeat32(int t, int lane, int j) { return 32 * t + 16 * (j >> 2) + 4 *
 // Builds one fragment block: out[mtile][ktile...] for a weight accessor
 // wfun(m_index, k_index) -> value (0 when padded).  For f64 the k tiles are
 // (t, v) pairs with ktiles16 = K/16; for lp they are t with ktiles32 = K/32.
+// Register-chained f64 blocks (embedding nets, read from LDS one v at a time)
+// are ordered [mt][t][v][lane]; memory-fed ones (fitting GEMMs, whose lanes
+// read all four v of a step with one 32-byte load) [mt][t][lane][v].
 template <class F>
 void frag_block64(std::vector<double>& out, int64_t base, int mtiles, int ktiles16, F wfun, bool chained) {
   for (int mt = 0; mt < mtiles; ++mt)
     for (int t = 0; t < ktiles16; ++t)
       for (int v = 0; v < 4; ++v)
-        for (int l = 0; l < 64; ++l)
-          out[base + (((int64_t)mt * ktiles16 + t) * 4 + v) * 64 + l] =
+        for (int l = 0; l < 64; ++l) {
+          const int64_t tile = (int64_t)mt * ktiles16 + t;
+          out[base + (chained ? (tile * 4 + v) * 64 + l : (tile * 64 + l) * 4 + v)] =
               wfun(16 * mt + (l & 15), chained ? kfeat64c(t, v, l) : kfeat64(t, v, l));
+        }
 }
 template <class F>
 void frag_block32(std::vector<float>& out, int64_t base, int mtiles, int ktiles32, F wfun) {

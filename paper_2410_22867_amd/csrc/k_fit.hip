@@ -49,7 +49,7 @@ struct GemmArgs {
 };
 
 // ---------------------------------------------------------------- FP64 GEMM
-template <int MT, int NT, bool XT, bool PF>
+template <int MT, int NT, bool XT>
 __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
@@ -84,34 +84,34 @@ __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
       for (int v = 0; v < 4; ++v) Tb[nt][v] = *reinterpret_cast<const d4*>(trow[nt] + (4 * gq + v) * 4);
     }
   }
-  // PF: operands of k-step S + 1 are loaded while S computes (register
-  // double buffer: X rows or T rows, and the weight fragments).  It pays for
-  // the short (K = 240, M = 240) products; for the long ones the extra
-  // registers cost more occupancy than the prefetch gains.
-  d4 xr[NT], xn[NT];
-  double ar[MT][4], an[MT][4];
+  // Operands of k-step S + 1 are requested before the products of step S
+  // issue: two register buffers used alternately (the loop is unrolled by
+  // two, so no copy between them forces an early wait); an odd last step
+  // runs after the loop on the buffer the loop filled last.
+  d4 xA[NT], xB[NT];
+  double aA[MT][4], aB[MT][4];
   auto load = [&](int S, d4* xv, double (*av)[4]) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
       xv[nt] = *reinterpret_cast<const d4*>(XT ? trow[nt] + S * 4 : xrow[nt] + 16 * S);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+      const d4 q = *reinterpret_cast<const d4*>(Afr + (((int64_t)mtv[mt] * KS + S) * 64 + lane) * 4);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) av[mt][v] = Afr[(((int64_t)mtv[mt] * KS + S) * 4 + v) * 64 + lane];
+      for (int v = 0; v < 4; ++v) av[mt][v] = q[v];
+    }
   };
-  load(0, xr, ar);
-  for (int S = 0; S < KS; ++S) {
-    if (PF && S + 1 < KS) load(S + 1, xn, an);
+  auto step = [&](const d4* xv, const double (*av)[4]) {
     d4 xb[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       if constexpr (XT) {
-        const d4 ta = xr[nt];
+        const d4 ta = xv[nt];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           xb[nt][v] = ta[0] * Tb[nt][v][0] + ta[1] * Tb[nt][v][1] + ta[2] * Tb[nt][v][2] + ta[3] * Tb[nt][v][3];
       } else {
-        xb[nt] = xr[nt];
+        xb[nt] = xv[nt];
       }
     }
 #pragma unroll
@@ -119,20 +119,22 @@ __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(ar[mt][v], xb[nt][v], acc[mt][nt]);
-    if (S + 1 < KS) {
-      if constexpr (PF) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) xr[nt] = xn[nt];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) ar[mt][v] = an[mt][v];
-      } else {
-        load(S + 1, xr, ar);
-      }
-    }
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(av[mt][v], xb[nt][v], acc[mt][nt]);
+  };
+  // (scheduling barriers keep each phase's loads ahead of the products)
+  load(0, xA, aA);
+  int S = 0;
+  for (; S + 1 < KS; S += 2) {
+    load(S + 1, xB, aB);
+    __builtin_amdgcn_sched_barrier(0);
+    step(xA, aA);
+    __builtin_amdgcn_sched_barrier(0);
+    load(S + 2 < KS ? S + 2 : KS - 1, xA, aA);
+    __builtin_amdgcn_sched_barrier(0);
+    step(xB, aB);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (S < KS) step(xA, aA);
   const double* vec = reinterpret_cast<const double*>(g.vec) + t * g.vec_type_stride;
   // D layout of the f64 MFMA: element v of lane n + 16g is row m = 16 mt + g + 4v.
 #pragma unroll
@@ -429,15 +431,15 @@ __global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ ato
 //   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
 //          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
-template <int MT, int NT, bool PF>
+template <int MT, int NT>
 static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 4 * NT * 16;
   const int mtiles = g.M / 16;
   dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + MT - 1) / MT), (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true, PF>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false, PF>), grid, dim3(256), 0, s, g);
+  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
 }
 
 template <int MTW, int NTW>
@@ -456,13 +458,19 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
 // (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the half-precision
 // GEMM 2x2 per wave (64 x 64 per work-group; larger tiles leave too few
 // work-groups at these sizes).
+#ifndef DPSE_F64_MT
+#define DPSE_F64_MT 3
+#define DPSE_F64_NT 2
+#define DPSE_F64_MTS 3
+#define DPSE_F64_NTS 2
+#endif
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
   if (mode != DP_FP64) {
     gemm_launch_lp<2, 2>(c, g, mode, s);
   } else if (g.T || g.M > 256 || g.K > 256) {
-    gemm_launch_f64<3, 2, false>(c, g, s);
+    gemm_launch_f64<DPSE_F64_MT, DPSE_F64_NT>(c, g, s);
   } else {
-    gemm_launch_f64<3, 2, true>(c, g, s);
+    gemm_launch_f64<DPSE_F64_MTS, DPSE_F64_NTS>(c, g, s);
   }
 }
 
