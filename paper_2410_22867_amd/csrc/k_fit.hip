@@ -455,23 +455,13 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
 }
 
 // Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
-// (4 passes per 16x16x4 step) wants a 3x2 tile per wave; the half-precision
-// GEMM 2x2 per wave (64 x 64 per work-group; larger tiles leave too few
-// work-groups at these sizes).
-#ifndef DPSE_F64_MT
-#define DPSE_F64_MT 3
-#define DPSE_F64_NT 2
-#define DPSE_F64_MTS 3
-#define DPSE_F64_NTS 2
-#endif
+// wants a 3x2 tile per wave (48 features x 32 columns; 5x2 and 3x1 were
+// slower: too few or too many work-groups for these sizes, and a 48-column
+// tile would cross the 128-column type segments); the half-precision GEMM
+// 2x2 per wave (64 x 64 per work-group).
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
-  if (mode != DP_FP64) {
-    gemm_launch_lp<2, 2>(c, g, mode, s);
-  } else if (g.T || g.M > 256 || g.K > 256) {
-    gemm_launch_f64<DPSE_F64_MT, DPSE_F64_NT>(c, g, s);
-  } else {
-    gemm_launch_f64<DPSE_F64_MTS, DPSE_F64_NTS>(c, g, s);
-  }
+  if (mode != DP_FP64) gemm_launch_lp<2, 2>(c, g, mode, s);
+  else gemm_launch_f64<3, 2>(c, g, s);
 }
 
 static GemmArgs gemm_base(dp_ctx* c, int mode) {
