@@ -50,7 +50,7 @@ struct GemmArgs {
 
 // ---------------------------------------------------------------- FP64 GEMM
 template <int MT, int NT, bool XT>
-__global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fit_gemm_f64(GemmArgs g) {
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -165,6 +165,175 @@ __global__ __launch_bounds__(256) void k_fit_gemm_f64(GemmArgs g) {
       }
     }
   }
+}
+
+// ------------------------------------------------- FP64 fitting layer pairs
+// The two equal-width hidden layers after the first, for 16 columns of one
+// centre type per work-group, with the 16 x fw activation tile resident in
+// LDS between them.  Forward: h2 = h1 + tanh(h1 W2 + b2), h3 = h2 +
+// tanh(h2 W3 + b3), E_i = h3 . w_o + b_o + e_bias, plus dz3 = w_o (1 - t3^2)
+// for the backward.  Backward: dh2 = w_o + W3 dz3, dz2 = dh2 (1 - t2^2),
+// dh1 = dh2 + W2 dz2, dz1 = dh1 (1 - t1^2).  Wave w owns m-tiles w, w + 4,
+// ...; operands as in k_fit_gemm_f64 (weight fragments lane-major from
+// memory, requested one k-step ahead; activations from LDS).
+struct PairArgs {
+  const int32_t* meta;
+  const int32_t* atom_at;
+  int fw;
+  const double* in;        // forward: h1; backward: dz3   [cols][fw]
+  const double* A[2];      // fragments of the first and second layer, type 0
+  int64_t a_type_stride;
+  const double* vec;       // per-type fitting vectors (b1 b2 b3 wo | bo ebias)
+  int64_t vec_type_stride;
+  const double* tprev[2];  // backward: t2, t1
+  double* out[4];          // forward: t2, h2, h3, dz3; backward: dz2, dz1
+  double* Ei_col;
+  double* Ei_atom;
+};
+
+constexpr int kPairCols = 16;
+
+template <bool BWD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_pair_f64(PairArgs p) {
+  extern __shared__ double hs[];  // [kPairCols][fw + 2]
+  const int t = blockIdx.z;
+  const int n_t = p.meta[2 * t], cb = p.meta[2 * t + 1];
+  const int c0 = blockIdx.x * kPairCols;
+  if (c0 >= n_t) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r16 = lane & 15, gq = lane >> 4;
+  const int fw = p.fw, KS = fw / 16, mtiles = fw / 16, ldh = fw + 2;
+  const int64_t col = cb + c0 + r16;
+  const double* vec = p.vec + t * p.vec_type_stride;
+  for (int e = threadIdx.x; e < kPairCols * fw; e += 256) {
+    const int c = e / fw, k = e - c * fw;
+    hs[c * ldh + k] = p.in[(int64_t)(cb + c0 + c) * fw + k];
+  }
+  bool own[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) own[j] = wv + 4 * j < mtiles;
+  // feature of element v of m-tile slot j: 16 (wv + 4 j) + gq + 4 v
+  auto feat = [&](int j, int v) { return 16 * (wv + 4 * j) + gq + 4 * v; };
+  d4 acc[4];
+  auto init = [&](int off) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[j][v] = own[j] ? vec[off + feat(j, v)] : 0.0;
+  };
+  auto layer = [&](const double* Afr) {
+    d4 aA[4], aB[4];
+    auto load = [&](int S, d4* a) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (own[j]) a[j] = *reinterpret_cast<const d4*>(Afr + (((int64_t)(wv + 4 * j) * KS + S) * 64 + lane) * 4);
+    };
+    auto step = [&](int S, const d4* a) {
+      const d4 x = *reinterpret_cast<const d4*>(hs + r16 * ldh + 16 * S + 4 * gq);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (own[j]) acc[j] = mfma_f64(a[j][v], x[v], acc[j]);
+    };
+    load(0, aA);
+    int S = 0;
+    for (; S + 1 < KS; S += 2) {
+      load(S + 1, aB);
+      step(S, aA);
+      load(S + 2 < KS ? S + 2 : KS - 1, aA);
+      step(S + 1, aB);
+    }
+    if (S < KS) step(S, aA);
+  };
+  const double* A0 = p.A[0] + t * p.a_type_stride;
+  const double* A1 = p.A[1] + t * p.a_type_stride;
+  if constexpr (!BWD) {
+#pragma unroll 1
+    for (int l = 0; l < 2; ++l) {
+      init((l + 1) * fw);  // b2, b3
+      __syncthreads();     // the tile (input or previous layer) is complete
+      layer(l == 0 ? A0 : A1);
+      __syncthreads();     // every wave has read the tile
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!own[j]) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = feat(j, v);
+          const double tv = tanh_d(acc[j][v]);
+          const double h = hs[r16 * ldh + m] + tv;
+          hs[r16 * ldh + m] = h;
+          if (l == 0) {
+            p.out[0][col * fw + m] = tv;
+            p.out[1][col * fw + m] = h;
+          } else {
+            p.out[2][col * fw + m] = h;
+            const double wo = vec[3 * fw + m];
+            p.out[3][col * fw + m] = wo * (1.0 - tv * tv);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // E_i: 16 threads per column, partial dots over features part, part + 16, ...
+    const int c = threadIdx.x >> 4, part = threadIdx.x & 15;
+    double e = 0.0;
+    for (int m = part; m < fw; m += 16) e += hs[c * ldh + m] * vec[3 * fw + m];
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (part == 0) {
+      const int64_t cc = cb + c0 + c;
+      const int i = p.atom_at[cc];
+      if (i >= 0) {
+        const double E = e + vec[4 * fw] + vec[4 * fw + 1];
+        p.Ei_col[cc] = E;
+        p.Ei_atom[i] = E;
+      }
+    }
+  } else {
+    // tanh of the layers below, requested before the products
+    double tp[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tp[j][v] = own[j] ? p.tprev[0][col * fw + feat(j, v)] : 0.0;
+    init(3 * fw);  // w_o
+    __syncthreads();
+    layer(A0);     // acc = dh2
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!own[j]) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = feat(j, v);
+        const double dz = acc[j][v] * (1.0 - tp[j][v] * tp[j][v]);
+        hs[r16 * ldh + m] = dz;
+        p.out[0][col * fw + m] = dz;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tp[j][v] = own[j] ? p.tprev[1][col * fw + feat(j, v)] : 0.0;
+    __syncthreads();
+    layer(A1);     // acc = dh1 = dh2 + W2 dz2
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!own[j]) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p.out[1][col * fw + feat(j, v)] = acc[j][v] * (1.0 - tp[j][v] * tp[j][v]);
+    }
+  }
+}
+
+static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
+  const dp_model* m = c->model;
+  dim3 grid((unsigned)((c->natoms_last + kPairCols - 1) / kPairCols), 1, (unsigned)m->desc.ntypes);
+  const size_t lds = (size_t)kPairCols * (m->fw + 2) * sizeof(double);
+  if (grid.x == 0) return;
+  if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true>), grid, dim3(256), lds, s, p);
+  else hipLaunchKernelGGL((k_fit_pair_f64<false>), grid, dim3(256), lds, s, p);
 }
 
 // ---------------------------------------------------------------- mixed GEMM
@@ -427,7 +596,7 @@ __global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ ato
 
 // ---------------------------------------------------------------- launchers
 // Activation buffer slots in dp_ctx::fa (FP64 / mixed):
-//   FP64 : 0 t1(=h1) 1 t2 2 h2 3 t3 4 h3 5 dz3 6 dh2 7 dz2 8 dz1         [cols][fw]
+//   FP64 : 0 t1(=h1) 1 t2 2 h2 4 h3 5 dz3 7 dz2 8 dz1 [cols][fw] (3, 6 unused)
 //   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
 //          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
@@ -535,6 +704,26 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
   g.ldlp = fwp;
   gemm_launch(c, g, mode, s);
   g.T = nullptr;
+  if (f64) {
+    PairArgs p = {};
+    p.meta = c->type_meta;
+    p.atom_at = c->atom_at;
+    p.fw = fw;
+    p.in = (const double*)c->fa[0];
+    p.A[0] = (const double*)frag + off_fwd[1];
+    p.A[1] = (const double*)frag + off_fwd[2];
+    p.a_type_stride = tstride;
+    p.vec = m->fit_vec64;
+    p.vec_type_stride = m->fit_vec_per_type;
+    p.out[0] = (double*)c->fa[1];
+    p.out[1] = (double*)c->fa[2];
+    p.out[2] = (double*)c->fa[4];
+    p.out[3] = (double*)c->fa[5];
+    p.Ei_col = c->Ei_col;
+    p.Ei_atom = c->Ei_atom;
+    launch_pair_f64(c, false, p, s);
+    return;
+  }
   // layers 2, 3
   for (int l = 1; l < 3; ++l) {
     g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[l]) : (const void*)((const uint16_t*)frag + off_fwd[l]);
@@ -592,41 +781,64 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
   auto fr = [&](int l) {
     return f64 ? (const void*)((const double*)frag + off_bwd[l]) : (const void*)((const uint16_t*)frag + off_bwd[l]);
   };
-  // layer 3: dh2 = w_out + W3 dz3 ; dz2 = dh2 (1 - t2^2)
-  g.Afr = fr(2);
-  g.X = f64 ? c->fa[5] : c->fa[7];
-  g.ldx = ld;
-  g.K = ld;
-  g.Kreal = fw;
-  g.M = fw;
-  g.epi = EPI_BWD;
-  g.res = nullptr;
-  g.tprev = c->fa[1];
-  g.ldt = ld;
-  g.out0 = f64 ? c->fa[6] : c->fa[10];
-  g.ld0 = ld;
-  g.out1 = f64 ? c->fa[7] : nullptr;
-  g.ld1 = ld;
-  g.outlp = f64 ? nullptr : c->fa[8];
-  g.ldlp = fwp;
-  gemm_launch(c, g, mode, s);
-  // layer 2: dh1 = dh2 + W2 dz2 ; dz1 = dh1 (1 - t1^2)
-  g.Afr = fr(1);
-  g.X = f64 ? c->fa[7] : c->fa[8];
-  g.res = f64 ? c->fa[6] : c->fa[10];
-  g.ldr = ld;
-  g.tprev = c->fa[0];
-  g.out0 = nullptr;
-  g.out1 = f64 ? c->fa[8] : nullptr;
-  g.outlp = f64 ? nullptr : c->fa[9];
-  gemm_launch(c, g, mode, s);
+  if (f64) {
+    // layers 3 and 2 in one pass: dz2 -> fa[7], dz1 -> fa[8]
+    PairArgs p = {};
+    p.meta = c->type_meta;
+    p.fw = fw;
+    p.in = (const double*)c->fa[5];
+    p.A[0] = (const double*)frag + off_bwd[2];
+    p.A[1] = (const double*)frag + off_bwd[1];
+    p.a_type_stride = tstride;
+    p.vec = m->fit_vec64;
+    p.vec_type_stride = m->fit_vec_per_type;
+    p.tprev[0] = (const double*)c->fa[1];
+    p.tprev[1] = (const double*)c->fa[0];
+    p.out[0] = (double*)c->fa[7];
+    p.out[1] = (double*)c->fa[8];
+    launch_pair_f64(c, true, p, s);
+  } else {
+    // layer 3: dh2 = w_out + W3 dz3 ; dz2 = dh2 (1 - t2^2)
+    g.Afr = fr(2);
+    g.X = c->fa[7];
+    g.ldx = ld;
+    g.K = ld;
+    g.Kreal = fw;
+    g.M = fw;
+    g.epi = EPI_BWD;
+    g.res = nullptr;
+    g.tprev = c->fa[1];
+    g.ldt = ld;
+    g.out0 = c->fa[10];
+    g.ld0 = ld;
+    g.out1 = nullptr;
+    g.ld1 = ld;
+    g.outlp = c->fa[8];
+    g.ldlp = fwp;
+    gemm_launch(c, g, mode, s);
+    // layer 2: dh1 = dh2 + W2 dz2 ; dz1 = dh1 (1 - t1^2)
+    g.Afr = fr(1);
+    g.X = c->fa[8];
+    g.res = c->fa[10];
+    g.ldr = ld;
+    g.tprev = c->fa[0];
+    g.out0 = nullptr;
+    g.out1 = nullptr;
+    g.outlp = c->fa[9];
+    gemm_launch(c, g, mode, s);
+  }
   // layer 1: dD = W1 dz1
   g.Afr = fr(0);
   g.X = f64 ? c->fa[8] : c->fa[9];
+  g.ldx = ld;
+  g.K = ld;
+  g.Kreal = fw;
   g.M = m->nd;
   g.epi = EPI_PLAIN;
+  g.res = nullptr;
   g.out0 = c->dD;
   g.ld0 = m->nd;
+  g.out1 = nullptr;
   g.outlp = nullptr;
   gemm_launch(c, g, mode, s);
 }

@@ -9,11 +9,12 @@
 //   reduction; MFMA with columns along K, split over column chunks whose
 //   partial sums are written to a workspace and summed in chunk order).
 // Embedding weights: the backward of each neighbour row is recomputed (as in
-//   the force path, with g_T scaled by w_col); per 16-row tile the activations
-//   and deltas are transposed through LDS so that the reduction over rows is
-//   an MFMA product, accumulated in per-work-group LDS sums that are written
-//   to the workspace and summed in work-group order.  No global atomics: the
-//   gradient is deterministic.
+//   the force path, with g_T scaled by w_col; the last layer's tanh is read
+//   from the forward's activation store when that was kept); per 16-row tile
+//   the activations and deltas are transposed through LDS so that the
+//   reduction over rows is an MFMA product, accumulated in per-work-group LDS
+//   sums that are written to the workspace and summed in work-group order.
+//   No global atomics: the gradient is deterministic.
 #include "dp_internal.h"
 #include "dp_device.h"
 
@@ -149,6 +150,11 @@ struct EGradArgs {
   int ntypes, nm, items;
   int sec[kMaxT + 1];
   double inv_nm;
+  // last embedding layer's tanh per 16-row tile of the forward pass
+  // ([N, tpa, m1, 16]) when it was stored, else null (recomputed)
+  const double* act;
+  int tpa;
+  int toff[kMaxT + 1];
 };
 
 template <int W>
@@ -161,31 +167,36 @@ __device__ __forceinline__ int e_feat3(int p) {
   return f < 0 ? -1 : (p >> 6) * 2 * W + f;
 }
 
-constexpr int kGWPB = 2;
+// waves per work-group of the embedding-gradient kernel: one work-group per
+// CU holds the slot-indexed accumulators (82 KB) and per-wave buffers
+// (16.5 KB + 32 B per feature); four waves fit in 160 KB up to M1 = 100.
+template <int W>
+constexpr int egw() { return 4 * W <= 100 ? 4 : 3; }
 // partial record of one work-group (slot-indexed): W3 | W2 | b3 | b2 | b1 | W1
 constexpr int kEgW3 = 0, kEgW2 = 64 * 128, kEgB3 = kEgW2 + 32 * 64, kEgB2 = kEgB3 + 128, kEgB1 = kEgB2 + 64,
               kEgW1 = kEgB1 + 32, kEgRec = kEgW1 + 32;
 
-template <int W>
-__global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
+template <int W, bool ST>
+__global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
+  constexpr int M1 = 4 * W, GW = egw<W>();
   // per-block accumulators (slot-indexed)
   __shared__ double aW3[64 * 128];
   __shared__ double aW2[32 * 64];
   __shared__ double aW1[32], aB1[32], aB2[64], aB3[128];
-  // per-wave transposition buffers: [row][slot]; buffer 0 holds h2 | dz3,
-  // then h1 | dz2 | dz1 | s
-  __shared__ double tb[kGWPB][16][65 + 129];
-  __shared__ d4 gts[kGWPB][128];
+  // per-wave transposition buffers [row][slot]: h2 | one half of dz3, then
+  // h1 | dz2 | dz1 | s
+  __shared__ double tb[GW][16][129];
+  __shared__ d4 gts[GW][M1];  // feature-indexed
   const int net = blockIdx.y;
   const int ti = net / A.ntypes, tj = net - ti * A.ntypes;
   const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];
-  const int chunk0 = blockIdx.x * kGWPB * A.items;
+  const int chunk0 = blockIdx.x * GW * A.items;
   if (chunk0 >= n_t) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) aW3[k] = 0.0;
-  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) aW2[k] = 0.0;
-  for (int k = threadIdx.x; k < 128; k += 64 * kGWPB) {
+  for (int k = threadIdx.x; k < 64 * 128; k += 64 * GW) aW3[k] = 0.0;
+  for (int k = threadIdx.x; k < 32 * 64; k += 64 * GW) aW2[k] = 0.0;
+  for (int k = threadIdx.x; k < 128; k += 64 * GW) {
     aB3[k] = 0.0;
     if (k < 64) aB2[k] = 0.0;
     if (k < 32) { aB1[k] = 0.0; aW1[k] = 0.0; }
@@ -201,9 +212,9 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
       w1s[mt][v] = vec[16 * mt + 4 * v + g];
       b1s[mt][v] = vec[32 + 16 * mt + 4 * v + g];
     }
-  double (*T)[65 + 129] = tb[wv];
+  double (*T)[129] = tb[wv];
   for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * kGWPB + wv;
+    const int c = chunk0 + it * GW + wv;
     if (c >= n_t) break;
     const int col = cb + c;
     const int i = A.atom_at[col];
@@ -211,12 +222,7 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
     {
       const double* gT = A.gT + (int64_t)col * (4 * W) * 4;
       wave_lds_sync();
-      for (int p = lane; p < 128; p += 64) {
-        const int a = e_feat3<W>(p);
-        d4 x = {0.0, 0.0, 0.0, 0.0};
-        if (a >= 0) x = *reinterpret_cast<const d4*>(gT + a * 4) * (A.inv_nm * wc);
-        gts[wv][p] = x;
-      }
+      for (int a = lane; a < M1; a += 64) gts[wv][a] = *reinterpret_cast<const d4*>(gT + a * 4) * (A.inv_nm * wc);
       wave_lds_sync();
     }
     const int nn = A.nnei[i * kMaxT + tj];
@@ -263,46 +269,68 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.0;
       }
+      // stored t3 of the tile: slot p = 64 oo + 16 o4 + 4 v + g holds feature
+      // 2W oo + W (o4 / 2) + 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g
+      // < W; a padding slot may read past its record (one record of slack at
+      // the end of the store) and its value is not used
+      const double* rec =
+          ST ? A.act + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + g * 16 + r16 : nullptr;
 #pragma unroll 1
       for (int oo = 0; oo < 2; ++oo) {
         const double* F3o = opaque(F3 + oo * 4 * 16 * 64);
         const double* B3o = opaque(B3 + oo * 4 * 4 * 64);
+        double t3v[16];
+        if constexpr (ST) {
+#pragma unroll
+          for (int o4 = 0; o4 < 4; ++o4)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lo = 16 * (o4 & 1) + 4 * v;
+              t3v[o4 * 4 + v] = (lo < W) ? rec[(oo * 2 * W + (o4 >> 1) * W + lo) * 16] : 0.0;
+            }
+        }
 #pragma unroll
         for (int o4 = 0; o4 < 4; ++o4) {
           d4 z = {0.0, 0.0, 0.0, 0.0};
+          if constexpr (!ST) {
+            const double* b3 = vec + 128 + 16 * (4 * oo + o4) + g;
+            z = d4{b3[0], b3[4], b3[8], b3[12]};
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) z = mfma_f64(F3o[((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+              for (int v = 0; v < 4; ++v) z = mfma_f64(F3o[((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+          }
           double dz3[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int p = 16 * (4 * oo + o4) + 4 * v + g;
-            const double t3 = tanh_d(z[v] + vec[128 + p]);
-            const d4 gt = gts[wv][p];
-            const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
-            dz3[v] = dG * (1.0 - t3 * t3);
+            const int a = e_feat3<W>(16 * (4 * oo + o4) + 4 * v + g);
+            const double t3 = ST ? t3v[o4 * 4 + v] : tanh_d(z[v]);
+            double dG = 0.0;
+            if (a >= 0) {
+              const d4 gt = gts[wv][a];
+              dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+            }
+            dz3[v] = a >= 0 ? dG * (1.0 - t3 * t3) : 0.0;
             skip2[o4][v] += dG;
-            T[r16][65 + p] = dz3[v];
+            T[r16][64 + 16 * o4 + 4 * v + g] = dz3[v];
           }
 #pragma unroll
           for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
             for (int v = 0; v < 4; ++v) dh2a[i2] = mfma_f64(B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
         }
-      }
-      wave_lds_sync();
-      // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]
-      {
+        wave_lds_sync();
+        // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]  (q in this half)
         const double one = 1.0;
 #pragma unroll 1
-        for (int qt = 0; qt < 8; ++qt) {
+        for (int qh = 0; qh < 4; ++qh) {
+          const int qt = 4 * oo + qh;
           d4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
           d4 bacc = {0, 0, 0, 0};
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int rr = 4 * ks + g;
-            const double bq = T[rr][65 + 16 * qt + r16];
+            const double bq = T[rr][64 + 16 * qh + r16];
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
             bacc = mfma_f64(one, bq, bacc);
@@ -313,6 +341,7 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
             for (int v = 0; v < 4; ++v) atomicAdd(&aW3[(16 * pt + 4 * v + g) * 128 + 16 * qt + r16], acc[pt][v]);
           if (g == 0) atomicAdd(&aB3[16 * qt + r16], bacc[0]);
         }
+        wave_lds_sync();  // the next half overwrites dz3
       }
       // dz2 = (dh2 + skip)(1 - t2^2); dh1 = W2 dz2 + skip; dz1 = dh1 (1 - t1^2)
       double dz2[4][4], skip1[2][4];
@@ -396,9 +425,9 @@ __global__ __launch_bounds__(64 * kGWPB) void k_embed_grad_f64(EGradArgs A) {
   __syncthreads();
   // slot-indexed block sums -> this work-group's partial record
   double* pr = A.part + ((int64_t)net * A.nslots + blockIdx.x) * kEgRec;
-  for (int k = threadIdx.x; k < 64 * 128; k += 64 * kGWPB) pr[kEgW3 + k] = aW3[k];
-  for (int k = threadIdx.x; k < 32 * 64; k += 64 * kGWPB) pr[kEgW2 + k] = aW2[k];
-  for (int k = threadIdx.x; k < 128; k += 64 * kGWPB) {
+  for (int k = threadIdx.x; k < 64 * 128; k += 64 * GW) pr[kEgW3 + k] = aW3[k];
+  for (int k = threadIdx.x; k < 32 * 64; k += 64 * GW) pr[kEgW2 + k] = aW2[k];
+  for (int k = threadIdx.x; k < 128; k += 64 * GW) {
     pr[kEgB3 + k] = aB3[k];
     if (k < 64) pr[kEgB2 + k] = aB2[k];
     if (k < 32) {
@@ -416,7 +445,7 @@ __global__ void k_egrad_reduce(EGradArgs A) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= kEgRec) return;
   const int ti = net / A.ntypes;
-  const int used = (A.meta[2 * ti] + kGWPB * A.items - 1) / (kGWPB * A.items);
+  const int used = (A.meta[2 * ti] + egw<W>() * A.items - 1) / (egw<W>() * A.items);
   int dst = -1;
   if (k < kEgW2) {
     const int fi = e_feat2<W>(k >> 7), fo = e_feat3<W>(k & 127);
@@ -540,18 +569,26 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
   A.ntypes = nt;
   A.nm = m->nm;
   // columns per wave such that a type's columns need at most nslots work-groups
-  int items = (n + kGWPB * A.nslots - 1) / (kGWPB * A.nslots);
+  const int gw = m->w1 == 25 ? egw<25>() : egw<32>();
+  int items = (n + gw * A.nslots - 1) / (gw * A.nslots);
   A.items = items < 1 ? 1 : items;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= nt ? m->sec[t] : m->nm;
   A.inv_nm = 1.0 / (double)m->nm;
-  const int per_block = kGWPB * A.items;
+  const int per_block = gw * A.items;
   dim3 grid((n + per_block - 1) / per_block, nt * nt);
   dim3 rgrid((kEgRec + 255) / 256, nt * nt);
+  // the forward's stored last-layer activations (FP64 computes that fit the
+  // workspace) replace the recomputation of the last embedding layer
+  A.act = c->act_used_last ? (const double*)c->act : nullptr;
+  A.tpa = m->tpa;
+  for (int t = 0; t <= kMaxT; ++t) A.toff[t] = t <= nt ? m->toff[t] : m->tpa;
   if (m->w1 == 25) {
-    hipLaunchKernelGGL(k_embed_grad_f64<25>, grid, dim3(64 * kGWPB), 0, s, A);
+    if (A.act) hipLaunchKernelGGL((k_embed_grad_f64<25, true>), grid, dim3(64 * gw), 0, s, A);
+    else hipLaunchKernelGGL((k_embed_grad_f64<25, false>), grid, dim3(64 * gw), 0, s, A);
     hipLaunchKernelGGL(k_egrad_reduce<25>, rgrid, dim3(256), 0, s, A);
   } else {
-    hipLaunchKernelGGL(k_embed_grad_f64<32>, grid, dim3(64 * kGWPB), 0, s, A);
+    if (A.act) hipLaunchKernelGGL((k_embed_grad_f64<32, true>), grid, dim3(64 * gw), 0, s, A);
+    else hipLaunchKernelGGL((k_embed_grad_f64<32, false>), grid, dim3(64 * gw), 0, s, A);
     hipLaunchKernelGGL(k_egrad_reduce<32>, rgrid, dim3(256), 0, s, A);
   }
 }

@@ -92,6 +92,32 @@ def test_param_grads_match_oracle(batch):
         assert np.allclose(gx[a0:a1], -F[a0:a1] * 2.0 * (E[f] - b["targets"][f]) / B, atol=1e-12)
 
 
+def test_param_grads_with_stored_activations(batch):
+    """A context whose workspace holds the last embedding layer's activations
+    (FP64 forward stores them; the gradient pass then reads them instead of
+    recomputing that layer) gives the same parameter gradient as the
+    recomputing context, and the oracle's."""
+    b = batch
+    _say("param grads with stored activations")
+    from paper_2410_22867_amd import dpse
+    ctx2 = dpse.Context(b["model"], int(b["off"][-1]), max_frames=len(b["frames"]), budget_bytes=1 << 30)
+    nl2, _ = ctx2.build_nlist_batch(b["x"], b["t"], b["boxes"], b["off"])
+    b2 = dict(b, ctx=ctx2, nl=nl2)
+    L2, E2, g2, _ = _loss_and_grad(b2)
+    assert ctx2.store_info()[1] is True
+    L1, E1, g1, _ = _loss_and_grad(b)
+    assert b["ctx"].store_info()[1] is False
+    scale = np.abs(g1).max()
+    assert np.abs(g2 - g1).max() <= 1e-12 * scale
+    B = len(b["frames"])
+    want = np.zeros_like(g2)
+    for f, fr in enumerate(b["frames"]):
+        dLdE = 2.0 * (E2[f] - b["targets"][f]) / B
+        want += oracle.compute(fr.coords, fr.types, fr.box, b["desc"], b["p"], grad_scale=dLdE)["grad"]
+    assert np.abs(g2 - want).max() <= 1e-9 * np.abs(want).max()
+    ctx2.close()
+
+
 def test_param_grads_finite_differences(batch):
     b = batch
     _say("param grads vs FD")
