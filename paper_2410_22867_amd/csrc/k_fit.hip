@@ -15,6 +15,8 @@
 #include "dp_internal.h"
 #include "dp_device.h"
 
+#include <type_traits>
+
 namespace dpse {
 
 enum { EPI_TANH = 0, EPI_RES = 1, EPI_BWD = 2, EPI_PLAIN = 3 };
@@ -168,9 +170,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ------------------------------------------------- FP64 fitting layer pairs
-// The two equal-width hidden layers after the first, for 16 columns of one
-// centre type per work-group, with the 16 x fw activation tile resident in
-// LDS between them.  Forward: h2 = h1 + tanh(h1 W2 + b2), h3 = h2 +
+// The two equal-width hidden layers after the first, for 16 NCT columns of
+// one centre type per work-group, with the activation tile resident in LDS
+// between them.  Forward: h2 = h1 + tanh(h1 W2 + b2), h3 = h2 +
 // tanh(h2 W3 + b3), E_i = h3 . w_o + b_o + e_bias, plus dz3 = w_o (1 - t3^2)
 // for the backward.  Backward: dh2 = w_o + W3 dz3, dz2 = dh2 (1 - t2^2),
 // dh1 = dh2 + W2 dz2, dz1 = dh1 (1 - t1^2).  Wave w owns m-tiles w, w + 4,
@@ -191,49 +193,65 @@ struct PairArgs {
   double* Ei_atom;
 };
 
-constexpr int kPairCols = 16;
-
-template <bool BWD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_pair_f64(PairArgs p) {
-  extern __shared__ double hs[];  // [kPairCols][fw + 2]
+template <bool BWD, int NCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 3 : 2))) void k_fit_pair_f64(PairArgs p) {
+  constexpr int NC = 16 * NCT;    // columns of the work-group
+  extern __shared__ double hs[];  // [NC][fw + 2]
   const int t = blockIdx.z;
   const int n_t = p.meta[2 * t], cb = p.meta[2 * t + 1];
-  const int c0 = blockIdx.x * kPairCols;
+  const int c0 = blockIdx.x * NC;
   if (c0 >= n_t) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, r16 = lane & 15, gq = lane >> 4;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, gq = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int fw = p.fw, KS = fw / 16, mtiles = fw / 16, ldh = fw + 2;
-  const int64_t col = cb + c0 + r16;
   const double* vec = p.vec + t * p.vec_type_stride;
-  for (int e = threadIdx.x; e < kPairCols * fw; e += 256) {
+  for (int e = threadIdx.x; e < NC * fw; e += 256) {
     const int c = e / fw, k = e - c * fw;
     hs[c * ldh + k] = p.in[(int64_t)(cb + c0 + c) * fw + k];
   }
+  // m-tile slots past the last tile (wave 3 when fw = 240) repeat the last
+  // tile in the products, which keeps the k-loop free of branches; their
+  // results are dropped
   bool own[4];
+  int mtj[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) own[j] = wv + 4 * j < mtiles;
-  // feature of element v of m-tile slot j: 16 (wv + 4 j) + gq + 4 v
-  auto feat = [&](int j, int v) { return 16 * (wv + 4 * j) + gq + 4 * v; };
-  d4 acc[4];
+  for (int j = 0; j < 4; ++j) {
+    own[j] = wv + 4 * j < mtiles;
+    mtj[j] = own[j] ? wv + 4 * j : mtiles - 1;
+  }
+  // element v of m-tile slot j, column tile nt: feature 16 mtj[j] + gq + 4 v
+  // of column c0 + 16 nt + r16
+  auto feat = [&](int j, int v) { return 16 * mtj[j] + gq + 4 * v; };
+  auto colof = [&](int nt) { return (int64_t)cb + c0 + 16 * nt + r16; };
+  auto hrow = [&](int nt) { return hs + (16 * nt + r16) * ldh; };
+  d4 acc[4][NCT];
   auto init = [&](int off) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[j][v] = own[j] ? vec[off + feat(j, v)] : 0.0;
+      for (int v = 0; v < 4; ++v) {
+        const double b = vec[off + feat(j, v)];
+#pragma unroll
+        for (int nt = 0; nt < NCT; ++nt) acc[j][nt][v] = b;
+      }
   };
   auto layer = [&](const double* Afr) {
     d4 aA[4], aB[4];
     auto load = [&](int S, d4* a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (own[j]) a[j] = *reinterpret_cast<const d4*>(Afr + (((int64_t)(wv + 4 * j) * KS + S) * 64 + lane) * 4);
+        a[j] = *reinterpret_cast<const d4*>(Afr + (((int64_t)mtj[j] * KS + S) * 64 + lane) * 4);
     };
     auto step = [&](int S, const d4* a) {
-      const d4 x = *reinterpret_cast<const d4*>(hs + r16 * ldh + 16 * S + 4 * gq);
+      d4 x[NCT];
+#pragma unroll
+      for (int nt = 0; nt < NCT; ++nt) x[nt] = *reinterpret_cast<const d4*>(hrow(nt) + 16 * S + 4 * gq);
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          if (own[j]) acc[j] = mfma_f64(a[j][v], x[v], acc[j]);
+#pragma unroll
+          for (int nt = 0; nt < NCT; ++nt) acc[j][nt] = mfma_f64(a[j][v], x[nt][v], acc[j][nt]);
     };
     load(0, aA);
     int S = 0;
@@ -248,39 +266,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const double* A0 = p.A[0] + t * p.a_type_stride;
   const double* A1 = p.A[1] + t * p.a_type_stride;
   if constexpr (!BWD) {
-#pragma unroll 1
-    for (int l = 0; l < 2; ++l) {
-      init((l + 1) * fw);  // b2, b3
-      __syncthreads();     // the tile (input or previous layer) is complete
-      layer(l == 0 ? A0 : A1);
-      __syncthreads();     // every wave has read the tile
+    // second (LAST false) or third layer with its epilogue: t2 and h2, or h3
+    // and dz3
+    auto fwd_layer = [&](const double* Afr, int bias_off, auto last_tag) {
+      constexpr bool LAST = decltype(last_tag)::value;
+      init(bias_off);
+      __syncthreads();  // the tile (input or previous layer) is complete
+      layer(Afr);
+      __syncthreads();  // every wave has read the tile
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (!own[j]) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = feat(j, v);
-          const double tv = tanh_d(acc[j][v]);
-          const double h = hs[r16 * ldh + m] + tv;
-          hs[r16 * ldh + m] = h;
-          if (l == 0) {
-            p.out[0][col * fw + m] = tv;
-            p.out[1][col * fw + m] = h;
-          } else {
-            p.out[2][col * fw + m] = h;
-            const double wo = vec[3 * fw + m];
-            p.out[3][col * fw + m] = wo * (1.0 - tv * tv);
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // E_i: 16 threads per column, partial dots over features part, part + 16, ...
-    const int c = threadIdx.x >> 4, part = threadIdx.x & 15;
-    double e = 0.0;
-    for (int m = part; m < fw; m += 16) e += hs[c * ldh + m] * vec[3 * fw + m];
+        for (int nt = 0; nt < NCT; ++nt)
 #pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
+          for (int v = 0; v < 4; ++v) {
+            const int m = feat(j, v);
+            const int64_t col = colof(nt);
+            const double tv = tanh_d(acc[j][nt][v]);
+            const double h = hrow(nt)[m] + tv;
+            hrow(nt)[m] = h;
+            if constexpr (!LAST) {
+              p.out[0][col * fw + m] = tv;
+              p.out[1][col * fw + m] = h;
+            } else {
+              p.out[2][col * fw + m] = h;
+              p.out[3][col * fw + m] = vec[3 * fw + m] * (1.0 - tv * tv);
+            }
+          }
+      }
+    };
+    fwd_layer(A0, fw, std::false_type{});
+    fwd_layer(A1, 2 * fw, std::true_type{});
+    __syncthreads();
+    // E_i: TPC threads per column, partial dots over features part, part + TPC, ...
+    constexpr int TPC = 256 / NC;
+    const int c = threadIdx.x / TPC, part = threadIdx.x % TPC;
+    double e = 0.0;
+    for (int m = part; m < fw; m += TPC) e += hs[c * ldh + m] * vec[3 * fw + m];
+#pragma unroll
+    for (int o = TPC / 2; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
     if (part == 0) {
       const int64_t cc = cb + c0 + c;
       const int i = p.atom_at[cc];
@@ -292,11 +317,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
   } else {
     // tanh of the layers below, requested before the products
-    double tp[4][4];
+    double tp[4][NCT][4];
+    auto load_t = [&](const double* src) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tp[j][v] = own[j] ? p.tprev[0][col * fw + feat(j, v)] : 0.0;
+        for (int nt = 0; nt < NCT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) tp[j][nt][v] = src[colof(nt) * fw + feat(j, v)];
+    };
+    load_t(p.tprev[0]);
     init(3 * fw);  // w_o
     __syncthreads();
     layer(A0);     // acc = dh2
@@ -305,35 +335,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int j = 0; j < 4; ++j) {
       if (!own[j]) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = feat(j, v);
-        const double dz = acc[j][v] * (1.0 - tp[j][v] * tp[j][v]);
-        hs[r16 * ldh + m] = dz;
-        p.out[0][col * fw + m] = dz;
-      }
+      for (int nt = 0; nt < NCT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = feat(j, v);
+          const double dz = acc[j][nt][v] * (1.0 - tp[j][nt][v] * tp[j][nt][v]);
+          hrow(nt)[m] = dz;
+          p.out[0][colof(nt) * fw + m] = dz;
+        }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) tp[j][v] = own[j] ? p.tprev[1][col * fw + feat(j, v)] : 0.0;
+    load_t(p.tprev[1]);
     __syncthreads();
     layer(A1);     // acc = dh1 = dh2 + W2 dz2
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (!own[j]) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) p.out[1][col * fw + feat(j, v)] = acc[j][v] * (1.0 - tp[j][v] * tp[j][v]);
+      for (int nt = 0; nt < NCT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          p.out[1][colof(nt) * fw + feat(j, v)] = acc[j][nt][v] * (1.0 - tp[j][nt][v] * tp[j][nt][v]);
     }
   }
 }
 
+// One 16-column tile per work-group (32 columns measured slower: fewer
+// work-groups than the CUs can balance at these sizes).
 static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
+  constexpr int NCT = 1;
   const dp_model* m = c->model;
-  dim3 grid((unsigned)((c->natoms_last + kPairCols - 1) / kPairCols), 1, (unsigned)m->desc.ntypes);
-  const size_t lds = (size_t)kPairCols * (m->fw + 2) * sizeof(double);
+  dim3 grid((unsigned)((c->natoms_last + 16 * NCT - 1) / (16 * NCT)), 1, (unsigned)m->desc.ntypes);
+  const size_t lds = (size_t)16 * NCT * (m->fw + 2) * sizeof(double);
   if (grid.x == 0) return;
-  if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true>), grid, dim3(256), lds, s, p);
-  else hipLaunchKernelGGL((k_fit_pair_f64<false>), grid, dim3(256), lds, s, p);
+  if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true, NCT>), grid, dim3(256), lds, s, p);
+  else hipLaunchKernelGGL((k_fit_pair_f64<false, NCT>), grid, dim3(256), lds, s, p);
 }
 
 // ---------------------------------------------------------------- mixed GEMM
