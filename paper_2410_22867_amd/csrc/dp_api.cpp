@@ -731,6 +731,12 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   c->max_frames = max_frames;
   c->max_cols = max_atoms + (int64_t)m->desc.ntypes * kColPad;
   c->max_cells = max_atoms + 27LL * max_frames + 1024;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu <= 0)
+      ncu = 256;
+    c->ncu = ncu;
+  }
   const int64_t N = max_atoms, C = c->max_cols;
   const int nm = m->nm, m1 = m->m1, nd = m->nd;
   const int fwp = ((m->fw + 31) / 32) * 32;
@@ -762,6 +768,7 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->col_of, N);
   ALLOC(c->atom_at, C);
   ALLOC(c->frame_of, N);
+  ALLOC(c->emb_ctr, (int64_t)kMaxT * kMaxT * 3 * c->ncu * 32);
   ALLOC(c->R, N * nm * 4);
   ALLOC(c->nnei, N * kMaxT);
   ALLOC(c->netd, N * nm * 4);
@@ -838,7 +845,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
-                  c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->R, c->nnei,
+                  c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
                   c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
                   c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
                   c->gpart};

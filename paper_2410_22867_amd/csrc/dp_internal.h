@@ -124,6 +124,8 @@ struct dp_ctx {
   int32_t* col_of;         // [max_atoms]
   int32_t* atom_at;        // [max_cols]
   int32_t* frame_of;       // [max_atoms]
+  int32_t ncu;             // compute units of the device
+  int32_t* emb_ctr;        // [nets][3 ncu][32] next-column counter of each embedding work-group (one per 128-byte line)
   // compute buffers
   double* R;               // [N, nm, 4] f64
   int32_t* nnei;           // [N, kMaxT]

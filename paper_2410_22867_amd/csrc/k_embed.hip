@@ -56,9 +56,10 @@ struct EmbArgs {
   void* act;             // last-layer tanh store [N][tpa][m1][16] (f64 / f32), or NULL
   int tpa;
   int toff[kMaxT];
-  int ntypes, nm, items;
+  int ntypes, nm;
   int sec[kMaxT + 1];
   double inv_nm;
+  int32_t* ctr;          // [nets][gridDim.x][32] per-work-group column counters
 };
 
 // Returns 0 in a register the optimiser cannot see through; added to LDS
@@ -83,18 +84,34 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   return (p >> 6) * 2 * W + (q >> 5) * W + (q & 31);
 }
 
-// Common prologue of the per-net kernels: block (x = column chunk, y = net)
-// handles centre type ti = y / ntypes, neighbour section tj = y % ntypes,
-// columns [cb + x*WPB*items, ...) of the ti segment; wave w takes every
-// WPB-th column of the chunk.
-#define DPSE_NET_PROLOGUE(WPB)                                   \
-  const int net = blockIdx.y;                                    \
-  const int ti = net / A.ntypes, tj = net - ti * A.ntypes;       \
-  const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];       \
-  const int chunk0 = blockIdx.x * (WPB) * A.items;               \
-  if (chunk0 >= n_t) return;                                     \
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;     \
-  const int r16 = lane & 15, g = lane >> 4;
+// Common prologue of the per-net kernels: block y = net handles centre type
+// ti = y / ntypes, neighbour section tj = y % ntypes.  Work assignment: the
+// net's columns are split into gridDim.x contiguous ranges, one per
+// work-group; inside its range a wavefront takes the next column from the
+// work-group's counter (a word in global memory that no other work-group
+// touches, set by the work-group itself before its first barrier; the next
+// column is requested one column ahead so the atomic's latency hides behind
+// the current column) until the range is exhausted.  Each column's work is
+// done by one wavefront, so results do not depend on the assignment; the
+// waves of a work-group end within about one column of each other, whatever
+// the spread of neighbour counts.
+#define DPSE_NET_PROLOGUE(WPB)                                            \
+  const int net = blockIdx.y;                                             \
+  const int ti = net / A.ntypes, tj = net - ti * A.ntypes;                \
+  const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];                \
+  const int c_lo = (int)((int64_t)n_t * blockIdx.x / gridDim.x);          \
+  const int c_hi = (int)((int64_t)n_t * (blockIdx.x + 1) / gridDim.x);    \
+  if (c_lo >= c_hi) return;                                               \
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;              \
+  const int r16 = lane & 15, g = lane >> 4;                               \
+  (void)wv;                                                               \
+  int* const next_col = A.ctr + (net * gridDim.x + blockIdx.x) * 32;      \
+  if (threadIdx.x == 0) atomicExch(next_col, c_lo);                       \
+  auto take = [&]() {                                                     \
+    int k = 0;                                                            \
+    if (lane == 0) k = atomicAdd(next_col, 1);                            \
+    return k;                                                             \
+  };
 
 // FP64 k-step (t, v) covers slots 16t + 4v + {0..3}; with w = 25 the slot
 // groups 28..31 (mod 32) hold only padding, so those k-steps are skipped and
@@ -123,9 +140,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
   __syncthreads();
 
-  for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * WPB + wv;
-    if (c >= n_t) break;
+  for (int c_next = take();;) {
+    const int c = __builtin_amdgcn_readfirstlane(c_next);
+    if (c >= c_hi) break;
+    c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     double accT[N3][4];
@@ -246,9 +264,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
-  for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * WPB + wv;
-    if (c >= n_t) break;
+  for (int c_next = take();;) {
+    const int c = __builtin_amdgcn_readfirstlane(c_next);
+    if (c >= c_hi) break;
+    c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     {
@@ -417,7 +436,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 // MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32,
 // contraction in FP32.
 template <class P, int W, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
@@ -450,9 +469,10 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
 
-  for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * WPB + wv;
-    if (c >= n_t) break;
+  for (int c_next = take();;) {
+    const int c = __builtin_amdgcn_readfirstlane(c_next);
+    if (c >= c_hi) break;
+    c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     float accT[N3][4];
@@ -546,7 +566,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_fwd_lp(EmbArgs A) {
 
 // ============================================================== mixed backward
 template <class P, int W, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
   __shared__ __attribute__((aligned(16))) uint16_t fr[NFR];
@@ -578,9 +598,10 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
     w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
     b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
   }
-  for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * WPB + wv;
-    if (c >= n_t) break;
+  for (int c_next = take();;) {
+    const int c = __builtin_amdgcn_readfirstlane(c_next);
+    if (c >= c_hi) break;
+    c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     {
@@ -723,7 +744,7 @@ __global__ __launch_bounds__(64 * WPB) void k_embed_bwd_lp(EmbArgs A) {
 // of the net's fragments.  The mixed kernels fit 3 work-groups of 4 waves.
 constexpr int kWPB64 = 8, kWPBlp = 4;
 
-static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
+static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
   const dp_model* m = c->model;
   EmbArgs A;
   A.atom_at = c->atom_at;
@@ -745,19 +766,20 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode, int items) {
   for (int t = 0; t < kMaxT; ++t) A.toff[t] = m->toff[t];
   A.ntypes = m->desc.ntypes;
   A.nm = m->nm;
-  A.items = items;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= m->desc.ntypes ? m->sec[t] : m->nm;
   A.inv_nm = 1.0 / (double)m->nm;
+  A.ctr = c->emb_ctr;
   return A;
 }
 
-// Columns per wave: about 1024 work-groups over all nets (4 per CU).
-static int emb_items(dp_ctx* c, int wpb) {
-  const int64_t n = c->natoms_last;
-  int64_t items = (n * c->model->desc.ntypes) / (1024LL * wpb);
-  if (items < 1) items = 1;
-  if (items > 16) items = 16;
-  return (int)items;
+// Work-groups per net: as many as the CUs hold at once (FP64: one 8-wave
+// work-group per CU; mixed: three 4-wave work-groups), fewer when the net
+// has fewer columns than that many waves.  Each takes a contiguous range of
+// the net's columns.
+static unsigned emb_groups(dp_ctx* c, int wpb, int per_cu) {
+  const int64_t need = (c->natoms_last + wpb - 1) / wpb;
+  const int64_t res = (int64_t)c->ncu * per_cu;
+  return (unsigned)(need < res ? need : res);
 }
 
 template <int W, bool ST>
@@ -769,10 +791,8 @@ static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, 
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int wpb = mode == DP_FP64 ? kWPB64 : kWPBlp;
-  const int items = emb_items(c, wpb);
-  EmbArgs A = emb_args(c, mode, items);
-  const int per_block = wpb * items;
-  dim3 grid((unsigned)((c->natoms_last + per_block - 1) / per_block), (unsigned)(A.ntypes * A.ntypes));
+  EmbArgs A = emb_args(c, mode);
+  dim3 grid(emb_groups(c, wpb, mode == DP_FP64 ? 1 : 3), (unsigned)(A.ntypes * A.ntypes));
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
     if (A.act) launch_embed_f64<W, true>(bwd, grid, block, A, s);
