@@ -14,7 +14,10 @@
 //   the activations and deltas are transposed through LDS so that the
 //   reduction over rows is an MFMA product, accumulated in per-work-group LDS
 //   sums that are written to the workspace and summed in work-group order.
-//   No global atomics: the gradient is deterministic.
+//   No global atomics.  The fitting gradients are bitwise deterministic; in
+//   the embedding gradients the LDS sums of a work-group take its waves'
+//   contributions in arrival order, so they can differ in the last bits
+//   from run to run (the work-group records are added in a fixed order).
 #include "dp_internal.h"
 #include "dp_device.h"
 
