@@ -150,7 +150,9 @@ struct EGradArgs {
   double* part;     // [net][slot][kEgRec] partial records
   int nslots;
   int64_t offW[kMaxT * kMaxT][3], offB[kMaxT * kMaxT][3];
-  int ntypes, nm, items;
+  int ntypes, nm;
+  int ngroups;      // work-groups per net (contiguous column ranges)
+  int32_t* ctr;     // [nets][ngroups][32] per-work-group column counters
   int sec[kMaxT + 1];
   double inv_nm;
   // last embedding layer's tanh per 16-row tile of the forward pass
@@ -193,10 +195,24 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
   const int net = blockIdx.y;
   const int ti = net / A.ntypes, tj = net - ti * A.ntypes;
   const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];
-  const int chunk0 = blockIdx.x * GW * A.items;
-  if (chunk0 >= n_t) return;
+  // contiguous column range of this work-group; its waves take the columns
+  // from a counter that only this work-group uses (next one requested ahead)
+  const int c_lo = (int)((int64_t)n_t * blockIdx.x / gridDim.x);
+  const int c_hi = (int)((int64_t)n_t * (blockIdx.x + 1) / gridDim.x);
+  double* pr = A.part + ((int64_t)net * A.nslots + blockIdx.x) * kEgRec;
+  if (c_lo >= c_hi) {
+    for (int k = threadIdx.x; k < kEgRec; k += 64 * GW) pr[k] = 0.0;
+    return;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
+  int* const next_col = A.ctr + (net * gridDim.x + blockIdx.x) * 32;
+  if (threadIdx.x == 0) atomicExch(next_col, c_lo);
+  auto take = [&]() {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(next_col, 1);
+    return k;
+  };
   for (int k = threadIdx.x; k < 64 * 128; k += 64 * GW) aW3[k] = 0.0;
   for (int k = threadIdx.x; k < 32 * 64; k += 64 * GW) aW2[k] = 0.0;
   for (int k = threadIdx.x; k < 128; k += 64 * GW) {
@@ -216,9 +232,10 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
       b1s[mt][v] = vec[32 + 16 * mt + 4 * v + g];
     }
   double (*T)[129] = tb[wv];
-  for (int it = 0; it < A.items; ++it) {
-    const int c = chunk0 + it * GW + wv;
-    if (c >= n_t) break;
+  for (int c_next = take();;) {
+    const int c = __builtin_amdgcn_readfirstlane(c_next);
+    if (c >= c_hi) break;
+    c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     const double wc = A.wcol[col];
@@ -427,7 +444,6 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
   }
   __syncthreads();
   // slot-indexed block sums -> this work-group's partial record
-  double* pr = A.part + ((int64_t)net * A.nslots + blockIdx.x) * kEgRec;
   for (int k = threadIdx.x; k < 64 * 128; k += 64 * GW) pr[kEgW3 + k] = aW3[k];
   for (int k = threadIdx.x; k < 32 * 64; k += 64 * GW) pr[kEgW2 + k] = aW2[k];
   for (int k = threadIdx.x; k < 128; k += 64 * GW) {
@@ -447,8 +463,7 @@ __global__ void k_egrad_reduce(EGradArgs A) {
   const int net = blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= kEgRec) return;
-  const int ti = net / A.ntypes;
-  const int used = (A.meta[2 * ti] + egw<W>() * A.items - 1) / (egw<W>() * A.items);
+  const int used = A.ngroups;
   int dst = -1;
   if (k < kEgW2) {
     const int fi = e_feat2<W>(k >> 7), fo = e_feat3<W>(k & 127);
@@ -571,14 +586,15 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     }
   A.ntypes = nt;
   A.nm = m->nm;
-  // columns per wave such that a type's columns need at most nslots work-groups
+  // one work-group per CU and net (at most nslots records per net)
   const int gw = m->w1 == 25 ? egw<25>() : egw<32>();
-  int items = (n + gw * A.nslots - 1) / (gw * A.nslots);
-  A.items = items < 1 ? 1 : items;
+  int groups = c->ncu < A.nslots ? c->ncu : A.nslots;
+  if ((int64_t)groups * gw > n) groups = (int)((n + gw - 1) / gw);
+  A.ngroups = groups < 1 ? 1 : groups;
+  A.ctr = c->emb_ctr;
   for (int t = 0; t <= kMaxT; ++t) A.sec[t] = t <= nt ? m->sec[t] : m->nm;
   A.inv_nm = 1.0 / (double)m->nm;
-  const int per_block = gw * A.items;
-  dim3 grid((n + per_block - 1) / per_block, nt * nt);
+  dim3 grid(A.ngroups, nt * nt);
   dim3 rgrid((kEgRec + 255) / 256, nt * nt);
   // the forward's stored last-layer activations (FP64 computes that fit the
   // workspace) replace the recomputation of the last embedding layer
