@@ -45,8 +45,15 @@ struct WGradArgs {
   double* part;     // [type][chunk][M][N] partial sums
 };
 
-template <int NTMAX>
-__global__ __launch_bounds__(256) void k_wgrad_cols(WGradArgs a) {
+// Work-group blockIdx.y owns MT m-tiles of out; its wave w owns n-tiles
+// NT w ... NT w + NT - 1 (slots past the last tile repeat it and are not
+// stored), so the four waves read the same X values (served once from L1)
+// and different Y; blockIdx.x = column chunk, blockIdx.z = type.  Per
+// k-step of 4 columns a lane loads one value of X (scaled by w) per m-tile
+// and one of Y per n-tile; the next step's operands are requested before
+// the current products issue (two register buffers used alternately).
+template <int MT, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_wgrad_cols(WGradArgs a) {
   const int t = blockIdx.z;
   const int n_t = a.meta[2 * t], cb = a.meta[2 * t + 1];
   const int c0 = blockIdx.x * a.chunk;
@@ -54,40 +61,58 @@ __global__ __launch_bounds__(256) void k_wgrad_cols(WGradArgs a) {
   const int c1 = min(n_t, c0 + a.chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int mt = blockIdx.y * 4 + wv;
-  if (mt * 16 >= a.M) return;
-  const int ntiles = a.N / 16;
-  d4 acc[NTMAX];
+  const int mtiles = a.M / 16, ntiles = a.N / 16;
+  const int mg = blockIdx.y, ng = wv;
+  if (ng * NT >= ntiles) return;
+  int mt[MT], nt[NT];
 #pragma unroll
-  for (int k = 0; k < NTMAX; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int c = c0; c < c1; c += 8) {  // two k-steps of 4 columns per trip, loads first
-    double xa[2], yb[2][NTMAX];
+  for (int j = 0; j < MT; ++j) mt[j] = min(mg * MT + j, mtiles - 1);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int col = cb + c + 4 * h + g;
-      const bool ok = c + 4 * h + g < c1;
-      const double wc = ok ? a.w[col] : 0.0;
-      xa[h] = ok ? a.X[(int64_t)col * a.ldx + mt * 16 + r16] * wc : 0.0;
+  for (int i = 0; i < NT; ++i) nt[i] = min(ng * NT + i, ntiles - 1);
+  d4 acc[MT][NT];
 #pragma unroll
-      for (int nt = 0; nt < NTMAX; ++nt)
-        yb[h][nt] = (ok && nt < ntiles) ? a.Y[(int64_t)col * a.ldy + nt * 16 + r16] : 0.0;
-    }
+  for (int j = 0; j < MT; ++j)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int i = 0; i < NT; ++i) acc[j][i] = d4{0.0, 0.0, 0.0, 0.0};
+  double xA[MT], yA[NT], xB[MT], yB[NT];
+  auto load = [&](int c, double* xv, double* yv) {
+    const int64_t col = cb + c + g;
+    const bool ok = c + g < c1;
+    const double wc = ok ? a.w[col] : 0.0;
 #pragma unroll
-      for (int nt = 0; nt < NTMAX; ++nt)
-        if (nt < ntiles) acc[nt] = mfma_f64(xa[h], yb[h][nt], acc[nt]);
+    for (int j = 0; j < MT; ++j) xv[j] = ok ? a.X[col * a.ldx + mt[j] * 16 + r16] * wc : 0.0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) yv[i] = ok ? a.Y[col * a.ldy + nt[i] * 16 + r16] : 0.0;
+  };
+  auto step = [&](const double* xv, const double* yv) {
+#pragma unroll
+    for (int j = 0; j < MT; ++j)
+#pragma unroll
+      for (int i = 0; i < NT; ++i) acc[j][i] = mfma_f64(xv[j], yv[i], acc[j][i]);
+  };
+  load(c0, xA, yA);
+  int c = c0;
+  for (; c + 4 < c1; c += 8) {
+    load(c + 4, xB, yB);
+    step(xA, yA);
+    load(c + 8, xA, yA);  // past c1: zero operands
+    step(xB, yB);
   }
+  if (c < c1) step(xA, yA);
   double* out = a.part + ((int64_t)t * a.nchunks + blockIdx.x) * a.M * a.N;
 #pragma unroll
-  for (int nt = 0; nt < NTMAX; ++nt) {
-    if (nt < ntiles)
+  for (int j = 0; j < MT; ++j) {
+    if (mg * MT + j >= mtiles) continue;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      if (ng * NT + i >= ntiles) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = mt * 16 + 4 * v + g;
-        const int n = nt * 16 + r16;
-        out[(int64_t)m * a.N + n] = acc[nt][v];
+        const int m = mt[j] * 16 + 4 * v + g;
+        const int n = nt[i] * 16 + r16;
+        out[(int64_t)m * a.N + n] = acc[j][i][v];
       }
+    }
   }
 }
 
@@ -525,11 +550,8 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
   // Column chunks of a type write partial sums into the workspace, which the
   // next kernel sums in chunk order; launches on one stream reuse it in turn.
   const int fw = m->fw, nd = m->nd;
-  const int nch = c->grad_chunks;
-  int chunk = (n + nch - 1) / nch;
-  chunk = chunk < 64 ? 64 : chunk;
   const int Kin[3] = {nd, fw, fw};
-  auto sum_chunks = [&](int E, int64_t stride, int64_t off) {
+  auto sum_chunks = [&](int E, int chunk, int nch, int64_t stride, int64_t off) {
     hipLaunchKernelGGL(k_sum_chunks, dim3((E + 255) / 256, nt), dim3(256), 0, s, c->gpart, c->type_meta, chunk, nch,
                        E, grad, stride, off);
   };
@@ -542,7 +564,22 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     hipLaunchKernelGGL(k_sum_chunks, dim3((N + 255) / 256, nt), dim3(256), 0, s, c->gpart, c->type_meta, bchunk, bnch,
                        N, grad, stride, off);
   };
+  // column chunks per layer: about two waves per SIMD in one round (4 x 4
+  // tiles per wave, four waves per work-group cover 16 n-tiles), within the
+  // workspace (sized for grad_chunks chunks of the first layer), chunks of
+  // at least 64 columns
+  constexpr int WMT = 4, WNT = 4;
+  const int64_t cap = (int64_t)c->grad_chunks * nd * fw;  // per type
   for (int l = 0; l < 3; ++l) {
+    const int mgroups = (Kin[l] / 16 + WMT - 1) / WMT;
+    int64_t want = (2LL * c->ncu) / ((int64_t)mgroups * nt);
+    if (want < 1) want = 1;
+    const int64_t fit = cap / ((int64_t)Kin[l] * fw);
+    const int64_t most = (n + 63) / 64;
+    if (want > fit) want = fit;
+    if (want > most) want = most;
+    const int nch = (int)(want < 1 ? 1 : want);
+    const int chunk = (n + nch - 1) / nch;
     WGradArgs a = {};
     a.X = in.X[l];
     a.ldx = in.ldx[l];
@@ -555,9 +592,9 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
     a.chunk = chunk;
     a.nchunks = nch;
     a.part = c->gpart;
-    dim3 grid(nch, (Kin[l] / 16 + 3) / 4, nt);
-    hipLaunchKernelGGL((k_wgrad_cols<16>), grid, dim3(256), 0, s, a);
-    sum_chunks(Kin[l] * fw, m->fit_param_stride, m->fit_param_off[l]);
+    dim3 grid(nch, mgroups, nt);
+    hipLaunchKernelGGL((k_wgrad_cols<WMT, WNT>), grid, dim3(256), 0, s, a);
+    sum_chunks(Kin[l] * fw, chunk, nch, m->fit_param_stride, m->fit_param_off[l]);
     bgrad(in.dz[l], fw, m->fit_param_stride, m->fit_param_off[3 + l]);
   }
   // w_out: sum w h3; b_out and e_bias: sum w
