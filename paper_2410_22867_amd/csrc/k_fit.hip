@@ -193,8 +193,9 @@ struct PairArgs {
   double* Ei_atom;
 };
 
-template <bool BWD, int NCT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 3 : 2))) void k_fit_pair_f64(PairArgs p) {
+template <bool BWD, int NCT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 3 : 6))) void k_fit_pair_f64(PairArgs p) {
+  constexpr int MW = 16 / NW;      // m-tile slots per wave (fw <= 256)
   constexpr int NC = 16 * NCT;    // columns of the work-group
   extern __shared__ double hs[];  // [NC][fw + 2]
   const int t = blockIdx.z;
@@ -205,29 +206,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int fw = p.fw, KS = fw / 16, mtiles = fw / 16, ldh = fw + 2;
   const double* vec = p.vec + t * p.vec_type_stride;
-  for (int e = threadIdx.x; e < NC * fw; e += 256) {
+  for (int e = threadIdx.x; e < NC * fw; e += 64 * NW) {
     const int c = e / fw, k = e - c * fw;
     hs[c * ldh + k] = p.in[(int64_t)(cb + c0 + c) * fw + k];
   }
   // m-tile slots past the last tile (wave 3 when fw = 240) repeat the last
   // tile in the products, which keeps the k-loop free of branches; their
   // results are dropped
-  bool own[4];
-  int mtj[4];
+  bool own[MW];
+  int mtj[MW];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    own[j] = wv + 4 * j < mtiles;
-    mtj[j] = own[j] ? wv + 4 * j : mtiles - 1;
+  for (int j = 0; j < MW; ++j) {
+    own[j] = wv + NW * j < mtiles;
+    mtj[j] = own[j] ? wv + NW * j : mtiles - 1;
   }
   // element v of m-tile slot j, column tile nt: feature 16 mtj[j] + gq + 4 v
   // of column c0 + 16 nt + r16
   auto feat = [&](int j, int v) { return 16 * mtj[j] + gq + 4 * v; };
   auto colof = [&](int nt) { return (int64_t)cb + c0 + 16 * nt + r16; };
   auto hrow = [&](int nt) { return hs + (16 * nt + r16) * ldh; };
-  d4 acc[4][NCT];
+  d4 acc[MW][NCT];
   auto init = [&](int off) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < MW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double b = vec[off + feat(j, v)];
@@ -236,10 +237,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
       }
   };
   auto layer = [&](const double* Afr) {
-    d4 aA[4], aB[4];
+    d4 aA[MW], aB[MW];
     auto load = [&](int S, d4* a) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < MW; ++j)
         a[j] = *reinterpret_cast<const d4*>(Afr + (((int64_t)mtj[j] * KS + S) * 64 + lane) * 4);
     };
     auto step = [&](int S, const d4* a) {
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < MW; ++j)
 #pragma unroll
           for (int nt = 0; nt < NCT; ++nt) acc[j][nt] = mfma_f64(a[j][v], x[nt][v], acc[j][nt]);
     };
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
       layer(Afr);
       __syncthreads();  // every wave has read the tile
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < MW; ++j) {
         if (!own[j]) continue;
 #pragma unroll
         for (int nt = 0; nt < NCT; ++nt)
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
     fwd_layer(A1, 2 * fw, std::true_type{});
     __syncthreads();
     // E_i: TPC threads per column, partial dots over features part, part + TPC, ...
-    constexpr int TPC = 256 / NC;
+    constexpr int TPC = 64 * NW / NC;
     const int c = threadIdx.x / TPC, part = threadIdx.x % TPC;
     double e = 0.0;
     for (int m = part; m < fw; m += TPC) e += hs[c * ldh + m] * vec[3 * fw + m];
@@ -317,10 +318,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
     }
   } else {
     // tanh of the layers below, requested before the products
-    double tp[4][NCT][4];
+    double tp[MW][NCT][4];
     auto load_t = [&](const double* src) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < MW; ++j)
 #pragma unroll
         for (int nt = 0; nt < NCT; ++nt)
 #pragma unroll
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
     layer(A0);     // acc = dh2
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < MW; ++j) {
       if (!own[j]) continue;
 #pragma unroll
       for (int nt = 0; nt < NCT; ++nt)
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
     __syncthreads();
     layer(A1);     // acc = dh1 = dh2 + W2 dz2
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < MW; ++j) {
       if (!own[j]) continue;
 #pragma unroll
       for (int nt = 0; nt < NCT; ++nt)
@@ -359,16 +360,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT == 1 ? 
   }
 }
 
-// One 16-column tile per work-group (32 columns measured slower: fewer
-// work-groups than the CUs can balance at these sizes).
+// One 16-column tile per work-group and four waves of four m-tile slots
+// (32 columns, or eight waves of two slots, measured no faster).
 static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
-  constexpr int NCT = 1;
+  constexpr int NCT = 1, NW = 4;
   const dp_model* m = c->model;
   dim3 grid((unsigned)((c->natoms_last + 16 * NCT - 1) / (16 * NCT)), 1, (unsigned)m->desc.ntypes);
   const size_t lds = (size_t)16 * NCT * (m->fw + 2) * sizeof(double);
   if (grid.x == 0) return;
-  if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true, NCT>), grid, dim3(256), lds, s, p);
-  else hipLaunchKernelGGL((k_fit_pair_f64<false, NCT>), grid, dim3(256), lds, s, p);
+  if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true, NCT, NW>), grid, dim3(64 * NW), lds, s, p);
+  else hipLaunchKernelGGL((k_fit_pair_f64<false, NCT, NW>), grid, dim3(64 * NW), lds, s, p);
 }
 
 // ---------------------------------------------------------------- mixed GEMM
