@@ -19,7 +19,7 @@
 
 namespace dpse {
 
-enum { EPI_TANH = 0, EPI_RES = 1, EPI_BWD = 2, EPI_PLAIN = 3 };
+enum { EPI_TANH = 0, EPI_PLAIN = 1 };
 
 struct GemmArgs {
   const void* Afr;       // fragments of this layer for type 0
@@ -34,18 +34,8 @@ struct GemmArgs {
   const void* vec;       // per-type fitting vectors (b1 b2 b3 wo | bo ebias)
   int64_t vec_type_stride;
   int bias_off;          // offset of the bias of this layer inside the vector block
-  int wo_off;
-  // epilogue operands (f64 or f32)
-  const void* res;       // EPI_RES: skip input [cols][ldr]; EPI_BWD: dh of the layer above or null (= wo)
-  int ldr;
-  const void* tprev;     // EPI_BWD: tanh of the layer below [cols][ldt]
-  int ldt;
-  void* out0;            // EPI_TANH/RES: tanh t; EPI_BWD: dh; EPI_PLAIN: out
+  void* out0;            // EPI_TANH: tanh(acc + bias); EPI_PLAIN: acc  (f64 or f32, [cols][ld0])
   int ld0;
-  void* out1;            // EPI_RES: h = res + t; EPI_BWD: dz
-  int ld1;
-  void* outlp;           // lp copy for the next GEMM (mixed): EPI_TANH/RES: h; EPI_BWD: dz
-  int ldlp;
   const double* T;       // FP64 layer 1: X[col][a*16 + b] = sum_k T[col][a][k] T[col][b][k] built on the fly
   int m1;
 };
@@ -151,18 +141,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int m = (mt0 + mt) * 16 + gq + 4 * v;
         if (g.epi == EPI_PLAIN) {
           reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = a[v];
-        } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
-          const double tv = tanh_d(a[v] + vec[g.bias_off + m]);
-          reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = tv;
-          if (g.epi == EPI_RES)
-            reinterpret_cast<double*>(g.out1)[col * g.ld1 + m] =
-                reinterpret_cast<const double*>(g.res)[col * g.ldr + m] + tv;
-        } else {  // EPI_BWD: dh = acc + (res ? res : wo); dz = dh (1 - tprev^2)
-          const double r = g.res ? reinterpret_cast<const double*>(g.res)[col * g.ldr + m] : vec[g.wo_off + m];
-          const double tp = reinterpret_cast<const double*>(g.tprev)[col * g.ldt + m];
-          const double dh = a[v] + r;
-          if (g.out0) reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = dh;
-          reinterpret_cast<double*>(g.out1)[col * g.ld1 + m] = dh * (1.0 - tp * tp);
+        } else {
+          reinterpret_cast<double*>(g.out0)[col * g.ld0 + m] = tanh_d(a[v] + vec[g.bias_off + m]);
         }
       }
     }
@@ -383,36 +363,14 @@ __device__ __forceinline__ void store4lp(uint16_t* p, const float* v) {
 // of column col.
 template <class P>
 __device__ __forceinline__ void epi_lp(const GemmArgs& g, const float* vec, int64_t col, int m0, const f4 a) {
+  float* out = reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0;
   if (g.epi == EPI_PLAIN) {
-    *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = a;
-  } else if (g.epi == EPI_TANH || g.epi == EPI_RES) {
-    f4 r = {0.f, 0.f, 0.f, 0.f};
-    if (g.epi == EPI_RES) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
-    float tv[4], hv[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      tv[v] = tanh_f(a[v] + vec[g.bias_off + m0 + v]);
-      hv[v] = r[v] + tv[v];
-    }
-    *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
-    if (g.out1)
-      *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out1) + col * g.ld1 + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
-    if (g.outlp) store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, hv);
+    *reinterpret_cast<f4*>(out) = a;
   } else {
-    f4 r;
-    if (g.res) r = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.res) + col * g.ldr + m0);
-    else
+    float tv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) r[v] = vec[g.wo_off + m0 + v];
-    const f4 tp = *reinterpret_cast<const f4*>(reinterpret_cast<const float*>(g.tprev) + col * g.ldt + m0);
-    float dh[4], dz[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      dh[v] = a[v] + r[v];
-      dz[v] = dh[v] * (1.f - tp[v] * tp[v]);
-    }
-    if (g.out0) *reinterpret_cast<f4*>(reinterpret_cast<float*>(g.out0) + col * g.ld0 + m0) = f4{dh[0], dh[1], dh[2], dh[3]};
-    store4lp<P>(reinterpret_cast<uint16_t*>(g.outlp) + col * g.ldlp + m0, dz);
+    for (int v = 0; v < 4; ++v) tv[v] = tanh_f(a[v] + vec[g.bias_off + m0 + v]);
+    *reinterpret_cast<f4*>(out) = f4{tv[0], tv[1], tv[2], tv[3]};
   }
 }
 
@@ -522,6 +480,209 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   }
 }
 
+// --------------------------------------------- mixed fitting layer pairs
+// The layer pair of k_fit_pair_f64 in the mixed forms: BF16/FP16 operands,
+// FP32 accumulation, tanh and skips.  The 16-column tile stays in LDS: FP32
+// activations in the forward (the skips add in FP32; each k-step's B operand
+// is converted from them), half-precision deltas in the backward (the B
+// operand as the unfused GEMM reads it).  K is padded to fwp = 32-multiple
+// with zeros.  Forward writes t2, h2, h3 (FP32), dz3 (half) and E_i;
+// backward writes dz2 and dz1 (half).
+struct PairArgsLp {
+  const int32_t* meta;
+  const int32_t* atom_at;
+  int fw, fwp;
+  const void* in;          // forward: h1 (FP32, ld fwp); backward: dz3 (half, ld fwp)
+  const uint16_t* A[2];    // fragments of the first and second layer, type 0
+  int64_t a_type_stride;
+  const float* vec;        // per-type fitting vectors (b1 b2 b3 wo | bo ebias)
+  int64_t vec_type_stride;
+  const float* tprev[2];   // backward: t2, t1 (FP32)
+  float* out[3];           // forward: t2, h2, h3
+  uint16_t* outlp[2];      // forward: dz3; backward: dz2, dz1
+  double* Ei_col;
+  double* Ei_atom;
+};
+
+template <class P, bool BWD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_pair_lp(PairArgsLp p) {
+  constexpr int NC = 16, NW = 4, MW = 4;
+  // forward: FP32 tile [16][fwp + 4]; backward: half tile [16][fwp + 8]
+  extern __shared__ __attribute__((aligned(16))) float hsf[];
+  uint16_t* const hsh = reinterpret_cast<uint16_t*>(hsf);
+  const int t = blockIdx.z;
+  const int n_t = p.meta[2 * t], cb = p.meta[2 * t + 1];
+  const int c0 = blockIdx.x * NC;
+  if (c0 >= n_t) return;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, gq = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fw = p.fw, fwp = p.fwp, KT = fwp / 32, mtiles = fw / 16;
+  const int ldf = fwp + 4, ldh = fwp + 8;
+  const float* vec = p.vec + t * p.vec_type_stride;
+  const int64_t col = cb + c0 + r16;
+  for (int e = threadIdx.x; e < NC * fwp; e += 64 * NW) {
+    const int c = e / fwp, k = e - c * fwp;
+    const int64_t src = (int64_t)(cb + c0 + c) * fwp + k;
+    if constexpr (BWD) hsh[c * ldh + k] = k < fw ? reinterpret_cast<const uint16_t*>(p.in)[src] : (uint16_t)0;
+    else hsf[c * ldf + k] = k < fw ? reinterpret_cast<const float*>(p.in)[src] : 0.f;
+  }
+  bool own[MW];
+  int mtj[MW];
+#pragma unroll
+  for (int j = 0; j < MW; ++j) {
+    own[j] = wv + NW * j < mtiles;
+    mtj[j] = own[j] ? wv + NW * j : mtiles - 1;
+  }
+  // element v of m-tile slot j: feature 16 mtj[j] + 4 gq + v of column c0 + r16
+  auto feat = [&](int j, int v) { return 16 * mtj[j] + 4 * gq + v; };
+  f4 acc[MW];
+  auto layer = [&](const uint16_t* Afr) {
+    u16x8 aA[MW], aB[MW];
+    auto load = [&](int kt, u16x8* a) {
+#pragma unroll
+      for (int j = 0; j < MW; ++j)
+        a[j] = *reinterpret_cast<const u16x8*>(Afr + (((int64_t)mtj[j] * KT + kt) * 64 + lane) * 8);
+    };
+    auto step = [&](int kt, const u16x8* a) {
+      // B operand: features 32 kt + 4 gq + {0..3} and 32 kt + 16 + 4 gq + {0..3}
+      typename P::vec8 x;
+      if constexpr (BWD) {
+        const uint16_t* rowp = hsh + r16 * ldh + 32 * kt + 4 * gq;
+        const u16x4 lo = *reinterpret_cast<const u16x4*>(rowp);
+        const u16x4 hi = *reinterpret_cast<const u16x4*>(rowp + 16);
+        x = __builtin_bit_cast(typename P::vec8, u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+      } else {
+        const float* rowp = hsf + r16 * ldf + 32 * kt + 4 * gq;
+        const f4 lo = *reinterpret_cast<const f4*>(rowp);
+        const f4 hi = *reinterpret_cast<const f4*>(rowp + 16);
+        const float v8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        x = pack8<P>(v8);
+      }
+#pragma unroll
+      for (int j = 0; j < MW; ++j) acc[j] = P::mfma(__builtin_bit_cast(typename P::vec8, a[j]), x, acc[j]);
+    };
+    load(0, aA);
+    int kt = 0;
+    for (; kt + 1 < KT; kt += 2) {
+      load(kt + 1, aB);
+      step(kt, aA);
+      load(kt + 2 < KT ? kt + 2 : KT - 1, aA);
+      step(kt + 1, aB);
+    }
+    if (kt < KT) step(kt, aA);
+  };
+  const uint16_t* A0 = p.A[0] + t * p.a_type_stride;
+  const uint16_t* A1 = p.A[1] + t * p.a_type_stride;
+  if constexpr (!BWD) {
+    auto fwd_layer = [&](const uint16_t* Afr, int bias_off, auto last_tag) {
+      constexpr bool LAST = decltype(last_tag)::value;
+#pragma unroll
+      for (int j = 0; j < MW; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[j][v] = vec[bias_off + feat(j, v)];
+      __syncthreads();  // the tile (input or previous layer) is complete
+      layer(Afr);
+      __syncthreads();  // every wave has read the tile
+#pragma unroll
+      for (int j = 0; j < MW; ++j) {
+        if (!own[j]) continue;
+        const int m0 = feat(j, 0);
+        float* hrow = hsf + r16 * ldf + m0;
+        const f4 hprev = *reinterpret_cast<const f4*>(hrow);
+        float tv[4], hv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          tv[v] = tanh_f(acc[j][v]);
+          hv[v] = hprev[v] + tv[v];
+        }
+        *reinterpret_cast<f4*>(hrow) = f4{hv[0], hv[1], hv[2], hv[3]};
+        if constexpr (!LAST) {
+          *reinterpret_cast<f4*>(p.out[0] + col * fwp + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
+          *reinterpret_cast<f4*>(p.out[1] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+        } else {
+          *reinterpret_cast<f4*>(p.out[2] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+          float dz[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dz[v] = vec[3 * fw + m0 + v] * (1.f - tv[v] * tv[v]);
+          store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
+        }
+      }
+    };
+    fwd_layer(A0, fw, std::false_type{});
+    fwd_layer(A1, 2 * fw, std::true_type{});
+    __syncthreads();
+    // E_i (summed in FP64 over the FP32 h3 w_o products): 16 threads per column
+    const int c = threadIdx.x >> 4, part = threadIdx.x & 15;
+    double e = 0.0;
+    for (int m = part; m < fw; m += 16) e += (double)(hsf[c * ldf + m] * vec[3 * fw + m]);
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
+    if (part == 0) {
+      const int64_t cc = cb + c0 + c;
+      const int i = p.atom_at[cc];
+      if (i >= 0) {
+        const double E = e + (double)vec[4 * fw] + (double)vec[4 * fw + 1];
+        p.Ei_col[cc] = E;
+        p.Ei_atom[i] = E;
+      }
+    }
+  } else {
+    float tp[MW][4];
+    auto load_t = [&](const float* src) {
+#pragma unroll
+      for (int j = 0; j < MW; ++j) {
+        const f4 x = *reinterpret_cast<const f4*>(src + col * fwp + feat(j, 0));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tp[j][v] = x[v];
+      }
+    };
+    load_t(p.tprev[0]);
+#pragma unroll
+    for (int j = 0; j < MW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[j][v] = vec[3 * fw + feat(j, v)];  // w_o
+    __syncthreads();
+    layer(A0);  // acc = dh2
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      if (!own[j]) continue;
+      const int m0 = feat(j, 0);
+      float dz[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
+      store4lp<P>(hsh + r16 * ldh + m0, dz);
+      store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
+    }
+    load_t(p.tprev[1]);
+    __syncthreads();
+    layer(A1);  // acc = dh1 = dh2 + W2 dz2
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      if (!own[j]) continue;
+      const int m0 = feat(j, 0);
+      float dz[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
+      store4lp<P>(p.outlp[1] + col * fwp + m0, dz);
+    }
+  }
+}
+
+static void launch_pair_lp(dp_ctx* c, bool bwd, int mode, const PairArgsLp& p, hipStream_t s) {
+  const dp_model* m = c->model;
+  dim3 grid((unsigned)((c->natoms_last + 15) / 16), 1, (unsigned)m->desc.ntypes);
+  const size_t lds = bwd ? (size_t)16 * (p.fwp + 8) * 2 : (size_t)16 * (p.fwp + 4) * 4;
+  if (grid.x == 0) return;
+  if (mode == DP_MIX_BF16) {
+    if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<PrecBF16, true>), grid, dim3(256), lds, s, p);
+    else hipLaunchKernelGGL((k_fit_pair_lp<PrecBF16, false>), grid, dim3(256), lds, s, p);
+  } else {
+    if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<PrecF16, true>), grid, dim3(256), lds, s, p);
+    else hipLaunchKernelGGL((k_fit_pair_lp<PrecF16, false>), grid, dim3(256), lds, s, p);
+  }
+}
+
 // ---------------------------------------------------------------- descriptor
 // D[a*m2 + b] = sum_k T[a][k] T[b][k], a < m1, b < m2 (m2 = 16).  One
 // work-group per column, thread a writes 16 consecutive entries.
@@ -597,44 +758,13 @@ __global__ __launch_bounds__(128) void k_desc_bwd(const int32_t* __restrict__ at
   for (int k = 0; k < 4; ++k) gT[((int64_t)col * m1 + a) * 4 + k] = acc[k];
 }
 
-// ---------------------------------------------------------------- fit output
-// E_i = h3 . w_out + b_out + e_bias[t]; dz3 = w_out (1 - t3^2).  One
-// wavefront per column.
-template <typename FT, class P>
-__global__ __launch_bounds__(256) void k_fit_out(const int32_t* __restrict__ atom_at, const int32_t* __restrict__ types,
-                                                 const FT* __restrict__ h3, const FT* __restrict__ t3, int ld,
-                                                 const FT* __restrict__ vec, int64_t vstride, int wo_off, int fw,
-                                                 void* __restrict__ dz3, int lddz, double* __restrict__ Ei_col,
-                                                 double* __restrict__ Ei_atom, int ncols, int ntypes) {
-  const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (col >= ncols) return;
-  const int i = atom_at[col];
-  if (i < 0) return;
-  const int t = min(max(types[i], 0), ntypes - 1);
-  const FT* v = vec + t * vstride;
-  double acc = 0.0;
-  for (int m = lane; m < fw; m += 64) {
-    const FT wo = v[wo_off + m];
-    acc += (double)(h3[(int64_t)col * ld + m] * wo);
-    const FT tt = t3[(int64_t)col * ld + m];
-    const FT dz = wo * ((FT)1 - tt * tt);
-    if constexpr (sizeof(FT) == 8) reinterpret_cast<double*>(dz3)[(int64_t)col * lddz + m] = dz;
-    else reinterpret_cast<uint16_t*>(dz3)[(int64_t)col * lddz + m] = P::bits(dz);
-  }
-  acc = wave_sum_d(acc);
-  if (lane == 0) {
-    const double e = acc + (double)v[wo_off + fw] + (double)v[wo_off + fw + 1];
-    Ei_col[col] = e;
-    Ei_atom[i] = e;
-  }
-}
-
 // ---------------------------------------------------------------- launchers
 // Activation buffer slots in dp_ctx::fa (FP64 / mixed):
-//   FP64 : 0 t1(=h1) 1 t2 2 h2 4 h3 5 dz3 7 dz2 8 dz1 [cols][fw] (3, 6 unused)
-//   mixed: 0 t1 1 t2 2 h2 3 t3 4 h3 (f32 [cols][fwp]); 5 h1lp 6 h2lp 7 dz3lp
-//          8 dz2lp 9 dz1lp (lp [cols][fwp]); 10 dh2 (f32)
+//   FP64 : 0 t1(=h1) 1 t2 2 h2 4 h3 5 dz3 7 dz2 8 dz1 [cols][fw]
+//   mixed: 0 t1 1 t2 2 h2 4 h3 (f32 [cols][fwp]); 7 dz3 8 dz2 9 dz1 (half
+//          [cols][fwp])
+// The other slots are free; the parameter gradients after a mixed compute
+// use them for FP64 copies.
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
 template <int MT, int NT>
 static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
@@ -675,7 +805,6 @@ static GemmArgs gemm_base(dp_ctx* c, int mode) {
   g.meta = c->type_meta;
   g.vec = mode == DP_FP64 ? (const void*)m->fit_vec64 : (const void*)m->fit_vec32;
   g.vec_type_stride = m->fit_vec_per_type;
-  g.wo_off = 3 * m->fw;
   return g;
 }
 
@@ -713,33 +842,28 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
   if (c->natoms_last <= 0) return;
   const int fw = m->fw;
   const int fwp = ((fw + 31) / 32) * 32;
-  const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
   GemmArgs g = gemm_base(c, mode);
   const bool f64 = mode == DP_FP64;
   const void* frag = f64 ? (const void*)m->fit_frag64
                          : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
   const int64_t* off_fwd = f64 ? m->ffo.fwd : m->ffo_lp.fwd;
   const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
-  const int ld = f64 ? fw : fwp;
-  // layer 1: X = D [cols][nd]
+  // layer 1: X = D [cols][nd] (FP64: built from T inside the GEMM)
   g.a_type_stride = tstride;
   g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[0]) : (const void*)((const uint16_t*)frag + off_fwd[0]);
   g.X = c->D;
   g.ldx = m->nd;
   g.K = m->nd;
   g.Kreal = m->nd;
-  g.T = f64 ? (const double*)c->T : nullptr;  // FP64: descriptor built inside the GEMM
+  g.T = f64 ? (const double*)c->T : nullptr;
   g.m1 = m->m1;
   g.M = fw;
   g.epi = EPI_TANH;
   g.bias_off = 0;
   g.out0 = c->fa[0];
-  g.ld0 = ld;
-  g.out1 = nullptr;
-  g.outlp = f64 ? nullptr : c->fa[5];
-  g.ldlp = fwp;
+  g.ld0 = f64 ? fw : fwp;
   gemm_launch(c, g, mode, s);
-  g.T = nullptr;
+  // layers 2, 3 and the output layer
   if (f64) {
     PairArgs p = {};
     p.meta = c->type_meta;
@@ -758,47 +882,26 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.Ei_col = c->Ei_col;
     p.Ei_atom = c->Ei_atom;
     launch_pair_f64(c, false, p, s);
-    return;
+  } else {
+    PairArgsLp p = {};
+    p.meta = c->type_meta;
+    p.atom_at = c->atom_at;
+    p.fw = fw;
+    p.fwp = fwp;
+    p.in = c->fa[0];
+    p.A[0] = (const uint16_t*)frag + off_fwd[1];
+    p.A[1] = (const uint16_t*)frag + off_fwd[2];
+    p.a_type_stride = tstride;
+    p.vec = m->fit_vec32;
+    p.vec_type_stride = m->fit_vec_per_type;
+    p.out[0] = (float*)c->fa[1];
+    p.out[1] = (float*)c->fa[2];
+    p.out[2] = (float*)c->fa[4];
+    p.outlp[0] = (uint16_t*)c->fa[7];
+    p.Ei_col = c->Ei_col;
+    p.Ei_atom = c->Ei_atom;
+    launch_pair_lp(c, false, mode, p, s);
   }
-  // layers 2, 3
-  for (int l = 1; l < 3; ++l) {
-    g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[l]) : (const void*)((const uint16_t*)frag + off_fwd[l]);
-    if (f64) {
-      g.X = l == 1 ? c->fa[0] : c->fa[2];
-      g.ldx = fw;
-      g.K = fw;
-      g.Kreal = fw;
-      g.res = g.X;
-    } else {
-      g.X = l == 1 ? c->fa[5] : c->fa[6];
-      g.ldx = fwp;
-      g.K = fwp;
-      g.Kreal = fw;
-      g.res = l == 1 ? c->fa[0] : c->fa[2];
-    }
-    g.ldr = ld;
-    g.epi = EPI_RES;
-    g.bias_off = l * fw;
-    g.out0 = l == 1 ? c->fa[1] : c->fa[3];
-    g.out1 = l == 1 ? c->fa[2] : c->fa[4];
-    g.ld1 = ld;
-    g.outlp = f64 ? nullptr : (l == 1 ? c->fa[6] : nullptr);
-    gemm_launch(c, g, mode, s);
-  }
-  // output
-  dim3 grid((ncols + 3) / 4);
-  if (f64)
-    hipLaunchKernelGGL((k_fit_out<double, PrecBF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
-                       (const double*)c->fa[4], (const double*)c->fa[3], ld, m->fit_vec64, m->fit_vec_per_type,
-                       3 * fw, fw, c->fa[5], ld, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
-  else if (mode == DP_MIX_BF16)
-    hipLaunchKernelGGL((k_fit_out<float, PrecBF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
-                       (const float*)c->fa[4], (const float*)c->fa[3], ld, m->fit_vec32, m->fit_vec_per_type, 3 * fw,
-                       fw, c->fa[7], fwp, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
-  else
-    hipLaunchKernelGGL((k_fit_out<float, PrecF16>), grid, dim3(256), 0, s, c->atom_at, c->types_last,
-                       (const float*)c->fa[4], (const float*)c->fa[3], ld, m->fit_vec32, m->fit_vec_per_type, 3 * fw,
-                       fw, c->fa[7], fwp, c->Ei_col, c->Ei_atom, ncols, m->desc.ntypes);
 }
 
 void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
@@ -811,14 +914,9 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
                          : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
   const int64_t* off_bwd = f64 ? m->ffo.bwd : m->ffo_lp.bwd;
   const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
-  const int ld = f64 ? fw : fwp;
-  GemmArgs g = gemm_base(c, mode);
-  g.a_type_stride = tstride;
-  auto fr = [&](int l) {
-    return f64 ? (const void*)((const double*)frag + off_bwd[l]) : (const void*)((const uint16_t*)frag + off_bwd[l]);
-  };
+  // layers 3 and 2: dh2 = w_out + W3 dz3, dz2 = dh2 (1 - t2^2), dh1 = dh2 +
+  // W2 dz2, dz1 = dh1 (1 - t1^2)
   if (f64) {
-    // layers 3 and 2 in one pass: dz2 -> fa[7], dz1 -> fa[8]
     PairArgs p = {};
     p.meta = c->type_meta;
     p.fw = fw;
@@ -834,48 +932,34 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.out[1] = (double*)c->fa[8];
     launch_pair_f64(c, true, p, s);
   } else {
-    // layer 3: dh2 = w_out + W3 dz3 ; dz2 = dh2 (1 - t2^2)
-    g.Afr = fr(2);
-    g.X = c->fa[7];
-    g.ldx = ld;
-    g.K = ld;
-    g.Kreal = fw;
-    g.M = fw;
-    g.epi = EPI_BWD;
-    g.res = nullptr;
-    g.tprev = c->fa[1];
-    g.ldt = ld;
-    g.out0 = c->fa[10];
-    g.ld0 = ld;
-    g.out1 = nullptr;
-    g.ld1 = ld;
-    g.outlp = c->fa[8];
-    g.ldlp = fwp;
-    gemm_launch(c, g, mode, s);
-    // layer 2: dh1 = dh2 + W2 dz2 ; dz1 = dh1 (1 - t1^2)
-    g.Afr = fr(1);
-    g.X = c->fa[8];
-    g.res = c->fa[10];
-    g.ldr = ld;
-    g.tprev = c->fa[0];
-    g.out0 = nullptr;
-    g.out1 = nullptr;
-    g.outlp = c->fa[9];
-    gemm_launch(c, g, mode, s);
+    PairArgsLp p = {};
+    p.meta = c->type_meta;
+    p.fw = fw;
+    p.fwp = fwp;
+    p.in = c->fa[7];
+    p.A[0] = (const uint16_t*)frag + off_bwd[2];
+    p.A[1] = (const uint16_t*)frag + off_bwd[1];
+    p.a_type_stride = tstride;
+    p.vec = m->fit_vec32;
+    p.vec_type_stride = m->fit_vec_per_type;
+    p.tprev[0] = (const float*)c->fa[1];
+    p.tprev[1] = (const float*)c->fa[0];
+    p.outlp[0] = (uint16_t*)c->fa[8];
+    p.outlp[1] = (uint16_t*)c->fa[9];
+    launch_pair_lp(c, true, mode, p, s);
   }
   // layer 1: dD = W1 dz1
-  g.Afr = fr(0);
+  GemmArgs g = gemm_base(c, mode);
+  g.a_type_stride = tstride;
+  g.Afr = f64 ? (const void*)((const double*)frag + off_bwd[0]) : (const void*)((const uint16_t*)frag + off_bwd[0]);
   g.X = f64 ? c->fa[8] : c->fa[9];
-  g.ldx = ld;
-  g.K = ld;
+  g.ldx = f64 ? fw : fwp;
+  g.K = f64 ? fw : fwp;
   g.Kreal = fw;
   g.M = m->nd;
   g.epi = EPI_PLAIN;
-  g.res = nullptr;
   g.out0 = c->dD;
   g.ld0 = m->nd;
-  g.out1 = nullptr;
-  g.outlp = nullptr;
   gemm_launch(c, g, mode, s);
 }
 
