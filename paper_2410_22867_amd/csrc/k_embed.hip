@@ -127,6 +127,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
+  // A last feature tile with at most 4 real features (w = 25: features
+  // 96..99) is evaluated transposed, features along M: its real outputs are
+  // then element 0 of every lane (one tanh per lane instead of four), and
+  // its contraction runs over the lane's own row
+  constexpr int REM = M1 % 16;
+  constexpr bool TLAST = REM > 0 && REM <= 4;
   __shared__ double fr[NF2 + NF3];
   __shared__ double h2s[WPB][16][kP2 + 1];
   __shared__ double vs[kVecPerNet];
@@ -151,6 +157,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int o = 0; o < N3; ++o)
 #pragma unroll
       for (int k = 0; k < 4; ++k) accT[o][k] = 0.0;
+    double accL[4] = {0.0, 0.0, 0.0, 0.0};  // last tile when transposed: feature 16 (N3 - 1) + g, over rows r16
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
     double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
@@ -160,9 +167,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const int row = r0 + r16;
       const double s = s_next;
       s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
-      double* rec =
-          ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + r16 * 16 + g
-             : nullptr;
+      double* const recb =
+          ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) : nullptr;
+      double* const rec = ST ? recb + r16 * 16 + g : nullptr;
+      // the lane's own row (contraction of a transposed last tile)
+      d4 Rown = {0.0, 0.0, 0.0, 0.0};
+      if (TLAST && row < nn) Rown = *reinterpret_cast<const d4*>(Rs + row * 4);
       // rows of the contraction, requested before layers 1-2 run
       double Rr[4][4];
 #pragma unroll
@@ -200,6 +210,25 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       wave_lds_sync();
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
+        if (TLAST && o == N3 - 1) {
+          // features 16 o + 4 v + g along M, rows along N: element 0 holds
+          // feature 16 o + g of row r0 + r16
+          const int f = 16 * o + g;
+          d4 z = {vec[kV_B3F + f], 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+          if (g < REM) {
+            const double t3 = tanh_d(z[0]);
+            if constexpr (ST) recb[f * 16 + r16] = t3;
+            const double G = h2s[wv][r16][slot2_of_feat<W>(f % (2 * W))] + t3;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) accL[k] = fma(G, Rown[k], accL[k]);
+          }
+          continue;
+        }
         const int feat = 16 * o + r16;
         const double b3 = vec[kV_B3F + feat];  // the table spans kP3 features
         d4 z = {b3, b3, b3, b3};
@@ -222,8 +251,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
       }
     }
+    constexpr int NR = TLAST ? N3 - 1 : N3;  // tiles in the row-sum layout
 #pragma unroll
-    for (int o = 0; o < N3; ++o)
+    for (int o = 0; o < NR; ++o)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         double x = accT[o][k];
@@ -231,13 +261,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         x += shfl_xor_d(x, 32);
         accT[o][k] = x * A.inv_nm;
       }
+    double* T = reinterpret_cast<double*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
     if (g == 0) {
-      double* T = reinterpret_cast<double*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
 #pragma unroll
-      for (int o = 0; o < N3; ++o) {
+      for (int o = 0; o < NR; ++o) {
         const int feat = 16 * o + r16;
         if (feat < M1) *reinterpret_cast<d4*>(T + feat * 4) = d4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
       }
+    }
+    if constexpr (TLAST) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double x = accL[k];
+#pragma unroll
+        for (int msk = 1; msk < 16; msk <<= 1) x += shfl_xor_d(x, msk);
+        accL[k] = x * A.inv_nm;
+      }
+      if (r16 == 0 && g < REM)
+        *reinterpret_cast<d4*>(T + (16 * (N3 - 1) + g) * 4) = d4{accL[0], accL[1], accL[2], accL[3]};
     }
   }
 }
