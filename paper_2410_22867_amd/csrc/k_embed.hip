@@ -406,6 +406,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           double dz3[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
+            dz3[v] = 0.0;
+            if (kpad<W>(o4, v)) continue;  // padding slots: G = 0 and no weights
             const int p = 16 * (4 * zo + o4) + 4 * v + g;
             double t3;
             if constexpr (ST) {
@@ -440,6 +442,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          dz2[i2][v] = 0.0;
+          if (kpad<W>(i2, v)) continue;
           const double dh2 = dh2a[i2][v] + skip2[i2][v];
           const double t2 = h2[i2][v] - t1[i2 & 1][v];
           dz2[i2][v] = dh2 * (1.0 - t2 * t2);
