@@ -150,6 +150,30 @@ int feat3(int w, int p) {
   return f < 0 ? -1 : (p >> 6) * 2 * w + f;
 }
 
+// Denser layout of the FP64 force kernels for w = 25 (the last feature of
+// each half of the width-2w layer shares one k-step; slots 26, 27 are
+// copies of features 24, 49 that feed nothing but the identity skip, and
+// layer-1 slots 25..27 copies of layer-1 feature 24 that feed only those).
+// val*: the feature whose value a slot carries; wt*: the feature whose
+// outgoing weights it carries (-1 for padding and copies).
+bool dense2(int w) { return w == 25; }
+int val1(int w, int p) { return dense2(w) && p >= w && p < w + 3 ? w - 1 : feat1(w, p); }
+int wt1(int w, int p) { return feat1(w, p); }
+int val2(int w, int q) {
+  if (!dense2(w)) return feat2(w, q);
+  if (q >= w - 1 && q < w + 3) return ((q - (w - 1)) & 1) ? 2 * w - 1 : w - 1;
+  if (q >= 32 + w - 1) return -1;
+  return feat2(w, q);
+}
+int wt2(int w, int q) { return dense2(w) && (q == w + 1 || q == w + 2) ? -1 : val2(w, q); }
+int val3(int w, int p) {
+  if (!dense2(w)) return feat3(w, p);
+  const int q = p & 63;
+  if (q >= w - 1 && q < w + 3) return p < 64 ? (w - 1) + w * (q - (w - 1)) : -1;
+  const int f = val2(w, q);
+  return f < 0 ? -1 : (p >> 6) * 2 * w + f;
+}
+
 // Packed-index helpers of the two fragment kinds.
 //   f64 16x16x4 : element (t, v, lane) with k-feature 16t + 4(lane/16) + v when
 //                 the other operand is read from memory, 16t + 4v + lane/16
@@ -206,7 +230,8 @@ int upload_lp(uint16_t** bf, uint16_t** hf, const std::vector<float>& v) {
 
 void free_model(dp_model* m) {
   if (!m) return;
-  void* ptrs[] = {m->params, m->emb_vec64, m->emb_vec32, m->emb_frag64, m->emb_frag_bf16, m->emb_frag_f16,
+  void* ptrs[] = {m->params, m->emb_vec64, m->emb_vec32, m->emb_frag64, m->emb_vec64d, m->emb_frag64d,
+                  m->emb_frag_bf16, m->emb_frag_f16,
                   m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_vec64, m->fit_vec32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -256,6 +281,24 @@ int prepare_model(dp_model* m, const double* P) {
       for (int f = 0; f < 4 * w; ++f) v[256 + f] = P[L.embB[a][b][2] + f];
     }
   std::vector<float> ev32(ev.begin(), ev.end());
+  std::vector<double> evd((size_t)nnets * 384, 0.0);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      double* v = &evd[(size_t)(a * nt + b) * 384];
+      for (int p = 0; p < 32; ++p) {
+        const int f = val1(w, p);
+        if (f >= 0) { v[p] = P[L.embW[a][b][0] + f]; v[32 + p] = P[L.embB[a][b][0] + f]; }
+      }
+      for (int p = 0; p < 64; ++p) {
+        const int f = val2(w, p);
+        if (f >= 0) v[64 + p] = P[L.embB[a][b][1] + f];
+      }
+      for (int p = 0; p < 128; ++p) {
+        const int f = val3(w, p);
+        if (f >= 0) v[128 + p] = P[L.embB[a][b][2] + f];
+      }
+      for (int f = 0; f < 4 * w; ++f) v[256 + f] = P[L.embB[a][b][2] + f];
+    }
   // ---- embedding fragments (same element counts for both kinds)
   EmbFragOffsets& fo = m->efo;
   fo.F2 = 0;
@@ -265,6 +308,7 @@ int prepare_model(dp_model* m, const double* P) {
   fo.B2 = fo.B3 + 8192;
   fo.per_net = fo.B2 + 2048;
   std::vector<double> e64((size_t)nnets * fo.per_net, 0.0);
+  std::vector<double> e64d((size_t)nnets * fo.per_net, 0.0);
   std::vector<float> e32((size_t)nnets * fo.per_net, 0.f);
   const int m1 = 4 * w;
   for (int a = 0; a < nt; ++a)
@@ -285,6 +329,25 @@ int prepare_model(dp_model* m, const double* P) {
         const int fi = feat2(w, in_slot);
         return (fi < 0 || out_feat >= m1) ? 0.0 : W3[(int64_t)fi * 4 * w + out_feat];
       };
+      // the denser layout (FP64 force kernels)
+      auto w2d = [&](int in_slot, int out_slot) -> double {
+        const int fi = wt1(w, in_slot), fo2 = val2(w, out_slot);
+        return (fi < 0 || fo2 < 0) ? 0.0 : W2[(int64_t)fi * 2 * w + fo2];
+      };
+      auto w3sd = [&](int in_slot, int out_slot) -> double {
+        if (in_slot >= 64 || out_slot >= 128) return 0.0;
+        const int fi = wt2(w, in_slot), fo3 = val3(w, out_slot);
+        return (fi < 0 || fo3 < 0) ? 0.0 : W3[(int64_t)fi * 4 * w + fo3];
+      };
+      auto w3fd = [&](int in_slot, int out_feat) -> double {
+        const int fi = wt2(w, in_slot);
+        return (fi < 0 || out_feat >= m1) ? 0.0 : W3[(int64_t)fi * 4 * w + out_feat];
+      };
+      frag_block64(e64d, base + fo.F2, 4, 2, [&](int mo, int ki) { return w2d(ki, mo); }, true);
+      frag_block64(e64d, base + fo.F3n, m->n3, 4, [&](int mo, int ki) { return w3fd(ki, mo); }, true);
+      frag_block64(e64d, base + fo.F3t, 8, 4, [&](int mo, int ki) { return w3sd(ki, mo); }, true);
+      frag_block64(e64d, base + fo.B3, 4, 8, [&](int mi, int ko) { return w3sd(mi, ko); }, true);
+      frag_block64(e64d, base + fo.B2, 2, 4, [&](int mi, int ko) { return w2d(mi, ko); }, true);
       // forward (A operand W^T: m = out, k = in)
       frag_block64(e64, base + fo.F2, 4, 2, [&](int mo, int ki) { return w2(ki, mo); }, true);
       frag_block32(e32, base + fo.F2, 4, 1, [&](int mo, int ki) { return w2(ki, mo); });
@@ -348,6 +411,8 @@ int prepare_model(dp_model* m, const double* P) {
     if ((rc = dev_alloc(&m->emb_vec64, ev.size(), "hipMalloc(emb vec)"))) return rc;
     if ((rc = dev_alloc(&m->emb_vec32, ev32.size(), "hipMalloc(emb vec32)"))) return rc;
     if ((rc = dev_alloc(&m->emb_frag64, e64.size(), "hipMalloc(emb frag)"))) return rc;
+    if ((rc = dev_alloc(&m->emb_vec64d, evd.size(), "hipMalloc(emb vec)"))) return rc;
+    if ((rc = dev_alloc(&m->emb_frag64d, e64d.size(), "hipMalloc(emb frag)"))) return rc;
     if ((rc = dev_alloc(&m->fit_frag64, f64v.size(), "hipMalloc(fit frag)"))) return rc;
     if ((rc = dev_alloc(&m->fit_vec64, fv.size(), "hipMalloc(fit vec)"))) return rc;
     if ((rc = dev_alloc(&m->fit_vec32, fv32.size(), "hipMalloc(fit vec32)"))) return rc;
@@ -359,6 +424,8 @@ int prepare_model(dp_model* m, const double* P) {
   if ((rc = upload(m->emb_vec64, ev.data(), ev.size() * 8))) return rc;
   if ((rc = upload(m->emb_vec32, ev32.data(), ev32.size() * 4))) return rc;
   if ((rc = upload(m->emb_frag64, e64.data(), e64.size() * 8))) return rc;
+  if ((rc = upload(m->emb_vec64d, evd.data(), evd.size() * 8))) return rc;
+  if ((rc = upload(m->emb_frag64d, e64d.data(), e64d.size() * 8))) return rc;
   if ((rc = upload(m->fit_frag64, f64v.data(), f64v.size() * 8))) return rc;
   if ((rc = upload(m->fit_vec64, fv.data(), fv.size() * 8))) return rc;
   if ((rc = upload(m->fit_vec32, fv32.data(), fv32.size() * 4))) return rc;

@@ -69,6 +69,11 @@ struct dp_model {
   float* emb_vec32;
   int64_t emb_vec_per_net;   // = 32+32+64+128+128
   double* emb_frag64;
+  // the FP64 force kernels' copies in the denser width-2w layout (w = 25;
+  // the same as the plain ones otherwise); the gradient kernels and the
+  // mixed kernels use the plain layout
+  double* emb_vec64d;
+  double* emb_frag64d;
   uint16_t* emb_frag_bf16;
   uint16_t* emb_frag_f16;
   dpse::EmbFragOffsets efo;

@@ -116,9 +116,48 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
 // FP64 k-step (t, v) covers slots 16t + 4v + {0..3}; with w = 25 the slot
 // groups 28..31 (mod 32) hold only padding, so those k-steps are skipped and
 // the activations of those slots (tanh(0) = 0) are not evaluated.
+//
+// The FP64 kernels use a denser layout of the width-2w layer for w = 25
+// (the mixed kernels, whose k-steps are 32 wide, keep the plain one).  Each
+// half of the layer ends in a k-step (slots 24..27, 56..59) holding a
+// single feature; both halves' last features (24 and 49) go to slots 24 and
+// 25, and slots 26 and 27 hold copies of them, so that slots 56..59 are
+// padding and their k-steps drop out.  A copy is computed like a feature
+// (its layer-1 slot partner, slots 25..27 of layer 1, holds a copy of
+// feature 24 of layer 1) but has no outgoing weights: the layer above
+// reads only the original, and a copy reaches the output only through the
+// identity skip.  That skip pairs layer-3 slot 64 zo + q with layer-2 slot
+// q, so slots 24..27 of the first layer-3 half hold features 24, 49, 74
+// and 99 (whose skip partners are 24, 49, 24, 49), and slots 24..27 of the
+// second half are padding.  Gradients flow through the copies like
+// through any other unit.
 template <int W>
-__device__ __forceinline__ constexpr bool kpad(int t, int v) {
+constexpr bool kDense2 = (W == 25);
+template <int W>
+__device__ __forceinline__ constexpr bool kpad(int t, int v) {  // layer-1 slots
   return W <= 28 && (t & 1) && v == 3;
+}
+template <int W>
+__device__ __forceinline__ constexpr bool kpad2(int t, int v) {  // layer-2 slots, FP64 layout
+  return kpad<W>(t, v) || (kDense2<W> && t == 3 && v == 2);
+}
+template <int W>
+__device__ __forceinline__ constexpr bool kpad3(int zo, int t, int v) {  // layer-3 slots 64 zo + 16 t + 4 v + g
+  return kpad2<W>(t, v) || (kDense2<W> && zo == 1 && t == 1 && v == 2);
+}
+template <int W>
+__device__ __forceinline__ int slot2d_of_feat(int f) {  // f in [0, 2W), FP64 layout
+  if (kDense2<W> && f == 2 * W - 1) return W;
+  return slot2_of_feat<W>(f);
+}
+template <int W>
+__device__ __forceinline__ int feat3d_of_slot(int p) {  // FP64 layout; -1 for padding slots
+  if constexpr (kDense2<W>) {
+    const int q = p & 63;
+    if (q >= W - 1 && q < W + 3) return p < 64 ? (W - 1) + W * (q - (W - 1)) : -1;
+    if (q >= 32 + W - 1) return -1;
+  }
+  return feat3_of_slot<W>(p);
 }
 
 // ============================================================== FP64 forward
@@ -200,7 +239,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v]);
       }
       wave_lds_sync();
 #pragma unroll
@@ -219,11 +258,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+              if (!kpad2<W>(mt, v)) z = mfma_f64(fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
           if (g < REM) {
             const double t3 = tanh_d(z[0]);
             if constexpr (ST) recb[f * 16 + r16] = t3;
-            const double G = h2s[wv][r16][slot2_of_feat<W>(f % (2 * W))] + t3;
+            const double G = h2s[wv][r16][slot2d_of_feat<W>(f % (2 * W))] + t3;
 #pragma unroll
             for (int k = 0; k < 4; ++k) accL[k] = fma(G, Rown[k], accL[k]);
           }
@@ -236,10 +275,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (!kpad<W>(mt, v))
+            if (!kpad2<W>(mt, v))
               z = mfma_f64(h2[mt][v], fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], z);
         if (feat < M1) {
-          const int src = slot2_of_feat<W>(feat % (2 * W));
+          const int src = slot2d_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const double t3 = tanh_d(z[v]);
@@ -315,7 +354,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const double* gT = reinterpret_cast<const double*>(A.gT) + (int64_t)col * M1 * 4;
       wave_lds_sync();
       for (int p = lane; p < kP3; p += 64) {
-        const int a = feat3_of_slot<W>(p);
+        const int a = feat3d_of_slot<W>(p);
         d4 x = {0.0, 0.0, 0.0, 0.0};
         if (a >= 0) x = *reinterpret_cast<const d4*>(gT + a * 4) * A.inv_nm;
         gts[wv][p] = x;
@@ -344,9 +383,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       // stored t3 of the whole tile, requested before layers 1-2 are
       // recomputed so that the loads are in flight meanwhile.  Slot
       // p = 64 zo + 16 o4 + 4 v + g holds feature 2W zo + W (o4 / 2) +
-      // 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g < W; a padding slot
-      // may read past its record (the store has one record of slack at its
-      // end) and its value is discarded.
+      // 16 (o4 % 2) + 4 v + g when 16 (o4 % 2) + 4 v + g < W, except the
+      // slots of the denser layout (features W - 1 + W g in the first half's
+      // k-step W - 1); a padding slot may read past its record (the store
+      // has one record of slack at its end) and its value is discarded.
       double t3v[2][16];
       if constexpr (ST) {
 #pragma unroll
@@ -356,7 +396,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int lo = 16 * (o4 & 1) + 4 * v;
-              t3v[oo][o4 * 4 + v] = (lo < W) ? rec[(oo * 2 * W + (o4 >> 1) * W + lo) * 16] : 0.0;
+              if (kpad3<W>(oo, o4, v)) {
+                t3v[oo][o4 * 4 + v] = 0.0;
+              } else if (kDense2<W> && oo == 0 && o4 == 1 && v == 2) {
+                t3v[oo][o4 * 4 + v] = rec[((W - 1) + (W - 1) * g) * 16];  // feature W - 1 + W g
+              } else {
+                t3v[oo][o4 * 4 + v] = (lo < W) ? rec[(oo * 2 * W + (o4 >> 1) * W + lo) * 16] : 0.0;
+              }
             }
       }
       double t1[2][4];
@@ -376,7 +422,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v]);
       }
       // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
@@ -401,18 +447,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
+                if (!kpad2<W>(mt, v)) z = mfma_f64(fr[z0 + zo * 4096 + ((o4 * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
           }
           double dz3[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             dz3[v] = 0.0;
-            if (kpad<W>(o4, v)) continue;  // padding slots: G = 0 and no weights
+            if (kpad2<W>(o4, v)) continue;  // padding slots: G = 0 and no weights
+            if (kDense2<W> && o4 == 1 && v == 2 && oo != 0) continue;
             const int p = 16 * (4 * zo + o4) + 4 * v + g;
             double t3;
             if constexpr (ST) {
               const double x = oo == 0 ? t3v[0][o4 * 4 + v] : t3v[1][o4 * 4 + v];
-              t3 = 16 * (o4 & 1) + 4 * v + g < W ? x : 0.0;
+              t3 = (kDense2<W> && o4 == 1 && v == 2) || 16 * (o4 & 1) + 4 * v + g < W ? x : 0.0;
             } else {
               t3 = tanh_d(z[v]);
             }
@@ -428,7 +475,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              if (!kpad<W>(o4, v))
+              if (!kpad2<W>(o4, v) && !(kDense2<W> && o4 == 1 && v == 2 && oo != 0))
                 dh2a[i2] = mfma_f64(fr[z0 + 8192 + zo * 1024 + ((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
         }
       }
@@ -443,7 +490,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           dz2[i2][v] = 0.0;
-          if (kpad<W>(i2, v)) continue;
+          if (kpad2<W>(i2, v)) continue;
           const double dh2 = dh2a[i2][v] + skip2[i2][v];
           const double t2 = h2[i2][v] - t1[i2 & 1][v];
           dz2[i2][v] = dh2 * (1.0 - t2 * t2);
@@ -457,7 +504,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int o = 0; o < 4; ++o)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (!kpad<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+            if (!kpad2<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double dh1 = z[v];
@@ -796,9 +843,9 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
   A.meta = c->type_meta;
   A.R = c->R;
   A.nnei = c->nnei;
-  A.frag64 = m->emb_frag64;
+  A.frag64 = m->emb_frag64d;
   A.fraglp = mode == DP_MIX_FP16 ? m->emb_frag_f16 : m->emb_frag_bf16;
-  A.vec64 = m->emb_vec64;
+  A.vec64 = m->emb_vec64d;
   A.vec32 = m->emb_vec32;
   A.vec_per_net = m->emb_vec_per_net;
   A.fo = m->efo;
