@@ -741,6 +741,22 @@ __global__ __launch_bounds__(128) void k_desc_bwd(const int32_t* __restrict__ at
     for (int b = 0; b < 16; ++b) dDs[a * 16 + b] = dD[((int64_t)col * m1 + a) * 16 + b];
   }
   __syncthreads();
+  // second term by the first wave: lane group q = a / 16 sums a' = q, q + 4,
+  // ..., then the four groups are added across lanes
+  TT s2[4] = {0, 0, 0, 0};
+  if (a < 64) {
+    const int c16 = a & 15;
+    for (int a2 = a >> 4; a2 < m1; a2 += 4) {
+      const TT w = dDs[a2 * 16 + c16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s2[k] += w * Ts[a2][k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s2[k] += __shfl_xor(s2[k], 16, 64);
+      s2[k] += __shfl_xor(s2[k], 32, 64);
+    }
+  }
   if (a >= m1) return;
   TT acc[4] = {0, 0, 0, 0};
   for (int b = 0; b < 16; ++b) {
@@ -749,11 +765,8 @@ __global__ __launch_bounds__(128) void k_desc_bwd(const int32_t* __restrict__ at
     for (int k = 0; k < 4; ++k) acc[k] += w * Ts[b][k];
   }
   if (a < 16)
-    for (int a2 = 0; a2 < m1; ++a2) {
-      const TT w = dDs[a2 * 16 + a];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] += w * Ts[a2][k];
-    }
+    for (int k = 0; k < 4; ++k) acc[k] += s2[k];
 #pragma unroll
   for (int k = 0; k < 4; ++k) gT[((int64_t)col * m1 + a) * 4 + k] = acc[k];
 }
