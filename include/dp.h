@@ -184,7 +184,11 @@ int dp_build_nlist_batch(dp_ctx* ctx, const double* coords, const int32_t* types
  *   virial      [9] device f64: W_ab = -sum_ij d_a (dE/dd)_b, row-major
  *   mode        DP_FP64, DP_MIX_BF16 or DP_MIX_FP16.
  * Positions may drift from where the list was built; r_ij uses the stored
- * image shift.  State for dp_backward_params is kept in the context. */
+ * image shift.  The types must be the ones the list was built with (its
+ * sections are by neighbour type): for a list built or formatted by this
+ * context, the column order by type from the last sort is reused while the
+ * types pointer, n and the frames are unchanged, so types changed in place
+ * need a new list.  State for dp_backward_params is kept in the context. */
 int dp_compute(dp_ctx* ctx, const double* coords, const int32_t* types, const double* box, int64_t n,
                const int32_t* nlist, int32_t mode, double* energy, double* atom_energy, double* forces,
                double* virial, hipStream_t stream);

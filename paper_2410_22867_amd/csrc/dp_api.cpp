@@ -499,6 +499,7 @@ int stage_frames(dp_ctx* c, const double* boxes, const int64_t* off, int32_t nfr
     memcpy(c->frames_host, F_new, sizeof(FrameInfo) * nframes);
     memcpy(c->frames_prev, F_new, sizeof(FrameInfo) * nframes);
     c->nframes_dev = nframes;
+    c->frames_gen++;
     HIPCHECK(hipMemcpyAsync(c->frames_dev, c->frames_host, sizeof(FrameInfo) * nframes, hipMemcpyHostToDevice, s));
     HIPCHECK(hipEventRecord(c->frames_ev, s));
     c->frames_ev_pending = true;
@@ -551,6 +552,25 @@ int set_device(int dev) {
   return DP_OK;
 }
 
+// Column order by type (atom_at, col_of, type_meta, frame_of) depends only on
+// the types, the atom count and the frame table.  A list is valid only for
+// the types it was built with, so a compute on a list this context built or
+// formatted keeps the order of the last sort when the types buffer, the
+// count and the frame table are the ones that sort used; building a list
+// (or a Verlet candidate list) always sorts anew, and a list from elsewhere
+// always triggers a sort.
+static void type_sort(dp_ctx* c, const int32_t* types, int64_t n, int32_t nframes, bool may_reuse, hipStream_t s) {
+  if (may_reuse && c->ts_valid && c->ts_types == types && c->ts_n == n && c->ts_nframes == nframes &&
+      c->ts_frames_gen == c->frames_gen)
+    return;
+  launch_type_sort(c, types, (int32_t)n, nframes, s);
+  c->ts_valid = true;
+  c->ts_types = types;
+  c->ts_n = n;
+  c->ts_nframes = nframes;
+  c->ts_frames_gen = c->frames_gen;
+}
+
 int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double* boxes, const int64_t* off,
                  int32_t nframes, const int32_t* nlist, int32_t mode, double* energies, double* atom_energy,
                  double* forces, double* virials, hipStream_t s) {
@@ -568,8 +588,9 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   c->mode_last = mode;
   c->last_stream = s;
   const int32_t ntot = (int32_t)n;
-  { StageScope p(c, DP_STAGE_TYPESORT, s); launch_type_sort(c, types, ntot, nframes, s); }
-  if (nlist != c->rev_list || n != c->natoms_rev) {
+  const bool own_list = nlist == c->rev_list && n == c->natoms_rev;
+  { StageScope p(c, DP_STAGE_TYPESORT, s); type_sort(c, types, n, nframes, own_list, s); }
+  if (!own_list) {
     // list not built by this context: derive its reverse index now (slots
     // whose reverse is not found fall back to atomics in the force pass)
     StageScope p(c, DP_STAGE_NLIST, s);
@@ -609,7 +630,7 @@ int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* b
   launch_nl_scan(c, (int32_t)ncells, s);
   launch_nl_scatter(c, ntot, s);
   launch_nl_search(c, x, types, ntot, nframes, nlist, overflow, s);
-  launch_type_sort(c, types, ntot, nframes, s);  // frame_of for the reverse index
+  type_sort(c, types, n, nframes, false, s);  // frame_of for the reverse index
   launch_nl_reverse(c, x, types, nlist, ntot, s);
   c->rev_list = nlist;
   c->natoms_rev = n;
@@ -643,6 +664,7 @@ int skin_build_impl(dp_ctx* c, double* x, const int32_t* types, const double* bo
   launch_nl_skin_build(c, x, types, ntot, s);
   c->skin_n = n;
   c->rev_list = nullptr;
+  c->ts_valid = false;
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }

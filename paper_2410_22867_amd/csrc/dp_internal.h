@@ -106,8 +106,15 @@ struct dp_ctx {
   dpse::FrameInfo* frames_host;  // pinned staging
   dpse::FrameInfo* frames_prev;  // host copy of the table on the device
   int32_t nframes_dev;           // entries of that table (-1: none)
+  int64_t frames_gen;            // bumped whenever the device table changes
   hipEvent_t frames_ev;
   bool frames_ev_pending;
+  // inputs of the last type sort (column order), see type_sort()
+  bool ts_valid;
+  const int32_t* ts_types;
+  int64_t ts_n;
+  int32_t ts_nframes;
+  int64_t ts_frames_gen;
   int32_t nframes_last;
   int64_t natoms_last;
   int32_t mode_last;
