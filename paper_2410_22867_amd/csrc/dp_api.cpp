@@ -596,7 +596,7 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
     StageScope p(c, DP_STAGE_NLIST, s);
     launch_nl_reverse(c, x, types, nlist, ntot, s);
   }
-  { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, s); }
+  { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, forces, s); }
   c->act_used_last = c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
   { StageScope p(c, DP_STAGE_EMBED_FWD, s); launch_embed_fwd(c, types, mode, s); }
   { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
@@ -873,6 +873,14 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->red_part, 10 * (N / kRedChunk + (int64_t)max_frames + 1));
   ALLOC(c->vatom, N * 9);
   ALLOC(c->ke_part, N / 256 + 2);
+  ALLOC(c->ke_ctr, 32);
+  {
+    const hipError_t e = hipMemset(c->ke_ctr, 0, 32 * sizeof(int32_t));
+    if (e != hipSuccess) {
+      dp_ctx_destroy(c);
+      return hip_fail(e, "hipMemset(ctx)");
+    }
+  }
   ALLOC(c->Ei_col, C);
   ALLOC(c->Ei_atom, N);
   ALLOC(c->gE_col, C);
@@ -935,7 +943,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
                   c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
                   c->gpart};
   for (void* p : ptrs)

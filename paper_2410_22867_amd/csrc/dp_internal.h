@@ -172,6 +172,7 @@ struct dp_ctx {
   int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]
   double* ke_part;         // [N/256 + 1] per-block kinetic energies
+  int32_t* ke_ctr;         // blocks of the kick that have written their partial (reset by the last)
   double* red_part;        // [chunks, 10] per-chunk energy + virial partial sums
   int32_t nchunks_last;
   // parameter-gradient scratch
@@ -212,7 +213,7 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void launch_type_sort(dp_ctx* c, const int32_t* types, int32_t ntot, int32_t nframes, hipStream_t s);
 // compute
-void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
+void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot, double* forces,
                 hipStream_t s);
 void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
 void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s);

@@ -141,6 +141,7 @@ struct EnvArgs {
   double* R;
   int32_t* nnei;
   int32_t* flags;
+  double* F;  // forces, cleared here for the force pass (which accumulates)
   int ntot, nm, ntypes;
   int sec[kMaxT + 1];
   double rs, rc, inv_std_s, inv_std_v;
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(256) void k_env(EnvArgs A) {
   if (i >= A.ntot) return;
   const FrameInfo& F = A.fr[A.frame_of[i]];
   const double xi = A.x[3 * i], yi = A.x[3 * i + 1], zi = A.x[3 * i + 2];
+  if (lane < 3) A.F[3 * i + lane] = 0.0;
   int cnt[kMaxT] = {0, 0, 0, 0};
   bool overlap = false;
   for (int q = lane; q < A.nm; q += 64) {
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256) void k_env(EnvArgs A) {
 }
 
 void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
-                hipStream_t s) {
+                double* forces, hipStream_t s) {
   if (ntot <= 0) return;
   const dp_model* m = c->model;
   EnvArgs A;
@@ -217,6 +219,7 @@ void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t*
   A.R = c->R;
   A.nnei = c->nnei;
   A.flags = c->flags_dev;
+  A.F = forces;
   A.ntot = ntot;
   A.nm = m->nm;
   A.ntypes = m->desc.ntypes;
@@ -342,7 +345,7 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
   A.rc = m->desc.rcut;
   A.inv_std_s = 1.0 / m->desc.std_s;
   A.inv_std_v = 1.0 / m->desc.std_v;
-  launch_fill_f64(forces, 0.0, 3 * (int64_t)ntot, s);
+  // forces were cleared by the environment pass of the same compute
   hipLaunchKernelGGL(k_force_pairs, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_force_gather, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
 }
@@ -475,8 +478,13 @@ __global__ void k_wrap(MdArgs A) {
 
 // Second half-kick; each block writes its partial kinetic energy, a second
 // single-block kernel sums the partials in a fixed order.
-__global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ part) {
+// Second half-kick and kinetic energy: each block writes its partial sum;
+// the block that finishes last (counted by an atomic that it resets) adds
+// the partials in block order.
+__global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ part, int32_t* __restrict__ ctr,
+                                              double scale) {
   __shared__ double red[256];
+  __shared__ bool last;
   double acc = 0.0;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < A.n) {
@@ -495,7 +503,27 @@ __global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ par
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0];
+    __threadfence();
+    last = atomicAdd(ctr, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = (int)gridDim.x;
+  double a2 = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) a2 += part[k];
+  red[threadIdx.x] = a2;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    A.ke[0] = red[0] * scale;
+    *ctr = 0;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int n, double scale,
@@ -552,8 +580,8 @@ void launch_kick(dp_ctx* c, double* v, const double* f, const int32_t* types, in
   MdArgs A = md_args(c, nullptr, v, f, types, n, dt);
   A.ke = ke;
   const int nb = (n + 255) / 256;
-  if (nb > 0) hipLaunchKernelGGL(k_kick, dim3(nb), dim3(256), 0, s, A, c->ke_part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, c->ke_part, nb, 1.0 / kFtm2v, ke);
+  if (nb > 0) hipLaunchKernelGGL(k_kick, dim3(nb), dim3(256), 0, s, A, c->ke_part, c->ke_ctr, 1.0 / kFtm2v);
+  else hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, c->ke_part, 0, 1.0 / kFtm2v, ke);
 }
 
 }  // namespace dpse

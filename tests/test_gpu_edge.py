@@ -201,3 +201,38 @@ def test_batch_with_empty_frames(dev, water):
         assert np.abs(F[a0:a1] - o["F"]).max() <= 1e-9
         assert np.abs(W[f] - o["W"]).max() <= 1e-9
     assert ctx.status() == 0
+
+
+def test_types_changed_in_place_need_new_list(dev, water):
+    """The column order by type is kept across computes on a list this
+    context built; rebuilding the list into the same buffers after the
+    types changed in place re-sorts, and a list from elsewhere always
+    re-sorts."""
+    from paper_2410_22867_amd import dpse
+    desc, p, model = water
+    fr = I.water_box(32, 10.5, seed=23)
+    _say("types changed in place", fr.n)
+    ctx = dpse.Context(model, fr.n)
+    x = torch.tensor(fr.coords, device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    nl, ov = ctx.build_nlist(x, t, fr.box)
+    ctx.compute(x, t, fr.box, nl)
+    ctx.compute(x, t, fr.box, nl)
+    types2 = fr.types.copy()
+    types2[::3] = 1 - types2[::3]
+    t.copy_(torch.tensor(types2, device=dev))
+    nl2, ov2 = ctx.build_nlist(x, t, fr.box, out=nl, overflow=ov)
+    assert nl2.data_ptr() == nl.data_ptr()
+    r = ctx.compute(x, t, fr.box, nl2, want_atom_energy=True)
+    torch.cuda.synchronize()
+    o = oracle.compute(fr.coords, types2, fr.box, desc, p)
+    assert np.array_equal(nl2.cpu().numpy(), o["nlist"])
+    rr = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+    _check_fp64(rr, o, fr.n)
+    # a list uploaded from the oracle (not built by this context)
+    ext = torch.tensor(o["nlist"], device=dev)
+    r = ctx.compute(x, t, fr.box, ext, want_atom_energy=True)
+    torch.cuda.synchronize()
+    rr = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+    _check_fp64(rr, o, fr.n)
+    assert ctx.status() == 0

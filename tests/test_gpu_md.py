@@ -95,3 +95,32 @@ def test_nve_verlet_list_matches_oracle():
     assert abs(E[-1][0] - hist[-1][0]) < 1e-9 * abs(hist[-1][0])
     assert abs(E[-1][1] - hist[-1][1]) < 1e-9 * max(1.0, abs(hist[-1][1]))
     assert ctx.status() == 0
+
+
+def test_half_kick_and_kinetic_energy_many_blocks():
+    """The second half-kick and the kinetic energy over 98,304 atoms (384
+    blocks whose partial sums the last block adds), twice in a row and then
+    on a smaller set, against the oracle's formulas."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_22867_amd import dpse
+    fr, desc, p, dt = I.workload("water98k")
+    model = dpse.Model(desc, p)
+    ctx = dpse.Context(model, fr.n)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    m = np.asarray(desc.masses)[fr.types]
+    for n in (fr.n, fr.n, 1000):
+        v0 = I.maxwell_boltzmann(fr.types[:n], desc.masses, 300.0, seed=int(rng.integers(1 << 30)))
+        f0 = rng.normal(0.0, 1.0, size=(n, 3))
+        v = torch.tensor(v0, device=dev)
+        f = torch.tensor(f0, device=dev)
+        t = torch.tensor(fr.types[:n], device=dev)
+        ke = torch.zeros(1, dtype=torch.float64, device=dev)
+        ctx.kick(v, f, t, dt, ke)
+        torch.cuda.synchronize()
+        v1 = v0 + 0.5 * dt * oracle.FTM2V * f0 / m[:n, None]
+        assert np.abs(v.cpu().numpy() - v1).max() <= 1e-15 * max(1.0, np.abs(v1).max())
+        k = oracle.kinetic_energy(v1, m[:n])
+        assert abs(ke.item() - k) <= 1e-12 * k
+    assert ctx.status() == 0
