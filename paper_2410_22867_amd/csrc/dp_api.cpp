@@ -874,8 +874,10 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->vatom, N * 9);
   ALLOC(c->ke_part, N / 256 + 2);
   ALLOC(c->ke_ctr, 32);
+  ALLOC(c->frame_ctr, max_frames);
   {
-    const hipError_t e = hipMemset(c->ke_ctr, 0, 32 * sizeof(int32_t));
+    hipError_t e = hipMemset(c->ke_ctr, 0, 32 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(c->frame_ctr, 0, (size_t)max_frames * sizeof(int32_t));
     if (e != hipSuccess) {
       dp_ctx_destroy(c);
       return hip_fail(e, "hipMemset(ctx)");
@@ -943,7 +945,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->frame_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
                   c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
                   c->gpart};
   for (void* p : ptrs)

@@ -353,11 +353,16 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
 // ---------------------------------------------------------------- reductions
 // Per-frame E_f = sum of E_i and W_f = sum of per-atom virial rows in two
 // fixed-order stages: one block per chunk of kRedChunk atoms of a frame,
-// then one block per frame over its chunks (deterministic).
+// then the frame's chunks in order (deterministic).  With a counter array
+// (no empty frame) the second stage is done by the frame's last chunk block
+// to finish, which resets the frame's counter; otherwise by k_frame_reduce.
 __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restrict__ fr, int nframes,
                                                       const double* __restrict__ Ei, const double* __restrict__ vatom,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, int32_t* __restrict__ ctr,
+                                                      double* __restrict__ E, double* __restrict__ W,
+                                                      int32_t* __restrict__ flags) {
   __shared__ double red[10][256];
+  __shared__ bool last;
   const int b = blockIdx.x;
   int lo = 0, hi = nframes - 1;
   while (lo < hi) {
@@ -382,7 +387,31 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restric
       for (int c = 0; c < 10; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x < 10) part[(int64_t)b * 10 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 10) {
+    part[(int64_t)b * 10 + threadIdx.x] = red[threadIdx.x][0];
+    if (ctr != nullptr) __threadfence();
+  }
+  if (ctr == nullptr) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nc = (F.natoms + kRedChunk - 1) / kRedChunk;
+    last = atomicAdd(ctr + lo, 1) == nc - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 10) {
+    const int nc = (F.natoms + kRedChunk - 1) / kRedChunk;
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[(int64_t)(F.chunk_off + c) * 10 + threadIdx.x];
+    if (threadIdx.x == 0) {
+      E[lo] = acc;
+      if (!isfinite(acc)) set_flag(flags, DP_FLAG_NONFINITE);
+      ctr[lo] = 0;
+    } else {
+      W[9 * lo + threadIdx.x - 1] = acc;
+    }
+  }
 }
 
 __global__ __launch_bounds__(64) void k_frame_reduce(const FrameInfo* __restrict__ fr, const double* __restrict__ part,
@@ -408,11 +437,14 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
 
 void launch_frame_reduce(dp_ctx* c, int32_t nframes, double* energies, double* atom_energy, double* virials,
                          hipStream_t s) {
+  bool empty = false;  // host copy of the table the kernels read
+  for (int f = 0; f < nframes; ++f) empty |= c->frames_prev[f].natoms == 0;
   if (c->nchunks_last > 0)
     hipLaunchKernelGGL(k_chunk_reduce, dim3(c->nchunks_last), dim3(256), 0, s, c->frames_dev, nframes, c->Ei_atom,
-                       c->vatom, c->red_part);
-  hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(64), 0, s, c->frames_dev, c->red_part, energies, virials,
-                     c->flags_dev);
+                       c->vatom, c->red_part, empty ? nullptr : c->frame_ctr, energies, virials, c->flags_dev);
+  if (empty || c->nchunks_last == 0)
+    hipLaunchKernelGGL(k_frame_reduce, dim3(nframes), dim3(64), 0, s, c->frames_dev, c->red_part, energies, virials,
+                       c->flags_dev);
   if (atom_energy && c->natoms_last > 0)
     hipLaunchKernelGGL(k_copy_f64, dim3((c->natoms_last + 255) / 256), dim3(256), 0, s, c->Ei_atom, atom_energy,
                        (int)c->natoms_last);
