@@ -681,7 +681,7 @@ int skin_format_impl(dp_ctx* c, const double* x, const int32_t* types, int64_t n
   if ((rc = set_device(c->device))) return rc;
   c->last_stream = s;
   StageScope p(c, DP_STAGE_NLIST, s);
-  launch_fill_i32(overflow, 0, 1, s);
+  if (n == 0) launch_fill_i32(overflow, 0, 1, s);  // otherwise written by the format's second pass
   launch_nl_skin_format(c, x, types, (int32_t)n, nlist, overflow, s);
   c->rev_list = nlist;
   c->natoms_rev = n;
@@ -875,9 +875,11 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->ke_part, N / 256 + 2);
   ALLOC(c->ke_ctr, 32);
   ALLOC(c->frame_ctr, max_frames);
+  ALLOC(c->ovf_ctr, 32);
   {
     hipError_t e = hipMemset(c->ke_ctr, 0, 32 * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->frame_ctr, 0, (size_t)max_frames * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(c->ovf_ctr, 0, 32 * sizeof(int32_t));
     if (e != hipSuccess) {
       dp_ctx_destroy(c);
       return hip_fail(e, "hipMemset(ctx)");
@@ -945,7 +947,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
-                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->frame_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
+                  c->netd, c->g3, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->frame_ctr, c->ovf_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
                   c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
                   c->gpart};
   for (void* p : ptrs)

@@ -172,6 +172,7 @@ struct dp_ctx {
   int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]
   double* ke_part;         // [N/256 + 1] per-block kinetic energies
+  int32_t* ovf_ctr;        // truncated neighbours counted by the Verlet format (moved out and reset by its second pass)
   int32_t* frame_ctr;      // [max_frames] chunk blocks of the frame reduction done (reset by the last)
   int32_t* ke_ctr;         // blocks of the kick that have written their partial (reset by the last)
   double* red_part;        // [chunks, 10] per-chunk energy + virial partial sums

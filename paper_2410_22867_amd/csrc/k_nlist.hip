@@ -448,10 +448,17 @@ __global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S
 }
 
 // Reverse index from the candidate bookkeeping of the format (same meaning
-// as the index built by binary search below).
+// as the index built by binary search below).  Its first thread also moves
+// the format's truncation count to the caller's buffer and clears the
+// internal counter for the next format (stream order: every format block
+// has finished, and the next format has not started).
 __global__ void k_nl_skin_revmap(const int32_t* __restrict__ nlist, SkinArgs S, int32_t* __restrict__ rev, int ntot,
-                                 int nm) {
+                                 int nm, int32_t* __restrict__ ovf_ctr, int32_t* __restrict__ overflow) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q == 0) {
+    *overflow = *ovf_ctr;
+    *ovf_ctr = 0;
+  }
   if (q >= (int64_t)ntot * nm) return;
   const int e = nlist[q];
   int out = -1;
@@ -613,13 +620,13 @@ void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int3
 void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* nlist,
                            int32_t* overflow, hipStream_t s) {
   if (ntot <= 0) return;
-  SearchArgs A = search_args(c, x, types, ntot, 1, nlist, overflow);
+  SearchArgs A = search_args(c, x, types, ntot, 1, nlist, c->ovf_ctr);
   SkinArgs S = skin_args(c);
   hipLaunchKernelGGL(k_nl_skin_format, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s,
                      A, S);
   const int64_t q = (int64_t)ntot * A.nm;
   hipLaunchKernelGGL(k_nl_skin_revmap, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, nlist, S, c->rev, ntot,
-                     A.nm);
+                     A.nm, c->ovf_ctr, overflow);
 }
 
 }  // namespace dpse

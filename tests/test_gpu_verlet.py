@@ -37,6 +37,11 @@ def dev():
 def _case(name):
     if name == "water192":
         fr, desc, p, _ = I.workload("water192")
+    elif name == "water192_sel":  # sections too short: truncation counted on every format
+        import dataclasses
+        fr, _, _, _ = I.workload("water192")
+        desc = dataclasses.replace(I.WATER, sel=(10, 20))
+        p = I.init_params(desc, 1)
     elif name == "water375":
         desc = I.WATER
         p = I.init_params(desc, 7)
@@ -58,7 +63,7 @@ def _displace(fr, max_disp, seed):
     return fr.coords + d
 
 
-@pytest.mark.parametrize("name", ["water192", "water375", "copper500"])
+@pytest.mark.parametrize("name", ["water192", "water192_sel", "water375", "copper500"])
 def test_format_equals_brute_force(dev, name):
     from paper_2410_22867_amd import dpse
     fr, desc, p = _case(name)
@@ -72,6 +77,7 @@ def test_format_equals_brute_force(dev, name):
     ref, rov = oracle.nlist(fr.coords, fr.types, fr.box, desc, use_cells=False)
     assert np.array_equal(nl.cpu().numpy(), ref)
     assert int(ov.cpu().item()) == rov
+    assert (rov > 0) == (name == "water192_sel")
     cell, _ = ctx.build_nlist(x, t, fr.box)
     assert np.array_equal(cell.cpu().numpy(), ref)
     # drift by up to 0.95 * skin/2, across the box faces, no rebuild
