@@ -269,9 +269,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
             hrow(nt)[m] = h;
             if constexpr (!LAST) {
               p.out[0][col * fw + m] = tv;
-              p.out[1][col * fw + m] = h;
+              if (p.out[1]) p.out[1][col * fw + m] = h;
             } else {
-              p.out[2][col * fw + m] = h;
+              if (p.out[2]) p.out[2][col * fw + m] = h;
               p.out[3][col * fw + m] = vec[3 * fw + m] * (1.0 - tv * tv);
             }
           }
@@ -598,9 +598,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         *reinterpret_cast<f4*>(hrow) = f4{hv[0], hv[1], hv[2], hv[3]};
         if constexpr (!LAST) {
           *reinterpret_cast<f4*>(p.out[0] + col * fwp + m0) = f4{tv[0], tv[1], tv[2], tv[3]};
-          *reinterpret_cast<f4*>(p.out[1] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+          if (p.out[1]) *reinterpret_cast<f4*>(p.out[1] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
         } else {
-          *reinterpret_cast<f4*>(p.out[2] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
+          if (p.out[2]) *reinterpret_cast<f4*>(p.out[2] + col * fwp + m0) = f4{hv[0], hv[1], hv[2], hv[3]};
           float dz[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) dz[v] = vec[3 * fw + m0 + v] * (1.f - tv[v] * tv[v]);
@@ -850,7 +850,8 @@ void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
                        (const float*)c->dD, (float*)c->gT, m->m1);
 }
 
-void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
+// keep_h: also store h2 and h3, which only the parameter gradients read.
+void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
   const dp_model* m = c->model;
   if (c->natoms_last <= 0) return;
   const int fw = m->fw;
@@ -889,8 +890,8 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.vec = m->fit_vec64;
     p.vec_type_stride = m->fit_vec_per_type;
     p.out[0] = (double*)c->fa[1];
-    p.out[1] = (double*)c->fa[2];
-    p.out[2] = (double*)c->fa[4];
+    p.out[1] = keep_h ? (double*)c->fa[2] : nullptr;
+    p.out[2] = keep_h ? (double*)c->fa[4] : nullptr;
     p.out[3] = (double*)c->fa[5];
     p.Ei_col = c->Ei_col;
     p.Ei_atom = c->Ei_atom;
@@ -908,8 +909,8 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.vec = m->fit_vec32;
     p.vec_type_stride = m->fit_vec_per_type;
     p.out[0] = (float*)c->fa[1];
-    p.out[1] = (float*)c->fa[2];
-    p.out[2] = (float*)c->fa[4];
+    p.out[1] = keep_h ? (float*)c->fa[2] : nullptr;
+    p.out[2] = keep_h ? (float*)c->fa[4] : nullptr;
     p.outlp[0] = (uint16_t*)c->fa[7];
     p.Ei_col = c->Ei_col;
     p.Ei_atom = c->Ei_atom;
