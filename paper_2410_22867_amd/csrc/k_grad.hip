@@ -202,6 +202,18 @@ __device__ __forceinline__ int e_feat3(int p) {
 // (16.5 KB + 32 B per feature); four waves fit in 160 KB up to M1 = 100.
 template <int W>
 constexpr int egw() { return 4 * W <= 100 ? 4 : 3; }
+// k-step (t, v) of 16 t + 4 v + {0..3} holds only padding (w = 25: slots
+// 28..31 mod 32); such products and activations are skipped
+template <int W>
+__device__ __forceinline__ constexpr bool g_kpad(int t, int v) {
+  return W <= 28 && (t & 1) && v == 3;
+}
+// With padding in every 32-slot group, slot 31 of the layer inputs h1 and
+// h2 holds 1.0 in the transposed buffers: the weight-gradient products then
+// also yield the bias gradients (row 31 of dW2 and dW3), with no products
+// of their own.
+template <int W>
+constexpr bool kBiasRow = W <= 28;
 // partial record of one work-group (slot-indexed): W3 | W2 | b3 | b2 | b1 | W1
 constexpr int kEgW3 = 0, kEgW2 = 64 * 128, kEgB3 = kEgW2 + 32 * 64, kEgB2 = kEgB3 + 128, kEgB1 = kEgB2 + 64,
               kEgW1 = kEgB1 + 32, kEgRec = kEgW1 + 32;
@@ -285,7 +297,7 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) t1[mt][v] = tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
+        for (int v = 0; v < 4; ++v) t1[mt][v] = g_kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
       double t2[4][4], h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -293,19 +305,21 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
+          for (int v = 0; v < 4; ++v)
+            if (!g_kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          t2[ot][v] = tanh_d(z[v] + vec[64 + 16 * ot + 4 * v + g]);
+          t2[ot][v] = g_kpad<W>(ot, v) ? 0.0 : tanh_d(z[v] + vec[64 + 16 * ot + 4 * v + g]);
           h2[ot][v] = t1[ot & 1][v] + t2[ot][v];
         }
       }
       wave_lds_sync();
-      // h2 -> T[row][0..64)
+      // h2 -> T[row][0..64) (slot 31: 1.0 for the bias gradient)
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int v = 0; v < 4; ++v) T[r16][16 * ot + 4 * v + g] = h2[ot][v];
+      if (kBiasRow<W> && g == 3) T[r16][31] = 1.0;
       double skip2[4][4];
       d4 dh2a[4];
 #pragma unroll
@@ -362,7 +376,8 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
           for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dh2a[i2] = mfma_f64(B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
+            for (int v = 0; v < 4; ++v)
+              if (!g_kpad<W>(o4, v)) dh2a[i2] = mfma_f64(B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
         }
         wave_lds_sync();
         // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]  (q in this half)
@@ -378,13 +393,13 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
             const double bq = T[rr][64 + 16 * qh + r16];
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
-            bacc = mfma_f64(one, bq, bacc);
+            if constexpr (!kBiasRow<W>) bacc = mfma_f64(one, bq, bacc);
           }
 #pragma unroll
           for (int pt = 0; pt < 4; ++pt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) atomicAdd(&aW3[(16 * pt + 4 * v + g) * 128 + 16 * qt + r16], acc[pt][v]);
-          if (g == 0) atomicAdd(&aB3[16 * qt + r16], bacc[0]);
+          if (!kBiasRow<W> && g == 0) atomicAdd(&aB3[16 * qt + r16], bacc[0]);
         }
         wave_lds_sync();  // the next half overwrites dz3
       }
@@ -409,7 +424,8 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+          for (int v = 0; v < 4; ++v)
+            if (!g_kpad<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) dz1[i2][v] = (z[v] + skip1[i2][v]) * (1.0 - t1[i2][v] * t1[i2][v]);
       }
@@ -427,6 +443,7 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) T[r16][32 + 16 * ot + 4 * v + g] = dz2[ot][v];
       if (g == 0) T[r16][128] = row < nn ? s : 0.0;
+      if (kBiasRow<W> && g == 3) T[r16][31] = 1.0;  // h1 slot 31 (padding)
       wave_lds_sync();
       {
         const double one = 1.0;
@@ -440,29 +457,27 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
             const double bq = T[rr][32 + 16 * qt + r16];
 #pragma unroll
             for (int pt = 0; pt < 2; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
-            bacc = mfma_f64(one, bq, bacc);
+            if constexpr (!kBiasRow<W>) bacc = mfma_f64(one, bq, bacc);
           }
 #pragma unroll
           for (int pt = 0; pt < 2; ++pt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) atomicAdd(&aW2[(16 * pt + 4 * v + g) * 64 + 16 * qt + r16], acc[pt][v]);
-          if (g == 0) atomicAdd(&aB2[16 * qt + r16], bacc[0]);
+          if (!kBiasRow<W> && g == 0) atomicAdd(&aB2[16 * qt + r16], bacc[0]);
         }
-        // dW1[q] = sum_row s dz1[q], db1[q] = sum_row dz1[q]
+        // dW1[q] = sum_row s dz1[q] and db1[q] = sum_row dz1[q] as rows 0
+        // and 1 of one product (A row 0: s, row 1: 1)
 #pragma unroll
         for (int qt = 0; qt < 2; ++qt) {
-          d4 wacc = {0, 0, 0, 0}, bacc = {0, 0, 0, 0};
+          d4 wacc = {0, 0, 0, 0};
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int rr = 4 * ks + g;
             const double bq = T[rr][96 + 16 * qt + r16];
-            wacc = mfma_f64(T[rr][128], bq, wacc);
-            bacc = mfma_f64(one, bq, bacc);
+            wacc = mfma_f64(r16 == 0 ? T[rr][128] : (r16 == 1 ? one : 0.0), bq, wacc);
           }
-          if (g == 0) {
-            atomicAdd(&aW1[16 * qt + r16], wacc[0]);
-            atomicAdd(&aB1[16 * qt + r16], bacc[0]);
-          }
+          if (g == 0) atomicAdd(&aW1[16 * qt + r16], wacc[0]);
+          if (g == 1) atomicAdd(&aB1[16 * qt + r16], wacc[0]);
         }
       }
     }
@@ -472,8 +487,8 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
   for (int k = threadIdx.x; k < 64 * 128; k += 64 * GW) pr[kEgW3 + k] = aW3[k];
   for (int k = threadIdx.x; k < 32 * 64; k += 64 * GW) pr[kEgW2 + k] = aW2[k];
   for (int k = threadIdx.x; k < 128; k += 64 * GW) {
-    pr[kEgB3 + k] = aB3[k];
-    if (k < 64) pr[kEgB2 + k] = aB2[k];
+    pr[kEgB3 + k] = kBiasRow<W> ? aW3[31 * 128 + k] : aB3[k];
+    if (k < 64) pr[kEgB2 + k] = kBiasRow<W> ? aW2[31 * 64 + k] : aB2[k];
     if (k < 32) {
       pr[kEgB1 + k] = aB1[k];
       pr[kEgW1 + k] = aW1[k];
