@@ -74,31 +74,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int j = 0; j < MT; ++j)
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[j][i] = d4{0.0, 0.0, 0.0, 0.0};
-  double xA[MT], yA[NT], xB[MT], yB[NT];
-  auto load = [&](int c, double* xv, double* yv) {
-    const int64_t col = cb + c + g;
-    const bool ok = c + g < c1;
-    const double wc = ok ? a.w[col] : 0.0;
+  // raw operands and the column weight are buffered and the weight is
+  // applied when the step consumes them; columns past the chunk load the
+  // chunk's last column (no branch around a load, so nothing forces an
+  // early wait) and get weight 0
+  double xA[MT], yA[NT], xB[MT], yB[NT], wA, wB;
+  auto load = [&](int c, double* xv, double* yv, double& wv_) {
+    const int64_t col = cb + min(c + g, c1 - 1);
+    wv_ = a.w[col];
 #pragma unroll
-    for (int j = 0; j < MT; ++j) xv[j] = ok ? a.X[col * a.ldx + mt[j] * 16 + r16] * wc : 0.0;
+    for (int j = 0; j < MT; ++j) xv[j] = a.X[col * a.ldx + mt[j] * 16 + r16];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) yv[i] = ok ? a.Y[col * a.ldy + nt[i] * 16 + r16] : 0.0;
+    for (int i = 0; i < NT; ++i) yv[i] = a.Y[col * a.ldy + nt[i] * 16 + r16];
   };
-  auto step = [&](const double* xv, const double* yv) {
+  auto step = [&](int c, const double* xv, const double* yv, double wl) {
+    const double wc = c + g < c1 ? wl : 0.0;
+    double ys[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) ys[i] = yv[i] * wc;
 #pragma unroll
     for (int j = 0; j < MT; ++j)
 #pragma unroll
-      for (int i = 0; i < NT; ++i) acc[j][i] = mfma_f64(xv[j], yv[i], acc[j][i]);
+      for (int i = 0; i < NT; ++i) acc[j][i] = mfma_f64(xv[j], ys[i], acc[j][i]);
   };
-  load(c0, xA, yA);
+  load(c0, xA, yA, wA);
   int c = c0;
   for (; c + 4 < c1; c += 8) {
-    load(c + 4, xB, yB);
-    step(xA, yA);
-    load(c + 8, xA, yA);  // past c1: zero operands
-    step(xB, yB);
+    load(c + 4, xB, yB, wB);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c, xA, yA, wA);
+    __builtin_amdgcn_sched_barrier(0);
+    load(c + 8, xA, yA, wA);  // past c1: weight 0
+    __builtin_amdgcn_sched_barrier(0);
+    step(c + 4, xB, yB, wB);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  if (c < c1) step(xA, yA);
+  if (c < c1) step(c, xA, yA, wA);
   double* out = a.part + ((int64_t)t * a.nchunks + blockIdx.x) * a.M * a.N;
 #pragma unroll
   for (int j = 0; j < MT; ++j) {
