@@ -310,14 +310,27 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) t1[mt][v] = g_kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, w1s[mt][v], b1s[mt][v]));
       double t2[4][4], h2[4][4];
+      // weight fragments are requested one group ahead of their products
+      // (one wave per SIMD: nothing else hides their latency)
+      double f2[2][8];
+      auto ld_f2 = [&](int ot, double* f) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            f[mt * 4 + v] = g_kpad<W>(mt, v) ? 0.0 : F2[((ot * 2 + mt) * 4 + v) * 64 + lane];
+      };
+      ld_f2(0, f2[0]);
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
+        if (ot + 1 < 4) ld_f2(ot + 1, f2[(ot + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
         d4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (!g_kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
+            if (!g_kpad<W>(mt, v)) z = mfma_f64(f2[ot & 1][mt * 4 + v], t1[mt][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           t2[ot][v] = g_kpad<W>(ot, v) ? 0.0 : tanh_d(z[v] + vec[64 + 16 * ot + 4 * v + g]);
@@ -359,8 +372,19 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
               t3v[o4 * 4 + v] = (lo < W) ? rec[(oo * 2 * W + (o4 >> 1) * W + lo) * 16] : 0.0;
             }
         }
+        double fb[2][16];
+        auto ld_b3 = [&](int o4, double* f) {
+#pragma unroll
+          for (int i2 = 0; i2 < 4; ++i2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              f[i2 * 4 + v] = g_kpad<W>(o4, v) ? 0.0 : B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane];
+        };
+        ld_b3(0, fb[0]);
 #pragma unroll
         for (int o4 = 0; o4 < 4; ++o4) {
+          if (o4 + 1 < 4) ld_b3(o4 + 1, fb[(o4 + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
           d4 z = {0.0, 0.0, 0.0, 0.0};
           if constexpr (!ST) {
             const double* b3 = vec + 128 + 16 * (4 * oo + o4) + g;
@@ -388,7 +412,7 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
           for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              if (!g_kpad<W>(o4, v)) dh2a[i2] = mfma_f64(B3o[((i2 * 8 + o4) * 4 + v) * 64 + lane], dz3[v], dh2a[i2]);
+              if (!g_kpad<W>(o4, v)) dh2a[i2] = mfma_f64(fb[o4 & 1][i2 * 4 + v], dz3[v], dh2a[i2]);
         }
         wave_lds_sync();
         // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]  (q in this half)
@@ -416,6 +440,16 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
       }
       // dz2 = (dh2 + skip)(1 - t2^2); dh1 = W2 dz2 + skip; dz1 = dh1 (1 - t1^2)
       double dz2[4][4], skip1[2][4];
+      double fb2[2][16];
+      auto ld_b2 = [&](int i2, double* f) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            f[o * 4 + v] = g_kpad<W>(o, v) ? 0.0 : B2[((i2 * 4 + o) * 4 + v) * 64 + lane];
+      };
+      ld_b2(0, fb2[0]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
@@ -431,12 +465,14 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
       double dz1[2][4];
 #pragma unroll
       for (int i2 = 0; i2 < 2; ++i2) {
+        if (i2 == 0) ld_b2(1, fb2[1]);
+        __builtin_amdgcn_sched_barrier(0);
         d4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (!g_kpad<W>(o, v)) z = mfma_f64(B2[((i2 * 4 + o) * 4 + v) * 64 + lane], dz2[o][v], z);
+            if (!g_kpad<W>(o, v)) z = mfma_f64(fb2[i2][o * 4 + v], dz2[o][v], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) dz1[i2][v] = (z[v] + skip1[i2][v]) * (1.0 - t1[i2][v] * t1[i2][v]);
       }
