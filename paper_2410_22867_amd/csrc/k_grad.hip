@@ -417,17 +417,25 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
         wave_lds_sync();
         // dW3[p][q] += sum_row h2[row][p] dz3[row][q];  db3[q] += sum_row dz3[row][q]  (q in this half)
         const double one = 1.0;
+        // the h2 operands are the same for every q tile: read once
+        double hA[4][4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+          for (int pt = 0; pt < 4; ++pt) hA[ks][pt] = T[4 * ks + g][16 * pt + r16];
 #pragma unroll 1
         for (int qh = 0; qh < 4; ++qh) {
           const int qt = 4 * oo + qh;
           d4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
           d4 bacc = {0, 0, 0, 0};
+          double bqv[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) bqv[ks] = T[4 * ks + g][64 + 16 * qh + r16];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
-            const int rr = 4 * ks + g;
-            const double bq = T[rr][64 + 16 * qh + r16];
+            const double bq = bqv[ks];
 #pragma unroll
-            for (int pt = 0; pt < 4; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
+            for (int pt = 0; pt < 4; ++pt) acc[pt] = mfma_f64(hA[ks][pt], bq, acc[pt]);
             if constexpr (!kBiasRow<W>) bacc = mfma_f64(one, bq, bacc);
           }
 #pragma unroll
@@ -494,16 +502,23 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
       wave_lds_sync();
       {
         const double one = 1.0;
+        double h1A[4][2];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+          for (int pt = 0; pt < 2; ++pt) h1A[ks][pt] = T[4 * ks + g][16 * pt + r16];
 #pragma unroll 1
         for (int qt = 0; qt < 4; ++qt) {
           d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
           d4 bacc = {0, 0, 0, 0};
+          double bqv[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) bqv[ks] = T[4 * ks + g][32 + 16 * qt + r16];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
-            const int rr = 4 * ks + g;
-            const double bq = T[rr][32 + 16 * qt + r16];
+            const double bq = bqv[ks];
 #pragma unroll
-            for (int pt = 0; pt < 2; ++pt) acc[pt] = mfma_f64(T[rr][16 * pt + r16], bq, acc[pt]);
+            for (int pt = 0; pt < 2; ++pt) acc[pt] = mfma_f64(h1A[ks][pt], bq, acc[pt]);
             if constexpr (!kBiasRow<W>) bacc = mfma_f64(one, bq, bacc);
           }
 #pragma unroll
