@@ -536,7 +536,8 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
           for (int ks = 0; ks < 4; ++ks) {
             const int rr = 4 * ks + g;
             const double bq = T[rr][96 + 16 * qt + r16];
-            wacc = mfma_f64(r16 == 0 ? T[rr][128] : (r16 == 1 ? one : 0.0), bq, wacc);
+            const double sr = T[rr][128];  // read by every lane, then selected
+            wacc = mfma_f64(r16 == 0 ? sr : (r16 == 1 ? one : 0.0), bq, wacc);
           }
           if (g == 0) atomicAdd(&aW1[16 * qt + r16], wacc[0]);
           if (g == 1) atomicAdd(&aB1[16 * qt + r16], wacc[0]);
