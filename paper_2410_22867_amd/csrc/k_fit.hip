@@ -381,7 +381,7 @@ __device__ __forceinline__ void epi_lp(const GemmArgs& g, const float* vec, int6
 // (rearranged into B-fragment order on the way) is loaded once per
 // work-group into double-buffered LDS, so a weight fragment serves 2 NTW
 // n-tiles and an X fragment 2 MTW m-tiles.
-template <class P, int MTW, int NTW>
+template <class P, int MTW, int NTW, int PF>
 __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   constexpr int MB = 2 * MTW, NB = 2 * NTW;  // m-tiles, n-tiles per work-group
   constexpr int BN = 16 * NB;
@@ -407,51 +407,48 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   // (col % 16) + 16 (2 (q % 2) + h), elements 4 (q / 2) .. +3, of n-tile
   // col / 16 (the k order of the fragments); BN * 4 / 256 columns each
   constexpr int XU = (BN * 4 + 255) / 256;
-  auto load = [&](int kt, u16x8* av, u16x8* xv) {
-#pragma unroll
-    for (int u = 0; u < AU; ++u) {
-      const int f = (tid >> 6) + 4 * u;
-      av[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (f < MB && mb0 + f < mtiles)
-        av[u] = *reinterpret_cast<const u16x8*>(Afr + (((int64_t)(mb0 + f) * KT + kt) * 64 + lane) * 8);
-    }
-#pragma unroll
-    for (int u = 0; u < XU; ++u) {
-      const int e = tid + 256 * u, col = e >> 2, q = e & 3;
-      xv[u] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      // the padded upper half of the last k-step may hold stale bits: zeros
-      if (col < BN && (q < 2 || 32 * kt + 16 < g.Kreal))
-        xv[u] = *reinterpret_cast<const u16x8*>(X + (int64_t)(cb + c0 + col) * g.ldx + 32 * kt + 8 * q);
-    }
+  // Operands travel global -> registers -> LDS.  Loads run PF k-steps
+  // ahead of the products through a ring of register buffers (PF = 8 for
+  // long reductions, 2 for short ones, where the ring's re-reads past the
+  // end would cost more than they hide); they have no
+  // branches around them (m-tiles past the last repeat it, their results
+  // are dropped), so no wait is forced before the ring slot is consumed.
+  static_assert((MB + 3) / 4 == 1 && (BN * 4 + 255) / 256 == 1, "one weight and one X vector per thread");
+  const int fA = tid >> 6;
+  const int mA = min(mb0 + fA, mtiles - 1);
+  const int colX = tid >> 2, qX = tid & 3;
+  const uint16_t* aSrc = Afr + ((int64_t)mA * KT * 64 + lane) * 8;
+  const uint16_t* xSrc = X + (int64_t)(cb + c0 + colX) * g.ldx + 8 * qX;
+  auto load = [&](int kt, u16x8& av, u16x8& xv) {
+    av = *reinterpret_cast<const u16x8*>(aSrc + (int64_t)kt * 512);
+    xv = *reinterpret_cast<const u16x8*>(xSrc + 32 * kt);
   };
-  auto store = [&](int buf, const u16x8* av, const u16x8* xv) {
-#pragma unroll
-    for (int u = 0; u < AU; ++u) {
-      const int f = (tid >> 6) + 4 * u;
-      if (f < MB) *reinterpret_cast<u16x8*>(&as[buf][(f * 64 + lane) * 8]) = av[u];
-    }
-#pragma unroll
-    for (int u = 0; u < XU; ++u) {
-      const int e = tid + 256 * u, col = e >> 2, q = e & 3;
-      if (col < BN) {
-        const int d0 = (((col >> 4) * 64 + 32 * (q & 1) + (col & 15)) * 8) + 4 * (q >> 1);
-        *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{xv[u][0], xv[u][1], xv[u][2], xv[u][3]};
-        *reinterpret_cast<u16x4*>(&xs[buf][d0 + 128]) = u16x4{xv[u][4], xv[u][5], xv[u][6], xv[u][7]};
-      }
-    }
+  auto store = [&](int buf, int kt, const u16x8& av, u16x8 xv) {
+    // the padded upper half of the last k-step may hold stale bits: zeros
+    if (!(qX < 2 || 32 * kt + 16 < g.Kreal)) xv = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (fA < MB) *reinterpret_cast<u16x8*>(&as[buf][(fA * 64 + lane) * 8]) = av;
+    const int d0 = (((colX >> 4) * 64 + 32 * (qX & 1) + (colX & 15)) * 8) + 4 * (qX >> 1);
+    *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{xv[0], xv[1], xv[2], xv[3]};
+    *reinterpret_cast<u16x4*>(&xs[buf][d0 + 128]) = u16x4{xv[4], xv[5], xv[6], xv[7]};
   };
   f4 acc[MTW][NTW];
 #pragma unroll
   for (int a = 0; a < MTW; ++a)
 #pragma unroll
     for (int b = 0; b < NTW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  u16x8 ar[AU], xr[XU];
-  load(0, ar, xr);
-  store(0, ar, xr);
+  u16x8 ar[PF], xr[PF];
+#pragma unroll
+  for (int d = 0; d < PF; ++d)
+    if (d < KT) load(d, ar[d], xr[d]);
+  store(0, 0, ar[0], xr[0]);
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
+  // one k-step: products from LDS buffer kt & 1, ring slot d refilled with
+  // k-step kt + PF (past the end the last k-step is read again and never
+  // stored, so neither the load nor the store needs a branch: the other LDS
+  // buffer after the last step is simply not read)
+  auto iter = [&](int kt, int d) {
     const int buf = kt & 1;
-    if (kt + 1 < KT) load(kt + 1, ar, xr);
+    load(min(kt + PF, KT - 1), ar[d], xr[d]);
     u16x8 aa[MTW], bb[NTW];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) aa[mt] = *reinterpret_cast<const u16x8*>(&as[buf][((wm * MTW + mt) * 64 + lane) * 8]);
@@ -463,9 +460,16 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
       for (int nt = 0; nt < NTW; ++nt)
         acc[mt][nt] = P::mfma(__builtin_bit_cast(typename P::vec8, aa[mt]), __builtin_bit_cast(typename P::vec8, bb[nt]),
                               acc[mt][nt]);
-    if (kt + 1 < KT) store(buf ^ 1, ar, xr);
+    store(buf ^ 1, min(kt + 1, KT - 1), ar[(d + 1) % PF], xr[(d + 1) % PF]);
     __syncthreads();
-  }
+  };
+  int kb = 0;
+  for (; kb + PF <= KT; kb += PF)
+#pragma unroll
+    for (int d = 0; d < PF; ++d) iter(kb + d, d);
+#pragma unroll
+  for (int d = 0; d < PF; ++d)
+    if (kb + d < KT) iter(kb + d, d);
   const float* vec = reinterpret_cast<const float*>(g.vec) + t * g.vec_type_stride;
 #pragma unroll
   for (int mt = 0; mt < MTW; ++mt) {
@@ -798,8 +802,14 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
   dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + 2 * MTW - 1) / (2 * MTW)),
             (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (mode == DP_MIX_BF16) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW>), grid, dim3(256), 0, s, g);
+  const bool deep = g.K / 32 >= 16;
+  if (mode == DP_MIX_BF16) {
+    if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
+  } else {
+    if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
+  }
 }
 
 // Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
