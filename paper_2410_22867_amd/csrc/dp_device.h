@@ -87,8 +87,11 @@ __device__ __forceinline__ typename P::vec8 load8(const uint16_t* p) {
 // to it in the Chebyshev (near-minimax) sense, fit error 3e-18 relative,
 // evaluated in w/32 with the coefficients scaled by 32^k (exact, so the
 // roundings are those of the unscaled form).  The reciprocal is the hardware
-// estimate refined by two Newton steps.  Absolute error below 5e-16 (about
-// 2 ulp of 1); relative accuracy is lost only for |x| below ~1e-3, where the
+// estimate q (relative error below 5e-8 on gfx950) refined in one step to
+// third order: with r = 1 - d q, 1/d = q (1 + r + r^2 + ...), and
+// q + q (r + r^2) leaves r^3 ~ 1e-22 (two Newton steps would cost one more
+// instruction and round twice).  Absolute error below 5e-16 (about 2 ulp
+// of 1); relative accuracy is lost only for |x| below ~1e-3, where the
 // absolute error still is ~1e-16.  A NaN argument gives +-0: every caller's
 // arguments derive from coordinates checked by the wrap test and parameters
 // checked finite when the model is created.
@@ -111,9 +114,9 @@ __device__ __forceinline__ double tanh_d(double x) {
   p = fma(p, w, 1.0);
   const double e = __builtin_amdgcn_ldexp(p, (int)n);
   const double d = 1.0 + e;
-  double q = __builtin_amdgcn_rcp(d);
-  q = q * fma(-d, q, 2.0);
-  q = q * fma(-d, q, 2.0);
+  const double q0 = __builtin_amdgcn_rcp(d);
+  const double r = fma(-d, q0, 1.0);
+  const double q = fma(q0, fma(r, r, r), q0);
   return __builtin_copysign(fma(2.0, q, -1.0), x);
 }
 
