@@ -120,8 +120,15 @@ struct CandRec {
   int8_t t;
   int8_t pad;
 };
+// CAP records per wave: kCandCap for the Verlet build (every pair within
+// r_c + skin); for the search and the format, which keep pairs within r_c
+// only, 256 when the sections hold at most 256 neighbours (half the LDS,
+// twice the resident work-groups), kCandCap otherwise.  More kept pairs
+// than CAP raise DP_FLAG_CAND_CAPACITY.
+constexpr int kKeepCapSmall = 256;
+template <int CAP>
 struct CandLds {
-  CandRec r[kSearchWaves][kCandCap];
+  CandRec r[kSearchWaves][CAP];
 };
 
 __device__ __forceinline__ int clamp_type(const int32_t* types, int j, int ntypes, int32_t* flags) {
@@ -135,8 +142,9 @@ __device__ __forceinline__ int clamp_type(const int32_t* types, int j, int ntype
 
 // Walks the 27 stencil cells of atom i (one wavefront) and appends every
 // (j, s) with r^2 < rad2 to the LDS buffers of wave w, in a fixed order.
-// Returns the candidate count (capped at kCandCap; *capacity set beyond).
-__device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds& L, int w, int lane, int i, const FrameInfo& F, double rad2,
+// Returns the candidate count (capped at CAP; *capacity set beyond).
+template <int CAP>
+__device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds<CAP>& L, int w, int lane, int i, const FrameInfo& F, double rad2,
                             bool* capacity) {
   const double xi = A.x[3 * i], yi = A.x[3 * i + 1], zi = A.x[3 * i + 2];
   const int ci[3] = {cell_coord(xi, F.L[0], F.ncell[0]), cell_coord(yi, F.L[1], F.ncell[1]),
@@ -202,7 +210,7 @@ __device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds& L, int
     const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
     const int slot = ncand + before;
-    if (keep && slot < kCandCap) {
+    if (keep && slot < CAP) {
       CandRec rec;
       rec.r2 = r2;
       rec.pk = 27 * j + scode;
@@ -213,9 +221,9 @@ __device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds& L, int
     }
     ncand += __popcll(mask);
   }
-  if (ncand > kCandCap) {
+  if (ncand > CAP) {
     *capacity = true;
-    ncand = kCandCap;
+    ncand = CAP;
   }
   return ncand;
 }
@@ -228,9 +236,10 @@ __device__ __forceinline__ int gather_cells(const SearchArgs& A, CandLds& L, int
 // with its own section.  With cof != NULL (Verlet format) it also records,
 // per written slot, the candidate it came from and, per kept candidate, its
 // slot (-1 when truncated).
-__device__ __forceinline__ void rank_and_write(const SearchArgs& A, CandLds& L, int w, int lane, int i, int ncand, bool capacity,
+template <int CAP>
+__device__ __forceinline__ void rank_and_write(const SearchArgs& A, CandLds<CAP>& L, int w, int lane, int i, int ncand, bool capacity,
                                int32_t* cof, int32_t* slot_of) {
-  constexpr int kPer = kCandCap / 64;
+  constexpr int kPer = CAP / 64;
   // records move as 16-byte vectors (r^2 bits | packed | k, type)
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   u32x4* R = reinterpret_cast<u32x4*>(&L.r[w][0]);
@@ -314,8 +323,9 @@ __device__ __forceinline__ void rank_and_write(const SearchArgs& A, CandLds& L, 
   }
 }
 
+template <int CAP>
 __global__ __launch_bounds__(256) void k_nl_search(SearchArgs A) {
-  __shared__ CandLds L;
+  __shared__ CandLds<CAP> L;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * kSearchWaves + w;
@@ -343,7 +353,7 @@ struct SkinArgs {
 };
 
 __global__ __launch_bounds__(256) void k_nl_skin_build(SearchArgs A, SkinArgs S, double rl2) {
-  __shared__ CandLds L;
+  __shared__ CandLds<kCandCap> L;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * kSearchWaves + w;
@@ -385,8 +395,9 @@ __global__ void k_nl_skin_crev(SkinArgs S, int ntot) {
 
 // Format: the sorted, truncated list on the current positions from the
 // candidates of the last build (same test and order as the cell search).
+template <int CAP>
 __global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S) {
-  __shared__ CandLds L;
+  __shared__ CandLds<CAP> L;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * kSearchWaves + w;
@@ -427,7 +438,8 @@ __global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S
     const uint64_t mask = __ballot(keep);
     const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-    if (keep) {
+    if (keep && ncand + before >= CAP) S.slot_of[(int64_t)i * kCandCap + k] = -1;  // beyond capacity (flagged)
+    if (keep && ncand + before < CAP) {
       int t = tj[m];
       if (t < 0 || t >= A.ntypes) {
         set_flag(A.flags, DP_FLAG_BAD_INPUT);
@@ -439,12 +451,14 @@ __global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S
       rec.k = (int16_t)k;
       rec.t = (int8_t)t;
       rec.pad = 0;
-      L.r[w][ncand + before] = rec;  // < nc <= kCandCap
+      L.r[w][ncand + before] = rec;
     }
     ncand += __popcll(mask);
   }
+  const bool capacity = ncand > CAP;
+  if (capacity) ncand = CAP;
   wave_lds_sync();
-  rank_and_write(A, L, w, lane, i, ncand, false, S.cof, S.slot_of);
+  rank_and_write(A, L, w, lane, i, ncand, capacity, S.cof, S.slot_of);
 }
 
 // Reverse index from the candidate bookkeeping of the format (same meaning
@@ -603,7 +617,9 @@ void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t 
                       int32_t* nlist, int32_t* overflow, hipStream_t s) {
   if (ntot <= 0) return;
   SearchArgs A = search_args(c, x, types, ntot, nframes, nlist, overflow);
-  hipLaunchKernelGGL(k_nl_search, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s, A);
+  const dim3 grid((ntot + kSearchWaves - 1) / kSearchWaves), block(64 * kSearchWaves);
+  if (A.nm <= kKeepCapSmall) hipLaunchKernelGGL(k_nl_search<kKeepCapSmall>, grid, block, 0, s, A);
+  else hipLaunchKernelGGL(k_nl_search<kCandCap>, grid, block, 0, s, A);
 }
 
 void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, hipStream_t s) {
@@ -622,8 +638,9 @@ void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int
   if (ntot <= 0) return;
   SearchArgs A = search_args(c, x, types, ntot, 1, nlist, c->ovf_ctr);
   SkinArgs S = skin_args(c);
-  hipLaunchKernelGGL(k_nl_skin_format, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s,
-                     A, S);
+  const dim3 grid((ntot + kSearchWaves - 1) / kSearchWaves), block(64 * kSearchWaves);
+  if (A.nm <= kKeepCapSmall) hipLaunchKernelGGL(k_nl_skin_format<kKeepCapSmall>, grid, block, 0, s, A, S);
+  else hipLaunchKernelGGL(k_nl_skin_format<kCandCap>, grid, block, 0, s, A, S);
   const int64_t q = (int64_t)ntot * A.nm;
   hipLaunchKernelGGL(k_nl_skin_revmap, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, nlist, S, c->rev, ntot,
                      A.nm, c->ovf_ctr, overflow);
