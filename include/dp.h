@@ -68,8 +68,10 @@ extern "C" {
 #define DP_FLAG_NOT_WRAPPED 1
 #define DP_FLAG_OVERLAP 2
 #define DP_FLAG_NONFINITE 4
-#define DP_FLAG_CAND_CAPACITY 8 /* more pairs than the per-atom capacity: 512 within r_c + skin for a \
-                                   Verlet build; within r_c, 256 when sum(sel) <= 256, else 512 */
+/* DP_FLAG_CAND_CAPACITY: more pairs than the per-atom capacity (512 within
+ * r_c + skin for a Verlet build; within r_c, 256 when sum(sel) <= 256, else
+ * 512). */
+#define DP_FLAG_CAND_CAPACITY 8
 #define DP_FLAG_SEL_OVERFLOW 16 /* some section had more neighbours than sel (truncated) */
 #define DP_FLAG_BAD_INPUT 32    /* a type outside [0, ntypes) or a neighbour index >= n (ignored) */
 #define DP_FLAG_SKIN_EXCEEDED 64 /* an atom moved more than skin/2 since the Verlet build (list may miss pairs) */
