@@ -236,3 +236,32 @@ def test_types_changed_in_place_need_new_list(dev, water):
     rr = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
     _check_fp64(rr, o, fr.n)
     assert ctx.status() == 0
+
+
+def test_candidate_capacity_flag(dev, water):
+    """More than 256 pairs within r_c per atom with sum(sel) = 138: the
+    search and the Verlet format (which then keep 256 pairs in LDS) raise the
+    capacity flag instead of writing past their buffers."""
+    from paper_2410_22867_amd import dpse
+    desc, p, model = water
+    rng = np.random.default_rng(31)
+    L = 12.5
+    pts = []
+    while len(pts) < 620:  # ~0.32 atoms per cubic angstrom, pairs at least 0.8 A apart
+        q = rng.random(3) * L
+        if all(np.linalg.norm((q - o + L / 2) % L - L / 2) > 0.8 for o in pts[-400:]):
+            pts.append(q)
+    fr = I.Frame(coords=np.array(pts), types=(np.arange(len(pts)) % 3 == 0).astype(np.int32) ^ 1,
+                 box=np.diag([L, L, L]))
+    _say("capacity flag", fr.n)
+    for verlet in (False, True):
+        ctx = dpse.Context(model, fr.n)
+        x = torch.tensor(fr.coords, device=dev)
+        t = torch.tensor(fr.types, device=dev)
+        if verlet:
+            ctx.skin_build(x, t, fr.box, 0.5)
+            nl, ov = ctx.skin_format(x, t)
+        else:
+            nl, ov = ctx.build_nlist(x, t, fr.box)
+        torch.cuda.synchronize()
+        assert ctx.status() & dpse.FLAG_CAND_CAPACITY
