@@ -153,7 +153,6 @@ struct dp_ctx {
   double* Ei_col;          // [cols]
   double* Ei_atom;         // [N]
   double* netd;            // [N, nm, 4] f64
-  double* g3;              // [N, nm, 4] f64 pair force terms
   int32_t* rev;            // [N, nm] reverse-entry index of the list in use
   // Verlet (skin) list of the last dp_nlist_skin_build
   int32_t* skin_cand;      // [N, kCandCap] packed candidates, sorted by packed value

@@ -232,12 +232,17 @@ void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t*
 }
 
 // ---------------------------------------------------------------- forces
-// g_ij = sum_k n_ij[k] dR_ij[k]/dd (d = x_j + s L - x_i).  Pass 1 (one
-// wavefront per atom i) writes g for every slot and the per-atom virial row
-// -sum d (x) g; a slot whose reverse entry is missing (j's section was
-// truncated) subtracts g from F_j with an atomic.  Pass 2 gathers
-// F_i = sum_q g_iq - sum_q g[rev(i, q)] in a fixed order, so forces do not
-// depend on scheduling when the list is symmetric.
+// g_ij = sum_k n_ij[k] dR_ij[k]/dd (d = x_j + s L - x_i), one pass with
+// one wavefront per atom i: for every own slot q, g_iq from n(i, q) adds to
+// F_i and to the atom's virial row -sum d (x) g; for the reverse entry r of
+// the slot ((i, -s) in j's list) the pair's g_ji is recomputed from n(r) and
+// d_ji = -d_ij, which is bit-identical to j's own g at r (fl(a - b) =
+// -fl(b - a) and the shift changes sign exactly), and subtracted from F_i.
+// F_i is therefore summed in a fixed order with no g buffer in HBM.  A slot
+// whose reverse entry is missing (j's section was truncated) subtracts g_iq
+// from F_j with an atomic; the atom's own total is added atomically too, so
+// the two never race (forces were cleared by the environment pass, and with
+// a symmetric list each F_i receives exactly one addition).
 struct ForceArgs {
   const double* x;
   const int32_t* nlist;
@@ -245,47 +250,64 @@ struct ForceArgs {
   const int32_t* frame_of;
   const FrameInfo* fr;
   const double* netd;
-  double* g3;      // [N, nm, 4] (4th entry unused)
   double* F;
   double* vatom;
   int ntot, nm;
   double rs, rc, inv_std_s, inv_std_v;
 };
 
-__global__ __launch_bounds__(256) void k_force_pairs(ForceArgs A) {
+__device__ __forceinline__ void pair_g(const double d[3], const d4 n, const ForceArgs& A, double g[3]) {
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double s, ds;
+  switch_fn(r, A.rs, A.rc, s, ds);
+  const double ir = 1.0 / r;
+  // dR0/dd_a = ds d_a / r (scaled); dRc/dd_a = ds d_a d_c / r^2 + s (delta_ca / r - d_c d_a / r^3)
+  const double n0 = n[0] * A.inv_std_s;
+  const double nv[3] = {n[1] * A.inv_std_v, n[2] * A.inv_std_v, n[3] * A.inv_std_v};
+  const double ndot = nv[0] * d[0] + nv[1] * d[1] + nv[2] * d[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ua = d[a] * ir;
+    g[a] = n0 * ds * ua + ndot * (ds * ua * ir) + s * (nv[a] * ir - ndot * ua * ir * ir);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_force(ForceArgs A) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= A.ntot) return;
   const FrameInfo& F = A.fr[A.frame_of[i]];
   const double xi = A.x[3 * i], yi = A.x[3 * i + 1], zi = A.x[3 * i + 2];
   double vir[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
   for (int q = lane; q < A.nm; q += 64) {
     const int64_t slot = (int64_t)i * A.nm + q;
     const int e = A.nlist[slot];
     if (e < 0 || e / 27 >= A.ntot) continue;
     const int j = e / 27, sc = e - 27 * (e / 27);
+    const int r = A.rev[slot];
+    const d4 n = *reinterpret_cast<const d4*>(A.netd + slot * 4);
+    d4 nr = {0.0, 0.0, 0.0, 0.0};
+    if (r >= 0) nr = *reinterpret_cast<const d4*>(A.netd + (int64_t)r * 4);
     const double d[3] = {(A.x[3 * j] - xi) + (double)(sc % 3 - 1) * F.L[0],
                          (A.x[3 * j + 1] - yi) + (double)((sc / 3) % 3 - 1) * F.L[1],
                          (A.x[3 * j + 2] - zi) + (double)(sc / 9 - 1) * F.L[2]};
-    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double s, ds;
-    switch_fn(r, A.rs, A.rc, s, ds);
-    const d4 n = *reinterpret_cast<const d4*>(A.netd + slot * 4);
-    const double ir = 1.0 / r;
-    // dR0/dd_a = ds d_a / r (scaled); dRc/dd_a = ds d_a d_c / r^2 + s (delta_ca / r - d_c d_a / r^3)
-    const double n0 = n[0] * A.inv_std_s;
-    const double nv[3] = {n[1] * A.inv_std_v, n[2] * A.inv_std_v, n[3] * A.inv_std_v};
-    const double ndot = nv[0] * d[0] + nv[1] * d[1] + nv[2] * d[2];
     double g[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double ua = d[a] * ir;
-      g[a] = n0 * ds * ua + ndot * (ds * ua * ir) + s * (nv[a] * ir - ndot * ua * ir * ir);
-    }
-    *reinterpret_cast<d4*>(A.g3 + slot * 4) = d4{g[0], g[1], g[2], 0.0};
-    if (A.rev[slot] < 0)
+    pair_g(d, n, A, g);
+    f[0] += g[0];
+    f[1] += g[1];
+    f[2] += g[2];
+    if (r >= 0) {
+      const double dm[3] = {-d[0], -d[1], -d[2]};
+      double gb[3];
+      pair_g(dm, nr, A, gb);
+      f[0] -= gb[0];
+      f[1] -= gb[1];
+      f[2] -= gb[2];
+    } else {
 #pragma unroll
       for (int a = 0; a < 3; ++a) atomicAdd(&A.F[3 * j + a], -g[a]);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -293,37 +315,14 @@ __global__ __launch_bounds__(256) void k_force_pairs(ForceArgs A) {
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = wave_sum_d(vir[k]);
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 9; ++k) A.vatom[(int64_t)i * 9 + k] = vir[k];
-}
-
-__global__ __launch_bounds__(256) void k_force_gather(ForceArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= A.ntot) return;
-  double f[3] = {0.0, 0.0, 0.0};
-  for (int q = lane; q < A.nm; q += 64) {
-    const int64_t slot = (int64_t)i * A.nm + q;
-    const int e = A.nlist[slot];
-    if (e < 0 || e / 27 >= A.ntot) continue;
-    const d4 own = *reinterpret_cast<const d4*>(A.g3 + slot * 4);
-    f[0] += own[0];
-    f[1] += own[1];
-    f[2] += own[2];
-    const int r = A.rev[slot];
-    if (r >= 0) {
-      const d4 back = *reinterpret_cast<const d4*>(A.g3 + (int64_t)r * 4);
-      f[0] -= back[0];
-      f[1] -= back[1];
-      f[2] -= back[2];
-    }
-  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = wave_sum_d(f[a]);
-  if (lane == 0)
+  if (lane == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) A.F[3 * i + a] += f[a];
+    for (int k = 0; k < 9; ++k) A.vatom[(int64_t)i * 9 + k] = vir[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(&A.F[3 * i + a], f[a]);
+  }
 }
 
 void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot, double* forces, hipStream_t s) {
@@ -336,7 +335,6 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
   A.frame_of = c->frame_of;
   A.fr = c->frames_dev;
   A.netd = c->netd;
-  A.g3 = c->g3;
   A.F = forces;
   A.vatom = c->vatom;
   A.ntot = ntot;
@@ -346,8 +344,7 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
   A.inv_std_s = 1.0 / m->desc.std_s;
   A.inv_std_v = 1.0 / m->desc.std_v;
   // forces were cleared by the environment pass of the same compute
-  hipLaunchKernelGGL(k_force_pairs, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
-  hipLaunchKernelGGL(k_force_gather, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_force, dim3((ntot + 3) / 4), dim3(256), 0, s, A);
 }
 
 // ---------------------------------------------------------------- reductions
