@@ -602,7 +602,7 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
   { StageScope p(c, DP_STAGE_FIT_FWD, s); launch_fit_forward(c, mode, c->train_h, s); }
   c->h_stored = c->train_h;
-  { StageScope p(c, DP_STAGE_FIT_BWD, s); launch_fit_backward(c, mode, s); }
+  { StageScope p(c, DP_STAGE_FIT_BWD, s); launch_fit_backward(c, mode, c->train_h, s); }
   { StageScope p(c, DP_STAGE_DESC_BWD, s); launch_desc_bwd(c, mode, s); }
   { StageScope p(c, DP_STAGE_EMBED_BWD, s); launch_embed_bwd(c, types, mode, s); }
   { StageScope p(c, DP_STAGE_FORCE, s); launch_force(c, x, nlist, ntot, forces, s); }
@@ -1010,12 +1010,14 @@ int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipS
   if ((rc = set_device(c->device))) return rc;
   const dp_model* m = c->model;
   const int fw = m->fw, nd = m->nd, fwp = ((fw + 31) / 32) * 32;
-  // computes store h2 and h3 (read only here) once a gradient pass has run
-  // on the context; the first time, the fitting forward runs again to form
-  // them (same inputs, same values for everything it rewrites)
+  // computes store h2, h3 and dz2 (read only here) once a gradient pass
+  // has run on the context; the first time, the fitting forward and
+  // backward run again to form them (same inputs, same values for
+  // everything they rewrite)
   c->train_h = true;
   if (!c->h_stored) {
     launch_fit_forward(c, c->mode_last, true, stream);
+    launch_fit_backward(c, c->mode_last, true, stream);
     c->h_stored = true;
   }
   ParamGradInputs in;

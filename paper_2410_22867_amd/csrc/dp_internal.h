@@ -119,8 +119,8 @@ struct dp_ctx {
   int64_t natoms_last;
   int32_t mode_last;
   bool have_state;
-  bool train_h;   // a parameter-gradient pass has run on this context: computes keep h2, h3
-  bool h_stored;  // the last compute stored h2, h3
+  bool train_h;   // a parameter-gradient pass has run on this context: computes keep h2, h3, dz2
+  bool h_stored;  // the last compute stored h2, h3, dz2
   const int32_t* types_last;
   // status
   int32_t* flags_dev;
@@ -222,7 +222,7 @@ void launch_embed_fwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t
 void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s);
 void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s);
-void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s);
+void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s);
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
 void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot, double* forces, hipStream_t s);

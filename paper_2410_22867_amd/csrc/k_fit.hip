@@ -322,7 +322,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
           const int m = feat(j, v);
           const double dz = acc[j][nt][v] * (1.0 - tp[j][nt][v] * tp[j][nt][v]);
           hrow(nt)[m] = dz;
-          p.out[0][colof(nt) * fw + m] = dz;
+          if (p.out[0]) p.out[0][colof(nt) * fw + m] = dz;
         }
     }
     load_t(p.tprev[1]);
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
       store4lp<P>(hsh + r16 * ldh + m0, dz);
-      store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
+      if (p.outlp[0]) store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
     }
     load_t(p.tprev[1]);
     __syncthreads();
@@ -928,7 +928,8 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
   }
 }
 
-void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
+// keep_dz2: also store dz2, which only the parameter gradients read.
+void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s) {
   const dp_model* m = c->model;
   if (c->natoms_last <= 0) return;
   const int fw = m->fw;
@@ -952,7 +953,7 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.vec_type_stride = m->fit_vec_per_type;
     p.tprev[0] = (const double*)c->fa[1];
     p.tprev[1] = (const double*)c->fa[0];
-    p.out[0] = (double*)c->fa[7];
+    p.out[0] = keep_dz2 ? (double*)c->fa[7] : nullptr;
     p.out[1] = (double*)c->fa[8];
     launch_pair_f64(c, true, p, s);
   } else {
@@ -968,7 +969,7 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, hipStream_t s) {
     p.vec_type_stride = m->fit_vec_per_type;
     p.tprev[0] = (const float*)c->fa[1];
     p.tprev[1] = (const float*)c->fa[0];
-    p.outlp[0] = (uint16_t*)c->fa[8];
+    p.outlp[0] = keep_dz2 ? (uint16_t*)c->fa[8] : nullptr;
     p.outlp[1] = (uint16_t*)c->fa[9];
     launch_pair_lp(c, true, mode, p, s);
   }
