@@ -125,16 +125,48 @@ def test_fp64_water192_all_stages(dev):
     assert ctx.status() == 0
 
 
+_ocache = {}
+
+
+def _oracle_full(name, fr, desc, p):
+    if name not in _ocache:
+        _ocache[name] = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    return _ocache[name]
+
+
 @pytest.mark.parametrize("name", ["water12k", "copper32k"])
 def test_fp64_full_frames(dev, name):
     fr, desc, p, model, ctx, x, t = _setup(name, dev)
     _say("fp64 full", name)
     r = _compute(ctx, x, t, fr.box, "fp64")
-    o = oracle.compute(fr.coords, fr.types, fr.box, desc, p)
+    o = _oracle_full(name, fr, desc, p)
     assert abs(r["E"][0] - o["E"]) <= 1e-10 * abs(o["E"])
     assert np.abs(r["F"] - o["F"]).max() <= 1e-9
     assert np.abs(r["W"].reshape(3, 3) - o["W"]).max() <= 1e-9 * max(1.0, np.abs(o["W"]).max())
     assert np.abs(r["Ei"] - o["Ei"]).max() <= 1e-10 * np.abs(o["Ei"]).max()
+    assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("name", ["water12k", "copper32k"])
+@pytest.mark.parametrize("mode", ["bf16", "fp16"])
+def test_mixed_full_frames(dev, name, mode):
+    """Mixed precision at full size against the FP64 oracle: the mixed
+    speedup is quoted at a force RMS error of at most 1 meV/A, asserted here
+    on both systems (measured: water BF16 0.95, FP16 0.13; copper BF16 0.16,
+    FP16 0.02 meV/A); energy within 5 meV/atom."""
+    fr, desc, p, model, ctx, x, t = _setup(name, dev)
+    _say("mixed full", name, mode)
+    r = _compute(ctx, x, t, fr.box, mode)
+    o = _oracle_full(name, fr, desc, p)
+    e_err = abs(r["E"][0] - o["E"]) / fr.n
+    f_rms = np.sqrt(((r["F"] - o["F"]) ** 2).mean())
+    f_scale = np.sqrt((o["F"] ** 2).mean())
+    w_err = np.abs(r["W"].reshape(3, 3) - o["W"]).max() / fr.n
+    _say(name, mode, "E err meV/atom", 1e3 * e_err, "F rms err meV/A", 1e3 * f_rms,
+         "F rms meV/A", 1e3 * f_scale, "W err meV/atom", 1e3 * w_err)
+    assert f_rms <= 1e-3
+    assert e_err <= 5e-3
+    assert np.isfinite(r["W"]).all()
     assert ctx.status() == 0
 
 
