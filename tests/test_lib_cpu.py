@@ -70,3 +70,15 @@ def test_null_arguments_rejected():
     assert L.dp_ctx_status(None, ctypes.byref(f)) == -1
     cap, used = ctypes.c_int64(0), ctypes.c_int32(0)
     assert L.dp_ctx_store_info(None, ctypes.byref(cap), ctypes.byref(used)) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises: there is no CPU
+    fallback behind the binding."""
+    monkeypatch.setattr(dpse, "LIB_PATH", str(tmp_path / "libdpse.so"))
+    monkeypatch.setattr(dpse, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        dpse.lib()
+    fr, desc, p, dt = I.workload("water192")
+    with pytest.raises(RuntimeError, match="not built"):
+        dpse.Model(desc, p)
