@@ -417,8 +417,14 @@ int prepare_model(dp_model* m, const double* P) {
     if ((rc = dev_alloc(&m->fit_vec64, fv.size(), "hipMalloc(fit vec)"))) return rc;
     if ((rc = dev_alloc(&m->fit_vec32, fv32.size(), "hipMalloc(fit vec32)"))) return rc;
   } else {
-    (void)hipFree(m->emb_frag_bf16); (void)hipFree(m->emb_frag_f16);
-    (void)hipFree(m->fit_frag_bf16); (void)hipFree(m->fit_frag_f16);
+    // the half-precision copies are reallocated below; cleared first so that
+    // a failed reallocation leaves nothing for free_model to free twice
+    void** lp[] = {(void**)&m->emb_frag_bf16, (void**)&m->emb_frag_f16, (void**)&m->fit_frag_bf16,
+                   (void**)&m->fit_frag_f16};
+    for (void** q : lp) {
+      (void)hipFree(*q);
+      *q = nullptr;
+    }
   }
   if ((rc = upload(m->params, P, (size_t)m->n_params * 8))) return rc;
   if ((rc = upload(m->emb_vec64, ev.data(), ev.size() * 8))) return rc;
