@@ -97,6 +97,46 @@ def test_format_equals_brute_force(dev, name):
     assert ctx.status() & ~dpse.FLAG_SEL_OVERFLOW == 0
 
 
+def test_exact_ties_perfect_lattice(dev):
+    """A perfect FCC lattice: every coordination shell is a set of exactly
+    equal r^2 (12, 6, 24, ... pairs), so the sections' order rests on the
+    tie-break by packed index j*27 + image code.  The cell-list build, the
+    Verlet build + format and the FP64 compute must all reproduce the
+    oracle's brute-force list and results."""
+    from paper_2410_22867_amd import dpse
+    desc = I.COPPER
+    p = I.init_params(desc, 13)
+    fr = I.copper_fcc(6, 3.634, 0.0, seed=0)
+    _say("ties", fr.n)
+    ref, rov = oracle.nlist(fr.coords, fr.types, fr.box, desc, use_cells=False)
+    assert rov == 0
+    # the premise: row 0 holds many exactly equal distances
+    L = np.diag(fr.box)
+    j, sc = ref[0][ref[0] >= 0] // 27, ref[0][ref[0] >= 0] % 27
+    s = np.stack([sc % 3 - 1, (sc // 3) % 3 - 1, sc // 9 - 1], axis=1)
+    d = (fr.coords[j] - fr.coords[0]) + s * L
+    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    assert len(np.unique(r2)) < len(r2) // 4
+    model = dpse.Model(desc, p)
+    ctx = dpse.Context(model, fr.n)
+    x = torch.tensor(fr.coords, device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    cell, ov = ctx.build_nlist(x, t, fr.box)
+    assert np.array_equal(cell.cpu().numpy(), ref)
+    assert int(ov.cpu().item()) == 0
+    ctx.skin_build(x, t, fr.box, SKIN)
+    nl, ov = ctx.skin_format(x, t)
+    assert np.array_equal(nl.cpu().numpy(), ref)
+    assert int(ov.cpu().item()) == 0
+    r = ctx.compute(x, t, fr.box, nl, want_atom_energy=True)
+    torch.cuda.synchronize()
+    o = oracle.compute(fr.coords, fr.types, fr.box, desc, p, use_cells=False)
+    assert abs(r["E"].item() - o["E"]) <= 1e-10 * abs(o["E"])
+    assert np.abs(r["F"].cpu().numpy() - o["F"]).max() <= 1e-9
+    assert np.abs(r["W"].cpu().numpy().reshape(3, 3) - o["W"]).max() <= 1e-9 * max(1.0, np.abs(o["W"]).max())
+    assert ctx.status() == 0
+
+
 def test_skin_exceeded_flag_and_rebuild(dev):
     from paper_2410_22867_amd import dpse
     fr, desc, p = _case("water192")
