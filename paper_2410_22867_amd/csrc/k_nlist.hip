@@ -295,13 +295,45 @@ __device__ __forceinline__ void rank_and_write(const SearchArgs& A, CandLds<CAP>
     const CandRec* sec = &L.r[w][off[u]];
     const int n_u = cnt[u];
     const int sel = A.sel[u];
-    for (int c = lane; c < n_u; c += 64) {
-      const CandRec me = sec[c];
-      int rank = 0;
+    // Rank of each candidate in its section on (r^2, packed).  Exact ties in
+    // r^2 are rare, so each candidate first counts the candidates whose r^2
+    // is <= its own (one compare per pair).  Without ties these counts are
+    // a permutation of 1..n_u; with T pairs of equal r^2 they sum to
+    // n_u (n_u + 1) / 2 + T, so one wave sum tells whether the section
+    // needs the full comparison with the packed-index tie-break.
+    int rk[kPer];
+    int sum = 0;
+#pragma clang loop unroll(full)
+    for (int m = 0; m < kPer; ++m) {
+      rk[m] = 0;
+      if (64 * m < n_u) {
+        const int c = 64 * m + lane;
+        if (c < n_u) {
+          const double r2 = sec[c].r2;
+          int le = 0;
 #pragma unroll 4
-      for (int o = 0; o < n_u; ++o) {
-        const CandRec ot = sec[o];
-        rank += (ot.r2 < me.r2 || (ot.r2 == me.r2 && ot.pk < me.pk));
+          for (int o = 0; o < n_u; ++o) le += sec[o].r2 <= r2;
+          rk[m] = le;
+          sum += le;
+        }
+      }
+    }
+#pragma unroll
+    for (int x = 32; x >= 1; x >>= 1) sum += __shfl_xor(sum, x, 64);
+    const bool ties = sum != n_u * (n_u + 1) / 2;
+#pragma clang loop unroll(full)
+    for (int m = 0; m < kPer; ++m) {
+      if (64 * m >= n_u) break;
+      const int c = 64 * m + lane;
+      if (c >= n_u) continue;
+      const CandRec me = sec[c];
+      int rank = rk[m] - 1;
+      if (ties) {
+        rank = 0;
+        for (int o = 0; o < n_u; ++o) {
+          const CandRec ot = sec[o];
+          rank += (ot.r2 < me.r2 || (ot.r2 == me.r2 && ot.pk < me.pk));
+        }
       }
       const bool kept = rank < sel;
       if (kept) row[A.sec[u] + rank] = me.pk;
