@@ -71,6 +71,26 @@ def measured_traffic(stage, workload):
     return None
 
 
+def stage_bytes(desc, real_rows, natoms, skin):
+    """Algorithmic HBM bytes per launch of the memory-bound stages (FP64
+    step; real neighbour rows only for gathers, the padded [n, nm] arrays as
+    written).  nlist: the Verlet format reads each candidate (4 B index, 24 B
+    position, 4 B type) for about real_rows * ((r_c + skin) / r_c)^3
+    candidates and writes the list and its bookkeeping (3 x 4 B per slot),
+    then the reverse map reads 3 and writes 1 word per slot.  env: list in,
+    24 B per real row gathered, R~ out (32 B per slot).  force: list and
+    reverse index in, two net_deriv rows (64 B), one position (24 B) and the
+    8 B reverse check per real row, forces and per-atom virial rows out."""
+    nm = desc.nm
+    cand = real_rows * ((desc.rcut + skin) / desc.rcut) ** 3
+    slots = natoms * nm
+    return {
+        "nlist": int(cand * 32 + slots * 4 * 3 + slots * 4 * 4),
+        "env": int(slots * (4 + 32) + real_rows * 24 + natoms * (24 + 16 + 24)),
+        "force": int(slots * 8 + real_rows * (64 + 24 + 8) + natoms * (24 + 72 + 24)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,8 +103,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--nlist", default="verlet", choices=["verlet", "rebuild"],
-                    help="verlet: Verlet list rebuilt every --rebuild-every steps with --skin, formatted every "
-                         "step; rebuild: cell-list build from scratch every step")
+                    help="verlet: Verlet list formatted every step and rebuilt on the device when an atom has "
+                         "moved beyond skin/2 or --rebuild-every steps have passed; rebuild: cell-list build "
+                         "from scratch every step")
     ap.add_argument("--skin", type=float, default=2.0)
     ap.add_argument("--rebuild-every", type=int, default=50)
     ap.add_argument("--workspace-gib", type=float, default=64.0,
@@ -104,6 +125,7 @@ def main():
     if args.workload == "waterbatch64":
         bench_batch(args, torch, dpse, I, dev)
         return
+    modes = args.modes.split(",")
     fr, desc, params, dt = I.workload(args.workload)
     wl_index = {"water192": 0, "water12k": 1, "copper32k": 2, "water98k": 3}[args.workload]
     n = fr.n
@@ -121,38 +143,27 @@ def main():
     W = torch.empty(9, dtype=torch.float64, device=dev)
     ke = torch.empty(1, dtype=torch.float64, device=dev)
     f = torch.empty((n, 3), dtype=torch.float64, device=dev)
-
+    nreb = torch.zeros(1, dtype=torch.int32, device=dev)
     verlet = args.nlist == "verlet"
-    counter = [0]
 
-    def neighbours(x):
+    def step(x, v, mode, h=dt):
+        """One MD step; every launch is asynchronous (no host wait)."""
+        ctx.kick_drift(x, v, f, t, box, h, wrap=not verlet)
         if verlet:
-            if counter[0] % args.rebuild_every == 0:
-                ctx.skin_build(x, t, box, args.skin)
-            ctx.skin_format(x, t, out=nl, overflow=ov)
+            ctx.skin_update(x, t, every=args.rebuild_every, out=nl, overflow=ov, rebuilds=nreb)
         else:
             ctx.build_nlist(x, t, box, out=nl, overflow=ov)
-
-    rebuilds = [0]
-
-    def step(x, v, mode, exact=False):
-        """One MD step.  exact: also rebuild the Verlet list whenever an atom
-        has moved beyond half the skin (checked on the host, with a sync)."""
-        counter[0] += 1
-        ctx.kick_drift(x, v, f, t, box, dt, wrap=not verlet)
-        neighbours(x)
-        if exact and verlet and ctx.status() & dpse.FLAG_SKIN_EXCEEDED:
-            ctx.skin_build(x, t, box, args.skin)
-            ctx.skin_format(x, t, out=nl, overflow=ov)
-            rebuilds[0] += 1
         ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
-        ctx.kick(v, f, t, dt, ke)
+        ctx.kick(v, f, t, h, ke)
 
     def init_state(mode):
         x = x0.clone()
         v = v0.clone()
-        counter[0] = 0
-        neighbours(x)
+        if verlet:
+            ctx.skin_build(x, t, box, args.skin)
+            ctx.skin_format(x, t, out=nl, overflow=ov)
+        else:
+            ctx.build_nlist(x, t, box, out=nl, overflow=ov)
         ctx.compute(x, t, box, nl, mode=mode, energy=E, forces=f, virial=W)
         activations[mode] = "stored" if ctx.store_info()[1] else "recomputed"
         return x, v
@@ -167,19 +178,18 @@ def main():
 
     # single-frame results on the initial configuration (accuracy)
     first = {}
-    for mode in args.modes.split(","):
+    for mode in modes:
         x, v = init_state(mode)
         torch.cuda.synchronize()
         first[mode] = dict(E=float(E.item()), F=f.cpu().numpy().copy(), W=W.cpu().numpy().copy())
     real_rows = int((nl >= 0).sum().item())
     fl = ctx.status()
-    if fl & ~dpse.FLAG_SEL_OVERFLOW:
-        raise RuntimeError(f"device status flags {fl}")
-    status_flags = fl
+    if fl:
+        raise RuntimeError(f"device status flags {fl} on the initial frame")
 
     # per-stage event timing (separate pass over all stages)
     stages = {}
-    for mode in args.modes.split(","):
+    for mode in modes:
         x, v = init_state(mode)
         torch.cuda.synchronize()
         ctx.profile(True)
@@ -196,65 +206,82 @@ def main():
     # recorded on its own stream inside the same region (roofline below)
     results = {}
     dom_live = None
-    for mode in args.modes.split(","):
+    timed_flags = 0
+    for mode in modes:
         x, v = init_state(mode)
         for _ in range(args.warmup):
             step(x, v, mode)
         live = mode == "fp64" and dom is not None
         if live:
             ctx.profile(True, stages=[dom])
+        ctx.status()                     # clears the status word before the timed steps
         torch.cuda.synchronize()
+        r0 = int(nreb.item())
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(x, v, mode)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        rebuilds = int(nreb.item()) - r0
         if live:
             ms_dom, cnt = ctx.stage_times()[dom]
             ctx.profile(False)
             dom_live = (ms_dom / cnt, cnt) if cnt else None
+        fl = ctx.status()
+        timed_flags |= fl
         ms = el / args.steps * 1e3
         results[mode] = dict(ms_per_step=ms, atom_steps_per_s=n * args.steps / el,
-                             ns_per_day=(args.steps / el) * dt * 0.0864)
-        print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s", file=sys.stderr, flush=True)
-    fl = ctx.status()
-    if fl & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED):
-        raise RuntimeError(f"device status flags {fl}")
-    status_flags = fl
+                             ns_per_day=(args.steps / el) * dt * 0.0864, verlet_rebuilds=rebuilds,
+                             status_flags=fl)
+        print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s, {rebuilds} rebuilds, "
+              f"flags {fl}", file=sys.stderr, flush=True)
+    if timed_flags & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED):
+        raise RuntimeError(f"device status flags {timed_flags}")
 
-    # NVE energy drift (velocity Verlet, metal units).  The Verlet list is
-    # rebuilt on schedule and, in addition, whenever an atom has moved beyond
-    # half the skin, so every step sees the complete list.  The drift is
-    # measured up to the first step whose list was truncated (sel overflow),
-    # after which the random-weight model's energy is no longer smooth.
-    drift = {}
-    for mode in args.modes.split(","):
-        if args.nve_steps <= 0:
-            break
+    # NVE energy drift (velocity Verlet, metal units) over every step: the
+    # same step as the timed one (rebuilds decided on the device, so every
+    # list is exact while no section overflows); the energies and the
+    # truncation counts are kept on the device and read once at the end.
+    def nve(mode, nsteps, h):
         x, v = init_state(mode)
-        hist = torch.empty((args.nve_steps + 1, 3), dtype=torch.float64, device=dev)
+        hist = torch.empty((nsteps + 1, 3), dtype=torch.float64, device=dev)
         ctx.kick(v, torch.zeros_like(f), t, 0.0, ke)
         hist[0, 0] = E[0]
         hist[0, 1] = ke[0]
         hist[0, 2] = 0.0
         ctx.status()
-        rebuilds[0] = 0
-        for k in range(args.nve_steps):
-            step(x, v, mode, exact=True)
+        torch.cuda.synchronize()
+        r0 = int(nreb.item())
+        for k in range(nsteps):
+            step(x, v, mode, h)
             hist[k + 1, 0] = E[0]
             hist[k + 1, 1] = ke[0]
             hist[k + 1, 2] = ov[0]
-        h = hist.cpu().numpy()
-        bad = np.nonzero(h[:, 2] > 0)[0]
-        clean = int(bad[0]) if len(bad) else len(h)
-        etot = h[:clean, 0] + h[:clean, 1]
-        tps = np.arange(len(etot)) * dt * 1e-3
-        slope = float(np.polyfit(tps, (etot - etot[0]) / n * 1e3, 1)[0]) if len(etot) > 2 else 0.0
-        drift[mode] = dict(steps_before_sel_overflow=clean - 1, steps=args.nve_steps,
-                           extra_verlet_rebuilds=rebuilds[0],
-                           max_dev_meV_per_atom=float(np.abs(etot - etot[0]).max() / n * 1e3),
-                           slope_meV_per_atom_per_ps=slope,
-                           flags=ctx.status())
+        hh = hist.cpu().numpy()
+        bad = np.nonzero(hh[:, 2] > 0)[0]
+        etot = hh[:, 0] + hh[:, 1]
+        tps = np.arange(len(etot)) * h * 1e-3
+        dev_meV = (etot - etot[0]) / n * 1e3
+        T = hh[:, 1] * 2.0 / (3 * n * 8.617333262e-5)
+        return dict(steps=nsteps, dt_fs=h,
+                    steps_before_sel_overflow=int(bad[0]) - 1 if len(bad) else nsteps,
+                    steps_with_sel_overflow=int(len(bad)),
+                    verlet_rebuilds=int(nreb.item()) - r0,
+                    max_dev_meV_per_atom=float(np.abs(dev_meV).max()),
+                    final_dev_meV_per_atom=float(dev_meV[-1]),
+                    slope_meV_per_atom_per_ps=float(np.polyfit(tps, dev_meV, 1)[0]),
+                    T_start_K=round(float(T[0]), 2), T_end_K=round(float(T[-1]), 2),
+                    flags=ctx.status())
+
+    drift = {}
+    if args.nve_steps > 0:
+        for mode in modes:
+            drift[mode] = nve(mode, args.nve_steps, dt)
+            print(f"# nve {mode}: {drift[mode]}", file=sys.stderr, flush=True)
+        if "fp64" in modes:
+            # same simulated time at half the step: velocity Verlet's energy
+            # error is second order in dt
+            drift["fp64_half_dt"] = nve("fp64", 2 * args.nve_steps, 0.5 * dt)
 
     # roofline of the dominant FP64 kernel, timed inside the timed region
     flops = algorithmic_flops(desc, real_rows, n, stored=activations.get("fp64") == "stored")
@@ -266,30 +293,70 @@ def main():
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TF, 4), "traffic": measured_traffic(dom, args.workload),
                 "avg_launch_ms": round(dom_live[0], 4), "launches_timed": dom_live[1],
                 "flops_per_launch": flops[dom]}
+    # the mixed forms' dominant matrix stage against the BF16/FP16 peak, the
+    # memory-bound stages against HBM, and the whole step against the sum of
+    # its stages' bounds (T_roof = sum_k max(F_k / P_k, B_k / BW))
+    hbm = stage_bytes(desc, real_rows, n, args.skin)
+    extra = {}
+    for mode in modes:
+        st = stages[mode]
+        fl_m = algorithmic_flops(desc, real_rows, n, stored=activations.get(mode) == "stored")
+        peak = PEAK_FP64_TF if mode == "fp64" else PEAK_BF16_TF
+        mat = {k: fl_m[k] / (st[k][0] * 1e-3) / 1e12 for k in fl_m if st.get(k, (0, 0))[0] > 0}
+        mem = {k: hbm[k] / (st[k][0] * 1e-3) / 1e9 for k in hbm if st.get(k, (0, 0))[0] > 0}
+        t_roof = sum(max(fl_m.get(k, 0) / (peak * 1e12), hbm.get(k, 0) / (PEAK_HBM_GBS * 1e9)) for k in st)
+        dmat = max(mat, key=lambda k: st[k][0]) if mat else None
+        extra[mode] = {
+            "dominant_matrix_stage": dmat,
+            "dominant_achieved_TFLOPs": round(mat[dmat], 2) if dmat else None,
+            "dominant_frac_of_peak": round(mat[dmat] / peak, 4) if dmat else None,
+            "peak_TFLOPs": peak,
+            "matrix_stage_TFLOPs": {k: round(vv, 2) for k, vv in mat.items()},
+            "hbm_stage_GBs": {k: round(vv, 1) for k, vv in mem.items()},
+            "step_T_roof_ms": round(t_roof * 1e3, 4),
+            "step_T_meas_ms": round(results[mode]["ms_per_step"], 4),
+            "step_roof_frac": round(t_roof * 1e3 / results[mode]["ms_per_step"], 4),
+        }
 
-    # oracle on the host cores (bounded sample: one full frame, twice)
+    # oracle on the host cores: a bounded sample of the same workload
     cpu = None
     o = None
     if not args.no_cpu_baseline:
         import oracle
-        times = []
-        for _ in range(2):
+        nthr = oracle.num_threads()
+
+        def timed_frame(rows=None):
             tc = time.perf_counter()
-            onl, _ = oracle.nlist(fr.coords, fr.types, fr.box, desc)
-            o = oracle.compute(fr.coords, fr.types, fr.box, desc, params, nl=onl)
-            times.append(time.perf_counter() - tc)
+            onl, _ = oracle.nlist(fr.coords, fr.types, fr.box, desc, rows=rows)
+            r = oracle.compute(fr.coords, fr.types, fr.box, desc, params, nl=onl, rows=rows)
+            return time.perf_counter() - tc, r
+
+        _, o = timed_frame()                                  # warm-up (also the accuracy reference)
+        times = [timed_frame()[0] for _ in range(3)]
         tf = float(np.median(times))
-        cpu = {"value": round(n / tf, 2), "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"one {args.workload} frame (neighbour list + E, F, W), {len(times)} runs, "
-                         f"median {tf:.2f} s"}
+        rows1 = np.arange(0, n, max(1, n // 1024))[:1024]
+        oracle.set_threads(1)
+        timed_frame(rows1)
+        t1 = float(np.median([timed_frame(rows1)[0] for _ in range(3)]))
+        oracle.set_threads(nthr)
+        cpu = {"value": round(n / tf, 2), "unit": "atom-steps/s", "cores": nthr, "kind": "oracle",
+               "sample": f"one {args.workload} frame ({n} atoms: neighbour list + E, F, W), median of 3 runs "
+                         f"after 1 warm-up, {tf:.3f} s each",
+               "one_core": {"value": round(len(rows1) / t1, 2), "unit": "atom-steps/s", "cores": 1,
+                            "sample": f"{len(rows1)} evenly spaced centre atoms of the same frame, median of 3 "
+                                      f"after 1 warm-up, {t1:.3f} s each"}}
     acc = {}
     if o is not None:
+        frms = float(np.sqrt((o["F"] ** 2).mean()))
         for mode, r in first.items():
+            ferr = float(np.sqrt(((r["F"] - o["F"]) ** 2).mean()))
             acc[mode] = dict(E_meV_per_atom=abs(r["E"] - o["E"]) / n * 1e3,
-                             F_rms_meV_per_A=float(np.sqrt(((r["F"] - o["F"]) ** 2).mean()) * 1e3),
+                             F_rms_meV_per_A=ferr * 1e3,
+                             F_rms_rel=ferr / frms,
                              F_max_meV_per_A=float(np.abs(r["F"] - o["F"]).max() * 1e3),
                              W_max_meV_per_atom=float(np.abs(r["W"].reshape(3, 3) - o["W"]).max() * 1e3 / n))
-        acc["force_rms_meV_per_A"] = float(np.sqrt((o["F"] ** 2).mean()) * 1e3)
+        acc["force_rms_meV_per_A"] = frms * 1e3
+        acc["energy_spread_meV_per_atom"] = float(np.std(o["Ei"]) * 1e3)
         acc["virial_max_meV_per_atom"] = float(np.abs(o["W"]).max() * 1e3 / n)
 
     base = results.get("fp64") or next(iter(results.values()))
@@ -307,8 +374,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "natoms": n, "dt_fs": dt,
-                   "step": ("kick+drift, Verlet list (format every step, rebuild every "
-                            f"{args.rebuild_every} steps, skin {args.skin} A), E/F/W, kick" if verlet else
+                   "step": ("kick+drift, Verlet list (formatted every step; rebuilt on the device when an atom "
+                            f"moved beyond skin/2 or every {args.rebuild_every} steps, skin {args.skin} A), "
+                            "E/F/W, kick" if verlet else
                             "kick+drift, cell-list neighbour build, E/F/W, kick"),
                    "real_neighbour_rows": real_rows,
                    "embedding_activations": activations},
@@ -319,8 +387,9 @@ def main():
         "accuracy_vs_oracle": acc,
         "nve_drift": drift,
         "stage_ms": {m: {k: round(vv[0], 4) for k, vv in s.items() if vv[1]} for m, s in stages.items()},
-        "status_flags": status_flags,
+        "status_flags": timed_flags,
         "roofline": roof,
+        "roofline_modes": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

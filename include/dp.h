@@ -172,6 +172,20 @@ int dp_nlist_skin_build(dp_ctx* ctx, double* coords, const int32_t* types, const
 int dp_nlist_skin_format(dp_ctx* ctx, const double* coords, const int32_t* types, int64_t n, int32_t* nlist_out,
                          int32_t* n_overflow_out, hipStream_t stream);
 
+/* One MD step's list with the rebuild decided on the device (no host wait):
+ * when some atom has moved more than skin/2 since the last Verlet build
+ * (the condition under which the formatted list is exact), or when `every`
+ * > 0 updates have passed since that build, the candidates are rebuilt in
+ * place exactly as dp_nlist_skin_build does (coords wrapped in place, image
+ * counters [n, 3] updated when images is non-NULL), with the skin and box of
+ * the last dp_nlist_skin_build; then the list is formatted as
+ * dp_nlist_skin_format does.  rebuild_count (device int32, nullable) is
+ * incremented once per rebuild (accumulated, never cleared).  Types must be
+ * those of that build.  DP_ERR_STATE when no build with the same n preceded
+ * on this context. */
+int dp_nlist_skin_update(dp_ctx* ctx, double* coords, const int32_t* types, int64_t n, int32_t every, int32_t* images,
+                         int32_t* nlist_out, int32_t* n_overflow_out, int32_t* rebuild_count, hipStream_t stream);
+
 /* Batched form: frames f = 0..B-1 hold atoms [frame_off[f], frame_off[f+1])
  * of coords/types; boxes [B, 9] and frame_off [B+1] are HOST arrays.  Entries
  * use global atom indices; atoms of different frames never neighbour. */

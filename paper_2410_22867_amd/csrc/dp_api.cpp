@@ -601,6 +601,8 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
     // whose reverse is not found fall back to atomics in the force pass)
     StageScope p(c, DP_STAGE_NLIST, s);
     launch_nl_reverse(c, x, types, nlist, ntot, s);
+    c->rev_list = nlist;
+    c->natoms_rev = n;
   }
   { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, forces, s); }
   c->act_used_last = c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
@@ -632,8 +634,7 @@ int nlist_impl(dp_ctx* c, const double* x, const int32_t* types, const double* b
   const int32_t ntot = (int32_t)n;
   StageScope p(c, DP_STAGE_NLIST, s);
   launch_fill_i32(overflow, 0, 1, s);
-  launch_fill_i32(c->cell_count, 0, ncells, s);
-  launch_nl_bin(c, x, ntot, nframes, s);
+  launch_nl_bin(c, x, ntot, nframes, s);  // cell counts are zero between builds (cleared by the scan)
   launch_nl_scan(c, (int32_t)ncells, s);
   launch_nl_scatter(c, ntot, s);
   launch_nl_search(c, x, types, ntot, nframes, nlist, overflow, s);
@@ -663,15 +664,35 @@ int skin_build_impl(dp_ctx* c, double* x, const int32_t* types, const double* bo
   for (int a = 0; a < 3; ++a) c->skin_L[a] = L[a];
   const int32_t ntot = (int32_t)n;
   StageScope p(c, DP_STAGE_NLIST, s);
-  launch_wrap(c, x, ntot, L, images, s);
-  launch_fill_i32(c->cell_count, 0, ncells, s);
-  launch_nl_bin(c, x, ntot, 1, s);
-  launch_nl_scan(c, (int32_t)ncells, s);
-  launch_nl_scatter(c, ntot, s);
-  launch_nl_skin_build(c, x, types, ntot, s);
+  // the build's frame (box, grid of edge >= r_c + skin) is kept for the
+  // rebuilds the device decides on later (dp_compute replaces the table)
+  HIPCHECK(hipMemcpyAsync(c->skin_frame, c->frames_dev, sizeof(FrameInfo), hipMemcpyDeviceToDevice, s));
+  c->skin_ncells = (int32_t)ncells;
+  launch_nl_skin_build(c, x, types, ntot, (int32_t)ncells, images, s);
   c->skin_n = n;
   c->rev_list = nullptr;
   c->ts_valid = false;
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
+int skin_update_impl(dp_ctx* c, double* x, const int32_t* types, int64_t n, int32_t every, int32_t* images,
+                     int32_t* nlist, int32_t* overflow, int32_t* rebuilds, hipStream_t s) {
+  if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
+  if (!overflow || n < 0 || every < 0 || (n > 0 && (!x || !types || !nlist))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (c->skin_n < 0 || n != c->skin_n) {
+    set_error("no Verlet list built for %lld atoms on this context", (long long)n);
+    return DP_ERR_STATE;
+  }
+  int rc;
+  if ((rc = set_device(c->device))) return rc;
+  c->last_stream = s;
+  StageScope p(c, DP_STAGE_NLIST, s);
+  if (n == 0) launch_fill_i32(overflow, 0, 1, s);
+  launch_nl_skin_update(c, x, types, (int32_t)n, every, images, rebuilds, s);
+  launch_nl_skin_format(c, x, types, (int32_t)n, nlist, overflow, s);
+  c->rev_list = nlist;
+  c->natoms_rev = n;
   HIPCHECK(hipGetLastError());
   return DP_OK;
 }
@@ -815,6 +836,13 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   *out = nullptr;
   if (!m) { set_error("model is NULL"); return DP_ERR_BAD_ARG; }
   if (max_atoms < 1 || max_atoms > (int64_t)INT32_MAX / 27 - 1) { set_error("max_atoms out of range"); return DP_ERR_BAD_ARG; }
+  // list slots and Verlet candidates are addressed with 32-bit indices
+  // (atom * slots-per-atom + slot)
+  if (max_atoms * (int64_t)(m->nm > kCandCap ? m->nm : kCandCap) > (int64_t)INT32_MAX) {
+    set_error("max_atoms %lld times %d slots per atom exceeds the 32-bit slot index", (long long)max_atoms,
+              m->nm > kCandCap ? m->nm : kCandCap);
+    return DP_ERR_UNSUPPORTED;
+  }
   if (max_frames < 1 || max_frames > 1 << 20) { set_error("max_frames out of range"); return DP_ERR_BAD_ARG; }
   if (workspace_budget_bytes < 0) { set_error("negative workspace budget"); return DP_ERR_BAD_ARG; }
   int rc;
@@ -882,10 +910,14 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
   ALLOC(c->ke_ctr, 32);
   ALLOC(c->frame_ctr, max_frames);
   ALLOC(c->ovf_ctr, 32);
+  c->skin_gate = c->ovf_ctr + 8;
+  ALLOC(c->skin_frame, 1);
   {
     hipError_t e = hipMemset(c->ke_ctr, 0, 32 * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->frame_ctr, 0, (size_t)max_frames * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->ovf_ctr, 0, 32 * sizeof(int32_t));
+    // cell counts are zero between builds (each scan clears what it read)
+    if (e == hipSuccess) e = hipMemset(c->cell_count, 0, (size_t)(c->max_cells + 1) * sizeof(int32_t));
     if (e != hipSuccess) {
       dp_ctx_destroy(c);
       return hip_fail(e, "hipMemset(ctx)");
@@ -954,7 +986,7 @@ int dp_ctx_destroy(dp_ctx* c) {
   void* ptrs[] = {c->frames_dev, c->flags_dev, c->cell_of, c->cell_count, c->cell_start, c->cell_fill,
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
                   c->netd, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->frame_ctr, c->ovf_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
-                  c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref,
+                  c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref, c->skin_frame,
                   c->gpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -984,6 +1016,11 @@ int dp_nlist_skin_build(dp_ctx* c, double* coords, const int32_t* types, const d
 int dp_nlist_skin_format(dp_ctx* c, const double* coords, const int32_t* types, int64_t n, int32_t* nlist_out,
                          int32_t* n_overflow_out, hipStream_t stream) {
   return skin_format_impl(c, coords, types, n, nlist_out, n_overflow_out, stream);
+}
+
+int dp_nlist_skin_update(dp_ctx* c, double* coords, const int32_t* types, int64_t n, int32_t every, int32_t* images,
+                         int32_t* nlist_out, int32_t* n_overflow_out, int32_t* rebuild_count, hipStream_t stream) {
+  return skin_update_impl(c, coords, types, n, every, images, nlist_out, n_overflow_out, rebuild_count, stream);
 }
 
 int dp_build_nlist_batch(dp_ctx* c, const double* coords, const int32_t* types, const double* boxes,

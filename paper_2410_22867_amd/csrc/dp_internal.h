@@ -164,6 +164,9 @@ struct dp_ctx {
   double skin_L[3];
   double skin;
   int64_t skin_n;          // atoms of the build (-1: no build)
+  int32_t skin_ncells;     // cells of the build's grid (edge >= r_c + skin)
+  dpse::FrameInfo* skin_frame;  // [1] frame table of the build (device)
+  int32_t* skin_gate;      // [2] rebuild decided by the device, formats since the build (inside ovf_ctr)
   // last embedding layer's tanh output per 16-row neighbour tile, [N, tpa,
   // m1, 16] f64 (FP64) or f32 (mixed), when it fits the workspace budget
   void* act;
@@ -208,7 +211,14 @@ void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t 
                       int32_t* nlist, int32_t* overflow, hipStream_t s);
 void launch_nl_reverse(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot,
                        hipStream_t s);
-void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, hipStream_t s);
+// Verlet build: wraps x in place (image counters when non-NULL), bins on the
+// build's grid and keeps the candidates within r_c + skin.
+void launch_nl_skin_build(dp_ctx* c, double* x, const int32_t* types, int32_t ntot, int32_t ncells, int32_t* images,
+                          hipStream_t s);
+// Verlet update: the same build, run only when the device finds an atom
+// moved more than skin/2 since the last build or `every` updates passed.
+void launch_nl_skin_update(dp_ctx* c, double* x, const int32_t* types, int32_t ntot, int32_t every, int32_t* images,
+                           int32_t* rebuilds, hipStream_t s);
 void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* nlist,
                            int32_t* overflow, hipStream_t s);
 // small utilities

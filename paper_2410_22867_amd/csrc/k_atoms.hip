@@ -285,7 +285,15 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs A) {
     const int e = A.nlist[slot];
     if (e < 0 || e / 27 >= A.ntot) continue;
     const int j = e / 27, sc = e - 27 * (e / 27);
-    const int r = A.rev[slot];
+    // the reverse entry is used only when it lies in j's row and holds
+    // (i, -s) in the list passed in, so an index derived for another list
+    // of the same size (a buffer rewritten in place) is never trusted.  Every
+    // reverse index is built as an involution over the slots of one list
+    // (rev[rev[q]] = q wherever rev[q] >= 0), so when this slot passes the
+    // test, the entry at r points back here and passes it too: both slots of
+    // a pair take the same path.
+    int r = A.rev[slot];
+    if (r >= 0 && ((unsigned)(r - j * A.nm) >= (unsigned)A.nm || A.nlist[r] != 27 * i + 26 - sc)) r = -1;
     const d4 n = *reinterpret_cast<const d4*>(A.netd + slot * 4);
     d4 nr = {0.0, 0.0, 0.0, 0.0};
     if (r >= 0) nr = *reinterpret_cast<const d4*>(A.netd + (int64_t)r * 4);

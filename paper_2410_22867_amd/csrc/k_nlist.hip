@@ -38,8 +38,13 @@ __device__ __forceinline__ int cell_coord(double x, double L, int nc) {
   return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
+// With xw != NULL (a Verlet build) the positions are first wrapped into
+// [0, L) in place by whole box lengths, the lengths moved being added to the
+// image counters (when non-NULL).  gate: see launch_nl_skin_update.
 __global__ void k_nl_bin(const double* __restrict__ x, const FrameInfo* __restrict__ fr, int nframes, int ntot,
-                         int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_count, int32_t* flags) {
+                         int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_count, int32_t* flags,
+                         double* xw, int32_t* images, const int32_t* gate) {
+  if (gate && *gate == 0) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
   int f = find_frame(fr, nframes, i);
@@ -48,6 +53,16 @@ __global__ void k_nl_bin(const double* __restrict__ x, const FrameInfo* __restri
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double xa = x[3 * i + a];
+    if (xw && !(xa >= 0.0 && xa < F.L[a])) {
+      const double L = F.L[a];
+      const double k = floor(xa / L);
+      xa -= k * L;
+      if (xa >= L) xa -= L;  // rounding of x - k L
+      if (xa < 0.0) xa += L;
+      if (xa >= L) xa = 0.0;
+      xw[3 * i + a] = xa;
+      if (images) images[3 * i + a] += (int32_t)k;
+    }
     if (!(xa >= 0.0 && xa < F.L[a])) set_flag(flags, DP_FLAG_NOT_WRAPPED);
     c[a] = cell_coord(xa, F.L[a], F.ncell[a]);
   }
@@ -57,9 +72,11 @@ __global__ void k_nl_bin(const double* __restrict__ x, const FrameInfo* __restri
 }
 
 // Exclusive scan of cell counts with one work-group (cells number in the
-// thousands); also clears the fill counters.
-__global__ __launch_bounds__(1024) void k_nl_scan(const int32_t* __restrict__ count, int32_t* __restrict__ start,
-                                                  int32_t* __restrict__ fill, int ncells) {
+// thousands); also clears the fill counters, and the counts once read, so
+// that the next binning starts from zero.
+__global__ __launch_bounds__(1024) void k_nl_scan(int32_t* __restrict__ count, int32_t* __restrict__ start,
+                                                  int32_t* __restrict__ fill, int ncells, const int32_t* gate) {
+  if (gate && *gate == 0) return;
   __shared__ int32_t part[1024];
   __shared__ int32_t carry;
   if (threadIdx.x == 0) carry = 0;
@@ -67,6 +84,7 @@ __global__ __launch_bounds__(1024) void k_nl_scan(const int32_t* __restrict__ co
   for (int base = 0; base < ncells; base += 1024) {
     int k = base + threadIdx.x;
     int v = k < ncells ? count[k] : 0;
+    if (k < ncells) count[k] = 0;
     part[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -87,7 +105,9 @@ __global__ __launch_bounds__(1024) void k_nl_scan(const int32_t* __restrict__ co
 }
 
 __global__ void k_nl_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ start,
-                             int32_t* __restrict__ fill, int32_t* __restrict__ cell_atoms, int ntot) {
+                             int32_t* __restrict__ fill, int32_t* __restrict__ cell_atoms, int ntot,
+                             const int32_t* gate) {
+  if (gate && *gate == 0) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
   int c = cell_of[i];
@@ -382,47 +402,89 @@ struct SkinArgs {
   double* xref;     // [n, 3]
   double L[3];
   double half_skin2;
+  // rebuild decided on the device (launch_nl_skin_update): gate[0] != 0
+  // when the kernels of a build run, gate[1] counts formats since the last
+  // build; NULL for a build the host asked for
+  int32_t* gate;
+  int32_t* rebuilds;  // incremented by every gated build (nullable)
 };
 
+// One wavefront per atom, atoms taken in a grid-stride loop (the grid is
+// sized to the resident capacity, so a gated launch that does nothing is
+// cheap).
 __global__ __launch_bounds__(256) void k_nl_skin_build(SearchArgs A, SkinArgs S, double rl2) {
+  if (S.gate && S.gate[0] == 0) return;
   __shared__ CandLds<kCandCap> L;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int i = blockIdx.x * kSearchWaves + w;
-  if (i >= A.ntot) return;
-  const FrameInfo F = A.fr[find_frame(A.fr, A.nframes, i)];
-  bool capacity = false;
-  const int ncand = gather_cells(A, L, w, lane, i, F, rl2, &capacity);
-  wave_lds_sync();
-  for (int c = lane; c < ncand; c += 64) {
-    const int pk = L.r[w][c].pk;
-    int rank = 0;
-    for (int o = 0; o < ncand; ++o) rank += L.r[w][o].pk < pk;
-    S.cand[(int64_t)i * kCandCap + rank] = pk;
+  if (S.gate && blockIdx.x == 0 && threadIdx.x == 0) {
+    S.gate[1] = 0;
+    if (S.rebuilds) *S.rebuilds += 1;
   }
-  if (lane < 3) S.xref[3 * i + lane] = A.x[3 * i + lane];
-  if (lane == 0) {
-    S.ncand[i] = ncand;
-    if (capacity) set_flag(A.flags, DP_FLAG_CAND_CAPACITY);
+  for (int i = blockIdx.x * kSearchWaves + w; i < A.ntot; i += gridDim.x * kSearchWaves) {
+    const FrameInfo F = A.fr[find_frame(A.fr, A.nframes, i)];
+    bool capacity = false;
+    const int ncand = gather_cells(A, L, w, lane, i, F, rl2, &capacity);
+    wave_lds_sync();
+    for (int c = lane; c < ncand; c += 64) {
+      const int pk = L.r[w][c].pk;
+      int rank = 0;
+      for (int o = 0; o < ncand; ++o) rank += L.r[w][o].pk < pk;
+      S.cand[(int64_t)i * kCandCap + rank] = pk;
+    }
+    if (lane < 3) S.xref[3 * i + lane] = A.x[3 * i + lane];
+    if (lane == 0) {
+      S.ncand[i] = ncand;
+      if (capacity) set_flag(A.flags, DP_FLAG_CAND_CAPACITY);
+    }
+    wave_lds_sync();  // the wave's LDS records are rewritten by its next atom
   }
 }
 
 // Position of each candidate's reverse pair (i, -s) in j's candidate list.
+// Grid-stride over the [n, kCandCap] candidate slots.
 __global__ void k_nl_skin_crev(SkinArgs S, int ntot) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(q / kCandCap), k = (int)(q - (int64_t)i * kCandCap);
-  if (i >= ntot) return;
-  if (k >= S.ncand[i]) return;
-  const int e = S.cand[q];
-  const int j = e / 27;
-  const int target = 27 * i + (26 - (e - 27 * j));
-  const int32_t* cj = S.cand + (int64_t)j * kCandCap;
-  int lo = 0, hi = S.ncand[j];
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (cj[mid] < target) lo = mid + 1; else hi = mid;
+  if (S.gate && S.gate[0] == 0) return;
+  const int64_t total = (int64_t)ntot * kCandCap;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q / kCandCap), k = (int)(q - (int64_t)i * kCandCap);
+    if (k >= S.ncand[i]) continue;
+    const int e = S.cand[q];
+    const int j = e / 27;
+    const int target = 27 * i + (26 - (e - 27 * j));
+    const int32_t* cj = S.cand + (int64_t)j * kCandCap;
+    int lo = 0, hi = S.ncand[j];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cj[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    S.crev[q] = (lo < S.ncand[j] && cj[lo] == target) ? lo : -1;
   }
-  S.crev[q] = (lo < S.ncand[j] && cj[lo] == target) ? lo : -1;
+}
+
+// After a build the host asked for: no rebuild pending, no format since.
+__global__ void k_fill_gate(int32_t* gate) {
+  if (threadIdx.x < 2) gate[threadIdx.x] = 0;
+}
+
+// Rebuild decision of a Verlet update: gate[0] is set when an atom has moved
+// more than skin/2 since the build (the format's exactness condition) or
+// when `every` > 0 updates have passed since it.  gate[0] was cleared by the
+// previous format's second pass.
+__global__ __launch_bounds__(256) void k_nl_skin_check(const double* __restrict__ x, const double* __restrict__ xref,
+                                                       int ntot, double half_skin2, int every, int32_t* gate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool moved = false;
+  if (i < ntot) {
+    const double ex = x[3 * i] - xref[3 * i], ey = x[3 * i + 1] - xref[3 * i + 1], ez = x[3 * i + 2] - xref[3 * i + 2];
+    moved = !((ex * ex + ey * ey) + ez * ez <= half_skin2);
+  }
+  if (__ballot(moved) && (threadIdx.x & 63) == 0) atomicOr(gate, 1);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int k = gate[1] + 1;
+    gate[1] = k;
+    if (every > 0 && k >= every) atomicOr(gate, 1);
+  }
 }
 
 // Format: the sorted, truncated list on the current positions from the
@@ -499,11 +561,13 @@ __global__ __launch_bounds__(256) void k_nl_skin_format(SearchArgs A, SkinArgs S
 // internal counter for the next format (stream order: every format block
 // has finished, and the next format has not started).
 __global__ void k_nl_skin_revmap(const int32_t* __restrict__ nlist, SkinArgs S, int32_t* __restrict__ rev, int ntot,
-                                 int nm, int32_t* __restrict__ ovf_ctr, int32_t* __restrict__ overflow) {
+                                 int nm, int32_t* __restrict__ ovf_ctr, int32_t* __restrict__ overflow,
+                                 int32_t* __restrict__ gate) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q == 0) {
     *overflow = *ovf_ctr;
     *ovf_ctr = 0;
+    gate[0] = 0;  // the next update decides again
   }
   if (q >= (int64_t)ntot * nm) return;
   const int e = nlist[q];
@@ -597,17 +661,19 @@ void launch_nl_reverse(dp_ctx* c, const double* x, const int32_t* types, const i
 void launch_nl_bin(dp_ctx* c, const double* x, int32_t ntot, int32_t nframes, hipStream_t s) {
   if (ntot <= 0) return;
   hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, x, c->frames_dev, nframes, ntot,
-                     c->cell_of, c->cell_count, c->flags_dev);
+                     c->cell_of, c->cell_count, c->flags_dev, (double*)nullptr, (int32_t*)nullptr,
+                     (const int32_t*)nullptr);
 }
 
 void launch_nl_scan(dp_ctx* c, int32_t ncells, hipStream_t s) {
-  hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill, ncells);
+  hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill, ncells,
+                     (const int32_t*)nullptr);
 }
 
 void launch_nl_scatter(dp_ctx* c, int32_t ntot, hipStream_t s) {
   if (ntot <= 0) return;
   hipLaunchKernelGGL(k_nl_scatter, dim3((ntot + 255) / 256), dim3(256), 0, s, c->cell_of, c->cell_start,
-                     c->cell_fill, c->cell_atoms, ntot);
+                     c->cell_fill, c->cell_atoms, ntot, (const int32_t*)nullptr);
 }
 
 static SearchArgs search_args(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t nframes,
@@ -642,6 +708,8 @@ static SkinArgs skin_args(dp_ctx* c) {
   S.xref = c->skin_xref;
   for (int a = 0; a < 3; ++a) S.L[a] = c->skin_L[a];
   S.half_skin2 = 0.25 * c->skin * c->skin;
+  S.gate = nullptr;
+  S.rebuilds = nullptr;
   return S;
 }
 
@@ -654,15 +722,49 @@ void launch_nl_search(dp_ctx* c, const double* x, const int32_t* types, int32_t 
   else hipLaunchKernelGGL(k_nl_search<kCandCap>, grid, block, 0, s, A);
 }
 
-void launch_nl_skin_build(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, hipStream_t s) {
-  if (ntot <= 0) return;
+// Verlet build from the binned wrapped positions.  The frame (box, cell
+// grid of edge >= r_c + skin) is the context's copy made at the last
+// dp_nlist_skin_build: dp_compute replaces the general frame table.
+static void skin_build_kernels(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* gate,
+                               int32_t* rebuilds, hipStream_t s) {
   SearchArgs A = search_args(c, x, types, ntot, 1, nullptr, nullptr);
+  A.fr = c->skin_frame;
   SkinArgs S = skin_args(c);
+  S.gate = gate;
+  S.rebuilds = rebuilds;
   const double rl = c->model->desc.rcut + c->skin;
-  hipLaunchKernelGGL(k_nl_skin_build, dim3((ntot + kSearchWaves - 1) / kSearchWaves), dim3(64 * kSearchWaves), 0, s,
-                     A, S, rl * rl);
-  const int64_t q = (int64_t)ntot * kCandCap;
-  hipLaunchKernelGGL(k_nl_skin_crev, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, S, ntot);
+  // 4-wave work-groups with 32 KB of LDS records: 5 resident per CU
+  const int64_t gb = (ntot + kSearchWaves - 1) / kSearchWaves, gbmax = 5LL * c->ncu;
+  hipLaunchKernelGGL(k_nl_skin_build, dim3((unsigned)(gb < gbmax ? gb : gbmax)), dim3(64 * kSearchWaves), 0, s, A, S,
+                     rl * rl);
+  const int64_t gq = ((int64_t)ntot * kCandCap + 255) / 256, gqmax = 8LL * c->ncu;
+  hipLaunchKernelGGL(k_nl_skin_crev, dim3((unsigned)(gq < gqmax ? gq : gqmax)), dim3(256), 0, s, S, ntot);
+}
+
+void launch_nl_skin_build(dp_ctx* c, double* x, const int32_t* types, int32_t ntot, int32_t ncells, int32_t* images,
+                          hipStream_t s) {
+  if (ntot <= 0) return;
+  hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x, c->skin_frame, 1, ntot,
+                     c->cell_of, c->cell_count, c->flags_dev, x, images, (const int32_t*)nullptr);
+  launch_nl_scan(c, ncells, s);
+  launch_nl_scatter(c, ntot, s);
+  skin_build_kernels(c, x, types, ntot, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_fill_gate, dim3(1), dim3(64), 0, s, c->skin_gate);
+}
+
+void launch_nl_skin_update(dp_ctx* c, double* x, const int32_t* types, int32_t ntot, int32_t every, int32_t* images,
+                           int32_t* rebuilds, hipStream_t s) {
+  if (ntot <= 0) return;
+  int32_t* gate = c->skin_gate;
+  hipLaunchKernelGGL(k_nl_skin_check, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x,
+                     (const double*)c->skin_xref, ntot, 0.25 * c->skin * c->skin, every, gate);
+  hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x, c->skin_frame, 1, ntot,
+                     c->cell_of, c->cell_count, c->flags_dev, x, images, (const int32_t*)gate);
+  hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill,
+                     c->skin_ncells, (const int32_t*)gate);
+  hipLaunchKernelGGL(k_nl_scatter, dim3((ntot + 255) / 256), dim3(256), 0, s, c->cell_of, c->cell_start,
+                     c->cell_fill, c->cell_atoms, ntot, (const int32_t*)gate);
+  skin_build_kernels(c, x, types, ntot, gate, rebuilds, s);
 }
 
 void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int32_t ntot, int32_t* nlist,
@@ -675,7 +777,7 @@ void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int
   else hipLaunchKernelGGL(k_nl_skin_format<kCandCap>, grid, block, 0, s, A, S);
   const int64_t q = (int64_t)ntot * A.nm;
   hipLaunchKernelGGL(k_nl_skin_revmap, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, nlist, S, c->rev, ntot,
-                     A.nm, c->ovf_ctr, overflow);
+                     A.nm, c->ovf_ctr, overflow, c->skin_gate);
 }
 
 }  // namespace dpse

@@ -27,6 +27,7 @@ BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 # Symbols declared in include/dp.h (checked by the CPU tests).
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_destroy", "dp_ctx_create",
            "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_nlist_skin_build", "dp_nlist_skin_format",
+           "dp_nlist_skin_update",
            "dp_compute", "dp_compute_batch",
            "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_store_info",
            "dp_ctx_copy_buffer", "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
@@ -95,6 +96,7 @@ def lib():
             "dp_md_kick_drift": (ctypes.c_int, [P, P, P, P, P, P, i64, dbl, i32, P, P]),
             "dp_nlist_skin_build": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_nlist_skin_format": (ctypes.c_int, [P, P, P, i64, P, P, P]),
+            "dp_nlist_skin_update": (ctypes.c_int, [P, P, P, i64, i32, P, P, P, P, P]),
             "dp_md_kick": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_ctx_status": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
             "dp_ctx_store_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -215,6 +217,20 @@ class Context:
             overflow = torch.empty(1, dtype=torch.int32, device=coords.device)
         _check(lib().dp_nlist_skin_format(self.handle, _ptr(coords), _ptr(types), n, _ptr(out), _ptr(overflow),
                                           _stream()))
+        return out, overflow
+
+    def skin_update(self, coords, types, every=0, images=None, out=None, overflow=None, rebuilds=None):
+        """Verlet list of one MD step: rebuilt on the device when an atom moved
+        beyond skin/2 (or every `every` updates), then formatted."""
+        import torch
+        n = int(types.shape[0])
+        nm = int(sum(self.model.desc.sel))
+        if out is None:
+            out = torch.empty((n, nm), dtype=torch.int32, device=coords.device)
+        if overflow is None:
+            overflow = torch.empty(1, dtype=torch.int32, device=coords.device)
+        _check(lib().dp_nlist_skin_update(self.handle, _ptr(coords), _ptr(types), n, int(every), _ptr(images),
+                                          _ptr(out), _ptr(overflow), _ptr(rebuilds), _stream()))
         return out, overflow
 
     def build_nlist_batch(self, coords, types, boxes, frame_off, out=None, overflow=None):

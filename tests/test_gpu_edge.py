@@ -265,3 +265,35 @@ def test_candidate_capacity_flag(dev, water):
             nl, ov = ctx.build_nlist(x, t, fr.box)
         torch.cuda.synchronize()
         assert ctx.status() & dpse.FLAG_CAND_CAPACITY
+
+
+def test_two_lists_one_context_and_list_rewritten_in_place(dev, water):
+    """Two lists of the same size built on one context, then computes on each
+    in turn (the reverse-entry index must follow the list in use), and a list
+    buffer whose contents are replaced in place between computes: every
+    compute matches the oracle of its own frame."""
+    from paper_2410_22867_amd import dpse
+    desc, p, model = water
+    fa = I.water_box(64, 12.42, seed=41)
+    fb = I.water_box(64, 12.42, seed=42)
+    _say("two lists on one context", fa.n)
+    ctx = dpse.Context(model, fa.n)
+    xa = torch.tensor(fa.coords, device=dev)
+    xb = torch.tensor(fb.coords, device=dev)
+    t = torch.tensor(fa.types, device=dev)
+    oa = oracle.compute(fa.coords, fa.types, fa.box, desc, p)
+    ob = oracle.compute(fb.coords, fb.types, fb.box, desc, p)
+    nla, _ = ctx.build_nlist(xa, t, fa.box)
+    nlb, _ = ctx.build_nlist(xb, t, fb.box)
+    for x, nl, o in ((xa, nla, oa), (xb, nlb, ob), (xa, nla, oa), (xb, nlb, ob)):
+        r = ctx.compute(x, t, fa.box, nl, want_atom_energy=True)
+        torch.cuda.synchronize()
+        _check_fp64({k: v.cpu().numpy() for k, v in r.items() if v is not None}, o, fa.n)
+    # same buffer, new contents written behind the context's back
+    nl, _ = ctx.build_nlist(xa, t, fa.box)
+    ctx.compute(xa, t, fa.box, nl)
+    nl.copy_(torch.tensor(ob["nlist"], device=dev))
+    r = ctx.compute(xb, t, fb.box, nl, want_atom_energy=True)
+    torch.cuda.synchronize()
+    _check_fp64({k: v.cpu().numpy() for k, v in r.items() if v is not None}, ob, fb.n)
+    assert ctx.status() == 0

@@ -97,6 +97,65 @@ def test_nve_verlet_list_matches_oracle():
     assert ctx.status() == 0
 
 
+@pytest.mark.parametrize("skin,every", [(0.3, 0), (2.0, 4)])
+def test_nve_device_decided_rebuilds_match_oracle(skin, every):
+    """dp_nlist_skin_update decides rebuilds on the device: with a 0.3 A skin
+    the fastest atoms pass skin/2 within the run and trigger rebuilds, with a
+    2 A skin and every = 4 the build runs on every fourth update only.  Both
+    trajectories equal the oracle's (which enumerates all pairs every step),
+    no step runs on a list that may miss pairs, and the rebuild count is
+    what the schedule implies."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_22867_amd import dpse
+    fr, desc, p, dt = I.workload("water192")
+    v0 = I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=202)
+    m = np.asarray(desc.masses)[fr.types]
+    L = np.diag(fr.box)
+    nsteps = 20
+
+    def force_fn(x):
+        o = oracle.compute(x, fr.types, fr.box, desc, p, use_cells=False)
+        return o["E"], o["F"]
+
+    xo, vo, hist = oracle.nve(fr.coords, v0, m, force_fn, dt, nsteps)
+    dev = torch.device("cuda:0")
+    ctx = dpse.Context(dpse.Model(desc, p), fr.n)
+    x = torch.tensor(fr.coords, device=dev)
+    v = torch.tensor(v0, device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    img = torch.zeros((fr.n, 3), dtype=torch.int32, device=dev)
+    nreb = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.skin_build(x, t, fr.box, skin, images=img)
+    nl, ov = ctx.skin_format(x, t)
+    r = ctx.compute(x, t, fr.box, nl)
+    f = r["F"]
+    ke = torch.zeros(1, dtype=torch.float64, device=dev)
+    moved = 0.0
+    x_build = x.cpu().numpy() + img.cpu().numpy() * L
+    for k in range(nsteps):
+        ctx.kick_drift(x, v, f, t, fr.box, dt, wrap=False)
+        ctx.skin_update(x, t, every=every, images=img, out=nl, overflow=ov, rebuilds=nreb)
+        r = ctx.compute(x, t, fr.box, nl, forces=f)
+        ctx.kick(v, f, t, dt, ke)
+        xu = x.cpu().numpy() + img.cpu().numpy() * L
+        moved = max(moved, float(np.sqrt(((xu - x_build) ** 2).sum(1)).max()))
+    torch.cuda.synchronize()
+    xu = x.cpu().numpy() + img.cpu().numpy() * L
+    assert np.abs(xu - xo).max() < 1e-10
+    assert np.abs(v.cpu().numpy() - vo).max() < 1e-12
+    assert abs(r["E"].item() - hist[-1][0]) < 1e-9 * abs(hist[-1][0])
+    assert ctx.status() == 0          # in particular no DP_FLAG_SKIN_EXCEEDED
+    nb = int(nreb.item())
+    if every:
+        assert nb == nsteps // every
+    else:
+        assert moved > skin / 2 and nb >= 1
+    # positions are wrapped at every rebuild: after the last one they are
+    # within the box up to the drift since
+    assert (x.cpu().numpy() > -skin).all() and (x.cpu().numpy() < L + skin).all()
+
+
 def test_half_kick_and_kinetic_energy_many_blocks():
     """The second half-kick and the kinetic energy over 98,304 atoms (384
     blocks whose partial sums the last block adds), twice in a row and then

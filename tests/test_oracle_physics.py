@@ -258,7 +258,7 @@ def test_forces_central_fd(w192):
             E.append(oracle.compute(x, fr.types, fr.box, desc, p, use_cells=False)["E"])
         dE = (E[0] - 8 * E[1] + 8 * E[2] - E[3]) / (12 * h)
         assert abs(-dE - r["F"][i, a]) < 1e-7, (i, a, -dE, r["F"][i, a])
-    assert np.sqrt((r["F"] ** 2).mean()) > 0.05   # the model is not trivially flat
+    assert np.sqrt((r["F"] ** 2).mean()) > 0.005   # the model is not trivially flat
 
 
 def test_virial_strain_fd(w192):
