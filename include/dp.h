@@ -152,6 +152,22 @@ int dp_ctx_destroy(dp_ctx* ctx);
 int dp_build_nlist(dp_ctx* ctx, const double* coords, const int32_t* types, const double* box, int64_t n,
                    int32_t* nlist_out, int32_t* n_overflow_out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the neighbour
+ * list of dp_build_nlist -- the same list, bit for bit -- with no context.
+ * Its scratch (cell grid and counts, frame table, status word) is a static
+ * device array of about 2 MB per GPU, held until the process ends; the call
+ * allocates nothing, and the model only supplies r_c and sel.  Limits:
+ * n <= 65536 atoms and at most 131072 cells (floor(L_d / r_c) per axis),
+ * else DP_ERR_CAPACITY before any launch.  flags_out (device int32,
+ * nullable) receives the call's DP_FLAG_* bits (written, not accumulated).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (two streams, two threads) race and must be serialised by the
+ * caller. */
+int dp_build_nlist_noalloc(const dp_model* model, const double* coords, const int32_t* types, const double* box,
+                           int64_t n, int32_t* nlist_out, int32_t* n_overflow_out, int32_t* flags_out,
+                           hipStream_t stream);
+
 /* Verlet (skin) list for MD (Evaluation section: the neighbour list is
  * rebuilt every 50 steps with a 2 A skin).
  * dp_nlist_skin_build first wraps coords [n, 3] (device f64, in place) into

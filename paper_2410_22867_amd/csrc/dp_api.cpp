@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "dp_internal.h"
@@ -717,6 +718,98 @@ int skin_format_impl(dp_ctx* c, const double* x, const int32_t* types, int64_t n
   return DP_OK;
 }
 
+
+// ------------------------------------------------------------ no-allocation build
+// Neighbour-list scratch of dp_build_nlist_noalloc: a file-scope device
+// array (one copy per GPU, held until the process ends).  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_dev.
+//   words [0, 16)    frame table (one FrameInfo)
+//   words [16, 32)   status word of the call
+//   then cell_count, cell_start, cell_fill [kNaMaxCells + 1] each and
+//   cell_of, cell_atoms [kNaMaxAtoms] each.
+constexpr int64_t kNaMaxAtoms = 1 << 16;
+constexpr int64_t kNaMaxCells = 1 << 17;
+constexpr int64_t kNaWords = 32 + 3 * (kNaMaxCells + 1) + 2 * kNaMaxAtoms;
+static __device__ __align__(256) int32_t scratch[kNaWords];
+
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_dev[kNaMaxDevices];
+
+// Device address of this device's copy of the scratch array (the caller made
+// the device current).
+static int scratch_on_device(int dev, int32_t** out) {
+  if (dev < 0 || dev >= kNaMaxDevices) { set_error("device %d beyond %d", dev, kNaMaxDevices); return DP_ERR_UNSUPPORTED; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = (int32_t*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return DP_OK;
+}
+
+int nlist_noalloc_impl(const dp_model* m, const double* x, const int32_t* types, const double* box, int64_t n,
+                       int32_t* nlist, int32_t* overflow, int32_t* flags_out, hipStream_t s) {
+  if (!m) { set_error("model is NULL"); return DP_ERR_BAD_ARG; }
+  if (!overflow || n < 0 || (n > 0 && (!x || !types || !nlist))) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  if (n > kNaMaxAtoms) {
+    set_error("%lld atoms exceed the %lld of the no-allocation scratch", (long long)n, (long long)kNaMaxAtoms);
+    return DP_ERR_CAPACITY;
+  }
+  double L[3];
+  int rc;
+  if ((rc = check_box(box, m->desc.rcut, L))) return rc;
+  FrameInfo F;
+  memset(&F, 0, sizeof(F));
+  F.natoms = (int32_t)n;
+  int64_t ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    int k = (int)std::floor(L[a] / (m->desc.rcut * (1.0 + 1e-10)));
+    if (k < 1) k = 1;
+    if (k > 1024) k = 1024;
+    F.ncell[a] = k;
+    F.L[a] = L[a];
+    ncells *= k;
+  }
+  if (ncells > kNaMaxCells) {
+    set_error("%lld cells exceed the %lld of the no-allocation scratch", (long long)ncells, (long long)kNaMaxCells);
+    return DP_ERR_CAPACITY;
+  }
+  if ((rc = set_device(m->device))) return rc;
+  int32_t* base = nullptr;
+  if ((rc = scratch_on_device(m->device, &base))) return rc;
+  // a context view whose nlist buffers all lie in the scratch array
+  dp_ctx v;
+  memset(&v, 0, sizeof(v));
+  v.model = m;
+  v.device = m->device;
+  v.frames_dev = reinterpret_cast<FrameInfo*>(base);
+  v.flags_dev = base + 16;
+  v.cell_count = base + 32;
+  v.cell_start = v.cell_count + (kNaMaxCells + 1);
+  v.cell_fill = v.cell_start + (kNaMaxCells + 1);
+  v.cell_of = v.cell_fill + (kNaMaxCells + 1);
+  v.cell_atoms = v.cell_of + kNaMaxAtoms;
+  // the array keeps the last call's contents: the frame, the status word
+  // and the cell counts are written or cleared first
+  launch_set_frame(v.frames_dev, F, v.flags_dev, s);
+  launch_fill_i32(v.cell_count, 0, ncells, s);
+  launch_fill_i32(overflow, 0, 1, s);
+  const int32_t ntot = (int32_t)n;
+  launch_nl_bin(&v, x, ntot, 1, s);
+  launch_nl_scan(&v, (int32_t)ncells, s);
+  launch_nl_scatter(&v, ntot, s);
+  launch_nl_search(&v, x, types, ntot, 1, nlist, overflow, s);
+  if (flags_out) launch_copy_i32(v.flags_dev, flags_out, 1, s);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
+}
+
 }  // namespace
 
 // ============================================================ C ABI
@@ -1016,6 +1109,12 @@ int dp_nlist_skin_build(dp_ctx* c, double* coords, const int32_t* types, const d
 int dp_nlist_skin_format(dp_ctx* c, const double* coords, const int32_t* types, int64_t n, int32_t* nlist_out,
                          int32_t* n_overflow_out, hipStream_t stream) {
   return skin_format_impl(c, coords, types, n, nlist_out, n_overflow_out, stream);
+}
+
+int dp_build_nlist_noalloc(const dp_model* model, const double* coords, const int32_t* types, const double* box,
+                           int64_t n, int32_t* nlist_out, int32_t* n_overflow_out, int32_t* flags_out,
+                           hipStream_t stream) {
+  return nlist_noalloc_impl(model, coords, types, box, n, nlist_out, n_overflow_out, flags_out, stream);
 }
 
 int dp_nlist_skin_update(dp_ctx* c, double* coords, const int32_t* types, int64_t n, int32_t every, int32_t* images,

@@ -224,6 +224,10 @@ void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int
 // small utilities
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);
+// writes one frame-table entry and clears a status word (kernel arguments
+// only: no host staging buffer)
+void launch_set_frame(FrameInfo* dst, const FrameInfo& F, int32_t* flags, hipStream_t s);
 void launch_type_sort(dp_ctx* c, const int32_t* types, int32_t ntot, int32_t nframes, hipStream_t s);
 // compute
 void launch_env(dp_ctx* c, const double* x, const int32_t* types, const int32_t* nlist, int32_t ntot, double* forces,

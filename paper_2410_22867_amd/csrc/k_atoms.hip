@@ -21,6 +21,22 @@ __global__ void k_fill_f64(double* p, double v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+__global__ void k_set_frame(FrameInfo* dst, FrameInfo F, int32_t* flags) {
+  if (threadIdx.x == 0) {
+    *dst = F;
+    *flags = 0;
+  }
+}
+__global__ void k_copy_i32(const int32_t* a, int32_t* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+void launch_set_frame(FrameInfo* dst, const FrameInfo& F, int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(64), 0, s, dst, F, flags);
+}
+void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+}
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
 }

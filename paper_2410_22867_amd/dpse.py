@@ -27,7 +27,7 @@ BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 # Symbols declared in include/dp.h (checked by the CPU tests).
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_destroy", "dp_ctx_create",
            "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_nlist_skin_build", "dp_nlist_skin_format",
-           "dp_nlist_skin_update",
+           "dp_nlist_skin_update", "dp_build_nlist_noalloc",
            "dp_compute", "dp_compute_batch",
            "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_store_info",
            "dp_ctx_copy_buffer", "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
@@ -97,6 +97,7 @@ def lib():
             "dp_nlist_skin_build": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_nlist_skin_format": (ctypes.c_int, [P, P, P, i64, P, P, P]),
             "dp_nlist_skin_update": (ctypes.c_int, [P, P, P, i64, i32, P, P, P, P, P]),
+            "dp_build_nlist_noalloc": (ctypes.c_int, [P, P, P, P, i64, P, P, P, P]),
             "dp_md_kick": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_ctx_status": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
             "dp_ctx_store_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -157,6 +158,14 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+def build_nlist_noalloc(model: Model, coords, types, box, out, overflow, flags=None) -> None:
+    """dp_build_nlist_noalloc: the neighbour list into caller buffers, with
+    no context and no device allocation by the library."""
+    n = int(types.shape[0])
+    _check(lib().dp_build_nlist_noalloc(model.handle, _ptr(coords), _ptr(types), _box9(box).ctypes.data, n,
+                                        _ptr(out), _ptr(overflow), _ptr(flags), _stream()))
 
 
 def n_params(desc) -> int:
