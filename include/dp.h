@@ -125,8 +125,19 @@ int64_t dp_model_n_params(const dp_model_desc* desc);
  * (Computation Optimization section: the transpose is prepared once at
  * start-up so that no transposed product runs in the step). */
 int dp_model_create(const dp_model_desc* desc, const double* params_host, int64_t n_params, dp_model** out);
-/* Replaces the parameters of an existing model (same descriptor). */
+/* Replaces the parameters of an existing model (same descriptor), host
+ * FP64 values checked finite (DP_ERR_BAD_ARG otherwise).  The operand copies
+ * are re-derived on the device by gathers through index maps built at
+ * creation; nothing is allocated.  Runs on the null stream and returns when
+ * the model is updated; computes using the model on other streams must not
+ * be in flight. */
 int dp_model_set_params(dp_model* model, const double* params_host, int64_t n_params);
+/* The same from device FP64 parameters [n_params], asynchronously on
+ * `stream` (a copy into the model, then the gathers): no allocation, no host
+ * wait, so a training loop can update the model every step.  Values are not
+ * checked on the host; non-finite parameters give non-finite energies, which
+ * the computes flag with DP_FLAG_NONFINITE. */
+int dp_model_set_params_device(dp_model* model, const double* params_dev, int64_t n_params, hipStream_t stream);
 int dp_model_destroy(dp_model* model);
 
 /* Allocates every work buffer for up to max_atoms atoms in up to max_frames

@@ -40,33 +40,6 @@ int hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-// ------------------------------------------------------------ precision helpers
-uint16_t f32_to_bf16(float f) {
-  uint32_t u;
-  memcpy(&u, &f, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-uint16_t f32_to_f16(float f) {
-  uint32_t x;
-  memcpy(&x, &f, 4);
-  const uint32_t sign = (x >> 16) & 0x8000u;
-  const uint32_t ax = x & 0x7fffffffu;
-  if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
-  if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);
-  if (ax < 0x38800000u) {
-    float v;
-    memcpy(&v, &ax, 4);
-    const uint32_t r = (uint32_t)std::nearbyint(v * 16777216.0f);
-    return (uint16_t)(sign | r);
-  }
-  uint32_t m = ax - 0x38000000u;
-  m += 0x0fffu + ((m >> 13) & 1u);
-  return (uint16_t)(sign | (m >> 13));
-}
-
 // ------------------------------------------------------------ descriptor
 int validate_desc(const dp_model_desc* d) {
   if (!d) { set_error("desc is NULL"); return DP_ERR_BAD_ARG; }
@@ -190,8 +163,8 @@ inline int kfeat32(int t, int lane, int j) { return 32 * t + 16 * (j >> 2) + 4 *
 // Register-chained f64 blocks (embedding nets, read from LDS one v at a time)
 // are ordered [mt][t][v][lane]; memory-fed ones (fitting GEMMs, whose lanes
 // read all four v of a step with one 32-byte load) [mt][t][lane][v].
-template <class F>
-void frag_block64(std::vector<double>& out, int64_t base, int mtiles, int ktiles16, F wfun, bool chained) {
+template <class T, class F>
+void frag_block64(std::vector<T>& out, int64_t base, int mtiles, int ktiles16, F wfun, bool chained) {
   for (int mt = 0; mt < mtiles; ++mt)
     for (int t = 0; t < ktiles16; ++t)
       for (int v = 0; v < 4; ++v)
@@ -201,32 +174,22 @@ void frag_block64(std::vector<double>& out, int64_t base, int mtiles, int ktiles
               wfun(16 * mt + (l & 15), chained ? kfeat64c(t, v, l) : kfeat64(t, v, l));
         }
 }
-template <class F>
-void frag_block32(std::vector<float>& out, int64_t base, int mtiles, int ktiles32, F wfun) {
+template <class T, class F>
+void frag_block32(std::vector<T>& out, int64_t base, int mtiles, int ktiles32, F wfun) {
   for (int mt = 0; mt < mtiles; ++mt)
     for (int t = 0; t < ktiles32; ++t)
       for (int l = 0; l < 64; ++l)
         for (int j = 0; j < 8; ++j)
-          out[base + (((int64_t)mt * ktiles32 + t) * 64 + l) * 8 + j] = (float)wfun(16 * mt + (l & 15), kfeat32(t, l, j));
+          out[base + (((int64_t)mt * ktiles32 + t) * 64 + l) * 8 + j] = wfun(16 * mt + (l & 15), kfeat32(t, l, j));
 }
 
-int upload(void* dst, const void* src, size_t bytes) {
-  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(model)");
-  return DP_OK;
-}
-
-int upload_lp(uint16_t** bf, uint16_t** hf, const std::vector<float>& v) {
-  std::vector<uint16_t> b(v.size()), h(v.size());
-  for (size_t k = 0; k < v.size(); ++k) {
-    b[k] = f32_to_bf16(v[k]);
-    h[k] = f32_to_f16(v[k]);
-  }
+template <class T>
+int upload_vec(T** dst, const std::vector<T>& v, const char* what) {
   int rc;
-  if ((rc = dev_alloc(bf, v.size(), "hipMalloc(frag bf16)"))) return rc;
-  if ((rc = dev_alloc(hf, v.size(), "hipMalloc(frag f16)"))) return rc;
-  if ((rc = upload(*bf, b.data(), b.size() * 2))) return rc;
-  return upload(*hf, h.data(), h.size() * 2);
+  if ((rc = dev_alloc(dst, v.size(), what))) return rc;
+  hipError_t e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return DP_OK;
 }
 
 void free_model(dp_model* m) {
@@ -236,11 +199,17 @@ void free_model(dp_model* m) {
                   m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_vec64, m->fit_vec32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (int k = 0; k < m->n_maps; ++k)
+    if (m->maps[k].idx) (void)hipFree(m->maps[k].idx);
   delete m;
 }
 
-// Derives every device copy of the parameters.
-int prepare_model(dp_model* m, const double* P) {
+// Every device copy of the parameters is a gather from the flat vector:
+// element k of a copy holds P[idx[k]] (0 where idx[k] < 0) converted to the
+// copy's precision.  The index maps depend only on the descriptor, so they
+// are derived once here; dp_model_create and both parameter updates then run
+// the same gathers on the device, with no allocation after creation.
+int build_maps(dp_model* m) {
   const dp_model_desc& d = m->desc;
   const ParamLayout L = layout_of(&d);
   const int w = m->w1, nt = d.ntypes, fw = m->fw, nd = m->nd;
@@ -261,44 +230,34 @@ int prepare_model(dp_model* m, const double* P) {
   m->fit_param_off[7] = L.bo[0];
   m->fit_param_stride = nt > 1 ? L.fitW[1][0] - L.fitW[0][0] : 0;
   m->ebias_off = L.ebias;
-  // ---- embedding vectors
+  typedef std::vector<int32_t> Map;
+  auto I = [](int64_t k) -> int32_t { return (int32_t)k; };
+  // ---- embedding vectors, slot order (plain and denser layouts)
   m->emb_vec_per_net = 384;
-  std::vector<double> ev((size_t)nnets * 384, 0.0);
+  Map ev((size_t)nnets * 384, -1), evd((size_t)nnets * 384, -1);
   for (int a = 0; a < nt; ++a)
     for (int b = 0; b < nt; ++b) {
-      double* v = &ev[(size_t)(a * nt + b) * 384];
+      int32_t* v = &ev[(size_t)(a * nt + b) * 384];
+      int32_t* vd = &evd[(size_t)(a * nt + b) * 384];
       for (int p = 0; p < 32; ++p) {
-        const int f = feat1(w, p);
-        if (f >= 0) { v[p] = P[L.embW[a][b][0] + f]; v[32 + p] = P[L.embB[a][b][0] + f]; }
+        int f = feat1(w, p);
+        if (f >= 0) { v[p] = I(L.embW[a][b][0] + f); v[32 + p] = I(L.embB[a][b][0] + f); }
+        f = val1(w, p);
+        if (f >= 0) { vd[p] = I(L.embW[a][b][0] + f); vd[32 + p] = I(L.embB[a][b][0] + f); }
       }
       for (int p = 0; p < 64; ++p) {
-        const int f = feat2(w, p);
-        if (f >= 0) v[64 + p] = P[L.embB[a][b][1] + f];
+        int f = feat2(w, p);
+        if (f >= 0) v[64 + p] = I(L.embB[a][b][1] + f);
+        f = val2(w, p);
+        if (f >= 0) vd[64 + p] = I(L.embB[a][b][1] + f);
       }
       for (int p = 0; p < 128; ++p) {
-        const int f = feat3(w, p);
-        if (f >= 0) v[128 + p] = P[L.embB[a][b][2] + f];
+        int f = feat3(w, p);
+        if (f >= 0) v[128 + p] = I(L.embB[a][b][2] + f);
+        f = val3(w, p);
+        if (f >= 0) vd[128 + p] = I(L.embB[a][b][2] + f);
       }
-      for (int f = 0; f < 4 * w; ++f) v[256 + f] = P[L.embB[a][b][2] + f];
-    }
-  std::vector<float> ev32(ev.begin(), ev.end());
-  std::vector<double> evd((size_t)nnets * 384, 0.0);
-  for (int a = 0; a < nt; ++a)
-    for (int b = 0; b < nt; ++b) {
-      double* v = &evd[(size_t)(a * nt + b) * 384];
-      for (int p = 0; p < 32; ++p) {
-        const int f = val1(w, p);
-        if (f >= 0) { v[p] = P[L.embW[a][b][0] + f]; v[32 + p] = P[L.embB[a][b][0] + f]; }
-      }
-      for (int p = 0; p < 64; ++p) {
-        const int f = val2(w, p);
-        if (f >= 0) v[64 + p] = P[L.embB[a][b][1] + f];
-      }
-      for (int p = 0; p < 128; ++p) {
-        const int f = val3(w, p);
-        if (f >= 0) v[128 + p] = P[L.embB[a][b][2] + f];
-      }
-      for (int f = 0; f < 4 * w; ++f) v[256 + f] = P[L.embB[a][b][2] + f];
+      for (int f = 0; f < 4 * w; ++f) v[256 + f] = vd[256 + f] = I(L.embB[a][b][2] + f);
     }
   // ---- embedding fragments (same element counts for both kinds)
   EmbFragOffsets& fo = m->efo;
@@ -308,41 +267,39 @@ int prepare_model(dp_model* m, const double* P) {
   fo.B3 = fo.F3t + 8192;
   fo.B2 = fo.B3 + 8192;
   fo.per_net = fo.B2 + 2048;
-  std::vector<double> e64((size_t)nnets * fo.per_net, 0.0);
-  std::vector<double> e64d((size_t)nnets * fo.per_net, 0.0);
-  std::vector<float> e32((size_t)nnets * fo.per_net, 0.f);
+  Map e64((size_t)nnets * fo.per_net, -1), e64d((size_t)nnets * fo.per_net, -1), e32((size_t)nnets * fo.per_net, -1);
   const int m1 = 4 * w;
   for (int a = 0; a < nt; ++a)
     for (int b = 0; b < nt; ++b) {
-      const double* W2 = P + L.embW[a][b][1];  // [w][2w]
-      const double* W3 = P + L.embW[a][b][2];  // [2w][4w]
+      const int64_t W2 = L.embW[a][b][1];  // [w][2w]
+      const int64_t W3 = L.embW[a][b][2];  // [2w][4w]
       const int64_t base = (int64_t)(a * nt + b) * fo.per_net;
-      auto w2 = [&](int in_slot, int out_slot) -> double {  // slots of layer 1 -> layer 2
+      auto w2 = [&](int in_slot, int out_slot) -> int32_t {  // slots of layer 1 -> layer 2
         const int fi = feat1(w, in_slot), fo2 = feat2(w, out_slot);
-        return (fi < 0 || fo2 < 0) ? 0.0 : W2[(int64_t)fi * 2 * w + fo2];
+        return (fi < 0 || fo2 < 0) ? -1 : I(W2 + (int64_t)fi * 2 * w + fo2);
       };
-      auto w3s = [&](int in_slot, int out_slot) -> double {  // layer-2 slot -> layer-3 slot
-        if (in_slot >= 64 || out_slot >= 128) return 0.0;
+      auto w3s = [&](int in_slot, int out_slot) -> int32_t {  // layer-2 slot -> layer-3 slot
+        if (in_slot >= 64 || out_slot >= 128) return -1;
         const int fi = feat2(w, in_slot), fo3 = feat3(w, out_slot);
-        return (fi < 0 || fo3 < 0) ? 0.0 : W3[(int64_t)fi * 4 * w + fo3];
+        return (fi < 0 || fo3 < 0) ? -1 : I(W3 + (int64_t)fi * 4 * w + fo3);
       };
-      auto w3f = [&](int in_slot, int out_feat) -> double {  // layer-2 slot -> layer-3 feature
+      auto w3f = [&](int in_slot, int out_feat) -> int32_t {  // layer-2 slot -> layer-3 feature
         const int fi = feat2(w, in_slot);
-        return (fi < 0 || out_feat >= m1) ? 0.0 : W3[(int64_t)fi * 4 * w + out_feat];
+        return (fi < 0 || out_feat >= m1) ? -1 : I(W3 + (int64_t)fi * 4 * w + out_feat);
       };
       // the denser layout (FP64 force kernels)
-      auto w2d = [&](int in_slot, int out_slot) -> double {
+      auto w2d = [&](int in_slot, int out_slot) -> int32_t {
         const int fi = wt1(w, in_slot), fo2 = val2(w, out_slot);
-        return (fi < 0 || fo2 < 0) ? 0.0 : W2[(int64_t)fi * 2 * w + fo2];
+        return (fi < 0 || fo2 < 0) ? -1 : I(W2 + (int64_t)fi * 2 * w + fo2);
       };
-      auto w3sd = [&](int in_slot, int out_slot) -> double {
-        if (in_slot >= 64 || out_slot >= 128) return 0.0;
+      auto w3sd = [&](int in_slot, int out_slot) -> int32_t {
+        if (in_slot >= 64 || out_slot >= 128) return -1;
         const int fi = wt2(w, in_slot), fo3 = val3(w, out_slot);
-        return (fi < 0 || fo3 < 0) ? 0.0 : W3[(int64_t)fi * 4 * w + fo3];
+        return (fi < 0 || fo3 < 0) ? -1 : I(W3 + (int64_t)fi * 4 * w + fo3);
       };
-      auto w3fd = [&](int in_slot, int out_feat) -> double {
+      auto w3fd = [&](int in_slot, int out_feat) -> int32_t {
         const int fi = wt2(w, in_slot);
-        return (fi < 0 || out_feat >= m1) ? 0.0 : W3[(int64_t)fi * 4 * w + out_feat];
+        return (fi < 0 || out_feat >= m1) ? -1 : I(W3 + (int64_t)fi * 4 * w + out_feat);
       };
       frag_block64(e64d, base + fo.F2, 4, 2, [&](int mo, int ki) { return w2d(ki, mo); }, true);
       frag_block64(e64d, base + fo.F3n, m->n3, 4, [&](int mo, int ki) { return w3fd(ki, mo); }, true);
@@ -380,14 +337,13 @@ int prepare_model(dp_model* m, const double* P) {
     ff.per_type = o;
     fl.per_type = ol;
   }
-  std::vector<double> f64v((size_t)nt * ff.per_type, 0.0);
-  std::vector<float> f32v((size_t)nt * fl.per_type, 0.f);
+  Map f64v((size_t)nt * ff.per_type, -1), f32v((size_t)nt * fl.per_type, -1);
   for (int t = 0; t < nt; ++t) {
     for (int l = 0; l < 3; ++l) {
-      const double* W = P + L.fitW[t][l];  // [Kin][fw]
+      const int64_t W = L.fitW[t][l];  // [Kin][fw]
       const int K = Kin[l];
-      auto wf = [&](int mo, int ki) -> double { return (ki < K && mo < fw) ? W[(int64_t)ki * fw + mo] : 0.0; };
-      auto wb = [&](int mi, int ko) -> double { return (mi < K && ko < fw) ? W[(int64_t)mi * fw + ko] : 0.0; };
+      auto wf = [&](int mo, int ki) -> int32_t { return (ki < K && mo < fw) ? I(W + (int64_t)ki * fw + mo) : -1; };
+      auto wb = [&](int mi, int ko) -> int32_t { return (mi < K && ko < fw) ? I(W + (int64_t)mi * fw + ko) : -1; };
       frag_block64(f64v, t * ff.per_type + ff.fwd[l], fw / 16, K / 16, wf, false);
       frag_block32(f32v, t * fl.per_type + fl.fwd[l], fw / 16, (K + 31) / 32, wf);
       frag_block64(f64v, t * ff.per_type + ff.bwd[l], K / 16, fw / 16, wb, false);
@@ -396,49 +352,56 @@ int prepare_model(dp_model* m, const double* P) {
   }
   // ---- fitting vectors: b1 b2 b3 wo | bo ebias
   m->fit_vec_per_type = 4 * fw + 2;
-  std::vector<double> fv((size_t)nt * m->fit_vec_per_type, 0.0);
+  Map fv((size_t)nt * m->fit_vec_per_type, -1);
   for (int t = 0; t < nt; ++t) {
-    double* v = &fv[(size_t)t * m->fit_vec_per_type];
+    int32_t* v = &fv[(size_t)t * m->fit_vec_per_type];
     for (int l = 0; l < 3; ++l)
-      for (int k = 0; k < fw; ++k) v[l * fw + k] = P[L.fitB[t][l] + k];
-    for (int k = 0; k < fw; ++k) v[3 * fw + k] = P[L.wo[t] + k];
-    v[4 * fw] = P[L.bo[t]];
-    v[4 * fw + 1] = P[L.ebias + t];
+      for (int k = 0; k < fw; ++k) v[l * fw + k] = I(L.fitB[t][l] + k);
+    for (int k = 0; k < fw; ++k) v[3 * fw + k] = I(L.wo[t] + k);
+    v[4 * fw] = I(L.bo[t]);
+    v[4 * fw + 1] = I(L.ebias + t);
   }
-  std::vector<float> fv32(fv.begin(), fv.end());
-  // ---- upload
-  if (!m->emb_vec64) {
-    if ((rc = dev_alloc(&m->params, (size_t)m->n_params, "hipMalloc(params)"))) return rc;
-    if ((rc = dev_alloc(&m->emb_vec64, ev.size(), "hipMalloc(emb vec)"))) return rc;
-    if ((rc = dev_alloc(&m->emb_vec32, ev32.size(), "hipMalloc(emb vec32)"))) return rc;
-    if ((rc = dev_alloc(&m->emb_frag64, e64.size(), "hipMalloc(emb frag)"))) return rc;
-    if ((rc = dev_alloc(&m->emb_vec64d, evd.size(), "hipMalloc(emb vec)"))) return rc;
-    if ((rc = dev_alloc(&m->emb_frag64d, e64d.size(), "hipMalloc(emb frag)"))) return rc;
-    if ((rc = dev_alloc(&m->fit_frag64, f64v.size(), "hipMalloc(fit frag)"))) return rc;
-    if ((rc = dev_alloc(&m->fit_vec64, fv.size(), "hipMalloc(fit vec)"))) return rc;
-    if ((rc = dev_alloc(&m->fit_vec32, fv32.size(), "hipMalloc(fit vec32)"))) return rc;
-  } else {
-    // the half-precision copies are reallocated below; cleared first so that
-    // a failed reallocation leaves nothing for free_model to free twice
-    void** lp[] = {(void**)&m->emb_frag_bf16, (void**)&m->emb_frag_f16, (void**)&m->fit_frag_bf16,
-                   (void**)&m->fit_frag_f16};
-    for (void** q : lp) {
-      (void)hipFree(*q);
-      *q = nullptr;
+  // ---- device buffers and the gathers that fill them
+  struct Target { const Map* map; void** dst; int kind; size_t esize; };
+  const Target tg[] = {
+      {&ev, (void**)&m->emb_vec64, 0, 8},      {&ev, (void**)&m->emb_vec32, 1, 4},
+      {&e64, (void**)&m->emb_frag64, 0, 8},    {&evd, (void**)&m->emb_vec64d, 0, 8},
+      {&e64d, (void**)&m->emb_frag64d, 0, 8},  {&e32, (void**)&m->emb_frag_bf16, 2, 2},
+      {&e32, (void**)&m->emb_frag_f16, 3, 2},  {&f64v, (void**)&m->fit_frag64, 0, 8},
+      {&f32v, (void**)&m->fit_frag_bf16, 2, 2}, {&f32v, (void**)&m->fit_frag_f16, 3, 2},
+      {&fv, (void**)&m->fit_vec64, 0, 8},      {&fv, (void**)&m->fit_vec32, 1, 4},
+  };
+  const Map* uploaded[16];
+  int32_t* uploaded_dev[16];
+  int nup = 0;
+  m->n_maps = 0;
+  for (const Target& t : tg) {
+    int32_t* idx = nullptr;
+    for (int k = 0; k < nup; ++k)
+      if (uploaded[k] == t.map) idx = uploaded_dev[k];
+    const bool own = idx == nullptr;
+    if (own) {
+      if ((rc = upload_vec(&idx, *t.map, "hipMalloc(parameter map)"))) return rc;
+      uploaded[nup] = t.map;
+      uploaded_dev[nup++] = idx;
     }
+    if ((rc = dev_alloc((char**)t.dst, t.map->size() * t.esize, "hipMalloc(model copy)"))) return rc;
+    ParamMap& pm = m->maps[m->n_maps++];
+    pm.idx = own ? idx : nullptr;   // freed once, by its first user
+    pm.idx_use = idx;
+    pm.n = (int64_t)t.map->size();
+    pm.kind = t.kind;
+    pm.dst = *t.dst;
   }
-  if ((rc = upload(m->params, P, (size_t)m->n_params * 8))) return rc;
-  if ((rc = upload(m->emb_vec64, ev.data(), ev.size() * 8))) return rc;
-  if ((rc = upload(m->emb_vec32, ev32.data(), ev32.size() * 4))) return rc;
-  if ((rc = upload(m->emb_frag64, e64.data(), e64.size() * 8))) return rc;
-  if ((rc = upload(m->emb_vec64d, evd.data(), evd.size() * 8))) return rc;
-  if ((rc = upload(m->emb_frag64d, e64d.data(), e64d.size() * 8))) return rc;
-  if ((rc = upload(m->fit_frag64, f64v.data(), f64v.size() * 8))) return rc;
-  if ((rc = upload(m->fit_vec64, fv.data(), fv.size() * 8))) return rc;
-  if ((rc = upload(m->fit_vec32, fv32.data(), fv32.size() * 4))) return rc;
-  if ((rc = upload_lp(&m->emb_frag_bf16, &m->emb_frag_f16, e32))) return rc;
-  if ((rc = upload_lp(&m->fit_frag_bf16, &m->fit_frag_f16, f32v))) return rc;
-  return DP_OK;
+  return dev_alloc(&m->params, (size_t)m->n_params, "hipMalloc(params)");
+}
+
+// Refreshes every device copy from m->params (stream-ordered).
+void gather_all(dp_model* m, hipStream_t s) {
+  for (int k = 0; k < m->n_maps; ++k) {
+    const ParamMap& pm = m->maps[k];
+    launch_param_gather(m->params, pm.idx_use, pm.n, pm.kind, pm.dst, s);
+  }
 }
 
 // ------------------------------------------------------------ frames
@@ -861,7 +824,15 @@ int dp_model_create(const dp_model_desc* desc, const double* params_host, int64_
   m->n_params = n_params;
   hipError_t e = hipGetDevice(&m->device);
   if (e != hipSuccess) { delete m; return hip_fail(e, "hipGetDevice"); }
-  rc = prepare_model(m, params_host);
+  rc = build_maps(m);
+  if (rc == DP_OK) {
+    e = hipMemcpy(m->params, params_host, (size_t)n_params * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      gather_all(m, nullptr);
+      e = hipStreamSynchronize(nullptr);
+    }
+    if (e != hipSuccess) rc = hip_fail(e, "model upload");
+  }
   if (rc) { free_model(m); return rc; }
   *out = m;
   return DP_OK;
@@ -869,10 +840,26 @@ int dp_model_create(const dp_model_desc* desc, const double* params_host, int64_
 
 int dp_model_set_params(dp_model* m, const double* params_host, int64_t n_params) {
   if (!m || !params_host || n_params != m->n_params) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  for (int64_t k = 0; k < n_params; ++k)
+    if (!std::isfinite(params_host[k])) { set_error("parameter %lld is not finite", (long long)k); return DP_ERR_BAD_ARG; }
   int rc;
   if ((rc = set_device(m->device))) return rc;
-  HIPCHECK(hipDeviceSynchronize());
-  return prepare_model(m, params_host);
+  HIPCHECK(hipMemcpy(m->params, params_host, (size_t)n_params * 8, hipMemcpyHostToDevice));
+  gather_all(m, nullptr);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(nullptr));
+  return DP_OK;
+}
+
+int dp_model_set_params_device(dp_model* m, const double* params_dev, int64_t n_params, hipStream_t stream) {
+  if (!m || !params_dev || n_params != m->n_params) { set_error("bad arguments"); return DP_ERR_BAD_ARG; }
+  int rc;
+  if ((rc = set_device(m->device))) return rc;
+  if (params_dev != m->params)
+    HIPCHECK(hipMemcpyAsync(m->params, params_dev, (size_t)n_params * 8, hipMemcpyDeviceToDevice, stream));
+  gather_all(m, stream);
+  HIPCHECK(hipGetLastError());
+  return DP_OK;
 }
 
 int dp_model_destroy(dp_model* m) {

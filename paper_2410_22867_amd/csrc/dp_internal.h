@@ -45,7 +45,15 @@ struct FitFragOffsets {
   int64_t fwd[3], bwd[3], per_type;
 };
 
-struct dp_model_impl;
+// One device copy of the parameters: dst[k] = P[idx[k]] (0 where
+// idx[k] < 0) in precision kind (0 f64, 1 f32, 2 bf16, 3 f16).
+struct ParamMap {
+  int32_t* idx;          // owned map (NULL when shared with an earlier entry)
+  const int32_t* idx_use;
+  int64_t n;
+  int kind;
+  void* dst;
+};
 
 }  // namespace dpse
 
@@ -91,6 +99,9 @@ struct dp_model {
   double* fit_vec64;   // per type: b1, b2, b3, wo [fw each], bo, ebias  (4*fw + 2)
   float* fit_vec32;
   int64_t fit_vec_per_type;
+  // index maps of every copy above (built once at creation)
+  dpse::ParamMap maps[16];
+  int n_maps;
   int device;
 };
 
@@ -225,6 +236,9 @@ void launch_nl_skin_format(dp_ctx* c, const double* x, const int32_t* types, int
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void launch_copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t s);
+// dst[k] = P[idx[k]] (0 where idx[k] < 0) converted to kind (0 f64, 1 f32,
+// 2 bf16, 3 f16; the half forms round through FP32, to nearest even)
+void launch_param_gather(const double* P, const int32_t* idx, int64_t n, int kind, void* dst, hipStream_t s);
 // writes one frame-table entry and clears a status word (kernel arguments
 // only: no host staging buffer)
 void launch_set_frame(FrameInfo* dst, const FrameInfo& F, int32_t* flags, hipStream_t s);

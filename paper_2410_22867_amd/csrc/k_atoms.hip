@@ -31,6 +31,25 @@ __global__ void k_copy_i32(const int32_t* a, int32_t* b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
 }
+template <int KIND>
+__global__ void k_param_gather(const double* __restrict__ P, const int32_t* __restrict__ idx, int64_t n, void* dst) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t q = idx[k];
+    const double v = q >= 0 ? P[q] : 0.0;
+    if (KIND == 0) reinterpret_cast<double*>(dst)[k] = v;
+    else if (KIND == 1) reinterpret_cast<float*>(dst)[k] = (float)v;
+    else if (KIND == 2) reinterpret_cast<__bf16*>(dst)[k] = (__bf16)(float)v;
+    else reinterpret_cast<_Float16*>(dst)[k] = (_Float16)(float)v;
+  }
+}
+void launch_param_gather(const double* P, const int32_t* idx, int64_t n, int kind, void* dst, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  if (kind == 0) hipLaunchKernelGGL(k_param_gather<0>, dim3(g), dim3(256), 0, s, P, idx, n, dst);
+  else if (kind == 1) hipLaunchKernelGGL(k_param_gather<1>, dim3(g), dim3(256), 0, s, P, idx, n, dst);
+  else if (kind == 2) hipLaunchKernelGGL(k_param_gather<2>, dim3(g), dim3(256), 0, s, P, idx, n, dst);
+  else hipLaunchKernelGGL(k_param_gather<3>, dim3(g), dim3(256), 0, s, P, idx, n, dst);
+}
 void launch_set_frame(FrameInfo* dst, const FrameInfo& F, int32_t* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(64), 0, s, dst, F, flags);
 }

@@ -25,7 +25,8 @@ FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED = 32, 64
 BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 
 # Symbols declared in include/dp.h (checked by the CPU tests).
-EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_destroy", "dp_ctx_create",
+EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_set_params_device",
+           "dp_model_destroy", "dp_ctx_create",
            "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_nlist_skin_build", "dp_nlist_skin_format",
            "dp_nlist_skin_update", "dp_build_nlist_noalloc",
            "dp_compute", "dp_compute_batch",
@@ -85,6 +86,7 @@ def lib():
             "dp_model_n_params": (i64, [P]),
             "dp_model_create": (ctypes.c_int, [P, P, i64, PP]),
             "dp_model_set_params": (ctypes.c_int, [P, P, i64]),
+            "dp_model_set_params_device": (ctypes.c_int, [P, P, i64, P]),
             "dp_model_destroy": (ctypes.c_int, [P]),
             "dp_ctx_create": (ctypes.c_int, [P, i64, i32, i64, PP]),
             "dp_ctx_destroy": (ctypes.c_int, [P]),
@@ -147,6 +149,14 @@ class Model:
     def set_params(self, params: np.ndarray) -> None:
         p = np.ascontiguousarray(params, dtype=np.float64)
         _check(lib().dp_model_set_params(self.handle, p.ctypes.data, p.size))
+
+    def load_params(self, params) -> None:
+        """Parameters from a device float64 tensor [n_params], on the current
+        stream (no host round trip, no wait)."""
+        if params.dtype != __import__("torch").float64 or not params.is_cuda or params.numel() != self.n_params:
+            raise ValueError("load_params needs a float64 device tensor of n_params values")
+        p = params.contiguous()
+        _check(lib().dp_model_set_params_device(self.handle, _ptr(p), self.n_params, _stream()))
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -365,18 +375,15 @@ def _autograd():
         mode is "fp64", "bf16" or "fp16" (the mixed forms give the mixed
         model's energies, forces and parameter gradients).
 
-        The model of ``ctx`` is updated from ``params`` when they changed since
-        the last call.  Backward must run before another compute on ``ctx``.
+        The model of ``ctx`` is loaded from ``params`` (a device float64
+        tensor) on every call, on the device and asynchronously, so in-place
+        updates and new tensors are always seen.  Backward must run before
+        another compute on ``ctx``.
         """
 
         @staticmethod
         def forward(fctx, params, coords, types, boxes, frame_off, dctx, nlist, mode="fp64"):
-            model = dctx.model
-            p = params.detach()
-            key = (p.data_ptr(), p._version)
-            if getattr(model, "_param_key", None) != key:
-                model.set_params(p.cpu().numpy())
-                model._param_key = key
+            dctx.model.load_params(params.detach())
             r = dctx.compute_batch(coords.detach(), types, boxes, frame_off, nlist, mode=mode)
             fctx.dctx = dctx
             fctx.frame_off = np.asarray(frame_off, dtype=np.int64)

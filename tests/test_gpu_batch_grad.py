@@ -134,7 +134,6 @@ def test_param_grads_finite_differences(batch):
 
     def loss(pv):
         b["model"].set_params(pv)
-        b["model"]._param_key = None
         r = b["ctx"].compute_batch(b["x"], b["t"], b["boxes"], b["off"], b["nl"], mode="fp64")
         return float(((r["E"] - tgt) ** 2).mean().item())
 
@@ -182,3 +181,65 @@ def test_mixed_param_grads_close_to_oracle(batch, mode, tol):
     for f in range(B):
         a0, a1 = b["off"][f], b["off"][f + 1]
         assert np.allclose(gx[a0:a1], -F[a0:a1] * 2.0 * (Em[f] - b["targets"][f]) / B, atol=1e-12)
+
+
+def test_parameter_updates_are_always_seen(batch):
+    """DPEnergy loads the parameters on the device at every call: a change
+    made in place through .data (which leaves the tensor's version counter
+    alone) and a new tensor that may reuse the freed block both give the
+    oracle's energies and gradients for the new parameters; the device
+    update of the model matches the host one bit for bit."""
+    b = batch
+    from paper_2410_22867_amd import dpse
+    _say("parameter updates")
+    dev = b["dev"]
+    tgt = torch.tensor(b["targets"], device=dev)
+    B = len(b["frames"])
+
+    def check(params, pnp):
+        E = dpse.dp_energy(params, b["x"], b["t"], b["boxes"], b["off"], b["ctx"], b["nl"], "fp64")
+        L = ((E - tgt) ** 2).mean()
+        L.backward()
+        torch.cuda.synchronize()
+        Em = E.detach().cpu().numpy()
+        g = params.grad.cpu().numpy()
+        want = np.zeros_like(g)
+        for f, fr in enumerate(b["frames"]):
+            o = oracle.compute(fr.coords, fr.types, fr.box, b["desc"], pnp,
+                               grad_scale=2.0 * (Em[f] - b["targets"][f]) / B)
+            assert abs(Em[f] - o["E"]) <= 1e-10 * abs(o["E"])
+            want += o["grad"]
+        assert np.abs(g - want).max() <= 1e-9 * np.abs(want).max()
+
+    p0 = b["p"].copy()
+    params = torch.tensor(p0, device=dev, requires_grad=True)
+    check(params, p0)
+    # in place through .data: the version counter does not move
+    off, shp = b["desc"].param_offsets()["fit1.W1"]
+    p1 = p0.copy()
+    p1[off:off + 1000] *= 1.5
+    v = params._version
+    params.data[off:off + 1000] *= 1.5
+    assert params._version == v
+    params.grad = None
+    check(params, p1)
+    # a new tensor after the old one is freed (the caching allocator may hand
+    # back the same block)
+    del params
+    p2 = p1.copy()
+    p2[5:200] += 0.01
+    params = torch.tensor(p2, device=dev, requires_grad=True)
+    check(params, p2)
+    # the device update equals the host update
+    m1 = dpse.Model(b["desc"], p0)
+    m1.set_params(p2)
+    m2 = dpse.Model(b["desc"], p0)
+    m2.load_params(torch.tensor(p2, device=dev))
+    c1 = dpse.Context(m1, int(b["off"][-1]), max_frames=B)
+    c2 = dpse.Context(m2, int(b["off"][-1]), max_frames=B)
+    for mode in ("fp64", "bf16", "fp16"):
+        r1 = c1.compute_batch(b["x"], b["t"], b["boxes"], b["off"], b["nl"], mode=mode)
+        r2 = c2.compute_batch(b["x"], b["t"], b["boxes"], b["off"], b["nl"], mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(r1["E"], r2["E"]) and torch.equal(r1["F"], r2["F"])
+    b["model"].set_params(b["p"])

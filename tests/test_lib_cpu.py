@@ -82,3 +82,28 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     fr, desc, p, dt = I.workload("water192")
     with pytest.raises(RuntimeError, match="not built"):
         dpse.Model(desc, p)
+
+
+def _body(src, name):
+    i = src.index(name + "(")
+    i = src.index("{", i)
+    depth, j = 0, i
+    while True:
+        if src[j] == "{":
+            depth += 1
+        elif src[j] == "}":
+            depth -= 1
+            if depth == 0:
+                return src[i:j + 1]
+        j += 1
+
+
+def test_parameter_updates_allocate_nothing():
+    """Both parameter-update entry points, and the gathers they run, call no
+    allocator and do not wait for the whole device (static check of the
+    source: the calls need a GPU to run)."""
+    src = open(os.path.join(ROOT, "paper_2410_22867_amd", "csrc", "dp_api.cpp")).read()
+    for fn in ("int dp_model_set_params", "int dp_model_set_params_device", "void gather_all"):
+        body = _body(src, fn)
+        for bad in ("hipMalloc", "hipFree", "hipDeviceSynchronize", "dev_alloc", "build_maps", "new ", "malloc"):
+            assert bad not in body, (fn, bad)
