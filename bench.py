@@ -112,6 +112,9 @@ def main():
                     help="embedding-activation store budget; 0 recomputes the activations in the backward pass")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to scale HBM counters")
+    ap.add_argument("--no-paper-size", action="store_true",
+                    help="skip the 0.56 M-atom water and 0.54 M-atom copper steps")
+    ap.add_argument("--no-latency", action="store_true", help="skip the 192-atom eager vs graph-replay step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -392,7 +395,141 @@ def main():
         "roofline_modes": extra,
         "cpu_baseline": cpu,
     }
+    del ctx, model
+    torch.cuda.synchronize()
+    if not args.no_latency:
+        line["latency_small"] = bench_latency(args, torch, dpse, I, dev)
+    if not args.no_paper_size:
+        line["paper_size"] = bench_paper_size(args, torch, dpse, I, dev)
     print(json.dumps(line), flush=True)
+
+
+def bench_paper_size(args, torch, dpse, I, dev):
+    """The Evaluation section's strong-scaling systems (0.56 M-atom water,
+    0.54 M-atom copper) on one GPU: MD steps as in the main bench (Verlet
+    list rebuilt on the device), FP64 and BF16, with the device memory the
+    model and context take and the activation-store choice."""
+    out = {}
+    for wl in ("water557k", "copper535k"):
+        fr, desc, params, dt = I.workload(wl)
+        n = fr.n
+        free0 = torch.cuda.mem_get_info()[0]
+        model = dpse.Model(desc, params)
+        # the activation store is allocated only when it holds every atom
+        tiles = sum((s_ + 15) // 16 for s_ in desc.sel)
+        store = n * tiles * desc.m1 * 16 * 8
+        budget = store if store <= args.workspace_gib * 2 ** 30 else 0
+        ctx = dpse.Context(model, n, budget_bytes=int(budget))
+        x0 = torch.tensor(fr.coords, device=dev)
+        v0 = torch.tensor(I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=205), device=dev)
+        t = torch.tensor(fr.types, device=dev)
+        nl = torch.empty((n, desc.nm), dtype=torch.int32, device=dev)
+        ov = torch.empty(1, dtype=torch.int32, device=dev)
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        W = torch.empty(9, dtype=torch.float64, device=dev)
+        ke = torch.empty(1, dtype=torch.float64, device=dev)
+        f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        nreb = torch.zeros(1, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        used = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 30
+        rec = {"natoms": n, "box_A": [round(float(v), 3) for v in np.diag(fr.box)], "dt_fs": dt,
+               "device_memory_GiB": round(used, 2)}
+        for mode in ("fp64", "bf16"):
+            x = x0.clone()
+            v = v0.clone()
+            ctx.skin_build(x, t, fr.box, args.skin)
+            ctx.skin_format(x, t, out=nl, overflow=ov)
+            ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+            stored = ctx.store_info()[1]
+
+            def step():
+                ctx.kick_drift(x, v, f, t, fr.box, dt, wrap=False)
+                ctx.skin_update(x, t, every=args.rebuild_every, out=nl, overflow=ov, rebuilds=nreb)
+                ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+                ctx.kick(v, f, t, dt, ke)
+
+            for _ in range(2):
+                step()
+            ctx.status()
+            torch.cuda.synchronize()
+            steps = 5
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rec[mode] = {"ms_per_step": round(el / steps * 1e3, 3), "atom_steps_per_s": round(n * steps / el, 1),
+                         "ns_per_day": round(steps / el * dt * 0.0864, 3), "steps": steps,
+                         "embedding_activations": "stored" if stored else "recomputed",
+                         "status_flags": ctx.status()}
+            print(f"# {wl} {mode}: {rec[mode]}", file=sys.stderr, flush=True)
+        out[wl] = rec
+        del ctx, model
+        torch.cuda.synchronize()
+    out["paper_context"] = ("Evaluation section, 12,000 Fugaku nodes: 149 ns/day (copper, 0.54 M atoms) and "
+                            "68.5 ns/day (water, 0.56 M atoms); context only, not a target")
+    return out
+
+
+def bench_latency(args, torch, dpse, I, dev):
+    """The 192-atom water step (launch-bound: ~20 small kernels) issued
+    eagerly and replayed from a HIP graph captured once (torch.cuda.CUDAGraph
+    records the library's launches on the capture stream)."""
+    fr, desc, params, dt = I.workload("water192")
+    n = fr.n
+    model = dpse.Model(desc, params)
+    ctx = dpse.Context(model, n)
+    out = {"workload": "water192", "natoms": n}
+    for mode in ("fp64", "bf16"):
+        x = torch.tensor(fr.coords, device=dev)
+        v = torch.tensor(I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=200), device=dev)
+        t = torch.tensor(fr.types, device=dev)
+        nl = torch.empty((n, desc.nm), dtype=torch.int32, device=dev)
+        ov = torch.empty(1, dtype=torch.int32, device=dev)
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        W = torch.empty(9, dtype=torch.float64, device=dev)
+        ke = torch.empty(1, dtype=torch.float64, device=dev)
+        f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            ctx.skin_build(x, t, fr.box, args.skin)
+            ctx.skin_format(x, t, out=nl, overflow=ov)
+            ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+
+            def step():
+                ctx.kick_drift(x, v, f, t, fr.box, dt, wrap=False)
+                ctx.skin_update(x, t, every=args.rebuild_every, out=nl, overflow=ov)
+                ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+                ctx.kick(v, f, t, dt, ke)
+
+            for _ in range(5):
+                step()
+        torch.cuda.synchronize()
+        steps = 200
+        with torch.cuda.stream(s):
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            s.synchronize()
+            eager = (time.perf_counter() - t0) / steps
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step()
+        torch.cuda.synchronize()
+        for _ in range(5):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t0) / steps
+        out[mode] = {"eager_ms_per_step": round(eager * 1e3, 4), "graph_ms_per_step": round(graph * 1e3, 4),
+                     "graph_atom_steps_per_s": round(n / graph, 1), "graph_ns_per_day": round(dt * 0.0864 / graph, 2),
+                     "status_flags": ctx.status()}
+        print(f"# latency {mode}: {out[mode]}", file=sys.stderr, flush=True)
+        del g
+    return out
 
 
 def bench_batch(args, torch, dpse, I, dev):

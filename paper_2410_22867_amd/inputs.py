@@ -246,18 +246,20 @@ def water_box(n_mol: int, L: float, seed: int) -> Frame:
     return Frame(np.ascontiguousarray(coords), types, np.diag([L, L, L]).astype(np.float64))
 
 
-def copper_fcc(ncell: int, a: float, sigma: float, seed: int) -> Frame:
-    """FCC copper, ncell^3 conventional cells of edge a, Gaussian displacements."""
+def copper_fcc(ncell, a: float, sigma: float, seed: int) -> Frame:
+    """FCC copper, ncell^3 (or nx x ny x nz for a triple) conventional cells
+    of edge a, Gaussian displacements."""
     rng = np.random.default_rng(seed)
+    nc = (ncell, ncell, ncell) if np.isscalar(ncell) else tuple(ncell)
     basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
-    g = np.stack(np.meshgrid(np.arange(ncell), np.arange(ncell), np.arange(ncell),
+    g = np.stack(np.meshgrid(np.arange(nc[0]), np.arange(nc[1]), np.arange(nc[2]),
                              indexing="ij"), axis=-1).reshape(-1, 3)
     x = ((g[:, None, :] + basis[None, :, :]) * a).reshape(-1, 3)
     x = x + rng.normal(0.0, sigma, size=x.shape)
-    L = ncell * a
+    L = np.array(nc, dtype=np.float64) * a
     coords = _wrap(x, L)
     types = np.zeros(coords.shape[0], dtype=np.int32)
-    return Frame(np.ascontiguousarray(coords), types, np.diag([L, L, L]).astype(np.float64))
+    return Frame(np.ascontiguousarray(coords), types, np.diag(L).astype(np.float64))
 
 
 def water_density_box(n_mol: int) -> float:
@@ -312,9 +314,19 @@ def workload(name: str):
     if name == "water98k":
         fr = water_box(32768, 99.4, seed=3)
         return fr, WATER, init_params(WATER, MODEL_SEED_WATER, WATER_OUTPUT_SCALE), DT_WATER_FS
+    # the strong-scaling systems of the Evaluation section, on one GPU:
+    # 0.56 M atoms of water (185,856 molecules at 1 g/cm^3) and 0.54 M atoms
+    # of copper (62 x 60 x 36 FCC cells)
+    if name == "water557k":
+        nmol = 185856
+        fr = water_box(nmol, water_density_box(nmol), seed=5)
+        return fr, WATER, init_params(WATER, MODEL_SEED_WATER, WATER_OUTPUT_SCALE), DT_WATER_FS
+    if name == "copper535k":
+        fr = copper_fcc((62, 60, 36), 3.634, 0.1, seed=6)
+        return fr, COPPER, init_params(COPPER, MODEL_SEED_COPPER), DT_COPPER_FS
     if name == "waterbatch64":
         return water_batch(64, seed=4), WATER, init_params(WATER, MODEL_SEED_WATER, WATER_OUTPUT_SCALE), DT_WATER_FS
     raise KeyError(name)
 
 
-WORKLOADS = ("water192", "water12k", "copper32k", "water98k", "waterbatch64")
+WORKLOADS = ("water192", "water12k", "copper32k", "water98k", "waterbatch64", "water557k", "copper535k")
