@@ -80,6 +80,10 @@ extern "C" {
 #define DP_FP64 0     /* everything in FP64 */
 #define DP_MIX_BF16 1 /* embedding layers 2.. and fitting GEMMs: BF16 inputs, FP32 accumulate */
 #define DP_MIX_FP16 2 /* same with FP16 inputs */
+/* The paper's own recipes (Evaluation section, accuracy: "MIX-fp32" and
+ * "MIX-fp16"; Computation Optimization section, mixed precision): */
+#define DP_MIX_FP32 3      /* embedding and fitting nets in FP32 (FP32 matrix-core products, FP32 tanh) */
+#define DP_MIX_FP16_FIT1 4 /* as DP_MIX_FP32, with the first fitting layer's products in FP16 */
 
 /* Model hyper-parameters (Evaluation section: cut-offs, sel, fitting widths).
  *   emb[0..n_emb)  embedding widths, input width 1; layer l adds an identity

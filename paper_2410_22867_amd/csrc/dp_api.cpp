@@ -195,8 +195,8 @@ int upload_vec(T** dst, const std::vector<T>& v, const char* what) {
 void free_model(dp_model* m) {
   if (!m) return;
   void* ptrs[] = {m->params, m->emb_vec64, m->emb_vec32, m->emb_frag64, m->emb_vec64d, m->emb_frag64d,
-                  m->emb_frag_bf16, m->emb_frag_f16,
-                  m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_vec64, m->fit_vec32};
+                  m->emb_frag_bf16, m->emb_frag_f16, m->emb_frag_f32,
+                  m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, m->fit_vec64, m->fit_vec32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < m->n_maps; ++k)
@@ -367,8 +367,10 @@ int build_maps(dp_model* m) {
       {&ev, (void**)&m->emb_vec64, 0, 8},      {&ev, (void**)&m->emb_vec32, 1, 4},
       {&e64, (void**)&m->emb_frag64, 0, 8},    {&evd, (void**)&m->emb_vec64d, 0, 8},
       {&e64d, (void**)&m->emb_frag64d, 0, 8},  {&e32, (void**)&m->emb_frag_bf16, 2, 2},
-      {&e32, (void**)&m->emb_frag_f16, 3, 2},  {&f64v, (void**)&m->fit_frag64, 0, 8},
+      {&e32, (void**)&m->emb_frag_f16, 3, 2},  {&e32, (void**)&m->emb_frag_f32, 1, 4},
+      {&f64v, (void**)&m->fit_frag64, 0, 8},
       {&f32v, (void**)&m->fit_frag_bf16, 2, 2}, {&f32v, (void**)&m->fit_frag_f16, 3, 2},
+      {&f32v, (void**)&m->fit_frag_f32, 1, 4},
       {&fv, (void**)&m->fit_vec64, 0, 8},      {&fv, (void**)&m->fit_vec32, 1, 4},
   };
   const Map* uploaded[16];
@@ -510,8 +512,8 @@ struct StageScope {
 };
 
 int check_mode(int32_t mode) {
-  if (mode != DP_FP64 && mode != DP_MIX_BF16 && mode != DP_MIX_FP16) {
-    set_error("mode %d is not DP_FP64/DP_MIX_BF16/DP_MIX_FP16", mode);
+  if (mode < DP_FP64 || mode > DP_MIX_FP16_FIT1) {
+    set_error("mode %d is not one of DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32, DP_MIX_FP16_FIT1", mode);
     return DP_ERR_BAD_ARG;
   }
   return DP_OK;
@@ -1165,18 +1167,20 @@ int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipS
     // mixed: the layer inputs, deltas and g_T of the mixed-precision passes,
     // widened to FP64 into buffers the force path no longer needs; the
     // weight-gradient reductions then run in FP64
-    const int lp = c->mode_last == DP_MIX_BF16 ? 1 : 2;
+    // launch_widen kinds: 0 FP32, 1 BF16, 2 FP16
+    const MixKinds mk = mix_kinds(c->mode_last);
+    const int k1 = mk.fit1 == 3 ? 0 : mk.fit1, k23 = mk.fit23 == 3 ? 0 : mk.fit23;
     const int64_t cols = c->natoms_last + (int64_t)m->desc.ntypes * kColPad;
     double* D64 = (double*)c->dD;
     double* f64[6] = {(double*)c->fa[1], (double*)c->fa[3], (double*)c->fa[10],
                       (double*)c->fa[11], (double*)c->fa[5], (double*)c->fa[6]};
-    launch_widen(c->D, lp, nd, D64, nd, nd, cols, stream);
+    launch_widen(c->D, k1, nd, D64, nd, nd, cols, stream);
     launch_widen(c->fa[0], 0, fwp, f64[0], fw, fw, cols, stream);  // h1
     launch_widen(c->fa[2], 0, fwp, f64[1], fw, fw, cols, stream);  // h2
     launch_widen(c->fa[4], 0, fwp, f64[2], fw, fw, cols, stream);  // h3
-    launch_widen(c->fa[9], lp, fwp, f64[3], fw, fw, cols, stream);  // dz1
-    launch_widen(c->fa[8], lp, fwp, f64[4], fw, fw, cols, stream);  // dz2
-    launch_widen(c->fa[7], lp, fwp, f64[5], fw, fw, cols, stream);  // dz3
+    launch_widen(c->fa[9], k1, fwp, f64[3], fw, fw, cols, stream);  // dz1
+    launch_widen(c->fa[8], k23, fwp, f64[4], fw, fw, cols, stream);  // dz2
+    launch_widen(c->fa[7], k23, fwp, f64[5], fw, fw, cols, stream);  // dz3
     double* gT64 = (double*)c->Tpart;
     launch_widen(c->gT, 0, m->m1 * 4, gT64, m->m1 * 4, m->m1 * 4, cols, stream);
     in.X[0] = D64;

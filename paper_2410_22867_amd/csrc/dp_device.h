@@ -13,6 +13,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
 // MFMA operand layouts on gfx950 (wave64; measured):
@@ -33,8 +34,18 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Precision traits of the mixed forms.  vec8 is the 8-element operand of
+// one 16x16x32 product; store_t the element type operands are kept in (in
+// HBM and LDS), raw8 / raw4 vectors of 8 / 4 of them.  kind: 1 BF16, 2 FP16,
+// 3 FP32 (the FP32 form issues the same 16x16x32 product as eight 16x16x4
+// FP32 products, element j of both operands in product j: lane group g
+// holds k = 8g + j in both layouts, so the sum over j is the full product).
 struct PrecBF16 {
   typedef bf16x8 vec8;
+  typedef uint16_t store_t;
+  typedef u16x8 raw8;
+  typedef u16x4 raw4;
+  static constexpr int kind = 1;
   static __device__ __forceinline__ f4 mfma(vec8 a, vec8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -49,6 +60,10 @@ struct PrecBF16 {
 
 struct PrecF16 {
   typedef h16x8 vec8;
+  typedef uint16_t store_t;
+  typedef u16x8 raw8;
+  typedef u16x4 raw4;
+  static constexpr int kind = 2;
   static __device__ __forceinline__ f4 mfma(vec8 a, vec8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
@@ -61,19 +76,66 @@ struct PrecF16 {
   }
 };
 
+struct PrecF32 {
+  typedef f32x8 vec8;
+  typedef float store_t;
+  typedef f32x8 raw8;
+  typedef f4 raw4;
+  static constexpr int kind = 3;
+  static __device__ __forceinline__ f4 mfma(vec8 a, vec8 b, f4 c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+    return c;
+  }
+  static __device__ __forceinline__ float bits(float x) { return x; }
+  static __device__ __forceinline__ float tof(float b) { return b; }
+};
+
 // Packs 8 floats into the 8-element operand of a 16x16x32 MFMA.
 template <class P>
 __device__ __forceinline__ typename P::vec8 pack8(const float* x) {
-  u16x8 u;
+  if constexpr (P::kind == 3) {
+    return f32x8{x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7]};
+  } else {
+    u16x8 u;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) u[j] = P::bits(x[j]);
+    for (int j = 0; j < 8; ++j) u[j] = P::bits(x[j]);
+    return __builtin_bit_cast(typename P::vec8, u);
+  }
+}
+
+template <class P>
+__device__ __forceinline__ typename P::vec8 load8(const typename P::store_t* p) {
+  typename P::raw8 u = *reinterpret_cast<const typename P::raw8*>(p);
   return __builtin_bit_cast(typename P::vec8, u);
 }
 
 template <class P>
-__device__ __forceinline__ typename P::vec8 load8(const uint16_t* p) {
-  u16x8 u = *reinterpret_cast<const u16x8*>(p);
-  return __builtin_bit_cast(typename P::vec8, u);
+__device__ __forceinline__ typename P::raw8 zero8() {
+  typename P::raw8 z;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) z[j] = 0;
+  return z;
+}
+
+template <class P>
+__device__ __forceinline__ typename P::raw8 join8(typename P::raw4 lo, typename P::raw4 hi) {
+  typename P::raw8 z;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    z[j] = lo[j];
+    z[4 + j] = hi[j];
+  }
+  return z;
+}
+
+// Stores 4 floats in the trait's element type.
+template <class P>
+__device__ __forceinline__ void store4(typename P::store_t* p, const float* v) {
+  typename P::raw4 u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) u[j] = P::bits(v[j]);
+  *reinterpret_cast<typename P::raw4*>(p) = u;
 }
 
 // ---------------------------------------------------------------------------

@@ -55,6 +55,25 @@ struct ParamMap {
   void* dst;
 };
 
+// Element kinds of the matrix stages of a mixed mode (1 BF16, 2 FP16,
+// 3 FP32): the embedding nets, the first fitting layer (forward GEMM and
+// its backward GEMM, hence D and dz1), the fitting layer pairs 2-3.
+struct MixKinds {
+  int emb, fit1, fit23;
+};
+inline MixKinds mix_kinds(int mode) {
+  switch (mode) {
+    case DP_MIX_BF16: return {1, 1, 1};
+    case DP_MIX_FP16: return {2, 2, 2};
+    case DP_MIX_FP32: return {3, 3, 3};
+    default: return {3, 2, 3};  // DP_MIX_FP16_FIT1
+  }
+}
+template <class T16, class T32>
+inline const void* frag_of(const T16* bf, const T16* hf, const T32* f32, int kind) {
+  return kind == 1 ? (const void*)bf : (kind == 2 ? (const void*)hf : (const void*)f32);
+}
+
 }  // namespace dpse
 
 struct dp_model {
@@ -84,11 +103,13 @@ struct dp_model {
   double* emb_frag64d;
   uint16_t* emb_frag_bf16;
   uint16_t* emb_frag_f16;
+  float* emb_frag_f32;
   dpse::EmbFragOffsets efo;
   // fitting
   double* fit_frag64;
   uint16_t* fit_frag_bf16;
   uint16_t* fit_frag_f16;
+  float* fit_frag_f32;
   dpse::FitFragOffsets ffo;     // FP64 fragment offsets
   dpse::FitFragOffsets ffo_lp;  // BF16/FP16 fragment offsets (K padded to 32)
   // flat-parameter offsets used by the gradient kernels

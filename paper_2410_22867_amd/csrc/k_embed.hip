@@ -44,7 +44,7 @@ struct EmbArgs {
   const double* R;
   const int32_t* nnei;
   const double* frag64;
-  const uint16_t* fraglp;
+  const void* fraglp;     // mixed forms: fragments in the form's element type
   const double* vec64;
   const float* vec32;
   int64_t vec_per_net;
@@ -532,16 +532,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
-  __shared__ __attribute__((aligned(16))) uint16_t fr[NF2 + NF3];
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  __shared__ __attribute__((aligned(16))) ST fr[NF2 + NF3];
   __shared__ float h2s[WPB][16][kP2 + 1];
   __shared__ float vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
-    const uint16_t* src = A.fraglp + net * A.fo.per_net;
+    const ST* src = reinterpret_cast<const ST*>(A.fraglp) + net * A.fo.per_net;
     for (int k = threadIdx.x; k < NF2 / 8; k += 64 * WPB)
-      reinterpret_cast<u16x8*>(fr)[k] = reinterpret_cast<const u16x8*>(src + A.fo.F2)[k];
+      reinterpret_cast<R8*>(fr)[k] = reinterpret_cast<const R8*>(src + A.fo.F2)[k];
     for (int k = threadIdx.x; k < NF3 / 8; k += 64 * WPB)
-      reinterpret_cast<u16x8*>(fr + NF2)[k] = reinterpret_cast<const u16x8*>(src + A.fo.F3n)[k];
+      reinterpret_cast<R8*>(fr + NF2)[k] = reinterpret_cast<const R8*>(src + A.fo.F3n)[k];
   }
   __syncthreads();
   {
@@ -661,18 +663,20 @@ template <class P, int W, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
-  __shared__ __attribute__((aligned(16))) uint16_t fr[NFR];
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  __shared__ __attribute__((aligned(16))) ST fr[NFR];
   __shared__ f4 gts[WPB][kP3];
   __shared__ float vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
-    const uint16_t* src = A.fraglp + net * A.fo.per_net;
+    const ST* src = reinterpret_cast<const ST*>(A.fraglp) + net * A.fo.per_net;
     const int64_t offs[4] = {A.fo.F2, A.fo.F3t, A.fo.B3, A.fo.B2};
     const int lens[4] = {2048, 8192, 8192, 2048};
     int dst = 0;
     for (int b = 0; b < 4; ++b) {
       for (int k = threadIdx.x; k < lens[b] / 8; k += 64 * WPB)
-        reinterpret_cast<u16x8*>(fr + dst)[k] = reinterpret_cast<const u16x8*>(src + offs[b])[k];
+        reinterpret_cast<R8*>(fr + dst)[k] = reinterpret_cast<const R8*>(src + offs[b])[k];
       dst += lens[b];
     }
   }
@@ -844,7 +848,7 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
   A.R = c->R;
   A.nnei = c->nnei;
   A.frag64 = m->emb_frag64d;
-  A.fraglp = mode == DP_MIX_FP16 ? m->emb_frag_f16 : m->emb_frag_bf16;
+  A.fraglp = mode == DP_FP64 ? nullptr : frag_of(m->emb_frag_bf16, m->emb_frag_f16, m->emb_frag_f32, mix_kinds(mode).emb);
   A.vec64 = m->emb_vec64d;
   A.vec32 = m->emb_vec32;
   A.vec_per_net = m->emb_vec_per_net;
@@ -880,21 +884,32 @@ static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, 
   else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
 }
 
+template <class P, int W>
+static void launch_embed_lp(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, hipStream_t s) {
+  if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<P, W, kWPBlp>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_embed_fwd_lp<P, W, kWPBlp>), grid, block, 0, s, A);
+}
+
+// Resident work-groups per CU: FP64 one 8-wave group; the 16-bit forms
+// three 4-wave groups; the FP32 form holds its fragments in twice the LDS
+// (forward 55 KB: two groups; backward 90 KB: one).
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int wpb = mode == DP_FP64 ? kWPB64 : kWPBlp;
   EmbArgs A = emb_args(c, mode);
-  dim3 grid(emb_groups(c, wpb, mode == DP_FP64 ? 1 : 3), (unsigned)(A.ntypes * A.ntypes));
+  const int kind = mode == DP_FP64 ? 0 : mix_kinds(mode).emb;
+  const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : 3);
+  dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)(A.ntypes * A.ntypes));
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
     if (A.act) launch_embed_f64<W, true>(bwd, grid, block, A, s);
     else launch_embed_f64<W, false>(bwd, grid, block, A, s);
-  } else if (mode == DP_MIX_BF16) {
-    if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_embed_fwd_lp<PrecBF16, W, kWPBlp>), grid, block, 0, s, A);
+  } else if (kind == 1) {
+    launch_embed_lp<PrecBF16, W>(bwd, grid, block, A, s);
+  } else if (kind == 2) {
+    launch_embed_lp<PrecF16, W>(bwd, grid, block, A, s);
   } else {
-    if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<PrecF16, W, kWPBlp>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_embed_fwd_lp<PrecF16, W, kWPBlp>), grid, block, 0, s, A);
+    launch_embed_lp<PrecF32, W>(bwd, grid, block, A, s);
   }
 }
 

@@ -353,12 +353,6 @@ static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t 
 }
 
 // ---------------------------------------------------------------- mixed GEMM
-template <class P>
-__device__ __forceinline__ void store4lp(uint16_t* p, const float* v) {
-  u16x4 u = {P::bits(v[0]), P::bits(v[1]), P::bits(v[2]), P::bits(v[3])};
-  *reinterpret_cast<u16x4*>(p) = u;
-}
-
 // Epilogue of one 16x16 output tile row group: lane holds features m0..m0+3
 // of column col.
 template <class P>
@@ -385,8 +379,11 @@ template <class P, int MTW, int NTW, int PF>
 __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   constexpr int MB = 2 * MTW, NB = 2 * NTW;  // m-tiles, n-tiles per work-group
   constexpr int BN = 16 * NB;
-  __shared__ __attribute__((aligned(16))) uint16_t as[2][MB * 512];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[2][NB * 512];
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  typedef typename P::raw4 R4;
+  __shared__ __attribute__((aligned(16))) ST as[2][MB * 512];
+  __shared__ __attribute__((aligned(16))) ST xs[2][NB * 512];
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
   const int c0 = blockIdx.x * BN;
@@ -398,8 +395,8 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   const int mtiles = g.M / 16;
   const int mb0 = blockIdx.y * MB;
   const int KT = g.K / 32;
-  const uint16_t* Afr = reinterpret_cast<const uint16_t*>(g.Afr) + t * g.a_type_stride;
-  const uint16_t* X = reinterpret_cast<const uint16_t*>(g.X);
+  const ST* Afr = reinterpret_cast<const ST*>(g.Afr) + t * g.a_type_stride;
+  const ST* X = reinterpret_cast<const ST*>(g.X);
   // weight copy: MB fragments of 64 lanes x 16 B per k-step; thread tid
   // moves lane tid % 64 of fragments tid / 64 + 4u
   constexpr int AU = (MB + 3) / 4;
@@ -417,26 +414,32 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   const int fA = tid >> 6;
   const int mA = min(mb0 + fA, mtiles - 1);
   const int colX = tid >> 2, qX = tid & 3;
-  const uint16_t* aSrc = Afr + ((int64_t)mA * KT * 64 + lane) * 8;
-  const uint16_t* xSrc = X + (int64_t)(cb + c0 + colX) * g.ldx + 8 * qX;
-  auto load = [&](int kt, u16x8& av, u16x8& xv) {
-    av = *reinterpret_cast<const u16x8*>(aSrc + (int64_t)kt * 512);
-    xv = *reinterpret_cast<const u16x8*>(xSrc + 32 * kt);
+  const ST* aSrc = Afr + ((int64_t)mA * KT * 64 + lane) * 8;
+  const ST* xSrc = X + (int64_t)(cb + c0 + colX) * g.ldx + 8 * qX;
+  auto load = [&](int kt, R8& av, R8& xv) {
+    av = *reinterpret_cast<const R8*>(aSrc + (int64_t)kt * 512);
+    xv = *reinterpret_cast<const R8*>(xSrc + 32 * kt);
   };
-  auto store = [&](int buf, int kt, const u16x8& av, u16x8 xv) {
+  auto store = [&](int buf, int kt, const R8& av, R8 xv) {
     // the padded upper half of the last k-step may hold stale bits: zeros
-    if (!(qX < 2 || 32 * kt + 16 < g.Kreal)) xv = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    if (fA < MB) *reinterpret_cast<u16x8*>(&as[buf][(fA * 64 + lane) * 8]) = av;
+    if (!(qX < 2 || 32 * kt + 16 < g.Kreal)) xv = zero8<P>();
+    if (fA < MB) *reinterpret_cast<R8*>(&as[buf][(fA * 64 + lane) * 8]) = av;
     const int d0 = (((colX >> 4) * 64 + 32 * (qX & 1) + (colX & 15)) * 8) + 4 * (qX >> 1);
-    *reinterpret_cast<u16x4*>(&xs[buf][d0]) = u16x4{xv[0], xv[1], xv[2], xv[3]};
-    *reinterpret_cast<u16x4*>(&xs[buf][d0 + 128]) = u16x4{xv[4], xv[5], xv[6], xv[7]};
+    R4 lo, hi;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      lo[j] = xv[j];
+      hi[j] = xv[4 + j];
+    }
+    *reinterpret_cast<R4*>(&xs[buf][d0]) = lo;
+    *reinterpret_cast<R4*>(&xs[buf][d0 + 128]) = hi;
   };
   f4 acc[MTW][NTW];
 #pragma unroll
   for (int a = 0; a < MTW; ++a)
 #pragma unroll
     for (int b = 0; b < NTW; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  u16x8 ar[PF], xr[PF];
+  R8 ar[PF], xr[PF];
 #pragma unroll
   for (int d = 0; d < PF; ++d)
     if (d < KT) load(d, ar[d], xr[d]);
@@ -449,11 +452,11 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   auto iter = [&](int kt, int d) {
     const int buf = kt & 1;
     load(min(kt + PF, KT - 1), ar[d], xr[d]);
-    u16x8 aa[MTW], bb[NTW];
+    R8 aa[MTW], bb[NTW];
 #pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) aa[mt] = *reinterpret_cast<const u16x8*>(&as[buf][((wm * MTW + mt) * 64 + lane) * 8]);
+    for (int mt = 0; mt < MTW; ++mt) aa[mt] = *reinterpret_cast<const R8*>(&as[buf][((wm * MTW + mt) * 64 + lane) * 8]);
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) bb[nt] = *reinterpret_cast<const u16x8*>(&xs[buf][((wn * NTW + nt) * 64 + lane) * 8]);
+    for (int nt = 0; nt < NTW; ++nt) bb[nt] = *reinterpret_cast<const R8*>(&xs[buf][((wn * NTW + nt) * 64 + lane) * 8]);
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
@@ -496,24 +499,29 @@ struct PairArgsLp {
   const int32_t* meta;
   const int32_t* atom_at;
   int fw, fwp;
-  const void* in;          // forward: h1 (FP32, ld fwp); backward: dz3 (half, ld fwp)
-  const uint16_t* A[2];    // fragments of the first and second layer, type 0
+  const void* in;          // forward: h1 (FP32, ld fwp); backward: dz3 (the form's element type, ld fwp)
+  const void* A[2];        // fragments of the first and second layer, type 0
   int64_t a_type_stride;
   const float* vec;        // per-type fitting vectors (b1 b2 b3 wo | bo ebias)
   int64_t vec_type_stride;
   const float* tprev[2];   // backward: t2, t1 (FP32)
   float* out[3];           // forward: t2, h2, h3
-  uint16_t* outlp[2];      // forward: dz3; backward: dz2, dz1
+  void* outlp[2];          // forward: dz3; backward: dz2 (element type of P), dz1 (of PO)
   double* Ei_col;
   double* Ei_atom;
 };
 
-template <class P, bool BWD>
+// PO: element type of dz1, the X operand of the first layer's backward GEMM
+// (the same as P except in the paper's MIX-fp16 recipe).
+template <class P, class PO, bool BWD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_pair_lp(PairArgsLp p) {
   constexpr int NC = 16, NW = 4, MW = 4;
-  // forward: FP32 tile [16][fwp + 4]; backward: half tile [16][fwp + 8]
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  typedef typename P::raw4 R4;
+  // forward: FP32 tile [16][fwp + 4]; backward: tile of ST [16][fwp + 8]
   extern __shared__ __attribute__((aligned(16))) float hsf[];
-  uint16_t* const hsh = reinterpret_cast<uint16_t*>(hsf);
+  ST* const hsh = reinterpret_cast<ST*>(hsf);
   const int t = blockIdx.z;
   const int n_t = p.meta[2 * t], cb = p.meta[2 * t + 1];
   const int c0 = blockIdx.x * NC;
@@ -527,7 +535,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (int e = threadIdx.x; e < NC * fwp; e += 64 * NW) {
     const int c = e / fwp, k = e - c * fwp;
     const int64_t src = (int64_t)(cb + c0 + c) * fwp + k;
-    if constexpr (BWD) hsh[c * ldh + k] = k < fw ? reinterpret_cast<const uint16_t*>(p.in)[src] : (uint16_t)0;
+    if constexpr (BWD) hsh[c * ldh + k] = k < fw ? reinterpret_cast<const ST*>(p.in)[src] : (ST)0;
     else hsf[c * ldf + k] = k < fw ? reinterpret_cast<const float*>(p.in)[src] : 0.f;
   }
   bool own[MW];
@@ -540,21 +548,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // element v of m-tile slot j: feature 16 mtj[j] + 4 gq + v of column c0 + r16
   auto feat = [&](int j, int v) { return 16 * mtj[j] + 4 * gq + v; };
   f4 acc[MW];
-  auto layer = [&](const uint16_t* Afr) {
-    u16x8 aA[MW], aB[MW];
-    auto load = [&](int kt, u16x8* a) {
+  auto layer = [&](const ST* Afr) {
+    R8 aA[MW], aB[MW];
+    auto load = [&](int kt, R8* a) {
 #pragma unroll
       for (int j = 0; j < MW; ++j)
-        a[j] = *reinterpret_cast<const u16x8*>(Afr + (((int64_t)mtj[j] * KT + kt) * 64 + lane) * 8);
+        a[j] = *reinterpret_cast<const R8*>(Afr + (((int64_t)mtj[j] * KT + kt) * 64 + lane) * 8);
     };
-    auto step = [&](int kt, const u16x8* a) {
+    auto step = [&](int kt, const R8* a) {
       // B operand: features 32 kt + 4 gq + {0..3} and 32 kt + 16 + 4 gq + {0..3}
       typename P::vec8 x;
       if constexpr (BWD) {
-        const uint16_t* rowp = hsh + r16 * ldh + 32 * kt + 4 * gq;
-        const u16x4 lo = *reinterpret_cast<const u16x4*>(rowp);
-        const u16x4 hi = *reinterpret_cast<const u16x4*>(rowp + 16);
-        x = __builtin_bit_cast(typename P::vec8, u16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+        const ST* rowp = hsh + r16 * ldh + 32 * kt + 4 * gq;
+        const R4 lo = *reinterpret_cast<const R4*>(rowp);
+        const R4 hi = *reinterpret_cast<const R4*>(rowp + 16);
+        x = __builtin_bit_cast(typename P::vec8, join8<P>(lo, hi));
       } else {
         const float* rowp = hsf + r16 * ldf + 32 * kt + 4 * gq;
         const f4 lo = *reinterpret_cast<const f4*>(rowp);
@@ -575,10 +583,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     if (kt < KT) step(kt, aA);
   };
-  const uint16_t* A0 = p.A[0] + t * p.a_type_stride;
-  const uint16_t* A1 = p.A[1] + t * p.a_type_stride;
+  const ST* A0 = reinterpret_cast<const ST*>(p.A[0]) + t * p.a_type_stride;
+  const ST* A1 = reinterpret_cast<const ST*>(p.A[1]) + t * p.a_type_stride;
   if constexpr (!BWD) {
-    auto fwd_layer = [&](const uint16_t* Afr, int bias_off, auto last_tag) {
+    auto fwd_layer = [&](const ST* Afr, int bias_off, auto last_tag) {
       constexpr bool LAST = decltype(last_tag)::value;
 #pragma unroll
       for (int j = 0; j < MW; ++j)
@@ -608,7 +616,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           float dz[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) dz[v] = vec[3 * fw + m0 + v] * (1.f - tv[v] * tv[v]);
-          store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
+          store4<P>(reinterpret_cast<ST*>(p.outlp[0]) + col * fwp + m0, dz);
         }
       }
     };
@@ -655,8 +663,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       float dz[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
-      store4lp<P>(hsh + r16 * ldh + m0, dz);
-      if (p.outlp[0]) store4lp<P>(p.outlp[0] + col * fwp + m0, dz);
+      store4<P>(hsh + r16 * ldh + m0, dz);
+      if (p.outlp[0]) store4<P>(reinterpret_cast<ST*>(p.outlp[0]) + col * fwp + m0, dz);
     }
     load_t(p.tprev[1]);
     __syncthreads();
@@ -668,23 +676,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       float dz[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
-      store4lp<P>(p.outlp[1] + col * fwp + m0, dz);
+      store4<PO>(reinterpret_cast<typename PO::store_t*>(p.outlp[1]) + col * fwp + m0, dz);
     }
   }
 }
 
+template <class P, class PO>
+static void launch_pair_lp_t(bool bwd, dim3 grid, size_t lds, const PairArgsLp& p, hipStream_t s) {
+  if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<P, PO, true>), grid, dim3(256), lds, s, p);
+  else hipLaunchKernelGGL((k_fit_pair_lp<P, P, false>), grid, dim3(256), lds, s, p);
+}
+
 static void launch_pair_lp(dp_ctx* c, bool bwd, int mode, const PairArgsLp& p, hipStream_t s) {
   const dp_model* m = c->model;
+  const MixKinds mk = mix_kinds(mode);
   dim3 grid((unsigned)((c->natoms_last + 15) / 16), 1, (unsigned)m->desc.ntypes);
-  const size_t lds = bwd ? (size_t)16 * (p.fwp + 8) * 2 : (size_t)16 * (p.fwp + 4) * 4;
+  const size_t esz = mk.fit23 == 3 ? 4 : 2;
+  const size_t lds = bwd ? (size_t)16 * (p.fwp + 8) * esz : (size_t)16 * (p.fwp + 4) * 4;
   if (grid.x == 0) return;
-  if (mode == DP_MIX_BF16) {
-    if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<PrecBF16, true>), grid, dim3(256), lds, s, p);
-    else hipLaunchKernelGGL((k_fit_pair_lp<PrecBF16, false>), grid, dim3(256), lds, s, p);
-  } else {
-    if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<PrecF16, true>), grid, dim3(256), lds, s, p);
-    else hipLaunchKernelGGL((k_fit_pair_lp<PrecF16, false>), grid, dim3(256), lds, s, p);
-  }
+  if (mk.fit23 == 1) launch_pair_lp_t<PrecBF16, PrecBF16>(bwd, grid, lds, p, s);
+  else if (mk.fit23 == 2) launch_pair_lp_t<PrecF16, PrecF16>(bwd, grid, lds, p, s);
+  else if (mk.fit1 == 2) launch_pair_lp_t<PrecF32, PrecF16>(bwd, grid, lds, p, s);
+  else launch_pair_lp_t<PrecF32, PrecF32>(bwd, grid, lds, p, s);
 }
 
 // ---------------------------------------------------------------- descriptor
@@ -724,7 +737,7 @@ __global__ __launch_bounds__(128) void k_descriptor(const int32_t* __restrict__ 
     if constexpr (sizeof(DT) == 2) {
       out[e] = mode_lp_f16 ? PrecF16::bits((float)acc) : PrecBF16::bits((float)acc);
     } else {
-      out[e] = (DT)acc;
+      out[e] = (DT)acc;  // FP64, or FP32 for an FP32 first fitting layer
     }
   }
 }
@@ -776,6 +789,12 @@ __global__ __launch_bounds__(128) void k_desc_bwd(const int32_t* __restrict__ at
 }
 
 // ---------------------------------------------------------------- launchers
+// Pointer to element `off` of a fragment array of element kind (1, 2: 2 B;
+// 3: 4 B).
+static const void* elem_offset(const void* base, int kind, int64_t off) {
+  return kind == 3 ? (const void*)((const float*)base + off) : (const void*)((const uint16_t*)base + off);
+}
+
 // Activation buffer slots in dp_ctx::fa (FP64 / mixed):
 //   FP64 : 0 t1(=h1) 1 t2 2 h2 4 h3 5 dz3 7 dz2 8 dz1 [cols][fw]
 //   mixed: 0 t1 1 t2 2 h2 4 h3 (f32 [cols][fwp]); 7 dz3 8 dz2 9 dz1 (half
@@ -794,8 +813,15 @@ static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
   else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
 }
 
+template <class P, int MTW, int NTW>
+static void gemm_launch_lp_t(dim3 grid, bool deep, const GemmArgs& g, hipStream_t s) {
+  if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
+}
+
+// kind: element kind of the first fitting layer (the only GEMM launched here)
 template <int MTW, int NTW>
-static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
+static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int kind, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 32 * NTW;
   const int mtiles = g.M / 16;
@@ -803,13 +829,9 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
             (unsigned)ntypes);
   if (grid.x == 0) return;
   const bool deep = g.K / 32 >= 16;
-  if (mode == DP_MIX_BF16) {
-    if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fit_gemm_lp<PrecBF16, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
-  } else {
-    if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fit_gemm_lp<PrecF16, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
-  }
+  if (kind == 1) gemm_launch_lp_t<PrecBF16, MTW, NTW>(grid, deep, g, s);
+  else if (kind == 2) gemm_launch_lp_t<PrecF16, MTW, NTW>(grid, deep, g, s);
+  else gemm_launch_lp_t<PrecF32, MTW, NTW>(grid, deep, g, s);
 }
 
 // Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
@@ -818,7 +840,7 @@ static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s
 // tile would cross the 128-column type segments); the half-precision GEMM
 // 2x2 per wave (64 x 64 per work-group).
 static void gemm_launch(dp_ctx* c, const GemmArgs& g, int mode, hipStream_t s) {
-  if (mode != DP_FP64) gemm_launch_lp<2, 2>(c, g, mode, s);
+  if (mode != DP_FP64) gemm_launch_lp<2, 2>(c, g, mix_kinds(mode).fit1, s);
   else gemm_launch_f64<3, 2>(c, g, s);
 }
 
@@ -842,10 +864,13 @@ void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s) 
     hipLaunchKernelGGL((k_descriptor<double, double>), dim3(ncols), dim3(128), 0, s, c->atom_at,
                        (const double*)c->Tpart, ts, m->desc.ntypes, (double*)c->T,
                        write_d ? (double*)c->D : (double*)nullptr, m->m1, 0);
+  else if (mix_kinds(mode).fit1 == 3)
+    hipLaunchKernelGGL((k_descriptor<float, float>), dim3(ncols), dim3(128), 0, s, c->atom_at,
+                       (const float*)c->Tpart, ts, m->desc.ntypes, (float*)c->T, (float*)c->D, m->m1, 0);
   else
     hipLaunchKernelGGL((k_descriptor<float, uint16_t>), dim3(ncols), dim3(128), 0, s, c->atom_at,
                        (const float*)c->Tpart, ts, m->desc.ntypes, (float*)c->T, (uint16_t*)c->D, m->m1,
-                       mode == DP_MIX_FP16 ? 1 : 0);
+                       mix_kinds(mode).fit1 == 2 ? 1 : 0);
 }
 
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
@@ -868,13 +893,14 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
   const int fwp = ((fw + 31) / 32) * 32;
   GemmArgs g = gemm_base(c, mode);
   const bool f64 = mode == DP_FP64;
-  const void* frag = f64 ? (const void*)m->fit_frag64
-                         : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
+  const MixKinds mk = mix_kinds(mode);
+  const void* frag1 = f64 ? (const void*)m->fit_frag64 : frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit1);
+  const void* frag = f64 ? (const void*)m->fit_frag64 : frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit23);
   const int64_t* off_fwd = f64 ? m->ffo.fwd : m->ffo_lp.fwd;
   const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
   // layer 1: X = D [cols][nd] (FP64: built from T inside the GEMM)
   g.a_type_stride = tstride;
-  g.Afr = f64 ? (const void*)((const double*)frag + off_fwd[0]) : (const void*)((const uint16_t*)frag + off_fwd[0]);
+  g.Afr = f64 ? (const void*)((const double*)frag1 + off_fwd[0]) : elem_offset(frag1, mk.fit1, off_fwd[0]);
   g.X = c->D;
   g.ldx = m->nd;
   g.K = m->nd;
@@ -913,15 +939,15 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
     p.fw = fw;
     p.fwp = fwp;
     p.in = c->fa[0];
-    p.A[0] = (const uint16_t*)frag + off_fwd[1];
-    p.A[1] = (const uint16_t*)frag + off_fwd[2];
+    p.A[0] = elem_offset(frag, mk.fit23, off_fwd[1]);
+    p.A[1] = elem_offset(frag, mk.fit23, off_fwd[2]);
     p.a_type_stride = tstride;
     p.vec = m->fit_vec32;
     p.vec_type_stride = m->fit_vec_per_type;
     p.out[0] = (float*)c->fa[1];
     p.out[1] = keep_h ? (float*)c->fa[2] : nullptr;
     p.out[2] = keep_h ? (float*)c->fa[4] : nullptr;
-    p.outlp[0] = (uint16_t*)c->fa[7];
+    p.outlp[0] = c->fa[7];
     p.Ei_col = c->Ei_col;
     p.Ei_atom = c->Ei_atom;
     launch_pair_lp(c, false, mode, p, s);
@@ -935,8 +961,9 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s) 
   const int fw = m->fw;
   const int fwp = ((fw + 31) / 32) * 32;
   const bool f64 = mode == DP_FP64;
-  const void* frag = f64 ? (const void*)m->fit_frag64
-                         : (const void*)(mode == DP_MIX_FP16 ? m->fit_frag_f16 : m->fit_frag_bf16);
+  const MixKinds mk = mix_kinds(mode);
+  const void* frag1 = f64 ? (const void*)m->fit_frag64 : frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit1);
+  const void* frag = f64 ? (const void*)m->fit_frag64 : frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit23);
   const int64_t* off_bwd = f64 ? m->ffo.bwd : m->ffo_lp.bwd;
   const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
   // layers 3 and 2: dh2 = w_out + W3 dz3, dz2 = dh2 (1 - t2^2), dh1 = dh2 +
@@ -962,21 +989,21 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s) 
     p.fw = fw;
     p.fwp = fwp;
     p.in = c->fa[7];
-    p.A[0] = (const uint16_t*)frag + off_bwd[2];
-    p.A[1] = (const uint16_t*)frag + off_bwd[1];
+    p.A[0] = elem_offset(frag, mk.fit23, off_bwd[2]);
+    p.A[1] = elem_offset(frag, mk.fit23, off_bwd[1]);
     p.a_type_stride = tstride;
     p.vec = m->fit_vec32;
     p.vec_type_stride = m->fit_vec_per_type;
     p.tprev[0] = (const float*)c->fa[1];
     p.tprev[1] = (const float*)c->fa[0];
-    p.outlp[0] = keep_dz2 ? (uint16_t*)c->fa[8] : nullptr;
-    p.outlp[1] = (uint16_t*)c->fa[9];
+    p.outlp[0] = keep_dz2 ? c->fa[8] : nullptr;
+    p.outlp[1] = c->fa[9];
     launch_pair_lp(c, true, mode, p, s);
   }
   // layer 1: dD = W1 dz1
   GemmArgs g = gemm_base(c, mode);
   g.a_type_stride = tstride;
-  g.Afr = f64 ? (const void*)((const double*)frag + off_bwd[0]) : (const void*)((const uint16_t*)frag + off_bwd[0]);
+  g.Afr = f64 ? (const void*)((const double*)frag1 + off_bwd[0]) : elem_offset(frag1, mk.fit1, off_bwd[0]);
   g.X = f64 ? c->fa[8] : c->fa[9];
   g.ldx = f64 ? fw : fwp;
   g.K = f64 ? fw : fwp;
@@ -1010,7 +1037,7 @@ void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, do
   const int width = which == 1 ? m->m1 * 4 : m->nd;
   const bool f64 = mode == DP_FP64;
   int kind_lp = 0;
-  if (!f64 && which == 2) kind_lp = mode == DP_MIX_FP16 ? 2 : 1;
+  if (!f64 && which == 2 && mix_kinds(mode).fit1 != 3) kind_lp = mix_kinds(mode).fit1;
   const int64_t tot = (int64_t)ntot * width;
   if (tot > 0)
     hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, c->col_of, src,

@@ -16,8 +16,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpse.so")
 
-DP_FP64, DP_MIX_BF16, DP_MIX_FP16 = 0, 1, 2
-MODES = {"fp64": DP_FP64, "bf16": DP_MIX_BF16, "fp16": DP_MIX_FP16}
+DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32, DP_MIX_FP16_FIT1 = 0, 1, 2, 3, 4
+# "mix_fp32" and "mix_fp16" are the paper's MIX-fp32 (both nets in FP32) and
+# MIX-fp16 (MIX-fp32 with the first fitting layer's products in FP16)
+MODES = {"fp64": DP_FP64, "bf16": DP_MIX_BF16, "fp16": DP_MIX_FP16, "mix_fp32": DP_MIX_FP32,
+         "mix_fp16": DP_MIX_FP16_FIT1}
 
 FLAG_NOT_WRAPPED, FLAG_OVERLAP, FLAG_NONFINITE, FLAG_CAND_CAPACITY, FLAG_SEL_OVERFLOW = 1, 2, 4, 8, 16
 FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED = 32, 64

@@ -148,7 +148,7 @@ def test_param_grads_finite_differences(batch):
     b["model"].set_params(b["p"])
 
 
-@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01)])
+@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01), ("mix_fp32", 1e-4), ("mix_fp16", 0.01)])
 def test_mixed_param_grads_close_to_oracle(batch, mode, tol):
     """Mixed-precision form of the training step: energies, forces and
     parameter gradients of the mixed model, compared with the FP64 oracle

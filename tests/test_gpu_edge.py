@@ -94,7 +94,7 @@ def _check_fp64(r, o, n):
     assert np.abs(r["W"].reshape(3, 3) - o["W"]).max() <= 1e-9
 
 
-@pytest.mark.parametrize("mode", ["fp64", "bf16", "fp16"])
+@pytest.mark.parametrize("mode", ["fp64", "bf16", "fp16", "mix_fp32", "mix_fp16"])
 def test_empty_frame(dev, water, mode):
     desc, p, model = water
     _say("empty frame", mode)
@@ -135,7 +135,7 @@ def test_dilute_frame_fp64(dev, water):
     assert r["status"] == 0
 
 
-@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01)])
+@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01), ("mix_fp32", 1e-5), ("mix_fp16", 0.01)])
 def test_dilute_frame_mixed(dev, water, mode, tol):
     desc, p, model = water
     fr = dilute_frame()
