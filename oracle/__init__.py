@@ -54,7 +54,11 @@ def lib():
         L.or_nlist.argtypes = [i64, P, P, P, P, P, P, i64, ctypes.c_int, P, P]
         L.or_nlist.restype = ctypes.c_int
         L.or_compute.argtypes = [i64, P, P, P, P, P, P, P, i64, P, P, P, P, P, P, ctypes.c_double,
-                                 P, P, P, P, P, P]
+                                 P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.or_tab_nint.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.or_tab_nint.restype = ctypes.c_int
+        L.or_tab_build.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.or_tab_build.restype = ctypes.c_int
         L.or_compute.restype = ctypes.c_int
         L.or_switch_fn.argtypes = [i64, P, ctypes.c_double, ctypes.c_double, P, P]
         L.or_switch_fn.restype = None
@@ -115,13 +119,31 @@ def nlist(coords, types, box, desc, rows: Optional[Sequence[int]] = None, use_ce
     return out, int(ov[0])
 
 
+def tabulate(desc, params, x1: float, x2: float, h: float) -> np.ndarray:
+    """DP-compress table of every embedding net: [ntypes^2, nint, 6, m1]
+    quintic coefficients on the grid (fine stride h on [0, x1), 10 h up to
+    x2; see dp_oracle.c)."""
+    i, d = desc_arrays(desc)
+    nint = int(lib().or_tab_nint(float(x1), float(x2), float(h)))
+    if nint <= 0:
+        raise ValueError("bad table grid")
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    out = np.empty((desc.ntypes ** 2, nint, 6, desc.m1), dtype=np.float64)
+    if lib().or_tab_build(_ptr(i), _ptr(d), _ptr(p), float(x1), float(x2), float(h), _ptr(out)) != 0:
+        raise ValueError("or_tab_build failed")
+    return out
+
+
 def compute(coords, types, box, desc, params, rows=None, nl=None, grad_scale: Optional[float] = None,
-            debug: bool = False, use_cells: bool = True):
+            debug: bool = False, use_cells: bool = True, table=None):
     """Energy, per-atom energies, forces [n,3], virial [3,3] of one frame.
 
     rows: centre atoms to evaluate (None: all).  With a subset, E and Ei cover
     only those atoms and F/W only their contributions.  grad_scale: if given,
-    also returns grad = grad_scale * dE/dtheta (flat parameter layout)."""
+    also returns grad = grad_scale * dE/dtheta (flat parameter layout).
+    table: (coefficients from tabulate(), x1, x2, h) to evaluate the
+    embedding nets from the DP-compress table instead; the result then also
+    holds "clipped", the count of inputs at or beyond the table's end."""
     x = np.ascontiguousarray(coords, dtype=np.float64)
     t = np.ascontiguousarray(types, dtype=np.int32)
     h = np.ascontiguousarray(box, dtype=np.float64).reshape(9)
@@ -144,14 +166,21 @@ def compute(coords, types, box, desc, params, rows=None, nl=None, grad_scale: Op
         dbg = dict(R=np.zeros((nrows, desc.nm, 4)), T=np.zeros((nrows, desc.m1, 4)),
                    D=np.zeros((nrows, desc.ndesc)), gD=np.zeros((nrows, desc.ndesc)),
                    gT=np.zeros((nrows, desc.m1, 4)), netd=np.zeros((nrows, desc.nm, 4)))
+    tab, tx1, tx2, th = (None, 0.0, 0.0, 0.0) if table is None else table
+    if tab is not None:
+        tab = np.ascontiguousarray(tab, dtype=np.float64)
+    nclip = np.zeros(1, dtype=np.int64)
     rc = lib().or_compute(n, _ptr(x), _ptr(t), _ptr(h), _ptr(i), _ptr(d), _ptr(p), _ptr(r), nrows, _ptr(nl),
                           _ptr(E), _ptr(Ei), _ptr(F), _ptr(W), _ptr(grad),
                           float(grad_scale) if grad_scale is not None else 0.0,
                           _ptr(dbg.get("R")), _ptr(dbg.get("T")), _ptr(dbg.get("D")), _ptr(dbg.get("gD")),
-                          _ptr(dbg.get("gT")), _ptr(dbg.get("netd")))
+                          _ptr(dbg.get("gT")), _ptr(dbg.get("netd")), _ptr(tab), float(tx1), float(tx2), float(th),
+                          _ptr(nclip))
     if rc != 0:
         raise ValueError("or_compute failed")
     out = dict(E=float(E[0]), Ei=Ei, F=F, W=W.reshape(3, 3), nlist=nl)
+    if table is not None:
+        out["clipped"] = int(nclip[0])
     if grad is not None:
         out["grad"] = grad
     out.update(dbg)

@@ -401,6 +401,151 @@ static void or_scratch_free(or_scratch* s) {
   free(s->tmp1); free(s->tmp2); free(s->tmp3);
 }
 
+/* ------------------------------------------------------------------------ */
+/* DP-compress (the compression of the embedding net cited in the Background
+ * section): each embedding net G(x) of one scalar input x = R~[0] is
+ * replaced by piecewise fifth-order polynomials in t = x - x_left on a grid
+ * of intervals; on each interval the quintic matches G, dG/dx and d2G/dx2 at
+ * both ends (Hermite interpolation).  Grid: a fine stride h on [0, X1)
+ * (n1 intervals, X1 = n1 h), a coarse stride H = 10 h on [X1, X2) (n2
+ * intervals); inputs at or beyond X2 take the value at X2 and are counted.
+ * Table layout: [net = ti*ntypes + tj][interval][power p = 0..5][feature]. */
+
+typedef struct {
+  double h, H, X1, X2;
+  int n1, n2, nint;
+} or_grid;
+
+static void or_grid_make(double x1, double x2, double h, or_grid* g) {
+  g->h = h;
+  g->H = h * 10.0;
+  g->n1 = (int)ceil(x1 / h);
+  g->X1 = (double)g->n1 * h;
+  g->n2 = x2 > g->X1 ? (int)ceil((x2 - g->X1) / g->H) : 0;
+  g->X2 = fma((double)g->n2, g->H, g->X1);
+  g->nint = g->n1 + g->n2;
+}
+
+int or_tab_nint(double x1, double x2, double h) {
+  or_grid g;
+  if (!(h > 0.0) || !(x1 > 0.0)) return -1;
+  or_grid_make(x1, x2, h, &g);
+  return g.nint;
+}
+
+/* Interval of input x and the offset t in it; *clip set when x >= X2. */
+static int or_interval(const or_grid* g, double x, double* t, int* clip) {
+  if (x < g->X1) {
+    int k = (int)floor(x / g->h);
+    if (k >= g->n1) k = g->n1 - 1;
+    if (k < 0) k = 0;
+    *t = fma(-(double)k, g->h, x);
+    return k;
+  }
+  if (x < g->X2) {
+    int m = (int)floor((x - g->X1) / g->H);
+    if (m >= g->n2) m = g->n2 - 1;
+    *t = fma(-(double)m, g->H, x - g->X1);
+    return g->n1 + m;
+  }
+  *clip = 1;
+  *t = g->n2 > 0 ? g->H : g->h;
+  return g->nint - 1;
+}
+
+/* G, dG/dx and d2G/dx2 of net (ti, tj) at input x, by forward-mode
+ * differentiation through the layers of or_dense_fwd: with z = h W + b,
+ * z' = h' W, z'' = h'' W and tau = tanh(z): tau' = (1 - tau^2) z',
+ * tau'' = (1 - tau^2) (z'' - 2 tau z'^2); the identity skips carry h, h', h''. */
+static void or_emb_derivs(const or_model* m, const double* P, int ti, int tj, double x, double* G, double* dG,
+                          double* d2G) {
+  double hv[OR_MAXL * 256], hd[OR_MAXL * 256], hdd[OR_MAXL * 256];
+  double in0 = x, in1 = 1.0, in2 = 0.0;
+  const double *pv = &in0, *pd = &in1, *pdd = &in2;
+  int wp = 1, off = 0;
+  for (int l = 0; l < m->nemb; l++) {
+    const int w = m->emb[l];
+    const double* W = P + m->emb_w[ti][tj][l];
+    const double* b = P + m->emb_b[ti][tj][l];
+    for (int q = 0; q < w; q++) {
+      double z = b[q], z1 = 0.0, z2 = 0.0;
+      for (int p = 0; p < wp; p++) {
+        z += pv[p] * W[(int64_t)p * w + q];
+        z1 += pd[p] * W[(int64_t)p * w + q];
+        z2 += pdd[p] * W[(int64_t)p * w + q];
+      }
+      const double tt = tanh(z);
+      const double g1 = 1.0 - tt * tt;
+      double v = tt, v1 = g1 * z1, v2 = g1 * (z2 - 2.0 * tt * z1 * z1);
+      if (w == wp) { v += pv[q]; v1 += pd[q]; v2 += pdd[q]; }
+      else if (w == 2 * wp) { v += pv[q % wp]; v1 += pd[q % wp]; v2 += pdd[q % wp]; }
+      hv[off + q] = v;
+      hd[off + q] = v1;
+      hdd[off + q] = v2;
+    }
+    pv = hv + off;
+    pd = hd + off;
+    pdd = hdd + off;
+    wp = w;
+    off += w;
+  }
+  for (int a = 0; a < m->m1; a++) {
+    G[a] = pv[a];
+    dG[a] = pd[a];
+    d2G[a] = pdd[a];
+  }
+}
+
+/* Quintic on [0, L] from value, first and second derivative at both ends:
+ * c0 = y0, c1 = d0, c2 = s0/2, and with A = y1 - y0 - d0 L - s0 L^2/2,
+ * B = d1 - d0 - s0 L, C = s1 - s0 the remaining three solve
+ * [L^3 L^4 L^5; 3L^2 4L^3 5L^4; 6L 12L^2 20L^3] c = [A B C]. */
+static void or_quintic(double L, double y0, double d0, double s0, double y1, double d1, double s1, double* c) {
+  const double A = y1 - y0 - d0 * L - 0.5 * s0 * L * L;
+  const double B = d1 - d0 - s0 * L;
+  const double C = s1 - s0;
+  c[0] = y0;
+  c[1] = d0;
+  c[2] = 0.5 * s0;
+  c[3] = (20.0 * A - 8.0 * B * L + C * L * L) / (2.0 * L * L * L);
+  c[4] = (-30.0 * A + 14.0 * B * L - 2.0 * C * L * L) / (2.0 * L * L * L * L);
+  c[5] = (12.0 * A - 6.0 * B * L + C * L * L) / (2.0 * L * L * L * L * L);
+}
+
+/* Builds the table of every net; table has ntypes^2 * nint * 6 * m1 values. */
+int or_tab_build(const int32_t* idesc, const double* ddesc, const double* P, double x1, double x2, double h,
+                 double* table) {
+  or_model m;
+  if (or_parse(idesc, ddesc, &m)) return -1;
+  if (!(h > 0.0) || !(x1 > 0.0) || m.m1 > 256) return -1;
+  or_grid g;
+  or_grid_make(x1, x2, h, &g);
+  const int nnets = m.ntypes * m.ntypes, m1 = m.m1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int job = 0; job < nnets * g.nint; job++) {
+    const int net = job / g.nint, k = job % g.nint;
+    const int ti = net / m.ntypes, tj = net % m.ntypes;
+    double xl, L;
+    if (k < g.n1) { xl = (double)k * g.h; L = g.h; }
+    else { xl = fma((double)(k - g.n1), g.H, g.X1); L = g.H; }
+    double G0[256], D0[256], S0[256], G1[256], D1[256], S1[256];
+    or_emb_derivs(&m, P, ti, tj, xl, G0, D0, S0);
+    or_emb_derivs(&m, P, ti, tj, xl + L, G1, D1, S1);
+    double* out = table + ((int64_t)net * g.nint + k) * 6 * m1;
+    for (int a = 0; a < m1; a++) {
+      double c[6];
+      or_quintic(L, G0[a], D0[a], S0[a], G1[a], D1[a], S1[a], c);
+      for (int q = 0; q < 6; q++) out[(int64_t)q * m1 + a] = c[q];
+    }
+  }
+  return 0;
+}
+
+typedef struct {
+  const double* table;  /* NULL: exact embedding nets */
+  or_grid g;
+} or_tab;
+
 /* Debug outputs for one atom (any may be NULL). */
 typedef struct {
   double* R;   /* nm x 4 */
@@ -415,7 +560,7 @@ typedef struct {
  * If grad != NULL, accumulates gscale * dE_i/dtheta into grad.            */
 static double or_atom(int64_t i, const double* x, const int32_t* type, const double* h, const or_model* m,
                       const double* P, const int32_t* row, or_scratch* S, double* g_rows, double* grad,
-                      double gscale, or_dbg* dbg) {
+                      double gscale, or_dbg* dbg, const or_tab* tab, int64_t* nclip) {
   const int nm = m->nm;
   const int ti = type[i];
   int sumw = 0;
@@ -458,12 +603,32 @@ static double or_atom(int64_t i, const double* x, const int32_t* type, const dou
     }
   }
 
-  /* embedding nets, G_ij = N_{ti,tj}(s_ij) */
+  /* embedding nets, G_ij = N_{ti,tj}(s_ij); tabulated: G and dG/dx from
+   * the interval's quintic (in the last layer's slots of act and tact) */
   for (int tj = 0; tj < m->ntypes; tj++) {
     for (int q = m->sec[tj]; q < m->sec[tj + 1]; q++) {
       if (row[q] < 0) continue;
       double* act = S->act + (int64_t)q * sumw;
       double* tac = S->tact + (int64_t)q * sumw;
+      if (tab->table) {
+        double t;
+        int clip = 0;
+        const int k = or_interval(&tab->g, S->R[4 * q], &t, &clip);
+        *nclip += clip;
+        const double* c = tab->table + ((int64_t)(ti * m->ntypes + tj) * tab->g.nint + k) * 6 * m->m1;
+        const int go = sumw - m->m1;
+        for (int a = 0; a < m->m1; a++) {
+          const double* ca = c + a;
+          const int64_t st = m->m1;
+          double v = ca[5 * st];
+          for (int p = 4; p >= 0; p--) v = fma(v, t, ca[p * st]);
+          double d = 5.0 * ca[5 * st];
+          for (int p = 4; p >= 1; p--) d = fma(d, t, (double)p * ca[p * st]);
+          act[go + a] = v;
+          tac[go + a] = clip ? 0.0 : d;
+        }
+        continue;
+      }
       double in0 = S->R[4 * q];
       const double* hp = &in0;
       int wp = 1, off = 0;
@@ -571,7 +736,11 @@ static double or_atom(int64_t i, const double* x, const int32_t* type, const dou
       }
       int off = goff;
       double ds = 0.0;
-      for (int l = m->nemb - 1; l >= 0; l--) {
+      if (tab->table) {
+        /* dE/dx = sum_a dE/dG_a dG_a/dx */
+        for (int a = 0; a < m->m1; a++) ds += dg[a] * tac[goff + a];
+      }
+      for (int l = tab->table ? -1 : m->nemb - 1; l >= 0; l--) {
         int win = l > 0 ? m->emb[l - 1] : 1;
         double in0 = R[0];
         const double* hin = l > 0 ? act + off - win : &in0;
@@ -613,9 +782,18 @@ static double or_atom(int64_t i, const double* x, const int32_t* type, const dou
 int or_compute(int64_t n, const double* x, const int32_t* type, const double* h, const int32_t* idesc,
                const double* ddesc, const double* params, const int64_t* rows, int64_t nrows,
                const int32_t* nlist, double* E, double* Ei, double* F, double* W, double* grad, double gscale,
-               double* dR, double* dT, double* dD, double* dgD, double* dgT, double* dnd) {
+               double* dR, double* dT, double* dD, double* dgD, double* dgT, double* dnd, const double* table,
+               double tab_x1, double tab_x2, double tab_h, int64_t* nclip) {
   or_model m;
   if (or_parse(idesc, ddesc, &m)) return -1;
+  or_tab tab;
+  memset(&tab, 0, sizeof(tab));
+  if (table) {
+    if (grad || !(tab_h > 0.0) || !(tab_x1 > 0.0)) return -1;  /* the tabulated model has no parameter gradient */
+    tab.table = table;
+    or_grid_make(tab_x1, tab_x2, tab_h, &tab.g);
+  }
+  int64_t clipped = 0;
   for (int64_t i = 0; i < n; i++)
     if (type[i] < 0 || type[i] >= m.ntypes) return -1;
   double* g_all = (double*)malloc(sizeof(double) * (size_t)(nrows > 0 ? nrows : 1) * m.nm * 3);
@@ -638,8 +816,13 @@ int or_compute(int64_t n, const double* x, const int32_t* type, const double* h,
       int64_t i = rows ? rows[r] : r;
       or_dbg dbg = {dR ? dR + r * m.nm * 4 : NULL, dT ? dT + r * m.m1 * 4 : NULL, dD ? dD + r * m.nd : NULL,
                     dgD ? dgD + r * m.nd : NULL, dgT ? dgT + r * m.m1 * 4 : NULL, dnd ? dnd + r * m.nm * 4 : NULL};
+      int64_t nc = 0;
       Ei[r] = or_atom(i, x, type, h, &m, params, nlist + r * m.nm, &S, g_all + r * m.nm * 3,
-                      grad ? gbuf + (size_t)tid * m.nparams : NULL, gscale, &dbg);
+                      grad ? gbuf + (size_t)tid * m.nparams : NULL, gscale, &dbg, &tab, &nc);
+      if (nc) {
+#pragma omp atomic
+        clipped += nc;
+      }
     }
     or_scratch_free(&S);
   }
@@ -680,6 +863,7 @@ int or_compute(int64_t n, const double* x, const int32_t* type, const double* h,
     free(gbuf);
   }
   free(g_all);
+  if (nclip) *nclip = clipped;
   return 0;
 }
 
