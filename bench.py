@@ -31,10 +31,11 @@ PEAK_FP32_TF = 157.3
 PEAK_HBM_GBS = 8000.0
 # element kinds of (embedding, first fitting layer, fitting layers 2-3) per
 # mode and the dense matrix peak of each kind (TFLOP/s)
-MODE_KINDS = {"fp64": (0, 0, 0), "bf16": (1, 1, 1), "fp16": (2, 2, 2), "mix_fp32": (3, 3, 3), "mix_fp16": (3, 2, 3)}
+MODE_KINDS = {"fp64": (0, 0, 0), "bf16": (1, 1, 1), "fp16": (2, 2, 2), "mix_fp32": (3, 3, 3), "mix_fp16": (3, 2, 3),
+              "fp64_tab": (0, 0, 0)}
 KIND_PEAK = {0: PEAK_FP64_TF, 1: PEAK_BF16_TF, 2: PEAK_BF16_TF, 3: PEAK_FP32_TF}
 TABLE2_NAMES = {"fp64": "Double", "mix_fp32": "MIX-fp32", "mix_fp16": "MIX-fp16", "bf16": "BF16 GEMMs",
-                "fp16": "FP16 GEMMs"}
+                "fp16": "FP16 GEMMs", "fp64_tab": "Double, tabulated embedding (DP-compress)"}
 
 
 def stage_peaks(desc, mode):
@@ -50,10 +51,13 @@ def stage_peaks(desc, mode):
             "desc_bwd": PEAK_FP64_TF if ke == 0 else PEAK_FP32_TF}
 
 
-def algorithmic_flops(desc, real_rows, natoms, stored=False):
+def algorithmic_flops(desc, real_rows, natoms, stored=False, tab=False):
     """Flops per launch of the matrix stages (real neighbour rows only).  The
     embedding backward recomputes layers 1-2 (and layer 3 unless its output
-    was stored by the forward), then back-propagates through all three."""
+    was stored by the forward), then back-propagates through all three.
+    Tabulated embedding (DP-compress): per row and feature a quintic (10) and
+    the contraction (8) forward; value and slope quintics (20), dE/dG (8),
+    the direct term (8) and the slope product (2) backward."""
     w1, fw, nd, m1 = desc.emb[0], desc.fit[0], desc.ndesc, desc.m1
     l12 = 2 * (w1 + desc.emb[0] * desc.emb[1])
     l3 = 2 * desc.emb[1] * desc.emb[2]
@@ -62,8 +66,8 @@ def algorithmic_flops(desc, real_rows, natoms, stored=False):
     fit_fwd = 2 * (nd * fw + 2 * fw * fw) + 2 * fw
     fit_bwd = 2 * (2 * fw * fw + fw * nd)
     return {
-        "embed_fwd": real_rows * (gemm_row + contr),
-        "embed_bwd": real_rows * ((l12 if stored else gemm_row) + gemm_row + 2 * contr),
+        "embed_fwd": real_rows * (m1 * 18 if tab else gemm_row + contr),
+        "embed_bwd": real_rows * (m1 * 38 if tab else (l12 if stored else gemm_row) + gemm_row + 2 * contr),
         "fit_fwd": natoms * fit_fwd,
         "fit_bwd": natoms * fit_bwd,
         "descriptor": natoms * 2 * m1 * desc.m2 * 4,
@@ -118,7 +122,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="water12k",
                     choices=["water192", "water12k", "copper32k", "water98k", "waterbatch64"])
-    ap.add_argument("--modes", default="fp64,bf16,fp16,mix_fp32,mix_fp16")
+    ap.add_argument("--modes", default="fp64,bf16,fp16,mix_fp32,mix_fp16,fp64_tab")
     ap.add_argument("--nve-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -153,6 +157,9 @@ def main():
     wl_index = {"water192": 0, "water12k": 1, "copper32k": 2, "water98k": 3}[args.workload]
     n = fr.n
     model = dpse.Model(desc, params)
+    grid = I.COMPRESS_GRID_COPPER if desc.ntypes == 1 else I.COMPRESS_GRID_WATER
+    if "fp64_tab" in modes:
+        model.compress(*grid)
     ctx = dpse.Context(model, n, budget_bytes=int(args.workspace_gib * 2 ** 30))
     activations = {}
     x0 = torch.tensor(fr.coords, device=dev)
@@ -323,7 +330,7 @@ def main():
     extra = {}
     for mode in modes:
         st = stages[mode]
-        fl_m = algorithmic_flops(desc, real_rows, n, stored=activations.get(mode) == "stored")
+        fl_m = algorithmic_flops(desc, real_rows, n, stored=activations.get(mode) == "stored", tab=mode == "fp64_tab")
         peaks = stage_peaks(desc, mode)
         mat = {k: fl_m[k] / (st[k][0] * 1e-3) / 1e12 for k in fl_m if st.get(k, (0, 0))[0] > 0}
         mem = {k: hbm[k] / (st[k][0] * 1e-3) / 1e9 for k in hbm if st.get(k, (0, 0))[0] > 0}
@@ -338,6 +345,9 @@ def main():
             "peak_TFLOPs": round(peak, 1) if peak else None,
             "matrix_stage_TFLOPs": {k: round(vv, 2) for k, vv in mat.items()},
             "hbm_stage_GBs": {k: round(vv, 1) for k, vv in mem.items()},
+            "table_read_GBs": ({k: round(real_rows * 6 * desc.m1 * 8 / (st[k][0] * 1e-3) / 1e9, 1)
+                                for k in ("embed_fwd", "embed_bwd") if st.get(k, (0, 0))[0] > 0}
+                               if mode == "fp64_tab" else None),
             "step_T_roof_ms": round(t_roof * 1e3, 4),
             "step_T_meas_ms": round(results[mode]["ms_per_step"], 4),
             "step_roof_frac": round(t_roof * 1e3 / results[mode]["ms_per_step"], 4),

@@ -36,9 +36,10 @@
  *              only the device can see (capacity, r = 0, non-finite energy,
  *              unwrapped coordinates) set bits in a device status word read
  *              by dp_ctx_status().
- *   memory     all device memory is allocated by dp_model_create and
- *              dp_ctx_create; no other call allocates (Computation
- *              Optimization section: memory is allocated at start-up).
+ *   memory     all device memory is allocated by dp_model_create,
+ *              dp_model_compress and dp_ctx_create (set-up calls); no other
+ *              call allocates (Computation Optimization section: memory is
+ *              allocated at start-up).
  */
 #ifndef DPSE_DP_H
 #define DPSE_DP_H
@@ -75,6 +76,7 @@ extern "C" {
 #define DP_FLAG_SEL_OVERFLOW 16 /* some section had more neighbours than sel (truncated) */
 #define DP_FLAG_BAD_INPUT 32    /* a type outside [0, ntypes) or a neighbour index >= n (ignored) */
 #define DP_FLAG_SKIN_EXCEEDED 64 /* an atom moved more than skin/2 since the Verlet build (list may miss pairs) */
+#define DP_FLAG_TABLE_RANGE 128  /* DP_FP64_TAB: an embedding input at or beyond the table's end (value held) */
 
 /* Precision modes (Computation Optimization section, mixed precision) */
 #define DP_FP64 0     /* everything in FP64 */
@@ -84,6 +86,10 @@ extern "C" {
  * "MIX-fp16"; Computation Optimization section, mixed precision): */
 #define DP_MIX_FP32 3      /* embedding and fitting nets in FP32 (FP32 matrix-core products, FP32 tanh) */
 #define DP_MIX_FP16_FIT1 4 /* as DP_MIX_FP32, with the first fitting layer's products in FP16 */
+/* FP64 with the embedding nets evaluated from the DP-compress table of
+ * dp_model_compress (Background section: the compression of the embedding
+ * net); energies, forces and virial only (no dp_backward_params). */
+#define DP_FP64_TAB 5
 
 /* Model hyper-parameters (Evaluation section: cut-offs, sel, fitting widths).
  *   emb[0..n_emb)  embedding widths, input width 1; layer l adds an identity
@@ -143,6 +149,25 @@ int dp_model_set_params(dp_model* model, const double* params_host, int64_t n_pa
  * the computes flag with DP_FLAG_NONFINITE. */
 int dp_model_set_params_device(dp_model* model, const double* params_dev, int64_t n_params, hipStream_t stream);
 int dp_model_destroy(dp_model* model);
+
+/* DP-compress (Background section: the compression of the embedding net):
+ * tabulates every embedding net G(x) of its input x = R~[0] as piecewise
+ * fifth-order polynomials that match G, dG/dx and d2G/dx2 at the ends of
+ * each interval, on a fine stride h over [0, X1) and a coarse stride 10 h
+ * over [X1, X2), where X1 = ceil(x_fine / h) h and X2 = X1 + ceil((x_max -
+ * X1) / (10 h)) 10 h.  Inputs at or beyond X2 take the value at X2 (zero
+ * slope) and raise DP_FLAG_TABLE_RANGE.  Computes with mode DP_FP64_TAB
+ * use it; the table is rebuilt on the device from the parameters at every
+ * dp_model_set_params[_device].  A set-up call: it allocates the table
+ * (n_types^2 * n_intervals * 6 * m1 doubles) and waits for the build.
+ * DP_ERR_BAD_ARG for h <= 0, x_fine <= 0, x_max < x_fine or more than
+ * 10^6 intervals. */
+int dp_model_compress(dp_model* model, double x_fine, double x_max, double h);
+/* Copies the table (layout [t_i * ntypes + t_j][interval][power 0..5][m1
+ * features], FP64) into dst (device, caller-owned) and writes its value
+ * count to *n_values; with dst NULL only the count.  Waits for the copy.
+ * DP_ERR_STATE when the model is not compressed. */
+int dp_model_copy_table(const dp_model* model, double* dst, int64_t* n_values);
 
 /* Allocates every work buffer for up to max_atoms atoms in up to max_frames
  * frames (Computation Optimization section: all memory is allocated in the

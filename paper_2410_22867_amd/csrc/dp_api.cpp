@@ -196,7 +196,8 @@ void free_model(dp_model* m) {
   if (!m) return;
   void* ptrs[] = {m->params, m->emb_vec64, m->emb_vec32, m->emb_frag64, m->emb_vec64d, m->emb_frag64d,
                   m->emb_frag_bf16, m->emb_frag_f16, m->emb_frag_f32,
-                  m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, m->fit_vec64, m->fit_vec32};
+                  m->fit_frag64, m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, m->fit_vec64, m->fit_vec32,
+                  m->table, m->tab_nodes};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < m->n_maps; ++k)
@@ -404,6 +405,7 @@ void gather_all(dp_model* m, hipStream_t s) {
     const ParamMap& pm = m->maps[k];
     launch_param_gather(m->params, pm.idx_use, pm.n, pm.kind, pm.dst, s);
   }
+  if (m->table) launch_tab_build(m, s);
 }
 
 // ------------------------------------------------------------ frames
@@ -512,8 +514,9 @@ struct StageScope {
 };
 
 int check_mode(int32_t mode) {
-  if (mode < DP_FP64 || mode > DP_MIX_FP16_FIT1) {
-    set_error("mode %d is not one of DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32, DP_MIX_FP16_FIT1", mode);
+  if (mode < DP_FP64 || mode > DP_FP64_TAB) {
+    set_error("mode %d is not one of DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32, DP_MIX_FP16_FIT1, DP_FP64_TAB",
+              mode);
     return DP_ERR_BAD_ARG;
   }
   return DP_OK;
@@ -555,10 +558,14 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   if ((rc = set_device(c->device))) return rc;
   int64_t ncells = 0;
   if ((rc = stage_frames(c, boxes, off, nframes, s, &ncells, c->model->desc.rcut))) return rc;
+  const bool tab = mode == DP_FP64_TAB;
+  if (tab && !c->model->table) { set_error("DP_FP64_TAB needs dp_model_compress on the model"); return DP_ERR_STATE; }
   c->natoms_last = n;
   c->types_last = types;
   c->mode_last = mode;
   c->last_stream = s;
+  // the tabulated form is the FP64 path with the embedding nets replaced
+  if (tab) mode = DP_FP64;
   const int32_t ntot = (int32_t)n;
   const bool own_list = nlist == c->rev_list && n == c->natoms_rev;
   { StageScope p(c, DP_STAGE_TYPESORT, s); type_sort(c, types, n, nframes, own_list, s); }
@@ -571,14 +578,22 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
     c->natoms_rev = n;
   }
   { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, forces, s); }
-  c->act_used_last = c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
-  { StageScope p(c, DP_STAGE_EMBED_FWD, s); launch_embed_fwd(c, types, mode, s); }
+  c->act_used_last = !tab && c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
+  {
+    StageScope p(c, DP_STAGE_EMBED_FWD, s);
+    if (tab) launch_embed_tab(c, false, s);
+    else launch_embed_fwd(c, types, mode, s);
+  }
   { StageScope p(c, DP_STAGE_DESCRIPTOR, s); launch_descriptor(c, mode, s); }
   { StageScope p(c, DP_STAGE_FIT_FWD, s); launch_fit_forward(c, mode, c->train_h, s); }
   c->h_stored = c->train_h;
   { StageScope p(c, DP_STAGE_FIT_BWD, s); launch_fit_backward(c, mode, c->train_h, s); }
   { StageScope p(c, DP_STAGE_DESC_BWD, s); launch_desc_bwd(c, mode, s); }
-  { StageScope p(c, DP_STAGE_EMBED_BWD, s); launch_embed_bwd(c, types, mode, s); }
+  {
+    StageScope p(c, DP_STAGE_EMBED_BWD, s);
+    if (tab) launch_embed_tab(c, true, s);
+    else launch_embed_bwd(c, types, mode, s);
+  }
   { StageScope p(c, DP_STAGE_FORCE, s); launch_force(c, x, nlist, ntot, forces, s); }
   { StageScope p(c, DP_STAGE_REDUCE, s); launch_frame_reduce(c, nframes, energies, atom_energy, virials, s); }
   HIPCHECK(hipGetLastError());
@@ -864,6 +879,63 @@ int dp_model_set_params_device(dp_model* m, const double* params_dev, int64_t n_
   return DP_OK;
 }
 
+int dp_model_compress(dp_model* m, double x_fine, double x_max, double h) {
+  if (!m) { set_error("model is NULL"); return DP_ERR_BAD_ARG; }
+  if (!(h > 0.0) || !(x_fine > 0.0) || !(x_max >= x_fine) || !std::isfinite(x_max)) {
+    set_error("need h > 0, x_fine > 0, x_max >= x_fine (finite)");
+    return DP_ERR_BAD_ARG;
+  }
+  TabGrid g;
+  g.h = h;
+  g.H = h * 10.0;
+  const double n1d = std::ceil(x_fine / h);
+  if (!(n1d <= 1e6)) { set_error("more than 10^6 table intervals"); return DP_ERR_BAD_ARG; }
+  g.n1 = (int)n1d;
+  g.X1 = (double)g.n1 * h;
+  const double n2d = x_max > g.X1 ? std::ceil((x_max - g.X1) / g.H) : 0.0;
+  if (!(n1d + n2d <= 1e6)) { set_error("more than 10^6 table intervals"); return DP_ERR_BAD_ARG; }
+  g.n2 = (int)n2d;
+  g.X2 = std::fma((double)g.n2, g.H, g.X1);
+  g.nint = g.n1 + g.n2;
+  int rc;
+  if ((rc = set_device(m->device))) return rc;
+  HIPCHECK(hipStreamSynchronize(nullptr));
+  if (m->table) (void)hipFree(m->table);
+  if (m->tab_nodes) (void)hipFree(m->tab_nodes);
+  m->table = m->tab_nodes = nullptr;
+  const int nnets = m->desc.ntypes * m->desc.ntypes;
+  if ((rc = dev_alloc(&m->table, (size_t)nnets * g.nint * 6 * m->m1, "hipMalloc(table)"))) return rc;
+  if ((rc = dev_alloc(&m->tab_nodes, (size_t)nnets * (g.nint + 1) * 3 * m->m1, "hipMalloc(table nodes)"))) {
+    (void)hipFree(m->table);
+    m->table = nullptr;
+    return rc;
+  }
+  m->tab_grid = g;
+  const ParamLayout L = layout_of(&m->desc);
+  for (int a = 0; a < m->desc.ntypes; ++a)
+    for (int b = 0; b < m->desc.ntypes; ++b)
+      for (int l = 0; l < 3; ++l) {
+        m->tab_off.W[a * m->desc.ntypes + b][l] = L.embW[a][b][l];
+        m->tab_off.b[a * m->desc.ntypes + b][l] = L.embB[a][b][l];
+      }
+  launch_tab_build(m, nullptr);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(nullptr));
+  return DP_OK;
+}
+
+int dp_model_copy_table(const dp_model* m, double* dst, int64_t* n_values) {
+  if (!m || !n_values) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
+  if (!m->table) { set_error("model not compressed"); return DP_ERR_STATE; }
+  const int64_t nv = (int64_t)m->desc.ntypes * m->desc.ntypes * m->tab_grid.nint * 6 * m->m1;
+  *n_values = nv;
+  if (!dst) return DP_OK;
+  int rc;
+  if ((rc = set_device(m->device))) return rc;
+  HIPCHECK(hipMemcpy(dst, m->table, (size_t)nv * 8, hipMemcpyDeviceToDevice));
+  return DP_OK;
+}
+
 int dp_model_destroy(dp_model* m) {
   if (!m) return DP_OK;
   (void)hipSetDevice(m->device);
@@ -1137,6 +1209,7 @@ int dp_compute_batch(dp_ctx* c, const double* coords, const int32_t* types, cons
 int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipStream_t stream) {
   if (!c || !dL_dE || !grad_params) { set_error("NULL argument"); return DP_ERR_BAD_ARG; }
   if (!c->have_state) { set_error("dp_backward_params needs a preceding dp_compute"); return DP_ERR_STATE; }
+  if (c->mode_last == DP_FP64_TAB) { set_error("the tabulated model has no parameter gradient"); return DP_ERR_UNSUPPORTED; }
   int rc;
   if ((rc = set_device(c->device))) return rc;
   const dp_model* m = c->model;
@@ -1265,8 +1338,9 @@ int dp_ctx_copy_buffer(dp_ctx* c, int32_t which, void* dst, int64_t* nbytes, hip
   if (which == 0) HIPCHECK(hipMemcpyAsync(dst, c->R, bytes, hipMemcpyDeviceToDevice, stream));
   else if (which == 4) HIPCHECK(hipMemcpyAsync(dst, c->netd, bytes, hipMemcpyDeviceToDevice, stream));
   else {
-    if (which == 2 && c->mode_last == DP_FP64) launch_descriptor_ex(c, DP_FP64, true, stream);
-    launch_gather_cols(c, which, c->mode_last, (int32_t)n, (double*)dst, stream);
+    const int32_t md = c->mode_last == DP_FP64_TAB ? DP_FP64 : c->mode_last;
+    if (which == 2 && md == DP_FP64) launch_descriptor_ex(c, DP_FP64, true, stream);
+    launch_gather_cols(c, which, md, (int32_t)n, (double*)dst, stream);
   }
   HIPCHECK(hipGetLastError());
   return DP_OK;

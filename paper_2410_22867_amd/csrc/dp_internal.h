@@ -55,6 +55,17 @@ struct ParamMap {
   void* dst;
 };
 
+// DP-compress grid (see k_tab.hip): fine stride h on [0, X1) with n1
+// intervals, coarse stride H = 10 h on [X1, X2) with n2 intervals.
+struct TabGrid {
+  double h, H, X1, X2;
+  int n1, n2, nint;
+};
+// Flat-parameter offsets of each embedding net's W_l and b_l.
+struct TabNetOffsets {
+  int64_t W[kMaxT * kMaxT][3], b[kMaxT * kMaxT][3];
+};
+
 // Element kinds of the matrix stages of a mixed mode (1 BF16, 2 FP16,
 // 3 FP32): the embedding nets, the first fitting layer (forward GEMM and
 // its backward GEMM, hence D and dz1), the fitting layer pairs 2-3.
@@ -123,6 +134,12 @@ struct dp_model {
   // index maps of every copy above (built once at creation)
   dpse::ParamMap maps[16];
   int n_maps;
+  // DP-compress table (dp_model_compress; NULL without): [nets][nint][6][m1]
+  // quintic coefficients, rebuilt from params whenever they change
+  double* table;
+  double* tab_nodes;         // [nets][nint + 1][3][m1] node values, slopes, curvatures
+  dpse::TabGrid tab_grid;
+  dpse::TabNetOffsets tab_off;
   int device;
 };
 
@@ -274,6 +291,10 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s);
 void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s);
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
+// DP-compress: table from the model's parameters; tabulated embedding
+// forward (T sections) or backward (net_deriv) of the FP64 path
+void launch_tab_build(const dp_model* m, hipStream_t s);
+void launch_embed_tab(dp_ctx* c, bool bwd, hipStream_t s);
 void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot, double* forces, hipStream_t s);
 void launch_frame_reduce(dp_ctx* c, int32_t nframes, double* energies, double* atom_energy, double* virials,
                          hipStream_t s);

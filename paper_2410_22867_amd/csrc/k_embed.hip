@@ -884,20 +884,21 @@ static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, 
   else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
 }
 
-template <class P, int W>
+template <class P, int W, int WPB>
 static void launch_embed_lp(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, hipStream_t s) {
-  if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<P, W, kWPBlp>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_embed_fwd_lp<P, W, kWPBlp>), grid, block, 0, s, A);
+  if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<P, W, WPB>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_embed_fwd_lp<P, W, WPB>), grid, block, 0, s, A);
 }
 
 // Resident work-groups per CU: FP64 one 8-wave group; the 16-bit forms
-// three 4-wave groups; the FP32 form holds its fragments in twice the LDS
-// (forward 55 KB: two groups; backward 90 KB: one).
+// three 4-wave groups; the FP32 form holds its fragments in twice the LDS:
+// the forward (55 KB) two 4-wave groups, the backward (80 KB of fragments)
+// one 8-wave group, so that two waves per SIMD share one LDS copy.
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
-  const int wpb = mode == DP_FP64 ? kWPB64 : kWPBlp;
-  EmbArgs A = emb_args(c, mode);
   const int kind = mode == DP_FP64 ? 0 : mix_kinds(mode).emb;
+  const int wpb = mode == DP_FP64 || (kind == 3 && bwd) ? 8 : kWPBlp;
+  EmbArgs A = emb_args(c, mode);
   const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : 3);
   dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)(A.ntypes * A.ntypes));
   dim3 block(64 * wpb);
@@ -905,11 +906,13 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
     if (A.act) launch_embed_f64<W, true>(bwd, grid, block, A, s);
     else launch_embed_f64<W, false>(bwd, grid, block, A, s);
   } else if (kind == 1) {
-    launch_embed_lp<PrecBF16, W>(bwd, grid, block, A, s);
+    launch_embed_lp<PrecBF16, W, kWPBlp>(bwd, grid, block, A, s);
   } else if (kind == 2) {
-    launch_embed_lp<PrecF16, W>(bwd, grid, block, A, s);
+    launch_embed_lp<PrecF16, W, kWPBlp>(bwd, grid, block, A, s);
+  } else if (bwd) {
+    hipLaunchKernelGGL((k_embed_bwd_lp<PrecF32, W, 8>), grid, block, 0, s, A);
   } else {
-    launch_embed_lp<PrecF32, W>(bwd, grid, block, A, s);
+    hipLaunchKernelGGL((k_embed_fwd_lp<PrecF32, W, kWPBlp>), grid, block, 0, s, A);
   }
 }
 

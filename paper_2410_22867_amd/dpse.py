@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(HERE, "libdpse.so")
 DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32, DP_MIX_FP16_FIT1 = 0, 1, 2, 3, 4
 # "mix_fp32" and "mix_fp16" are the paper's MIX-fp32 (both nets in FP32) and
 # MIX-fp16 (MIX-fp32 with the first fitting layer's products in FP16)
+DP_FP64_TAB = 5
 MODES = {"fp64": DP_FP64, "bf16": DP_MIX_BF16, "fp16": DP_MIX_FP16, "mix_fp32": DP_MIX_FP32,
-         "mix_fp16": DP_MIX_FP16_FIT1}
+         "mix_fp16": DP_MIX_FP16_FIT1, "fp64_tab": DP_FP64_TAB}
 
 FLAG_NOT_WRAPPED, FLAG_OVERLAP, FLAG_NONFINITE, FLAG_CAND_CAPACITY, FLAG_SEL_OVERFLOW = 1, 2, 4, 8, 16
-FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED = 32, 64
+FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED, FLAG_TABLE_RANGE = 32, 64, 128
 
 BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 
@@ -31,7 +32,7 @@ BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_set_params_device",
            "dp_model_destroy", "dp_ctx_create",
            "dp_ctx_destroy", "dp_build_nlist", "dp_build_nlist_batch", "dp_nlist_skin_build", "dp_nlist_skin_format",
-           "dp_nlist_skin_update", "dp_build_nlist_noalloc",
+           "dp_nlist_skin_update", "dp_build_nlist_noalloc", "dp_model_compress", "dp_model_copy_table",
            "dp_compute", "dp_compute_batch",
            "dp_backward_params", "dp_md_kick_drift", "dp_md_kick", "dp_ctx_status", "dp_ctx_store_info",
            "dp_ctx_copy_buffer", "dp_ctx_profile", "dp_ctx_stage_times", "dp_last_error")
@@ -103,6 +104,8 @@ def lib():
             "dp_nlist_skin_format": (ctypes.c_int, [P, P, P, i64, P, P, P]),
             "dp_nlist_skin_update": (ctypes.c_int, [P, P, P, i64, i32, P, P, P, P, P]),
             "dp_build_nlist_noalloc": (ctypes.c_int, [P, P, P, P, i64, P, P, P, P]),
+            "dp_model_compress": (ctypes.c_int, [P, dbl, dbl, dbl]),
+            "dp_model_copy_table": (ctypes.c_int, [P, P, ctypes.POINTER(i64)]),
             "dp_md_kick": (ctypes.c_int, [P, P, P, P, i64, dbl, P, P]),
             "dp_ctx_status": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
             "dp_ctx_store_info": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -152,6 +155,21 @@ class Model:
     def set_params(self, params: np.ndarray) -> None:
         p = np.ascontiguousarray(params, dtype=np.float64)
         _check(lib().dp_model_set_params(self.handle, p.ctypes.data, p.size))
+
+    def compress(self, x_fine: float, x_max: float, h: float) -> None:
+        """DP-compress tables of the embedding nets (dp_model_compress)."""
+        self.tab_grid = (float(x_fine), float(x_max), float(h))
+        _check(lib().dp_model_compress(self.handle, *self.tab_grid))
+
+    def table(self):
+        """The device table as a float64 tensor [ntypes^2, nint, 6, m1]."""
+        import torch
+        nv = ctypes.c_int64(0)
+        _check(lib().dp_model_copy_table(self.handle, None, ctypes.byref(nv)))
+        out = torch.empty(int(nv.value), dtype=torch.float64, device="cuda")
+        _check(lib().dp_model_copy_table(self.handle, _ptr(out), ctypes.byref(nv)))
+        nt = self.desc.ntypes
+        return out.reshape(nt * nt, -1, 6, self.desc.m1)
 
     def load_params(self, params) -> None:
         """Parameters from a device float64 tensor [n_params], on the current

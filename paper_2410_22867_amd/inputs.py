@@ -116,6 +116,13 @@ COPPER = ModelDesc(ntypes=1, rcut=8.0, rcut_smth=2.0, sel=(500,),
                    emb=(32, 64, 128), m2=16, fit=(240, 240, 240),
                    masses=(MASS_CU,), std_s=0.05, std_v=0.035)
 
+# DP-compress grids (x_fine, x_max, h) of the embedding input x = s(r)/std_s:
+# the fine stride covers r >= 0.5 A for water (r_s, where s = 2/A) and
+# r >= 1.5 A for copper; a coarse stride of 10 h continues to r ~ 0.3 A and
+# ~1 A.
+COMPRESS_GRID_WATER = (25.0, 42.0, 0.1)
+COMPRESS_GRID_COPPER = (14.0, 20.0, 0.1)
+
 DT_WATER_FS = 0.5
 DT_COPPER_FS = 1.0
 MODEL_SEED_WATER = 100
