@@ -265,7 +265,7 @@ def main():
                              status_flags=fl)
         print(f"# {mode}: {ms:.3f} ms/step, {n * args.steps / el:.4g} atom-steps/s, {rebuilds} rebuilds, "
               f"flags {fl}", file=sys.stderr, flush=True)
-    if timed_flags & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED):
+    if timed_flags & ~(dpse.FLAG_SEL_OVERFLOW | dpse.FLAG_SKIN_EXCEEDED | dpse.FLAG_TABLE_RANGE):
         raise RuntimeError(f"device status flags {timed_flags}")
 
     # NVE energy drift (velocity Verlet, metal units) over every step: the
