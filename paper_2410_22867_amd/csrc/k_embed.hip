@@ -525,8 +525,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 
 // ============================================================== mixed forward
 // Layer 1 in FP32 on the vector ALUs (K = 1), layers 2 and 3 on 16x16x32
-// MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32,
-// contraction in FP32.
+// MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32.
+// The contraction T = G^T R~ of the 16-bit forms is a matrix-core product
+// too, with FP16 operands in both 16-bit forms (BF16's 8-bit mantissa raised
+// the BF16 form's copper force error by half; G, R~ and g_T are well inside FP16's
+// range) and FP32 accumulation: per 16-feature tile o, T[feature][k] += sum
+// over the tile's 16 rows
+// of G[row][feature] R~[row][k], with M = feature, N = k (4 of 16 used) and
+// K = rows (16 of 32 used: lane group g's elements 0..3 carry rows 4g..4g+3,
+// which is where layer 3's output puts them, elements 4..7 are zero), so
+// neither operand moves between lanes and the per-atom T needs no
+// cross-lane reduction.  The FP32 form keeps the vector contraction (its
+// 16x16x4 products would cost more than the multiply-adds they replace).
 template <class P, int W, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
@@ -563,6 +573,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
     for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
 
+  constexpr bool MC = P::kind != 3;  // contraction on the matrix cores
   for (int c_next = take();;) {
     const int c = __builtin_amdgcn_readfirstlane(c_next);
     if (c >= c_hi) break;
@@ -582,15 +593,28 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       const int row = r0 + r16;
       const float s = (float)s_next;
       s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
-      // rows of the contraction, requested before layers 1-2 run
+      // rows of the contraction, requested before layers 1-2 run: the vector
+      // form needs all four columns of rows 4g..4g+3, the matrix form column
+      // r16 (< 4) of them as its B operand
       float Rr[4][4];
+      PrecF16::vec8 bR;
+      if constexpr (MC) {
+        float rv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = r0 + 4 * g + v;
-        d4 x = {0.0, 0.0, 0.0, 0.0};
-        if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+        for (int v = 0; v < 4; ++v) {
+          const int rr = r0 + 4 * g + v;
+          if (r16 < 4 && rr < nn) rv[v] = (float)Rs[rr * 4 + r16];
+        }
+        bR = pack8<PrecF16>(rv);
+      } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
+        for (int v = 0; v < 4; ++v) {
+          const int rr = r0 + 4 * g + v;
+          d4 x = {0.0, 0.0, 0.0, 0.0};
+          if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
+        }
       }
 
       float h1[8];
@@ -626,7 +650,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
         f4 z = {b3, b3, b3, b3};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
-        if (feat < M1) {
+        if constexpr (MC) {
+          // A operand: G of rows 4g..4g+3 of this lane's feature (0 past m1)
+          float gv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          if (feat < M1) {
+            const int src = slot2_of_feat<W>(feat % (2 * W));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gv[v] = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
+          }
+          const f4 t4 = PrecF16::mfma(pack8<PrecF16>(gv), bR, f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]});
+#pragma unroll
+          for (int k = 0; k < 4; ++k) accT[o][k] = t4[k];
+        } else if (feat < M1) {
           const int src = slot2_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -638,21 +673,34 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       }
     }
     const float inv_nm = (float)A.inv_nm;
+    float* T = reinterpret_cast<float*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
+    if constexpr (MC) {
+      // lane (k = r16 < 4, g) holds T[16 o + 4 g + e][k] in element e
+      if (r16 < 4) {
 #pragma unroll
-    for (int o = 0; o < N3; ++o)
+        for (int o = 0; o < N3; ++o)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        float x = accT[o][k];
-        x += shfl_xor_f(x, 16);
-        x += shfl_xor_f(x, 32);
-        accT[o][k] = x * inv_nm;
+          for (int e = 0; e < 4; ++e) {
+            const int feat = 16 * o + 4 * g + e;
+            if (feat < M1) T[feat * 4 + r16] = accT[o][e] * inv_nm;
+          }
       }
-    if (g == 0) {
-      float* T = reinterpret_cast<float*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
+    } else {
 #pragma unroll
-      for (int o = 0; o < N3; ++o) {
-        const int feat = 16 * o + r16;
-        if (feat < M1) *reinterpret_cast<f4*>(T + feat * 4) = f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+      for (int o = 0; o < N3; ++o)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float x = accT[o][k];
+          x += shfl_xor_f(x, 16);
+          x += shfl_xor_f(x, 32);
+          accT[o][k] = x * inv_nm;
+        }
+      if (g == 0) {
+#pragma unroll
+        for (int o = 0; o < N3; ++o) {
+          const int feat = 16 * o + r16;
+          if (feat < M1) *reinterpret_cast<f4*>(T + feat * 4) = f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+        }
       }
     }
   }
