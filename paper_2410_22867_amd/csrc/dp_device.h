@@ -22,6 +22,8 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 //   16x16x32 bf16/f16 : A[m][k] at lane m + 16*(k/8), element k%8;
 //                 B[k][n] at lane n + 16*(k/8), element k%8;
 //                 D[m][n] (f32) at lane n + 16*(m/4), element m%4.
+//   16x16x16 f16 : A[m][k] at lane m + 16*(k/4), element k%4;
+//                 B[k][n] at lane n + 16*(k/4), element k%4; D as above.
 // A D-layout tile (m = feature, n = row) therefore serves unchanged as the
 // B operand of the next product (k = feature, n = row) and as the A operand
 // of a product with rows as m, once the k index is permuted as below.
@@ -32,6 +34,18 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 // FP64 fitting GEMM uses 16t + 4g + v there (4 contiguous values per lane).
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x16 FP16 product with FP32 accumulation (4 elements per lane).
+__device__ __forceinline__ f4 mfma_f16k16(h16x4 a, h16x4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// Rounds 4 floats to FP16 (round to nearest even).
+__device__ __forceinline__ h16x4 pack4_f16(const float* x) {
+  return h16x4{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
 }
 
 // Precision traits of the mixed forms.  vec8 is the 8-element operand of

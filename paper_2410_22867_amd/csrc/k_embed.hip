@@ -527,16 +527,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 // Layer 1 in FP32 on the vector ALUs (K = 1), layers 2 and 3 on 16x16x32
 // MFMA with BF16/FP16 operands and FP32 accumulation, tanh and skips in FP32.
 // The contraction T = G^T R~ of the 16-bit forms is a matrix-core product
-// too, with FP16 operands in both 16-bit forms (BF16's 8-bit mantissa raised
-// the BF16 form's copper force error by half; G, R~ and g_T are well inside FP16's
-// range) and FP32 accumulation: per 16-feature tile o, T[feature][k] += sum
-// over the tile's 16 rows
-// of G[row][feature] R~[row][k], with M = feature, N = k (4 of 16 used) and
-// K = rows (16 of 32 used: lane group g's elements 0..3 carry rows 4g..4g+3,
-// which is where layer 3's output puts them, elements 4..7 are zero), so
-// neither operand moves between lanes and the per-atom T needs no
-// cross-lane reduction.  The FP32 form keeps the vector contraction (its
-// 16x16x4 products would cost more than the multiply-adds they replace).
+// too, a 16x16x16 one with FP16 operands in both 16-bit forms (BF16's 8-bit
+// mantissa raised the BF16 form's copper force error by half; G and R~ are
+// well inside FP16's range) and FP32 accumulation: per 16-feature tile o,
+// T[feature][k] += sum over the tile's 16 rows of G[row][feature] R~[row][k],
+// with M = feature, N = k (4 of 16 used) and K = rows (lane group g carries
+// rows 4g..4g+3, which is where layer 3's output puts them), so neither
+// operand moves between lanes and the per-atom T needs no cross-lane
+// reduction.  The FP32 form keeps the vector contraction (its 16x16x4
+// products would cost more than the multiply-adds they replace).
 template <class P, int W, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
@@ -574,6 +573,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
 
   constexpr bool MC = P::kind != 3;  // contraction on the matrix cores
+  // layer-3 biases of this lane's features, the accumulator seeds of every
+  // tile (held in registers by the 16-bit forms, re-read by the FP32 form,
+  // whose registers are taken)
+  f4 b3s[MC ? N3 : 1];
+  if constexpr (MC) {
+#pragma unroll
+    for (int o = 0; o < N3; ++o) {
+      const float b3 = vec[kV_B3F + 16 * o + r16];  // the table spans kP3 features
+      b3s[o] = f4{b3, b3, b3, b3};
+    }
+  }
   for (int c_next = take();;) {
     const int c = __builtin_amdgcn_readfirstlane(c_next);
     if (c >= c_hi) break;
@@ -588,6 +598,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
     double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
+    // 16-bit forms: column r16 % 4 of rows 4g..4g+3 of the next tile, also in
+    // flight (row indices clamped into the section, unused values discarded)
+    double rc_next[4];
+    if constexpr (MC) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rc_next[v] = Rs[min(4 * g + v, nn - 1) * 4 + (r16 & 3)];
+    }
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
@@ -597,15 +614,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       // form needs all four columns of rows 4g..4g+3, the matrix form column
       // r16 (< 4) of them as its B operand
       float Rr[4][4];
-      PrecF16::vec8 bR;
+      h16x4 bR;
       if constexpr (MC) {
-        float rv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float rv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int rr = r0 + 4 * g + v;
-          if (r16 < 4 && rr < nn) rv[v] = (float)Rs[rr * 4 + r16];
+          float x = (float)rc_next[v];
+          asm volatile("" : "+v"(x));  // FP64 -> FP32 -> FP16, as the FP32 form sees it
+          rv[v] = r16 < 4 && r0 + 4 * g + v < nn ? x : 0.f;
+          rc_next[v] = Rs[min(r0 + 16 + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
         }
-        bR = pack8<PrecF16>(rv);
+        bR = pack4_f16(rv);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -646,19 +665,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
         const int feat = 16 * o + r16;
-        const float b3 = vec[kV_B3F + feat];  // the table spans kP3 features
-        f4 z = {b3, b3, b3, b3};
+        f4 z;
+        if constexpr (MC) {
+          z = b3s[o];
+        } else {
+          const float b3 = vec[kV_B3F + feat];
+          z = f4{b3, b3, b3, b3};
+        }
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
         if constexpr (MC) {
           // A operand: G of rows 4g..4g+3 of this lane's feature (0 past m1)
-          float gv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          float gv[4] = {0.f, 0.f, 0.f, 0.f};
           if (feat < M1) {
             const int src = slot2_of_feat<W>(feat % (2 * W));
 #pragma unroll
             for (int v = 0; v < 4; ++v) gv[v] = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
           }
-          const f4 t4 = PrecF16::mfma(pack8<PrecF16>(gv), bR, f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]});
+          const f4 t4 = mfma_f16k16(pack4_f16(gv), bR, f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]});
 #pragma unroll
           for (int k = 0; k < 4; ++k) accT[o][k] = t4[k];
         } else if (feat < M1) {
@@ -707,14 +731,34 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 }
 
 // ============================================================== mixed backward
+// Every quantity of the backward is linear in g_T, so g_T enters unscaled
+// and the 1/nm factor is applied once to each output row (g_T / nm sits
+// below FP16's normal range for most slots).
+// The 16-bit forms run the two per-row contractions with g_T on the matrix
+// cores, as 16x16x16 products with FP16 operands and FP32 accumulation:
+//  * dE/dG[slot][row] = g_T[slot] . R~[row]: M = slot (16 per tile o),
+//    N = row, K = the 4 columns of R~ (lane group 0; the B elements of the
+//    other groups are zero, so their A elements may hold anything finite).
+//    The result lands in layer 3's output layout.
+//  * the direct term dE/dR~[row][k] = sum_slot g_T[slot][k] G[slot][row]:
+//    M = k (4 of 16 used), N = row, K = the 16 slots of tile o (lane group
+//    g, element v: slot 16o + 4g + v), so G is the B operand as layer 3
+//    leaves it; column k of each row ends in lane group 0, element k, with
+//    no cross-lane reduction.
+// g_T is kept in LDS as FP16 per slot (A of the first product) and
+// transposed per column k (A of the second, built once per centre atom).
+// The FP32 form keeps the vector multiply-adds.
 template <class P, int W, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
+  constexpr bool MC = P::kind != 3;  // contractions on the matrix cores
   typedef typename P::store_t ST;
   typedef typename P::raw8 R8;
   __shared__ __attribute__((aligned(16))) ST fr[NFR];
-  __shared__ f4 gts[WPB][kP3];
+  __shared__ f4 gts[MC ? 1 : WPB][kP3];           // FP32 form: g_T per slot
+  __shared__ u16x4 gth[MC ? WPB : 1][kP3];        // 16-bit forms: g_T per slot, FP16
+  __shared__ u16x4 gtt[MC ? WPB : 1][4][kP3 / 4];  // 16-bit forms: column k of g_T, FP16
   __shared__ float vs[kVecPerNet];
   DPSE_NET_PROLOGUE(WPB)
   {
@@ -750,15 +794,31 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     const int i = A.atom_at[col];
     {
       const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
-      const float inv_nm = (float)A.inv_nm;
       wave_lds_sync();
       for (int p = lane; p < kP3; p += 64) {
         const int a = feat3_of_slot<W>(p);
         f4 x = {0.f, 0.f, 0.f, 0.f};
-        if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4) * inv_nm;
-        gts[wv][p] = x;
+        if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4);
+        if constexpr (MC) {
+          u16x4 h;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) h[k] = PrecF16::bits(x[k]);
+          gth[wv][p] = h;
+          uint16_t* tk = reinterpret_cast<uint16_t*>(&gtt[wv][0][0]);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tk[k * kP3 + p] = h[k];
+        } else {
+          gts[wv][p] = x;
+        }
       }
       wave_lds_sync();
+    }
+    // A operands of the direct-term product, per centre atom: lane (m, g),
+    // tile o, element v holds g_T[16o + 4g + v][m % 4]
+    h16x4 aD[8];
+    if constexpr (MC) {
+#pragma unroll
+      for (int o = 0; o < 8; ++o) aD[o] = __builtin_bit_cast(h16x4, gtt[wv][r16 & 3][4 * o + g]);
     }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
@@ -798,44 +858,65 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
         for (int j = 0; j < 8; ++j) tmp[j] = h2[2 * kt + (j >> 2)][j & 3];
         b2v[kt] = pack8<P>(tmp);
       }
-      float dz3[8][4], skip2[4][4];
+      // B operand of the dE/dG product: R~[row][0..3] in lane group 0
+      h16x4 bR;
+      if constexpr (MC) {
+        // the FP32 values are rounded to FP16 (the empty asm keeps the
+        // compiler from fusing both roundings into one from FP64)
+        float v4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float x = Rrow[k];
+          asm volatile("" : "+v"(x));
+          v4[k] = g == 0 ? x : 0.f;
+        }
+        bR = pack4_f16(v4);
+      }
+      float skip2[4][4];
       float dRd[4] = {0.f, 0.f, 0.f, 0.f};
+      f4 accD = {0.f, 0.f, 0.f, 0.f};
+      typename P::vec8 bz3[4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int v = 0; v < 4; ++v) skip2[ot][v] = 0.f;
+      float dz3p[8];  // k-step pairs of tiles (2t, 2t + 1)
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
         const float* b3 = vec + kV_B3S + 16 * o + 4 * g;
         f4 z = {b3[0], b3[1], b3[2], b3[3]};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oF3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
+        f4 dGv;
+        if constexpr (MC) {
+          dGv = mfma_f16k16(__builtin_bit_cast(h16x4, gth[wv][16 * o + r16]), bR, f4{0.f, 0.f, 0.f, 0.f});
+        }
+        float G4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int p = 16 * o + 4 * g + v;
           const float t3 = tanh_f(z[v]);
           const float G = h2[o & 3][v] + t3;
-          const f4 gt = gts[wv][p];
-          const float dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
+          float dG;
+          if constexpr (MC) {
+            dG = dGv[v];
+            G4[v] = G;
+          } else {
+            const f4 gt = gts[wv][16 * o + 4 * g + v];
+            dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) dRd[k] = fmaf(gt[k], G, dRd[k]);
-          dz3[o][v] = dG * (1.f - t3 * t3);
+            for (int k = 0; k < 4; ++k) dRd[k] = fmaf(gt[k], G, dRd[k]);
+          }
+          dz3p[4 * (o & 1) + v] = dG * (1.f - t3 * t3);
           skip2[o & 3][v] += dG;
         }
+        if constexpr (MC) accD = mfma_f16k16(aD[o], pack4_f16(G4), accD);
+        if (o & 1) bz3[o >> 1] = pack8<P>(dz3p);
       }
       float dz2[4][4], skip1[2][4];
 #pragma unroll
       for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
         for (int v = 0; v < 4; ++v) skip1[i2][v] = 0.f;
-      typename P::vec8 bz3[4];
-#pragma unroll
-      for (int kt = 0; kt < 4; ++kt) {
-        float tmp[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) tmp[j] = dz3[2 * kt + (j >> 2)][j & 3];
-        bz3[kt] = pack8<P>(tmp);
-      }
 #pragma unroll
       for (int i2 = 0; i2 < 4; ++i2) {
         f4 z = {skip2[i2][0], skip2[i2][1], skip2[i2][2], skip2[i2][3]};
@@ -871,14 +952,21 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       }
       dsp += shfl_xor_f(dsp, 16);
       dsp += shfl_xor_f(dsp, 32);
+      if constexpr (MC) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        dRd[k] += shfl_xor_f(dRd[k], 16);
-        dRd[k] += shfl_xor_f(dRd[k], 32);
+        for (int k = 0; k < 4; ++k) dRd[k] = accD[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          dRd[k] += shfl_xor_f(dRd[k], 16);
+          dRd[k] += shfl_xor_f(dRd[k], 32);
+        }
       }
+      const double inv_nm = A.inv_nm;
       if (g == 0 && valid)
         *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) =
-            d4{(double)dRd[0] + (double)dsp, (double)dRd[1], (double)dRd[2], (double)dRd[3]};
+            d4{((double)dRd[0] + (double)dsp) * inv_nm, (double)dRd[1] * inv_nm, (double)dRd[2] * inv_nm,
+               (double)dRd[3] * inv_nm};
     }
   }
 }
