@@ -75,6 +75,28 @@ def algorithmic_flops(desc, real_rows, natoms, stored=False, tab=False):
     }
 
 
+# Vector-ALU model of the FP32 elementwise work of the embedding nets (the
+# bound of the mixed forms' embedding kernels, whose products run on the
+# matrix cores): 1024 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations/s
+# for FP32 add/mul/fma, a quarter of that for the transcendental exp2 and
+# reciprocal.  A tanh costs 2 transcendentals + 3 operations (argument scale,
+# 1 + e, the final fma); every unit of a width-keeping or width-doubling
+# layer adds its skip (1), layer 1 its input fma (1); the backward adds per
+# unit the derivative (1 - t^2) dh (2) and the skip's accumulation or, in
+# layer 1, the dot product with W1 (1), and recomputes the forward.
+ALU_OPS_PER_S = 1024 * 16 * 2.4e9
+ALU_TRANS_PER_S = ALU_OPS_PER_S / 4
+
+
+def embed_alu_seconds(desc, real_rows, stage):
+    units = sum(desc.emb)
+    fwd_t = units * 2 / ALU_TRANS_PER_S
+    fwd_o = (units * 3 + units) / ALU_OPS_PER_S
+    if stage == "embed_fwd":
+        return real_rows * (fwd_t + fwd_o)
+    return real_rows * (fwd_t + fwd_o + units * 3 / ALU_OPS_PER_S)
+
+
 def measured_traffic(stage, workload):
     """HBM bytes per launch of an embedding kernel from the committed rocprofv3
     counter summary, only while the kernel source is the one it was taken on."""
@@ -334,7 +356,11 @@ def main():
         peaks = stage_peaks(desc, mode)
         mat = {k: fl_m[k] / (st[k][0] * 1e-3) / 1e12 for k in fl_m if st.get(k, (0, 0))[0] > 0}
         mem = {k: hbm[k] / (st[k][0] * 1e-3) / 1e9 for k in hbm if st.get(k, (0, 0))[0] > 0}
-        t_roof = sum(max(fl_m.get(k, 0) / (peaks.get(k, PEAK_FP64_TF) * 1e12), hbm.get(k, 0) / (PEAK_HBM_GBS * 1e9))
+        # FP32 forms (all but fp64 and the table): the embedding stages' ALU bound
+        alu = ({k: embed_alu_seconds(desc, real_rows, k) for k in ("embed_fwd", "embed_bwd")}
+               if MODE_KINDS[mode][0] != 0 else {})
+        t_roof = sum(max(fl_m.get(k, 0) / (peaks.get(k, PEAK_FP64_TF) * 1e12), hbm.get(k, 0) / (PEAK_HBM_GBS * 1e9),
+                         alu.get(k, 0.0))
                      for k in st)
         dmat = max(mat, key=lambda k: st[k][0]) if mat else None
         peak = peaks[dmat] if dmat else None
@@ -348,6 +374,9 @@ def main():
             "table_read_GBs": ({k: round(real_rows * 6 * desc.m1 * 8 / (st[k][0] * 1e-3) / 1e9, 1)
                                 for k in ("embed_fwd", "embed_bwd") if st.get(k, (0, 0))[0] > 0}
                                if mode == "fp64_tab" else None),
+            "embed_alu": ({k: {"bound": "alu", "T_alu_ms": round(alu[k] * 1e3, 4),
+                               "T_meas_ms": round(st[k][0], 4), "frac": round(alu[k] * 1e3 / st[k][0], 4)}
+                           for k in alu if st.get(k, (0, 0))[0] > 0} or None),
             "step_T_roof_ms": round(t_roof * 1e3, 4),
             "step_T_meas_ms": round(results[mode]["ms_per_step"], 4),
             "step_roof_frac": round(t_roof * 1e3 / results[mode]["ms_per_step"], 4),
