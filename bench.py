@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-paper-size", action="store_true",
                     help="skip the 0.56 M-atom water and 0.54 M-atom copper steps")
     ap.add_argument("--no-latency", action="store_true", help="skip the 192-atom eager vs graph-replay step")
+    ap.add_argument("--no-nve98k", action="store_true",
+                    help="skip the 98,304-atom water NVE runs (FP64, BF16, FP16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -467,9 +469,83 @@ def main():
     torch.cuda.synchronize()
     if not args.no_latency:
         line["latency_small"] = bench_latency(args, torch, dpse, I, dev)
+    if args.nve_steps > 0 and not args.no_nve98k and args.workload == "water12k":
+        line["nve_water98k"] = bench_nve_water98k(args, torch, dpse, I, dev)
     if not args.no_paper_size:
         line["paper_size"] = bench_paper_size(args, torch, dpse, I, dev)
     print(json.dumps(line), flush=True)
+
+
+def bench_nve_water98k(args, torch, dpse, I, dev):
+    """The 98,304-atom water system: 1000 velocity-Verlet steps at 0.5 fs in
+    FP64, BF16 and FP16 (Verlet list rebuilt on the device; energies kept on
+    the device and read at the end), and the mixed forms' difference from
+    the FP64 GPU form on the identical initial frame."""
+    fr, desc, params, dt = I.workload("water98k")
+    n = fr.n
+    model = dpse.Model(desc, params)
+    ctx = dpse.Context(model, n, budget_bytes=int(args.workspace_gib * 2 ** 30))
+    x0 = torch.tensor(fr.coords, device=dev)
+    v0 = torch.tensor(I.maxwell_boltzmann(fr.types, desc.masses, 300.0, seed=203), device=dev)
+    t = torch.tensor(fr.types, device=dev)
+    nl = torch.empty((n, desc.nm), dtype=torch.int32, device=dev)
+    ov = torch.empty(1, dtype=torch.int32, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    W = torch.empty(9, dtype=torch.float64, device=dev)
+    ke = torch.empty(1, dtype=torch.float64, device=dev)
+    f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    nreb = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"natoms": n, "dt_fs": dt}
+    first = {}
+    for mode in ("fp64", "bf16", "fp16"):
+        x = x0.clone()
+        v = v0.clone()
+        ctx.skin_build(x, t, fr.box, args.skin)
+        ctx.skin_format(x, t, out=nl, overflow=ov)
+        ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+        torch.cuda.synchronize()
+        first[mode] = (float(E.item()), f.cpu().numpy().copy())
+        hist = torch.empty((args.nve_steps + 1, 3), dtype=torch.float64, device=dev)
+        ctx.kick(v, torch.zeros_like(f), t, 0.0, ke)
+        hist[0, 0] = E[0]
+        hist[0, 1] = ke[0]
+        hist[0, 2] = 0.0
+        ctx.status()
+        torch.cuda.synchronize()
+        r0 = int(nreb.item())
+        t0 = time.perf_counter()
+        for k in range(args.nve_steps):
+            ctx.kick_drift(x, v, f, t, fr.box, dt, wrap=False)
+            ctx.skin_update(x, t, every=args.rebuild_every, out=nl, overflow=ov, rebuilds=nreb)
+            ctx.compute(x, t, fr.box, nl, mode=mode, energy=E, forces=f, virial=W)
+            ctx.kick(v, f, t, dt, ke)
+            hist[k + 1, 0] = E[0]
+            hist[k + 1, 1] = ke[0]
+            hist[k + 1, 2] = ov[0]
+        hh = hist.cpu().numpy()
+        el = time.perf_counter() - t0
+        bad = np.nonzero(hh[:, 2] > 0)[0]
+        etot = hh[:, 0] + hh[:, 1]
+        tps = np.arange(len(etot)) * dt * 1e-3
+        dev_meV = (etot - etot[0]) / n * 1e3
+        T = hh[:, 1] * 2.0 / (3 * n * 8.617333262e-5)
+        out[mode] = dict(steps=args.nve_steps, ms_per_step=round(el / max(1, args.nve_steps) * 1e3, 3),
+                         steps_before_sel_overflow=int(bad[0]) - 1 if len(bad) else args.nve_steps,
+                         steps_with_sel_overflow=int(len(bad)), verlet_rebuilds=int(nreb.item()) - r0,
+                         max_dev_meV_per_atom=float(np.abs(dev_meV).max()),
+                         final_dev_meV_per_atom=float(dev_meV[-1]),
+                         slope_meV_per_atom_per_ps=float(np.polyfit(tps, dev_meV, 1)[0]),
+                         T_start_K=round(float(T[0]), 2), T_end_K=round(float(T[-1]), 2), flags=ctx.status())
+        print(f"# water98k nve {mode}: {out[mode]}", file=sys.stderr, flush=True)
+    e64, f64 = first["fp64"]
+    out["initial_frame_vs_fp64_gpu"] = {
+        m: {"E_meV_per_atom": abs(first[m][0] - e64) / n * 1e3,
+            "F_rms_meV_per_A": float(np.sqrt(((first[m][1] - f64) ** 2).mean())) * 1e3,
+            "F_rms_rel": float(np.sqrt(((first[m][1] - f64) ** 2).mean() / (f64 ** 2).mean()))}
+        for m in ("bf16", "fp16")}
+    del ctx, model
+    torch.cuda.synchronize()
+    return out
 
 
 def bench_paper_size(args, torch, dpse, I, dev):

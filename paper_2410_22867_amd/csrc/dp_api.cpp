@@ -1105,6 +1105,12 @@ int dp_ctx_create(const dp_model* m, int64_t max_atoms, int32_t max_frames, int6
     c->fa[k] = tmp;
   }
   {
+    const int64_t sc = kSplitCols + (int64_t)m->desc.ntypes * kColPad;
+    c->split_cols = C < sc ? C : sc;
+    ALLOC(tmp, (int64_t)kSplitMax * c->split_cols * fwp);
+    c->split_part = tmp;
+  }
+  {
     // activation store: as much of the full [max_atoms, tpa, m1, 16] f64
     // store as the budget allows; each compute uses it when its atoms fit
     // (plus one record of slack: padding slots of the last record may be
@@ -1141,7 +1147,7 @@ int dp_ctx_destroy(dp_ctx* c) {
                   c->cell_atoms, c->chunk_counts, c->type_meta, c->col_of, c->atom_at, c->frame_of, c->emb_ctr, c->R, c->nnei,
                   c->netd, c->rev, c->red_part, c->vatom, c->ke_part, c->ke_ctr, c->frame_ctr, c->ovf_ctr, c->Ei_col, c->Ei_atom, c->gE_col, c->grad_tmp, c->Tpart, c->T, c->D, c->dD, c->gT, c->act,
                   c->skin_cand, c->skin_ncand, c->skin_crev, c->skin_slot, c->skin_cof, c->skin_xref, c->skin_frame,
-                  c->gpart};
+                  c->gpart, c->split_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 12; ++k)

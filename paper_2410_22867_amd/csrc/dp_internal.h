@@ -10,6 +10,10 @@ namespace dpse {
 
 constexpr int kMaxT = DP_MAX_TYPES;
 constexpr int kColPad = 128;     // fitting-GEMM column tile; type segments are padded to it
+// Split-K form of the first fitting layer for frames with few atoms: at most
+// kSplitMax partial sums over K ranges, for up to kSplitCols columns (plus
+// the type segments' padding)
+constexpr int kSplitMax = 16, kSplitCols = 2048;
 constexpr int kCandCap = 512;    // neighbour candidates inside r_c per atom (LDS capacity)
 constexpr int kMaxNm = 1024;     // sum(sel)
 constexpr int kRedChunk = 1024;  // atoms per partial sum of the per-frame reductions
@@ -199,6 +203,8 @@ struct dp_ctx {
   void* gT;                // [cols, m1, 4]   f64 / f32
   // fitting activations [cols, fw]
   void* fa[12];
+  double* split_part;   // [kSplitMax][split_cols][fw] partial sums (FP64, or FP32 in the same bytes)
+  int64_t split_cols;
   double* Ei_col;          // [cols]
   double* Ei_atom;         // [N]
   double* netd;            // [N, nm, 4] f64

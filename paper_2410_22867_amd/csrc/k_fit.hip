@@ -38,10 +38,16 @@ struct GemmArgs {
   int ld0;
   const double* T;       // FP64 layer 1: X[col][a*16 + b] = sum_k T[col][a][k] T[col][b][k] built on the fly
   int m1;
+  // split-K form: work-group row blockIdx.y = m-block * nsplit + split; split
+  // s covers k-steps [KS s / nsplit, KS (s + 1) / nsplit) and writes its raw
+  // sums to part[s][col][M] (FP64, or FP32 for the half-precision GEMM)
+  void* part;
+  int nsplit;
+  int64_t part_cols;
 };
 
 // ---------------------------------------------------------------- FP64 GEMM
-template <int MT, int NT, bool XT>
+template <int MT, int NT, bool XT, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fit_gemm_f64(GemmArgs g) {
   const int t = blockIdx.z;
   const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
@@ -50,8 +56,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int c0 = (blockIdx.x * 4 + wv) * NT * 16;
   if (c0 >= n_t) return;
   const int mtiles = g.M / 16;
-  const int mt0 = blockIdx.y * MT;
+  const int mb = SPLIT ? (int)blockIdx.y / g.nsplit : (int)blockIdx.y;
+  const int sp = SPLIT ? (int)blockIdx.y - mb * g.nsplit : 0;
+  const int mt0 = mb * MT;
   const int KS = g.K / 16;
+  // k-steps of this work-group: all of them, or one split's range
+  const int S0 = SPLIT ? (int)((int64_t)KS * sp / g.nsplit) : 0;
+  const int S1 = SPLIT ? (int)((int64_t)KS * (sp + 1) / g.nsplit) : KS;
   const double* Afr = reinterpret_cast<const double*>(g.Afr) + t * g.a_type_stride;
   const double* X = reinterpret_cast<const double*>(g.X);
   d4 acc[MT][NT];
@@ -114,19 +125,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(av[mt][v], xb[nt][v], acc[mt][nt]);
   };
   // (scheduling barriers keep each phase's loads ahead of the products)
-  load(0, xA, aA);
-  int S = 0;
-  for (; S + 1 < KS; S += 2) {
+  load(S0, xA, aA);
+  int S = S0;
+  for (; S + 1 < S1; S += 2) {
     load(S + 1, xB, aB);
     __builtin_amdgcn_sched_barrier(0);
     step(xA, aA);
     __builtin_amdgcn_sched_barrier(0);
-    load(S + 2 < KS ? S + 2 : KS - 1, xA, aA);
+    load(S + 2 < S1 ? S + 2 : S1 - 1, xA, aA);
     __builtin_amdgcn_sched_barrier(0);
     step(xB, aB);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (S < KS) step(xA, aA);
+  if (S < S1) step(xA, aA);
+  if constexpr (SPLIT) {
+    double* part = static_cast<double*>(g.part) + (int64_t)sp * g.part_cols * g.M;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      if (mt0 + mt >= mtiles) break;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int64_t col = cb + c0 + nt * 16 + r16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[col * g.M + (mt0 + mt) * 16 + gq + 4 * v] = acc[mt][nt][v];
+      }
+    }
+    return;
+  }
   const double* vec = reinterpret_cast<const double*>(g.vec) + t * g.vec_type_stride;
   // D layout of the f64 MFMA: element v of lane n + 16g is row m = 16 mt + g + 4v.
 #pragma unroll
@@ -375,7 +400,7 @@ __device__ __forceinline__ void epi_lp(const GemmArgs& g, const float* vec, int6
 // (rearranged into B-fragment order on the way) is loaded once per
 // work-group into double-buffered LDS, so a weight fragment serves 2 NTW
 // n-tiles and an X fragment 2 MTW m-tiles.
-template <class P, int MTW, int NTW, int PF>
+template <class P, int MTW, int NTW, int PF, bool SPLIT>
 __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   constexpr int MB = 2 * MTW, NB = 2 * NTW;  // m-tiles, n-tiles per work-group
   constexpr int BN = 16 * NB;
@@ -393,8 +418,13 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   const int wm = wv >> 1, wn = wv & 1;
   const int r16 = lane & 15, gq = lane >> 4;
   const int mtiles = g.M / 16;
-  const int mb0 = blockIdx.y * MB;
-  const int KT = g.K / 32;
+  const int mb = SPLIT ? (int)blockIdx.y / g.nsplit : (int)blockIdx.y;
+  const int sp = SPLIT ? (int)blockIdx.y - mb * g.nsplit : 0;
+  const int mb0 = mb * MB;
+  const int KTall = g.K / 32;
+  // k-steps of this work-group: [kt0, kt0 + KT)
+  const int kt0 = SPLIT ? (int)((int64_t)KTall * sp / g.nsplit) : 0;
+  const int KT = SPLIT ? (int)((int64_t)KTall * (sp + 1) / g.nsplit) - kt0 : KTall;
   const ST* Afr = reinterpret_cast<const ST*>(g.Afr) + t * g.a_type_stride;
   const ST* X = reinterpret_cast<const ST*>(g.X);
   // weight copy: MB fragments of 64 lanes x 16 B per k-step; thread tid
@@ -414,15 +444,15 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
   const int fA = tid >> 6;
   const int mA = min(mb0 + fA, mtiles - 1);
   const int colX = tid >> 2, qX = tid & 3;
-  const ST* aSrc = Afr + ((int64_t)mA * KT * 64 + lane) * 8;
-  const ST* xSrc = X + (int64_t)(cb + c0 + colX) * g.ldx + 8 * qX;
+  const ST* aSrc = Afr + ((int64_t)mA * KTall * 64 + lane) * 8 + (int64_t)kt0 * 512;
+  const ST* xSrc = X + (int64_t)(cb + c0 + colX) * g.ldx + 8 * qX + 32 * kt0;
   auto load = [&](int kt, R8& av, R8& xv) {
     av = *reinterpret_cast<const R8*>(aSrc + (int64_t)kt * 512);
     xv = *reinterpret_cast<const R8*>(xSrc + 32 * kt);
   };
   auto store = [&](int buf, int kt, const R8& av, R8 xv) {
     // the padded upper half of the last k-step may hold stale bits: zeros
-    if (!(qX < 2 || 32 * kt + 16 < g.Kreal)) xv = zero8<P>();
+    if (!(qX < 2 || 32 * (kt0 + kt) + 16 < g.Kreal)) xv = zero8<P>();
     if (fA < MB) *reinterpret_cast<R8*>(&as[buf][(fA * 64 + lane) * 8]) = av;
     const int d0 = (((colX >> 4) * 64 + 32 * (qX & 1) + (colX & 15)) * 8) + 4 * (qX >> 1);
     R4 lo, hi;
@@ -482,8 +512,40 @@ __global__ __launch_bounds__(256) void k_fit_gemm_lp(GemmArgs g) {
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt) {
       const int cl = c0 + (wn * NTW + nt) * 16;
-      if (cl < n_t) epi_lp<P>(g, vec, (int64_t)(cb + cl + r16), m0, acc[mt][nt]);
+      if (cl >= n_t) continue;
+      const int64_t col = cb + cl + r16;
+      if constexpr (SPLIT) {
+        float* part = static_cast<float*>(g.part) + (int64_t)sp * g.part_cols * g.M;
+        *reinterpret_cast<f4*>(part + col * g.M + m0) = acc[mt][nt];
+      } else {
+        epi_lp<P>(g, vec, col, m0, acc[mt][nt]);
+      }
     }
+  }
+}
+
+// Completion of the split-K form: out[col][m] = epi(sum over the splits, in
+// split order, of part[s][col][m] (+ bias)) for the columns and features the
+// unsplit GEMM writes (16-column tiles of each type's segment).
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_finish(GemmArgs g) {
+  const int t = blockIdx.y;
+  const int n_t = g.meta[2 * t], cb = g.meta[2 * t + 1];
+  const int ncol = (n_t + 15) & ~15;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (int64_t)ncol * g.M) return;
+  const int64_t col = cb + k / g.M;
+  const int m = (int)(k % g.M);
+  const T* part = static_cast<const T*>(g.part);
+  T acc = 0;
+  for (int s = 0; s < g.nsplit; ++s) acc += part[((int64_t)s * g.part_cols + col) * g.M + m];
+  T* out = static_cast<T*>(g.out0) + col * g.ld0 + m;
+  if (g.epi == EPI_PLAIN) {
+    *out = acc;
+  } else {
+    const T b = static_cast<const T*>(g.vec)[t * g.vec_type_stride + g.bias_off + m];
+    if constexpr (sizeof(T) == 8) *out = tanh_d(acc + b);
+    else *out = tanh_f(acc + b);
   }
 }
 
@@ -802,36 +864,92 @@ static const void* elem_offset(const void* base, int kind, int64_t off) {
 // The other slots are free; the parameter gradients after a mixed compute
 // use them for FP64 copies.
 // Tile shapes (m-tiles x n-tiles per wave, 4 waves along the columns).
+// Small-M form (the paper's concern with GEMMs of few rows, here few atoms
+// per type): when the unsplit grid would leave most of the chip idle and the
+// reduction is long, the k-steps are split over up to kSplitMax work-groups
+// per tile (at least 8 k-steps each) and k_split_finish adds the partial
+// sums in a fixed order.  Returns the split count (1: no split).
+static int split_count(const dp_ctx* c, int64_t wgs_unsplit, int ksteps) {
+  const int64_t cols = c->natoms_last + (int64_t)c->model->desc.ntypes * kColPad;
+  if (cols > c->split_cols || wgs_unsplit <= 0) return 1;
+  int64_t ns = (int64_t)c->ncu / wgs_unsplit;  // about one work-group per CU
+  if (ns > kSplitMax) ns = kSplitMax;
+  if (ns > ksteps / 8) ns = ksteps / 8;
+  return ns >= 2 ? (int)ns : 1;
+}
+
+// Work-groups of the unsplit grid that have columns to do (per-type counts
+// live on the device; the types' columns sum to natoms_last, and each type
+// may end in a partial tile).
+static int64_t unsplit_wgs(const dp_ctx* c, int BN, int mblocks) {
+  return ((c->natoms_last + BN - 1) / BN + c->model->desc.ntypes - 1) * mblocks;
+}
+
+template <typename T>
+static void split_finish(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
+  // each type's columns are at most natoms_last (bounded per type on the device)
+  const int64_t work = ((c->natoms_last + 15) & ~15) * (int64_t)g.M;
+  dim3 grid((unsigned)((work + 255) / 256), (unsigned)c->model->desc.ntypes);
+  if (work > 0) hipLaunchKernelGGL((k_split_finish<T>), grid, dim3(256), 0, s, g);
+}
+
 template <int MT, int NT>
-static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g, hipStream_t s) {
+static void gemm_launch_f64(dp_ctx* c, const GemmArgs& g0, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 4 * NT * 16;
-  const int mtiles = g.M / 16;
-  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + MT - 1) / MT), (unsigned)ntypes);
+  const int mtiles = g0.M / 16;
+  const int mblocks = (mtiles + MT - 1) / MT;
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)mblocks, (unsigned)ntypes);
   if (grid.x == 0) return;
-  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false>), grid, dim3(256), 0, s, g);
+  GemmArgs g = g0;
+  g.nsplit = split_count(c, unsplit_wgs(c, BN, mblocks), g.K / 16);
+  if (g.nsplit > 1) {
+    g.part = c->split_part;
+    g.part_cols = c->split_cols;
+    grid.y = (unsigned)(mblocks * g.nsplit);
+    if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true, true>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false, true>), grid, dim3(256), 0, s, g);
+    split_finish<double>(c, g, s);
+    return;
+  }
+  if (g.T) hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, true, false>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_f64<MT, NT, false, false>), grid, dim3(256), 0, s, g);
+}
+
+template <class P, int MTW, int NTW, bool SPLIT>
+static void gemm_launch_lp_t(dim3 grid, bool deep, const GemmArgs& g, hipStream_t s) {
+  if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 8, SPLIT>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 2, SPLIT>), grid, dim3(256), 0, s, g);
 }
 
 template <class P, int MTW, int NTW>
-static void gemm_launch_lp_t(dim3 grid, bool deep, const GemmArgs& g, hipStream_t s) {
-  if (deep) hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 8>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_fit_gemm_lp<P, MTW, NTW, 2>), grid, dim3(256), 0, s, g);
+static void gemm_launch_lp_k(dim3 grid, bool deep, const GemmArgs& g, hipStream_t s) {
+  if (g.nsplit > 1) gemm_launch_lp_t<P, MTW, NTW, true>(grid, deep, g, s);
+  else gemm_launch_lp_t<P, MTW, NTW, false>(grid, deep, g, s);
 }
 
 // kind: element kind of the first fitting layer (the only GEMM launched here)
 template <int MTW, int NTW>
-static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g, int kind, hipStream_t s) {
+static void gemm_launch_lp(dp_ctx* c, const GemmArgs& g0, int kind, hipStream_t s) {
   const int ntypes = c->model->desc.ntypes;
   const int BN = 32 * NTW;
-  const int mtiles = g.M / 16;
-  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)((mtiles + 2 * MTW - 1) / (2 * MTW)),
-            (unsigned)ntypes);
+  const int mtiles = g0.M / 16;
+  const int mblocks = (mtiles + 2 * MTW - 1) / (2 * MTW);
+  dim3 grid((unsigned)((c->natoms_last + BN - 1) / BN), (unsigned)mblocks, (unsigned)ntypes);
   if (grid.x == 0) return;
-  const bool deep = g.K / 32 >= 16;
-  if (kind == 1) gemm_launch_lp_t<PrecBF16, MTW, NTW>(grid, deep, g, s);
-  else if (kind == 2) gemm_launch_lp_t<PrecF16, MTW, NTW>(grid, deep, g, s);
-  else gemm_launch_lp_t<PrecF32, MTW, NTW>(grid, deep, g, s);
+  GemmArgs g = g0;
+  g.nsplit = split_count(c, unsplit_wgs(c, BN, mblocks), g.K / 32);
+  if (g.nsplit > 1) {
+    g.part = c->split_part;
+    g.part_cols = c->split_cols;
+    grid.y = (unsigned)(mblocks * g.nsplit);
+  }
+  // the ring depth follows the k-steps one work-group walks
+  const bool deep = g.K / 32 / g.nsplit >= 16;
+  if (kind == 1) gemm_launch_lp_k<PrecBF16, MTW, NTW>(grid, deep, g, s);
+  else if (kind == 2) gemm_launch_lp_k<PrecF16, MTW, NTW>(grid, deep, g, s);
+  else gemm_launch_lp_k<PrecF32, MTW, NTW>(grid, deep, g, s);
+  if (g.nsplit > 1) split_finish<float>(c, g, s);
 }
 
 // Tile shapes picked by sweeps on the 12,288-atom water model: FP64 MFMA
