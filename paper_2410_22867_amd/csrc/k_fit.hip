@@ -199,7 +199,7 @@ struct PairArgs {
 };
 
 template <bool BWD, int NCT, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 3 : 6))) void k_fit_pair_f64(PairArgs p) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 3 : (NW == 8 ? 6 : 4)))) void k_fit_pair_f64(PairArgs p) {
   constexpr int MW = 16 / NW;      // m-tile slots per wave (fw <= 256)
   constexpr int NC = 16 * NCT;    // columns of the work-group
   extern __shared__ double hs[];  // [NC][fw + 2]
@@ -366,15 +366,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4
 }
 
 // One 16-column tile per work-group and four waves of four m-tile slots
-// (32 columns, or eight waves of two slots, measured no faster).
-static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
-  constexpr int NCT = 1, NW = 4;
+// (32 columns, or eight waves of two slots, measured no faster).  Frames
+// too small to give every CU a work-group (few atoms) take sixteen waves of
+// one slot each instead: the same work in a quarter of the serial chain.
+template <int NW>
+static void launch_pair_f64_t(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
+  constexpr int NCT = 1;
   const dp_model* m = c->model;
   dim3 grid((unsigned)((c->natoms_last + 16 * NCT - 1) / (16 * NCT)), 1, (unsigned)m->desc.ntypes);
   const size_t lds = (size_t)16 * NCT * (m->fw + 2) * sizeof(double);
   if (grid.x == 0) return;
   if (bwd) hipLaunchKernelGGL((k_fit_pair_f64<true, NCT, NW>), grid, dim3(64 * NW), lds, s, p);
   else hipLaunchKernelGGL((k_fit_pair_f64<false, NCT, NW>), grid, dim3(64 * NW), lds, s, p);
+}
+
+static void launch_pair_f64(dp_ctx* c, bool bwd, const PairArgs& p, hipStream_t s) {
+  const int64_t wgs = (c->natoms_last + 15) / 16 + c->model->desc.ntypes - 1;
+  if (wgs < c->ncu) launch_pair_f64_t<16>(c, bwd, p, s);
+  else launch_pair_f64_t<4>(c, bwd, p, s);
 }
 
 // ---------------------------------------------------------------- mixed GEMM
