@@ -161,7 +161,12 @@ __device__ __forceinline__ int feat3d_of_slot(int p) {  // FP64 layout; -1 for p
 }
 
 // ============================================================== FP64 forward
-template <int W, int WPB, bool ST>
+// Group mode (GM, frames of few atoms): the work-group's waves share one
+// column at a time, wave w taking its tiles w, w + WPB, ...; the waves'
+// partial T are added in wave order through LDS.  Without it each wave owns
+// a column and walks its tiles alone, which leaves most of the chip idle
+// when there are fewer columns than wave slots.
+template <int W, int WPB, bool ST, bool GM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_fwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   __shared__ double fr[NF2 + NF3];
   __shared__ double h2s[WPB][16][kP2 + 1];
   __shared__ double vs[kVecPerNet];
+  __shared__ int col_sh;  // group mode: the work-group's column
   DPSE_NET_PROLOGUE(WPB)
   {
     const double* src = A.frag64 + net * A.fo.per_net;
@@ -184,11 +190,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
   }
   __syncthreads();
+  constexpr int RSTEP = GM ? 16 * WPB : 16;  // rows between a wave's tiles
+  const int rfirst = GM ? 16 * wv : 0;
 
-  for (int c_next = take();;) {
-    const int c = __builtin_amdgcn_readfirstlane(c_next);
+  for (int c_next = GM ? 0 : take();;) {
+    int c;
+    if constexpr (GM) {
+      if (threadIdx.x == 0) col_sh = atomicAdd(next_col, 1);
+      __syncthreads();
+      c = __builtin_amdgcn_readfirstlane(col_sh);
+    } else {
+      c = __builtin_amdgcn_readfirstlane(c_next);
+    }
     if (c >= c_hi) break;
-    c_next = take();
+    if constexpr (!GM) c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     double accT[N3][4];
@@ -199,13 +214,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     double accL[4] = {0.0, 0.0, 0.0, 0.0};  // last tile when transposed: feature 16 (N3 - 1) + g, over rows r16
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
-    double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
-    for (int r0 = 0; r0 < nn; r0 += 16) {
+    double s_next = rfirst + r16 < nn ? Rs[(rfirst + r16) * 4] : 0.0;  // s of the next tile is always in flight
+    for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const double* vec = vs + z0;  // per-tile LDS reads instead of hoisted registers
       const int row = r0 + r16;
       const double s = s_next;
-      s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
+      s_next = row + RSTEP < nn ? Rs[(row + RSTEP) * 4] : 0.0;
       double* const recb =
           ST ? static_cast<double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) : nullptr;
       double* const rec = ST ? recb + r16 * 16 + g : nullptr;
@@ -301,13 +316,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         accT[o][k] = x * A.inv_nm;
       }
     double* T = reinterpret_cast<double*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
-    if (g == 0) {
-#pragma unroll
-      for (int o = 0; o < NR; ++o) {
-        const int feat = 16 * o + r16;
-        if (feat < M1) *reinterpret_cast<d4*>(T + feat * 4) = d4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
-      }
-    }
     if constexpr (TLAST) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -316,20 +324,46 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (int msk = 1; msk < 16; msk <<= 1) x += shfl_xor_d(x, msk);
         accL[k] = x * A.inv_nm;
       }
+    }
+    // group mode: each wave's partial T to LDS (the h2s tiles, free once
+    // every wave has left its tile loop), then the sum in wave order
+    double* const dst = GM ? &h2s[0][0][0] + wv * M1 * 4 : T;
+    if constexpr (GM) __syncthreads();
+    if (g == 0) {
+#pragma unroll
+      for (int o = 0; o < NR; ++o) {
+        const int feat = 16 * o + r16;
+        if (feat < M1) *reinterpret_cast<d4*>(dst + feat * 4) = d4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+      }
+    }
+    if constexpr (TLAST) {
       if (r16 == 0 && g < REM)
-        *reinterpret_cast<d4*>(T + (16 * (N3 - 1) + g) * 4) = d4{accL[0], accL[1], accL[2], accL[3]};
+        *reinterpret_cast<d4*>(dst + (16 * (N3 - 1) + g) * 4) = d4{accL[0], accL[1], accL[2], accL[3]};
+    }
+    if constexpr (GM) {
+      static_assert(WPB * M1 * 4 <= WPB * 16 * (kP2 + 1), "partials fit the h2s tiles");
+      __syncthreads();
+      const double* red = &h2s[0][0][0];
+      for (int e = threadIdx.x; e < M1 * 4; e += 64 * WPB) {
+        double x = red[e];
+        for (int w = 1; w < WPB; ++w) x += red[w * M1 * 4 + e];
+        T[e] = x;
+      }
+      __syncthreads();  // h2s and col_sh are reused by the next column
     }
   }
 }
 
 // ============================================================== FP64 backward
-template <int W, int WPB, bool ST>
+// GM: group mode as in the forward (the waves share the column's g_T tile).
+template <int W, int WPB, bool ST, bool GM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_embed_bwd_f64(EmbArgs A) {
   constexpr int M1 = 4 * W;
   // F3t | B3; with the activation store F3t is not needed and its space
   // holds F2 | B2 | the vector block instead (no global operand loads)
   __shared__ double fr[8192 + 8192];
-  __shared__ d4 gts[WPB][kP3];
+  __shared__ d4 gts[GM ? 1 : WPB][kP3];
+  __shared__ int col_sh;  // group mode: the work-group's column
   DPSE_NET_PROLOGUE(WPB)
   const double* gsrc = A.frag64 + net * A.fo.per_net;
   const double* vecg = A.vec64 + net * A.vec_per_net;
@@ -344,29 +378,40 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
-  for (int c_next = take();;) {
-    const int c = __builtin_amdgcn_readfirstlane(c_next);
+  const int gw = GM ? 0 : wv;  // this wave's g_T tile
+  constexpr int RSTEP = GM ? 16 * WPB : 16;
+  const int rfirst = GM ? 16 * wv : 0;
+  for (int c_next = GM ? 0 : take();;) {
+    int c;
+    if constexpr (GM) {
+      if (threadIdx.x == 0) col_sh = atomicAdd(next_col, 1);
+      __syncthreads();
+      c = __builtin_amdgcn_readfirstlane(col_sh);
+    } else {
+      c = __builtin_amdgcn_readfirstlane(c_next);
+    }
     if (c >= c_hi) break;
-    c_next = take();
+    if constexpr (!GM) c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     {
       const double* gT = reinterpret_cast<const double*>(A.gT) + (int64_t)col * M1 * 4;
-      wave_lds_sync();
-      for (int p = lane; p < kP3; p += 64) {
+      if constexpr (!GM) wave_lds_sync();
+      for (int p = GM ? (int)threadIdx.x : lane; p < kP3; p += GM ? 64 * WPB : 64) {
         const int a = feat3d_of_slot<W>(p);
         d4 x = {0.0, 0.0, 0.0, 0.0};
         if (a >= 0) x = *reinterpret_cast<const d4*>(gT + a * 4) * A.inv_nm;
-        gts[wv][p] = x;
+        gts[gw][p] = x;
       }
-      wave_lds_sync();
+      if constexpr (GM) __syncthreads();
+      else wave_lds_sync();
     }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
     d4 R_next = {0.0, 0.0, 0.0, 0.0};  // row of the next tile is always in flight
-    if (r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + r16 * 4);
-    for (int r0 = 0; r0 < nn; r0 += 16) {
+    if (rfirst + r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (rfirst + r16) * 4);
+    for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const double* F2 = ST ? fr + z0 : opaque(gsrc + A.fo.F2);
       const double* B2 = ST ? fr + 2048 + z0 : opaque(gsrc + A.fo.B2);
@@ -375,7 +420,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       const bool valid = row < nn;
       const d4 Rrow = R_next;
       R_next = d4{0.0, 0.0, 0.0, 0.0};
-      if (row + 16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + 16) * 4);
+      if (row + RSTEP < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + RSTEP) * 4);
       const double s = Rrow[0];
       const double* rec =
           ST ? static_cast<const double*>(A.act) + ((int64_t)i * A.tpa + A.toff[tj] + (r0 >> 4)) * (M1 * 16) + g * 16 + r16
@@ -464,7 +509,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
               t3 = tanh_d(z[v]);
             }
             const double G = h2[o4][v] + t3;
-            const d4 gt = gts[wv][p];
+            const d4 gt = gts[gw][p];
             const double dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
 #pragma unroll
             for (int k = 0; k < 4; ++k) dRd[k] = fma(gt[k], G, dRd[k]);
@@ -520,6 +565,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
       if (g == 0 && valid) *reinterpret_cast<d4*>(A.netd + (rbase + row) * 4) = d4{dRd[0] + dsp, dRd[1], dRd[2], dRd[3]};
     }
+    if constexpr (GM) __syncthreads();  // the g_T tile and col_sh are reused by the next column
   }
 }
 
@@ -1014,10 +1060,10 @@ static unsigned emb_groups(dp_ctx* c, int wpb, int per_cu) {
   return (unsigned)(need < res ? need : res);
 }
 
-template <int W, bool ST>
+template <int W, bool ST, bool GM>
 static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, hipStream_t s) {
-  if (bwd) hipLaunchKernelGGL((k_embed_bwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST>), grid, block, 0, s, A);
+  if (bwd) hipLaunchKernelGGL((k_embed_bwd_f64<W, kWPB64, ST, GM>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST, GM>), grid, block, 0, s, A);
 }
 
 template <class P, int W, int WPB>
@@ -1039,8 +1085,20 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)(A.ntypes * A.ntypes));
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
-    if (A.act) launch_embed_f64<W, true>(bwd, grid, block, A, s);
-    else launch_embed_f64<W, false>(bwd, grid, block, A, s);
+    // group mode when the columns (one per atom and neighbour section) are
+    // fewer than the chip's wave slots: about one work-group per CU in all,
+    // each taking whole columns with all its waves
+    const int nnets = A.ntypes * A.ntypes;
+    const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb;
+    if (gm) {
+      const int64_t per = c->ncu / nnets > 0 ? c->ncu / nnets : 1;
+      grid.x = (unsigned)(c->natoms_last < per ? c->natoms_last : per);
+      if (A.act) launch_embed_f64<W, true, true>(bwd, grid, block, A, s);
+      else launch_embed_f64<W, false, true>(bwd, grid, block, A, s);
+    } else {
+      if (A.act) launch_embed_f64<W, true, false>(bwd, grid, block, A, s);
+      else launch_embed_f64<W, false, false>(bwd, grid, block, A, s);
+    }
   } else if (kind == 1) {
     launch_embed_lp<PrecBF16, W, kWPBlp>(bwd, grid, block, A, s);
   } else if (kind == 2) {
