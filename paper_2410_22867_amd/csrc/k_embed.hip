@@ -582,7 +582,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 // operand moves between lanes and the per-atom T needs no cross-lane
 // reduction.  The FP32 form keeps the vector contraction (its 16x16x4
 // products would cost more than the multiply-adds they replace).
-template <class P, int W, int WPB>
+// GM: group mode as in the FP64 kernels (a work-group's waves share a column).
+template <class P, int W, int WPB, bool GM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
@@ -592,6 +593,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
   __shared__ __attribute__((aligned(16))) ST fr[NF2 + NF3];
   __shared__ float h2s[WPB][16][kP2 + 1];
   __shared__ float vs[kVecPerNet];
+  __shared__ int col_sh;  // group mode: the work-group's column
   DPSE_NET_PROLOGUE(WPB)
   {
     const ST* src = reinterpret_cast<const ST*>(A.fraglp) + net * A.fo.per_net;
@@ -630,10 +632,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       b3s[o] = f4{b3, b3, b3, b3};
     }
   }
-  for (int c_next = take();;) {
-    const int c = __builtin_amdgcn_readfirstlane(c_next);
+  constexpr int RSTEP = GM ? 16 * WPB : 16;  // rows between a wave's tiles
+  const int rfirst = GM ? 16 * wv : 0;
+  for (int c_next = GM ? 0 : take();;) {
+    int c;
+    if constexpr (GM) {
+      if (threadIdx.x == 0) col_sh = atomicAdd(next_col, 1);
+      __syncthreads();
+      c = __builtin_amdgcn_readfirstlane(col_sh);
+    } else {
+      c = __builtin_amdgcn_readfirstlane(c_next);
+    }
     if (c >= c_hi) break;
-    c_next = take();
+    if constexpr (!GM) c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     float accT[N3][4];
@@ -643,19 +654,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
-    double s_next = r16 < nn ? Rs[r16 * 4] : 0.0;  // s of the next tile is always in flight
+    double s_next = rfirst + r16 < nn ? Rs[(rfirst + r16) * 4] : 0.0;  // s of the next tile is always in flight
     // 16-bit forms: column r16 % 4 of rows 4g..4g+3 of the next tile, also in
     // flight (row indices clamped into the section, unused values discarded)
     double rc_next[4];
     if constexpr (MC) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) rc_next[v] = Rs[min(4 * g + v, nn - 1) * 4 + (r16 & 3)];
+      for (int v = 0; v < 4; ++v) rc_next[v] = Rs[min(rfirst + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
     }
-    for (int r0 = 0; r0 < nn; r0 += 16) {
+    for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
       const float s = (float)s_next;
-      s_next = row + 16 < nn ? Rs[(row + 16) * 4] : 0.0;
+      s_next = row + RSTEP < nn ? Rs[(row + RSTEP) * 4] : 0.0;
       // rows of the contraction, requested before layers 1-2 run: the vector
       // form needs all four columns of rows 4g..4g+3, the matrix form column
       // r16 (< 4) of them as its B operand
@@ -668,7 +679,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
           float x = (float)rc_next[v];
           asm volatile("" : "+v"(x));  // FP64 -> FP32 -> FP16, as the FP32 form sees it
           rv[v] = r16 < 4 && r0 + 4 * g + v < nn ? x : 0.f;
-          rc_next[v] = Rs[min(r0 + 16 + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
+          rc_next[v] = Rs[min(r0 + RSTEP + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
         }
         bR = pack4_f16(rv);
       } else {
@@ -744,6 +755,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     }
     const float inv_nm = (float)A.inv_nm;
     float* T = reinterpret_cast<float*>(A.Tpart) + tj * A.tpart_stride + (int64_t)col * M1 * 4;
+    // group mode: each wave's partial T to LDS (the h2s tiles, free once every
+    // wave has left its tile loop), then the sum in wave order
+    float* const dst = GM ? &h2s[0][0][0] + wv * M1 * 4 : T;
+    if constexpr (GM) __syncthreads();
     if constexpr (MC) {
       // lane (k = r16 < 4, g) holds T[16 o + 4 g + e][k] in element e
       if (r16 < 4) {
@@ -752,7 +767,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int feat = 16 * o + 4 * g + e;
-            if (feat < M1) T[feat * 4 + r16] = accT[o][e] * inv_nm;
+            if (feat < M1) dst[feat * 4 + r16] = accT[o][e] * inv_nm;
           }
       }
     } else {
@@ -769,9 +784,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
         for (int o = 0; o < N3; ++o) {
           const int feat = 16 * o + r16;
-          if (feat < M1) *reinterpret_cast<f4*>(T + feat * 4) = f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
+          if (feat < M1) *reinterpret_cast<f4*>(dst + feat * 4) = f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]};
         }
       }
+    }
+    if constexpr (GM) {
+      static_assert(WPB * M1 * 4 <= WPB * 16 * (kP2 + 1), "partials fit the h2s tiles");
+      __syncthreads();
+      const float* red = &h2s[0][0][0];
+      for (int e = threadIdx.x; e < M1 * 4; e += 64 * WPB) {
+        float x = red[e];
+        for (int w = 1; w < WPB; ++w) x += red[w * M1 * 4 + e];
+        T[e] = x;
+      }
+      __syncthreads();  // h2s and col_sh are reused by the next column
     }
   }
 }
@@ -794,7 +820,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 // g_T is kept in LDS as FP16 per slot (A of the first product) and
 // transposed per column k (A of the second, built once per centre atom).
 // The FP32 form keeps the vector multiply-adds.
-template <class P, int W, int WPB>
+template <class P, int W, int WPB, bool GM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
@@ -802,10 +828,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
   typedef typename P::store_t ST;
   typedef typename P::raw8 R8;
   __shared__ __attribute__((aligned(16))) ST fr[NFR];
-  __shared__ f4 gts[MC ? 1 : WPB][kP3];           // FP32 form: g_T per slot
-  __shared__ u16x4 gth[MC ? WPB : 1][kP3];        // 16-bit forms: g_T per slot, FP16
-  __shared__ u16x4 gtt[MC ? WPB : 1][4][kP3 / 4];  // 16-bit forms: column k of g_T, FP16
+  constexpr int NG = GM ? 1 : WPB;                // g_T tiles (group mode: one, shared)
+  __shared__ f4 gts[MC ? 1 : NG][kP3];            // FP32 form: g_T per slot
+  __shared__ u16x4 gth[MC ? NG : 1][kP3];         // 16-bit forms: g_T per slot, FP16
+  __shared__ u16x4 gtt[MC ? NG : 1][4][kP3 / 4];   // 16-bit forms: column k of g_T, FP16
   __shared__ float vs[kVecPerNet];
+  __shared__ int col_sh;  // group mode: the work-group's column
   DPSE_NET_PROLOGUE(WPB)
   {
     const ST* src = reinterpret_cast<const ST*>(A.fraglp) + net * A.fo.per_net;
@@ -832,16 +860,26 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
     b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
   }
-  for (int c_next = take();;) {
-    const int c = __builtin_amdgcn_readfirstlane(c_next);
+  const int gw = GM ? 0 : wv;  // this wave's g_T tile
+  constexpr int RSTEP = GM ? 16 * WPB : 16;
+  const int rfirst = GM ? 16 * wv : 0;
+  for (int c_next = GM ? 0 : take();;) {
+    int c;
+    if constexpr (GM) {
+      if (threadIdx.x == 0) col_sh = atomicAdd(next_col, 1);
+      __syncthreads();
+      c = __builtin_amdgcn_readfirstlane(col_sh);
+    } else {
+      c = __builtin_amdgcn_readfirstlane(c_next);
+    }
     if (c >= c_hi) break;
-    c_next = take();
+    if constexpr (!GM) c_next = take();
     const int col = cb + c;
     const int i = A.atom_at[col];
     {
       const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
-      wave_lds_sync();
-      for (int p = lane; p < kP3; p += 64) {
+      if constexpr (!GM) wave_lds_sync();
+      for (int p = GM ? (int)threadIdx.x : lane; p < kP3; p += GM ? 64 * WPB : 64) {
         const int a = feat3_of_slot<W>(p);
         f4 x = {0.f, 0.f, 0.f, 0.f};
         if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4);
@@ -849,35 +887,36 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
           u16x4 h;
 #pragma unroll
           for (int k = 0; k < 4; ++k) h[k] = PrecF16::bits(x[k]);
-          gth[wv][p] = h;
-          uint16_t* tk = reinterpret_cast<uint16_t*>(&gtt[wv][0][0]);
+          gth[gw][p] = h;
+          uint16_t* tk = reinterpret_cast<uint16_t*>(&gtt[gw][0][0]);
 #pragma unroll
           for (int k = 0; k < 4; ++k) tk[k * kP3 + p] = h[k];
         } else {
-          gts[wv][p] = x;
+          gts[gw][p] = x;
         }
       }
-      wave_lds_sync();
+      if constexpr (GM) __syncthreads();
+      else wave_lds_sync();
     }
     // A operands of the direct-term product, per centre atom: lane (m, g),
     // tile o, element v holds g_T[16o + 4g + v][m % 4]
     h16x4 aD[8];
     if constexpr (MC) {
 #pragma unroll
-      for (int o = 0; o < 8; ++o) aD[o] = __builtin_bit_cast(h16x4, gtt[wv][r16 & 3][4 * o + g]);
+      for (int o = 0; o < 8; ++o) aD[o] = __builtin_bit_cast(h16x4, gtt[gw][r16 & 3][4 * o + g]);
     }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
     d4 R_next = {0.0, 0.0, 0.0, 0.0};  // row of the next tile is always in flight
-    if (r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + r16 * 4);
-    for (int r0 = 0; r0 < nn; r0 += 16) {
+    if (rfirst + r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (rfirst + r16) * 4);
+    for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
       const bool valid = row < nn;
       const d4 Rd = R_next;
       R_next = d4{0.0, 0.0, 0.0, 0.0};
-      if (row + 16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + 16) * 4);
+      if (row + RSTEP < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + RSTEP) * 4);
       const float Rrow[4] = {(float)Rd[0], (float)Rd[1], (float)Rd[2], (float)Rd[3]};
       const float s = Rrow[0];
       float t1[8];
@@ -935,7 +974,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oF3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
         f4 dGv;
         if constexpr (MC) {
-          dGv = mfma_f16k16(__builtin_bit_cast(h16x4, gth[wv][16 * o + r16]), bR, f4{0.f, 0.f, 0.f, 0.f});
+          dGv = mfma_f16k16(__builtin_bit_cast(h16x4, gth[gw][16 * o + r16]), bR, f4{0.f, 0.f, 0.f, 0.f});
         }
         float G4[4];
 #pragma unroll
@@ -947,7 +986,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
             dG = dGv[v];
             G4[v] = G;
           } else {
-            const f4 gt = gts[wv][16 * o + 4 * g + v];
+            const f4 gt = gts[gw][16 * o + 4 * g + v];
             dG = gt[0] * Rrow[0] + gt[1] * Rrow[1] + gt[2] * Rrow[2] + gt[3] * Rrow[3];
 #pragma unroll
             for (int k = 0; k < 4; ++k) dRd[k] = fmaf(gt[k], G, dRd[k]);
@@ -1014,6 +1053,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
             d4{((double)dRd[0] + (double)dsp) * inv_nm, (double)dRd[1] * inv_nm, (double)dRd[2] * inv_nm,
                (double)dRd[3] * inv_nm};
     }
+    if constexpr (GM) __syncthreads();  // the g_T tile and col_sh are reused by the next column
   }
 }
 
@@ -1066,10 +1106,17 @@ static void launch_embed_f64(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, 
   else hipLaunchKernelGGL((k_embed_fwd_f64<W, kWPB64, ST, GM>), grid, block, 0, s, A);
 }
 
-template <class P, int W, int WPB>
-static void launch_embed_lp(bool bwd, dim3 grid, dim3 block, const EmbArgs& A, hipStream_t s) {
-  if (bwd) hipLaunchKernelGGL((k_embed_bwd_lp<P, W, WPB>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_embed_fwd_lp<P, W, WPB>), grid, block, 0, s, A);
+// Mixed kernels: the forward with WPBF waves per work-group, the backward
+// with WPBB; GM selects group mode.
+template <class P, int W, int WPBF, int WPBB>
+static void launch_embed_lp_gm(bool bwd, bool gm, dim3 grid, const EmbArgs& A, hipStream_t s) {
+  if (bwd) {
+    if (gm) hipLaunchKernelGGL((k_embed_bwd_lp<P, W, WPBB, true>), grid, dim3(64 * WPBB), 0, s, A);
+    else hipLaunchKernelGGL((k_embed_bwd_lp<P, W, WPBB, false>), grid, dim3(64 * WPBB), 0, s, A);
+  } else {
+    if (gm) hipLaunchKernelGGL((k_embed_fwd_lp<P, W, WPBF, true>), grid, dim3(64 * WPBF), 0, s, A);
+    else hipLaunchKernelGGL((k_embed_fwd_lp<P, W, WPBF, false>), grid, dim3(64 * WPBF), 0, s, A);
+  }
 }
 
 // Resident work-groups per CU: FP64 one 8-wave group; the 16-bit forms
@@ -1099,14 +1146,17 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
       if (A.act) launch_embed_f64<W, true, false>(bwd, grid, block, A, s);
       else launch_embed_f64<W, false, false>(bwd, grid, block, A, s);
     }
-  } else if (kind == 1) {
-    launch_embed_lp<PrecBF16, W, kWPBlp>(bwd, grid, block, A, s);
-  } else if (kind == 2) {
-    launch_embed_lp<PrecF16, W, kWPBlp>(bwd, grid, block, A, s);
-  } else if (bwd) {
-    hipLaunchKernelGGL((k_embed_bwd_lp<PrecF32, W, 8>), grid, block, 0, s, A);
   } else {
-    hipLaunchKernelGGL((k_embed_fwd_lp<PrecF32, W, kWPBlp>), grid, block, 0, s, A);
+    // group mode on the same rule as FP64 (columns fewer than wave slots)
+    const int nnets = A.ntypes * A.ntypes;
+    const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb * per_cu;
+    if (gm) {
+      const int64_t per = (int64_t)c->ncu * per_cu / nnets > 0 ? (int64_t)c->ncu * per_cu / nnets : 1;
+      grid.x = (unsigned)(c->natoms_last < per ? c->natoms_last : per);
+    }
+    if (kind == 1) launch_embed_lp_gm<PrecBF16, W, kWPBlp, kWPBlp>(bwd, gm, grid, A, s);
+    else if (kind == 2) launch_embed_lp_gm<PrecF16, W, kWPBlp, kWPBlp>(bwd, gm, grid, A, s);
+    else launch_embed_lp_gm<PrecF32, W, kWPBlp, 8>(bwd, gm, grid, A, s);
   }
 }
 
