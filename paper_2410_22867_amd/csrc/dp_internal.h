@@ -16,7 +16,7 @@ constexpr int kColPad = 128;     // fitting-GEMM column tile; type segments are 
 constexpr int kSplitMax = 16, kSplitCols = 2048;
 constexpr int kCandCap = 512;    // neighbour candidates inside r_c per atom (LDS capacity)
 constexpr int kMaxNm = 1024;     // sum(sel)
-constexpr int kRedChunk = 1024;  // atoms per partial sum of the per-frame reductions
+constexpr int kRedChunk = 256;  // atoms per partial sum of the per-frame reductions
 
 // Slot layout of the embedding activations (see k_embed.hip): widths
 // (w, 2w, 4w) with w <= 32 occupy 32, 64 and 128 slots.

@@ -392,8 +392,10 @@ void launch_force(dp_ctx* c, const double* x, const int32_t* nlist, int32_t ntot
 
 // ---------------------------------------------------------------- reductions
 // Per-frame E_f = sum of E_i and W_f = sum of per-atom virial rows in two
-// fixed-order stages: one block per chunk of kRedChunk atoms of a frame,
-// then the frame's chunks in order (deterministic).  With a counter array
+// fixed-order stages (deterministic): one block per chunk of kRedChunk atoms
+// of a frame (one atom per thread, wave shuffle trees, the four waves in
+// order), then the frame's chunks (lane l of one wave adds chunks l, l + 64,
+// ..., then a shuffle tree).  With a counter array
 // (no empty frame) the second stage is done by the frame's last chunk block
 // to finish, which resets the frame's counter; otherwise by k_frame_reduce.
 __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restrict__ fr, int nframes,
@@ -401,9 +403,11 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restric
                                                       double* __restrict__ part, int32_t* __restrict__ ctr,
                                                       double* __restrict__ E, double* __restrict__ W,
                                                       int32_t* __restrict__ flags) {
-  __shared__ double red[10][256];
+  static_assert(kRedChunk == 256, "one atom per thread");
+  __shared__ double red[4][10];
   __shared__ bool last;
   const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int lo = 0, hi = nframes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -412,23 +416,24 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restric
   const FrameInfo F = fr[lo];
   const int a0 = F.atom_off + (b - F.chunk_off) * kRedChunk;
   const int a1 = min(F.atom_off + F.natoms, a0 + kRedChunk);
+  const int k = a0 + (int)threadIdx.x;
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = a0 + (int)threadIdx.x; k < a1; k += 256) {
-    acc[0] += Ei[k];
+  if (k < a1) {
+    acc[0] = Ei[k];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[1 + c] += vatom[(int64_t)k * 9 + c];
+    for (int c = 0; c < 9; ++c) acc[1 + c] = vatom[(int64_t)k * 9 + c];
   }
+  // wave sums (a fixed shuffle tree), then the four waves in order
 #pragma unroll
-  for (int c = 0; c < 10; ++c) red[c][threadIdx.x] = acc[c];
+  for (int c = 0; c < 10; ++c) acc[c] = wave_sum_d(acc[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 10; ++c) red[wv][c] = acc[c];
+  }
   __syncthreads();
-  for (int off = 128; off >= 1; off >>= 1) {
-    if (threadIdx.x < off)
-#pragma unroll
-      for (int c = 0; c < 10; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
-    __syncthreads();
-  }
   if (threadIdx.x < 10) {
-    part[(int64_t)b * 10 + threadIdx.x] = red[threadIdx.x][0];
+    part[(int64_t)b * 10 + threadIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
     if (ctr != nullptr) __threadfence();
   }
   if (ctr == nullptr) return;
@@ -440,33 +445,42 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const FrameInfo* __restric
   __syncthreads();
   if (!last) return;
   __threadfence();
-  if (threadIdx.x < 10) {
+  // the frame's chunks: lane l of the first wave sums chunks l, l + 64, ...
+  // (a fixed order), then a shuffle tree
+  if (wv == 0) {
     const int nc = (F.natoms + kRedChunk - 1) / kRedChunk;
-    double acc = 0.0;
-    for (int c = 0; c < nc; ++c) acc += part[(int64_t)(F.chunk_off + c) * 10 + threadIdx.x];
-    if (threadIdx.x == 0) {
-      E[lo] = acc;
-      if (!isfinite(acc)) set_flag(flags, DP_FLAG_NONFINITE);
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = lane; c < nc; c += 64)
+#pragma unroll
+      for (int q = 0; q < 10; ++q) s[q] += part[(int64_t)(F.chunk_off + c) * 10 + q];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) s[q] = wave_sum_d(s[q]);
+    if (lane == 0) {
+      E[lo] = s[0];
+      if (!isfinite(s[0])) set_flag(flags, DP_FLAG_NONFINITE);
       ctr[lo] = 0;
-    } else {
-      W[9 * lo + threadIdx.x - 1] = acc;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) W[9 * lo + q] = s[1 + q];
     }
   }
 }
 
 __global__ __launch_bounds__(64) void k_frame_reduce(const FrameInfo* __restrict__ fr, const double* __restrict__ part,
                                                      double* __restrict__ E, double* __restrict__ W, int32_t* flags) {
-  const int f = blockIdx.x;
+  // the same order as the last chunk block's sum in k_chunk_reduce
+  const int f = blockIdx.x, lane = threadIdx.x;
   const int c0 = fr[f].chunk_off, nc = (fr[f].natoms + kRedChunk - 1) / kRedChunk;
-  if (threadIdx.x < 10) {
-    double acc = 0.0;
-    for (int c = 0; c < nc; ++c) acc += part[(int64_t)(c0 + c) * 10 + threadIdx.x];
-    if (threadIdx.x == 0) {
-      E[f] = acc;
-      if (!isfinite(acc)) set_flag(flags, DP_FLAG_NONFINITE);
-    } else {
-      W[9 * f + threadIdx.x - 1] = acc;
-    }
+  double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = lane; c < nc; c += 64)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) s[q] += part[(int64_t)(c0 + c) * 10 + q];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) s[q] = wave_sum_d(s[q]);
+  if (lane == 0) {
+    E[f] = s[0];
+    if (!isfinite(s[0])) set_flag(flags, DP_FLAG_NONFINITE);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) W[9 * f + q] = s[1 + q];
   }
 }
 
@@ -555,8 +569,11 @@ __global__ void k_wrap(MdArgs A) {
 // the partials in block order.
 __global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ part, int32_t* __restrict__ ctr,
                                               double scale) {
-  __shared__ double red[256];
+  // block and grid sums in a fixed order: wave shuffle trees, the four
+  // waves in order, then the blocks' partials lane-strided in the last block
+  __shared__ double red[4];
   __shared__ bool last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double acc = 0.0;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < A.n) {
@@ -569,31 +586,23 @@ __global__ __launch_bounds__(256) void k_kick(MdArgs A, double* __restrict__ par
       acc += 0.5 * m * v * v;
     }
   }
-  red[threadIdx.x] = acc;
+  acc = wave_sum_d(acc);
+  if (lane == 0) red[wv] = acc;
   __syncthreads();
-  for (int off = 128; off >= 1; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = red[0];
+    part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
     __threadfence();
     last = atomicAdd(ctr, 1) == (int)gridDim.x - 1;
   }
   __syncthreads();
-  if (!last) return;
+  if (!last || wv != 0) return;
   __threadfence();
   const int nb = (int)gridDim.x;
   double a2 = 0.0;
-  for (int k = threadIdx.x; k < nb; k += 256) a2 += part[k];
-  red[threadIdx.x] = a2;
-  __syncthreads();
-  for (int off = 128; off >= 1; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    A.ke[0] = red[0] * scale;
+  for (int k = lane; k < nb; k += 64) a2 += part[k];
+  a2 = wave_sum_d(a2);
+  if (lane == 0) {
+    A.ke[0] = a2 * scale;
     *ctr = 0;
   }
 }
