@@ -84,19 +84,40 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   return (p >> 6) * 2 * W + (q >> 5) * W + (q & 31);
 }
 
-// Common prologue of the per-net kernels: block y = net handles centre type
-// ti = y / ntypes, neighbour section tj = y % ntypes.  Work assignment: the
+// The net that work-group row y serves: the nets in decreasing order of
+// their work, the centre type's columns times the neighbour section's row
+// tiles (ceil(sel / 16)), ties in net order.  Rows are dispatched in order,
+// so the heaviest net's work-groups start first and the lighter ones fill
+// the end of the launch.
+__device__ __forceinline__ int net_of_row(const int32_t* meta, const int* sec, int ntypes, int y) {
+  const int nnets = ntypes * ntypes;
+  int64_t wt[kMaxT * kMaxT];
+  for (int k = 0; k < nnets; ++k) {
+    const int kti = k / ntypes, ktj = k - kti * ntypes;
+    wt[k] = (int64_t)meta[2 * kti] * ((sec[ktj + 1] - sec[ktj] + 15) / 16);
+  }
+  for (int k = 0; k < nnets; ++k) {
+    int rank = 0;
+    for (int q = 0; q < nnets; ++q) rank += wt[q] > wt[k] || (wt[q] == wt[k] && q < k);
+    if (rank == y) return k;
+  }
+  return 0;
+}
+
+// Common prologue of the per-net kernels: net = t_i * ntypes + t_j (centre
+// type t_i, neighbour section t_j) from net_of_row.  Work assignment: the
 // net's columns are split into gridDim.x contiguous ranges, one per
 // work-group; inside its range a wavefront takes the next column from the
 // work-group's counter (a word in global memory that no other work-group
 // touches, set by the work-group itself before its first barrier; the next
 // column is requested one column ahead so the atomic's latency hides behind
 // the current column) until the range is exhausted.  Each column's work is
-// done by one wavefront, so results do not depend on the assignment; the
-// waves of a work-group end within about one column of each other, whatever
-// the spread of neighbour counts.
+// done by one wavefront (or, in group mode, by the work-group's waves in a
+// fixed split), so results do not depend on the assignment; the waves of a
+// work-group end within about one column of each other, whatever the spread
+// of neighbour counts.
 #define DPSE_NET_PROLOGUE(WPB)                                            \
-  const int net = blockIdx.y;                                             \
+  const int net = net_of_row(A.meta, A.sec, A.ntypes, blockIdx.y);        \
   const int ti = net / A.ntypes, tj = net - ti * A.ntypes;                \
   const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];                \
   const int c_lo = (int)((int64_t)n_t * blockIdx.x / gridDim.x);          \
@@ -105,7 +126,7 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;              \
   const int r16 = lane & 15, g = lane >> 4;                               \
   (void)wv;                                                               \
-  int* const next_col = A.ctr + (net * gridDim.x + blockIdx.x) * 32;      \
+  int* const next_col = A.ctr + (blockIdx.y * gridDim.x + blockIdx.x) * 32; \
   if (threadIdx.x == 0) atomicExch(next_col, c_lo);                       \
   auto take = [&]() {                                                     \
     int k = 0;                                                            \
@@ -1093,7 +1114,7 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
 // Work-groups per net: as many as the CUs hold at once (FP64: one 8-wave
 // work-group per CU; mixed: three 4-wave work-groups), fewer when the net
 // has fewer columns than that many waves.  Each takes a contiguous range of
-// the net's columns.
+// the net's columns; the nets are ordered by net_of_row.
 static unsigned emb_groups(dp_ctx* c, int wpb, int per_cu) {
   const int64_t need = (c->natoms_last + wpb - 1) / wpb;
   const int64_t res = (int64_t)c->ncu * per_cu;
@@ -1129,13 +1150,13 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int wpb = mode == DP_FP64 || (kind == 3 && bwd) ? 8 : kWPBlp;
   EmbArgs A = emb_args(c, mode);
   const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : 3);
-  dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)(A.ntypes * A.ntypes));
+  const int nnets = A.ntypes * A.ntypes;
+  dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)nnets);  // row y: the y-th heaviest net
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
     // group mode when the columns (one per atom and neighbour section) are
     // fewer than the chip's wave slots: about one work-group per CU in all,
     // each taking whole columns with all its waves
-    const int nnets = A.ntypes * A.ntypes;
     const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb;
     if (gm) {
       const int64_t per = c->ncu / nnets > 0 ? c->ncu / nnets : 1;
@@ -1148,7 +1169,6 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
     }
   } else {
     // group mode on the same rule as FP64 (columns fewer than wave slots)
-    const int nnets = A.ntypes * A.ntypes;
     const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb * per_cu;
     if (gm) {
       const int64_t per = (int64_t)c->ncu * per_cu / nnets > 0 ? (int64_t)c->ncu * per_cu / nnets : 1;
