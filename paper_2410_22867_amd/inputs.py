@@ -118,10 +118,11 @@ COPPER = ModelDesc(ntypes=1, rcut=8.0, rcut_smth=2.0, sel=(500,),
 
 # DP-compress grids (x_fine, x_max, h) of the embedding input x = s(r)/std_s:
 # the fine stride covers r >= 0.5 A for water (r_s, where s = 2/A) and
-# r >= 1.5 A for copper; a coarse stride of 10 h continues to r = 0.1 A and
-# 0.5 A (the random models let atoms approach far closer than real ones).
-COMPRESS_GRID_WATER = (25.0, 125.0, 0.1)
-COMPRESS_GRID_COPPER = (14.0, 40.0, 0.1)
+# r >= 1.5 A for copper; a coarse stride of 10 h continues to r = 0.01 A and
+# 0.05 A (the random models let atoms approach far closer than real ones; at
+# such inputs the first layer's tanh is saturated and G nearly constant).
+COMPRESS_GRID_WATER = (25.0, 1250.0, 0.1)
+COMPRESS_GRID_COPPER = (14.0, 400.0, 0.1)
 
 DT_WATER_FS = 0.5
 DT_COPPER_FS = 1.0
