@@ -165,8 +165,8 @@ def main():
                     help="skip the 98,304-atom water NVE runs (FP64, BF16, FP16)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU spatial decomposition is designed, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (one box of atoms per GPU; the "
+              "spatial decomposition over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
