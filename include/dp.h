@@ -255,7 +255,11 @@ int dp_build_nlist_batch(dp_ctx* ctx, const double* coords, const int32_t* types
  *   atom_energy [n] device f64 or NULL: E_i
  *   forces      [n, 3] device f64: F_i = -dE/dx_i (overwritten)
  *   virial      [9] device f64: W_ab = -sum_ij d_a (dE/dd)_b, row-major
- *   mode        DP_FP64, DP_MIX_BF16 or DP_MIX_FP16.
+ *   mode        DP_FP64, DP_MIX_BF16, DP_MIX_FP16, DP_MIX_FP32,
+ *               DP_MIX_FP16_FIT1 or DP_FP64_TAB.
+ * The list has the layout dp_build_nlist writes: per neighbour-type section
+ * the real entries first, then -1 padding (entries after a section's padding
+ * starts are not used).
  * Positions may drift from where the list was built; r_ij uses the stored
  * image shift.  The types must be the ones the list was built with (its
  * sections are by neighbour type): for a list built or formatted by this
