@@ -308,7 +308,10 @@ int dp_ctx_status(dp_ctx* ctx, int32_t* flags);
  * dp_ctx_create): *capacity_bytes receives its size (0 when the budget was 0),
  * *last_used 1 when the last dp_compute / dp_compute_batch kept the last
  * embedding layer's activations there instead of recomputing them in the
- * backward pass, else 0.  Either pointer may be NULL.  Host-only; no wait. */
+ * backward pass; 2 when that compute was a mixed-precision one and a
+ * dp_backward_params after it filled the store (FP64 embedding forward of the
+ * same frame) for its embedding-gradient pass to read; else 0.  Either
+ * pointer may be NULL.  Host-only; no wait. */
 int dp_ctx_store_info(dp_ctx* ctx, int64_t* capacity_bytes, int32_t* last_used);
 
 /* Inspection of intermediate buffers of the last compute (tests, debugging).

@@ -579,6 +579,7 @@ int compute_impl(dp_ctx* c, const double* x, const int32_t* types, const double*
   }
   { StageScope p(c, DP_STAGE_ENV, s); launch_env(c, x, types, nlist, ntot, forces, s); }
   c->act_used_last = !tab && c->act && mode == DP_FP64 && n * c->model->tpa * (int64_t)c->model->m1 * 16 * 8 <= c->act_bytes;
+  c->grad_act = false;
   {
     StageScope p(c, DP_STAGE_EMBED_FWD, s);
     if (tab) launch_embed_tab(c, false, s);
@@ -1250,6 +1251,16 @@ int dp_backward_params(dp_ctx* c, const double* dL_dE, double* grad_params, hipS
     const MixKinds mk = mix_kinds(c->mode_last);
     const int k1 = mk.fit1 == 3 ? 0 : mk.fit1, k23 = mk.fit23 == 3 ? 0 : mk.fit23;
     const int64_t cols = c->natoms_last + (int64_t)m->desc.ntypes * kColPad;
+    // the embedding gradient recomputes the FP64 activations of the frame;
+    // when the workspace holds them, the FP64 embedding forward with its
+    // store runs first (same inputs, same values) and the gradient reads the
+    // last layer back, which costs less than recomputing it there.  The
+    // forward also writes Tpart, which the widened g_T takes below.
+    if (!c->grad_act && c->act &&
+        (int64_t)c->natoms_last * m->tpa * (int64_t)m->m1 * 16 * 8 <= c->act_bytes) {
+      c->grad_act = true;
+      launch_embed_fwd(c, nullptr, DP_FP64, stream);
+    }
     double* D64 = (double*)c->dD;
     double* f64[6] = {(double*)c->fa[1], (double*)c->fa[3], (double*)c->fa[10],
                       (double*)c->fa[11], (double*)c->fa[5], (double*)c->fa[6]};
@@ -1321,7 +1332,7 @@ int dp_ctx_status(dp_ctx* c, int32_t* flags) {
 int dp_ctx_store_info(dp_ctx* c, int64_t* capacity_bytes, int32_t* last_used) {
   if (!c) { set_error("ctx is NULL"); return DP_ERR_BAD_ARG; }
   if (capacity_bytes) *capacity_bytes = c->act_bytes;
-  if (last_used) *last_used = c->act_used_last ? 1 : 0;
+  if (last_used) *last_used = c->act_used_last ? 1 : (c->grad_act ? 2 : 0);
   return DP_OK;
 }
 

@@ -227,6 +227,7 @@ struct dp_ctx {
   void* act;
   int64_t act_bytes;
   bool act_used_last;
+  bool grad_act;       // act holds the FP64 records of the last compute's frame, written by the gradient pass
   const int32_t* rev_list; // neighbour list rev was built for (by dp_build_nlist on this ctx)
   int64_t natoms_rev;      // atom count of that build
   double* vatom;           // [N, 9]

@@ -1100,7 +1100,7 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
   A.tpart_stride = c->max_cols * m->m1 * 4;
   A.gT = c->gT;
   A.netd = c->netd;
-  A.act = c->act_used_last ? c->act : nullptr;
+  A.act = c->act_used_last || c->grad_act ? c->act : nullptr;
   A.tpa = m->tpa;
   for (int t = 0; t < kMaxT; ++t) A.toff[t] = m->toff[t];
   A.ntypes = m->desc.ntypes;

@@ -713,7 +713,7 @@ void launch_param_grads(dp_ctx* c, const ParamGradInputs& in, const double* dLdE
   dim3 rgrid((kEgRec + 255) / 256, nt * nt);
   // the forward's stored last-layer activations (FP64 computes that fit the
   // workspace) replace the recomputation of the last embedding layer
-  A.act = c->act_used_last ? (const double*)c->act : nullptr;
+  A.act = c->act_used_last || c->grad_act ? (const double*)c->act : nullptr;
   A.tpa = m->tpa;
   for (int t = 0; t <= kMaxT; ++t) A.toff[t] = t <= nt ? m->toff[t] : m->tpa;
   if (m->w1 == 25) {

@@ -351,10 +351,12 @@ class Context:
         return int(f.value)
 
     def store_info(self) -> tuple:
-        """(capacity in bytes, whether the last compute used the activation store)."""
+        """(capacity in bytes, whether the last compute used the activation
+        store, whether a parameter-gradient pass after a mixed-precision
+        compute filled it)."""
         cap, used = ctypes.c_int64(0), ctypes.c_int32(0)
         _check(lib().dp_ctx_store_info(self.handle, ctypes.byref(cap), ctypes.byref(used)))
-        return int(cap.value), bool(used.value)
+        return int(cap.value), used.value == 1, used.value == 2
 
     def profile(self, enable, stages=None) -> None:
         """Per-stage event timing: enable=False releases it; stages (names from

@@ -148,6 +148,42 @@ def test_param_grads_finite_differences(batch):
     b["model"].set_params(b["p"])
 
 
+@pytest.mark.parametrize("mode", ["bf16", "mix_fp32"])
+def test_mixed_param_grads_with_store(batch, mode):
+    """After a mixed-precision compute, a context whose workspace holds the
+    FP64 activations fills it in the gradient pass (FP64 embedding forward
+    of the same frame) and reads the last layer back: the parameter
+    gradient matches that of the recomputing context, and a second gradient
+    pass over the same compute gives the same result (up to the order of
+    the FP64 atomic sums)."""
+    b = batch
+    _say("mixed param grads with store", mode)
+    from paper_2410_22867_amd import dpse
+    ctx2 = dpse.Context(b["model"], int(b["off"][-1]), max_frames=len(b["frames"]), budget_bytes=1 << 30)
+    nl2, _ = ctx2.build_nlist_batch(b["x"], b["t"], b["boxes"], b["off"])
+    B = len(b["frames"])
+    dLdE = torch.linspace(-0.3, 0.5, B, dtype=torch.float64, device=b["dev"])
+    grads = []
+    for ctx, nl in ((b["ctx"], b["nl"]), (ctx2, nl2)):
+        ctx.compute_batch(b["x"], b["t"], b["boxes"], b["off"], nl, mode=mode)
+        g = [ctx.backward_params(dLdE).cpu().numpy() for _ in range(2)]
+        torch.cuda.synchronize()
+        grads.append(g)
+    assert b["ctx"].store_info()[1:] == (False, False)
+    assert ctx2.store_info()[1:] == (False, True)
+    (g1, g1b), (g2, g2b) = grads
+    scale = np.abs(g1).max()
+    # the weight-gradient sums use FP64 atomics: equal up to summation order
+    assert np.abs(g1b - g1).max() <= 1e-13 * scale
+    assert np.abs(g2b - g2).max() <= 1e-13 * scale
+    assert np.abs(g2 - g1).max() <= 1e-12 * scale
+    # a following FP64 compute on the same context uses the store itself
+    ctx2.compute_batch(b["x"], b["t"], b["boxes"], b["off"], nl2, mode="fp64")
+    torch.cuda.synchronize()
+    assert ctx2.store_info()[1:] == (True, False)
+    ctx2.close()
+
+
 @pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01), ("mix_fp32", 1e-4), ("mix_fp16", 0.01)])
 def test_mixed_param_grads_close_to_oracle(batch, mode, tol):
     """Mixed-precision form of the training step: energies, forces and
