@@ -201,6 +201,43 @@ __device__ __forceinline__ float tanh_f(float x) {
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
+// Rows of an environment-matrix section through a buffer resource that
+// spans its nn valid rows (32 bytes each): the hardware's range check returns
+// zeros for rows past them, so a load needs no branch around it and no
+// select on its value.  With either, the compiler waits for every
+// outstanding load at that point, where these loads are meant to stay in
+// flight until their values are used.  Rs and nn are wave-uniform.
+typedef __amdgpu_buffer_rsrc_t env_rsrc_t;
+// Resource word 3 of an untyped buffer on this family: 32-bit data format
+// (a zero format makes every load return zero).
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ env_rsrc_t env_rsrc(const double* Rs, int nn) {
+  // uniform by the caller's contract; read from lane 0 so that the resource
+  // is formed once in scalar registers
+  const unsigned long long a = reinterpret_cast<unsigned long long>(Rs);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  void* const base = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, __builtin_amdgcn_readfirstlane(nn) * 32, kBufWord3);
+}
+__device__ __forceinline__ d4 env_row(env_rsrc_t r, int q) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const u4v a = __builtin_amdgcn_raw_buffer_load_b128(r, q * 32, 0, 0);
+  const u4v b = __builtin_amdgcn_raw_buffer_load_b128(r, q * 32 + 16, 0, 0);
+  d4 x;
+  x[0] = __builtin_bit_cast(double, (unsigned long long)a[0] | ((unsigned long long)a[1] << 32));
+  x[1] = __builtin_bit_cast(double, (unsigned long long)a[2] | ((unsigned long long)a[3] << 32));
+  x[2] = __builtin_bit_cast(double, (unsigned long long)b[0] | ((unsigned long long)b[1] << 32));
+  x[3] = __builtin_bit_cast(double, (unsigned long long)b[2] | ((unsigned long long)b[3] << 32));
+  return x;
+}
+// Element c of row q (same rule).
+__device__ __forceinline__ double env_elt(env_rsrc_t r, int q, int c) {
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
+  const u2v a = __builtin_amdgcn_raw_buffer_load_b64(r, q * 32 + c * 8, 0, 0);
+  return __builtin_bit_cast(double, (unsigned long long)a[0] | ((unsigned long long)a[1] << 32));
+}
+
 // ---------------------------------------------------------------------------
 // Wavefront helpers (wave64).
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }

@@ -675,19 +675,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       for (int k = 0; k < 4; ++k) accT[o][k] = 0.f;
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
-    double s_next = rfirst + r16 < nn ? Rs[(rfirst + r16) * 4] : 0.0;  // s of the next tile is always in flight
+    const env_rsrc_t Rb = env_rsrc(Rs, nn);
+    double s_next = env_elt(Rb, rfirst + r16, 0);  // s of the next tile is always in flight
     // 16-bit forms: column r16 % 4 of rows 4g..4g+3 of the next tile, also in
     // flight (row indices clamped into the section, unused values discarded)
     double rc_next[4];
     if constexpr (MC) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) rc_next[v] = Rs[min(rfirst + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
+      for (int v = 0; v < 4; ++v) rc_next[v] = Rs[max(min(rfirst + 4 * g + v, nn - 1), 0) * 4 + (r16 & 3)];
     }
     for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
       const float s = (float)s_next;
-      s_next = row + RSTEP < nn ? Rs[(row + RSTEP) * 4] : 0.0;
+      s_next = env_elt(Rb, row + RSTEP, 0);
       // rows of the contraction, requested before layers 1-2 run: the vector
       // form needs all four columns of rows 4g..4g+3, the matrix form column
       // r16 (< 4) of them as its B operand
@@ -700,15 +701,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
           float x = (float)rc_next[v];
           asm volatile("" : "+v"(x));  // FP64 -> FP32 -> FP16, as the FP32 form sees it
           rv[v] = r16 < 4 && r0 + 4 * g + v < nn ? x : 0.f;
-          rc_next[v] = Rs[min(r0 + RSTEP + 4 * g + v, nn - 1) * 4 + (r16 & 3)];
+          rc_next[v] = Rs[max(min(r0 + RSTEP + 4 * g + v, nn - 1), 0) * 4 + (r16 & 3)];
         }
         bR = pack4_f16(rv);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int rr = r0 + 4 * g + v;
-          d4 x = {0.0, 0.0, 0.0, 0.0};
-          if (rr < nn) x = *reinterpret_cast<const d4*>(Rs + rr * 4);
+          const d4 x = env_row(Rb, r0 + 4 * g + v);
 #pragma unroll
           for (int k = 0; k < 4; ++k) Rr[v][k] = (float)x[k];
         }
@@ -929,15 +928,14 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
-    d4 R_next = {0.0, 0.0, 0.0, 0.0};  // row of the next tile is always in flight
-    if (rfirst + r16 < nn) R_next = *reinterpret_cast<const d4*>(Rs + (rfirst + r16) * 4);
+    const env_rsrc_t Rb = env_rsrc(Rs, nn);
+    d4 R_next = env_row(Rb, rfirst + r16);  // row of the next tile is always in flight
     for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
       const int row = r0 + r16;
       const bool valid = row < nn;
       const d4 Rd = R_next;
-      R_next = d4{0.0, 0.0, 0.0, 0.0};
-      if (row + RSTEP < nn) R_next = *reinterpret_cast<const d4*>(Rs + (row + RSTEP) * 4);
+      R_next = env_row(Rb, row + RSTEP);
       const float Rrow[4] = {(float)Rd[0], (float)Rd[1], (float)Rd[2], (float)Rd[3]};
       const float s = Rrow[0];
       float t1[8];

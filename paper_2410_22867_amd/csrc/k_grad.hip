@@ -295,14 +295,16 @@ __global__ __launch_bounds__(256) void k_embed_grad_f64(EGradArgs A) {
     }
     const int nn = A.nnei[i * kMaxT + tj];
     const double* Rs = A.R + ((int64_t)i * A.nm + A.sec[tj]) * 4;
+    const env_rsrc_t Rb = env_rsrc(Rs, nn);
+    d4 R_next = env_row(Rb, r16);  // row of the next tile is always in flight
     for (int r0 = 0; r0 < nn; r0 += 16) {
       const double* F2 = opaque(base + A.fo.F2);
       const double* F3 = opaque(base + A.fo.F3t);
       const double* B3 = opaque(base + A.fo.B3);
       const double* B2 = opaque(base + A.fo.B2);
       const int row = r0 + r16;
-      d4 Rrow = {0.0, 0.0, 0.0, 0.0};
-      if (row < nn) Rrow = *reinterpret_cast<const d4*>(Rs + row * 4);
+      const d4 Rrow = R_next;  // zero past the section's real rows
+      R_next = env_row(Rb, row + 16);
       const double s = Rrow[0];
       double t1[2][4];
 #pragma unroll

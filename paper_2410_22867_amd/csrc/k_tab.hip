@@ -197,13 +197,12 @@ __global__ __launch_bounds__(256) void k_embed_fwd_tab(TabArgs A) {
     for (int u = 0; u < NF; ++u)
 #pragma unroll
       for (int k = 0; k < 4; ++k) acc[u][k] = 0.0;
-    d4 Rn = {0.0, 0.0, 0.0, 0.0};
-    if (rg < nn) Rn = *reinterpret_cast<const d4*>(Rs + rg * 4);
+    const env_rsrc_t Rb = env_rsrc(Rs, nn);
+    d4 Rn = env_row(Rb, rg);
     for (int r0 = 0; r0 < nn; r0 += 4) {
       const int row = r0 + rg;
       const d4 Rv = Rn;  // zero past the section's real rows
-      Rn = d4{0.0, 0.0, 0.0, 0.0};
-      if (row + 4 < nn) Rn = *reinterpret_cast<const d4*>(Rs + (row + 4) * 4);
+      Rn = env_row(Rb, row + 4);
       double t;
       bool cl;
       const int k = tab_interval(A.g, Rv[0], t, cl);
@@ -266,13 +265,12 @@ __global__ __launch_bounds__(256) void k_embed_bwd_tab(TabArgs A) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) gt[u][q] = v[q] * A.inv_nm;
     }
-    d4 Rn = {0.0, 0.0, 0.0, 0.0};
-    if (rg < nn) Rn = *reinterpret_cast<const d4*>(Rs + rg * 4);
+    const env_rsrc_t Rb = env_rsrc(Rs, nn);
+    d4 Rn = env_row(Rb, rg);
     for (int r0 = 0; r0 < nn; r0 += 4) {
       const int row = r0 + rg;
       const d4 Rv = Rn;
-      Rn = d4{0.0, 0.0, 0.0, 0.0};
-      if (row + 4 < nn) Rn = *reinterpret_cast<const d4*>(Rs + (row + 4) * 4);
+      Rn = env_row(Rb, row + 4);
       double t;
       bool cl;
       const int k = tab_interval(A.g, Rv[0], t, cl);
