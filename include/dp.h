@@ -319,9 +319,13 @@ int dp_ctx_store_info(dp_ctx* ctx, int64_t* capacity_bytes, int32_t* last_used);
  *        1 = T [n, m1, 4] f64 (atom order; FP32 in mixed modes, widened);
  *        2 = descriptor D [n, m1*m2] f64 (atom order);
  *        3 = dE/dD [n, m1*m2] f64 (atom order);
- *        4 = net_deriv = dE/dR~ [n, nm, 4] f64 (atom order).
- * Copies into dst (device, caller-owned, at least the stated size) on
- * stream; *nbytes receives the size. */
+ *        4 = net_deriv = dE/dR~ [n, nm, 4] f64 (atom order);
+ *        5 = g_T = dE/dT [n, m1, 4] f64 (atom order; FP32 in mixed modes).
+ * Where the compute folded D and dE/dD into the first fitting layer (the
+ * BF16 / FP16 first layer on frames of many atoms) they are formed on
+ * request from the compute's T and dz1 by the plain descriptor and GEMM
+ * passes.  Copies into dst (device, caller-owned, at least the stated size)
+ * on stream; *nbytes receives the size. */
 int dp_ctx_copy_buffer(dp_ctx* ctx, int32_t which, void* dst, int64_t* nbytes, hipStream_t stream);
 
 /* Opt-in per-stage timing with HIP events recorded on the call's stream

@@ -1343,7 +1343,7 @@ int dp_ctx_copy_buffer(dp_ctx* c, int32_t which, void* dst, int64_t* nbytes, hip
   int64_t bytes;
   switch (which) {
     case 0: case 4: bytes = n * m->nm * 4 * 8; break;
-    case 1: bytes = n * m->m1 * 4 * 8; break;
+    case 1: case 5: bytes = n * m->m1 * 4 * 8; break;
     case 2: case 3: bytes = n * m->nd * 8; break;
     default: set_error("which %d out of range", which); return DP_ERR_BAD_ARG;
   }
@@ -1356,7 +1356,11 @@ int dp_ctx_copy_buffer(dp_ctx* c, int32_t which, void* dst, int64_t* nbytes, hip
   else if (which == 4) HIPCHECK(hipMemcpyAsync(dst, c->netd, bytes, hipMemcpyDeviceToDevice, stream));
   else {
     const int32_t md = c->mode_last == DP_FP64_TAB ? DP_FP64 : c->mode_last;
-    if (which == 2 && md == DP_FP64) launch_descriptor_ex(c, DP_FP64, true, stream);
+    // buffers the compute did not form: D on the FP64 path (built inside
+    // the GEMM), D and dE/dD with the fused half-precision first layer (which
+    // writes D only on contexts that keep the layer inputs for gradients)
+    if (which == 2 && (md == DP_FP64 || (fit1_fused(c, md) && !c->h_stored))) launch_descriptor_ex(c, md, true, stream);
+    if (which == 3 && fit1_fused(c, md)) launch_fit1_bwd_gemm(c, md, stream);
     launch_gather_cols(c, which, md, (int32_t)n, (double*)dst, stream);
   }
   HIPCHECK(hipGetLastError());

@@ -297,6 +297,8 @@ void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s);
 void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s);
 void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s);
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s);
+bool fit1_fused(const dp_ctx* c, int32_t mode);
+void launch_fit1_bwd_gemm(dp_ctx* c, int32_t mode, hipStream_t s);
 void launch_embed_bwd(dp_ctx* c, const int32_t* types, int32_t mode, hipStream_t s);
 // DP-compress: table from the model's parameters; tabulated embedding
 // forward (T sections) or backward (net_deriv) of the FP64 path

@@ -771,6 +771,329 @@ static void launch_pair_lp(dp_ctx* c, bool bwd, int mode, const PairArgsLp& p, h
   else launch_pair_lp_t<PrecF32, PrecF32>(bwd, grid, lds, p, s);
 }
 
+// ---------------------------------------------------------------- fused first fitting layer
+// Half-precision forms (16-bit operands, FP32 accumulation) of the first
+// fitting layer with the descriptor folded in on both sides:
+//   forward : h1[col][m] = tanh(sum_k D[col][k] W1[k][m] + b1[m]), D built
+//             from T = sum of the section partials inside the GEMM;
+//   backward: dE/dD = dz1 W1^T is contracted with T in the GEMM's epilogue,
+//             g_T[a][k] = sum_b dD[a][b] T[b][k] + [a < m2] sum_a' dD[a'][a] T[a'][k],
+//             so neither D nor dE/dD passes through HBM.
+// The k order of a 32-wide step is the fragments' (lane group g, element j:
+// k = 32 kt + 16 (j / 4) + 4 g + j % 4), so a lane of a D fragment always
+// holds b = 4 g .. 4 g + 3 and a = 2 kt + j / 4: the four T rows b are kept
+// in registers and one row a is read per step.
+constexpr int kFit1MaxM1 = 128;  // LDS copy of T: 16 B per column and row
+
+struct Fit1Args {
+  const int32_t* meta;   // n_t, cbase_t per centre type
+  const float* Tpart;    // forward: [sections][cols][m1][4] partial T
+  int64_t tstride;       // elements between sections
+  int ntypes;
+  float* T;              // [cols][m1][4]: written by the forward, read by the backward
+  void* D;               // forward: D in the operand type [cols][16 m1], or NULL
+  const void* Afr;       // layer-1 fragments of type 0 (forward W1^T, backward W1)
+  int64_t a_type_stride;
+  const float* vec;      // fitting vectors per type (b1 at offset 0)
+  int64_t vec_type_stride;
+  void* X;               // forward: h1 out, FP32 [cols][ldx]; backward: dz1 in, operand type [cols][ldx]
+  int ldx;
+  float* gT;             // backward: [cols][m1][4]
+  int m1, fw;
+};
+
+// Forward.  A work-group of NW waves owns 16 NB columns of one type and all
+// output features (at most 16 m-tiles): wave w computes m-tiles w + NW i,
+// i < 16 / NW (a tile past the last repeats it; its results are dropped),
+// for the NB column tiles.  Per 32-wide k-step the work-group forms the D
+// fragments of its columns into double-buffered LDS (8 NB / NW values per
+// thread) from an LDS copy of T, and each wave reads its weight fragments
+// from memory, PF k-steps ahead through a ring of registers.
+template <class P, int NB, int NW, int PF>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_fit1_fwd_lp(Fit1Args f) {
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  typedef typename P::raw4 R4;
+  constexpr int NT = 64 * NW;      // threads
+  constexpr int CW = 16 * NB;
+  constexpr int MPW = 16 / NW;     // m-tiles per wave
+  constexpr int EPT = 8 * NB / NW; // D elements per thread and k-step
+  static_assert(EPT == 1 || EPT == 2 || EPT == 4, "D elements of a thread share one half of a lane's fragment");
+  __shared__ f4 Ts[CW * kFit1MaxM1];  // [CW][m1]
+  __shared__ __attribute__((aligned(16))) ST bfr[2][NB][64 * 8];
+  const int t = blockIdx.z;
+  const int n_t = f.meta[2 * t], cb = f.meta[2 * t + 1];
+  const int c0 = blockIdx.x * CW;
+  if (c0 >= n_t) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, gq = lane >> 4;
+  const int m1 = f.m1, nd = 16 * m1, KT = nd / 32;
+  // T of the work-group's columns (zero past the type's atoms), also to HBM:
+  // thread tid sums rows e = tid + NT u of the column-major [CW][m1] tile;
+  // every load of a section is issued before any is used
+  {
+    constexpr int U = (CW * kFit1MaxM1 + NT - 1) / NT;
+    const float* base = f.Tpart + (int64_t)(cb + c0) * m1 * 4;
+    const int lim = min(CW, n_t - c0) * m1;  // rows of real columns
+    f4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < f.ntypes; ++s) {
+      f4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = tid + NT * u;
+        x[u] = e < lim ? *reinterpret_cast<const f4*>(base + s * f.tstride + (int64_t)e * 4) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] += x[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + NT * u;
+      if (e < CW * m1) {
+        Ts[e] = v[u];
+        *reinterpret_cast<f4*>(f.T + (int64_t)(cb + c0) * m1 * 4 + (int64_t)e * 4) = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  // this thread's D elements: column tile dq, fragment lane dl, elements
+  // dj0 .. dj0 + EPT - 1, all with j / 4 = dh (a = 2 kt + dh):
+  // tid = dq 64 (8 / EPT) + dl (8 / EPT) + dj0 / EPT
+  constexpr int TPL = 8 / EPT;  // threads per fragment lane
+  const int dq = tid / (64 * TPL);
+  const int dl = (tid / TPL) & 63;
+  const int dj0 = (tid % TPL) * EPT;
+  const int dh = dj0 >> 2;
+  const int dcol = dq * 16 + (dl & 15);
+  f4 Tb[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) Tb[u] = Ts[dcol * m1 + 4 * (dl >> 4) + ((dj0 + u) & 3)];
+  ST* const dglob = f.D ? static_cast<ST*>(f.D) + (int64_t)(cb + c0 + dcol) * nd + 4 * (dl >> 4) + (dj0 & 3) : nullptr;
+  auto form = [&](int buf, int kt) {
+    const int a = 2 * kt + dh;
+    const f4 Ta = Ts[dcol * m1 + a];
+    float d[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) d[u] = Ta[0] * Tb[u][0] + Ta[1] * Tb[u][1] + Ta[2] * Tb[u][2] + Ta[3] * Tb[u][3];
+    ST* dst = &bfr[buf][dq][dl * 8 + dj0];
+    if constexpr (EPT == 4) {
+      R4 u4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) u4[u] = P::bits(d[u]);
+      *reinterpret_cast<R4*>(dst) = u4;
+      if (dglob) *reinterpret_cast<R4*>(dglob + 16 * a) = u4;
+    } else {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        dst[u] = P::bits(d[u]);
+        if (dglob) dglob[16 * a + u] = P::bits(d[u]);
+      }
+    }
+  };
+  const int mtiles = f.fw / 16;
+  const ST* Afr = static_cast<const ST*>(f.Afr) + t * f.a_type_stride;
+  const ST* aSrc[MPW];
+#pragma unroll
+  for (int i = 0; i < MPW; ++i) aSrc[i] = Afr + ((int64_t)min(wv + NW * i, mtiles - 1) * KT * 64 + lane) * 8;
+  f4 acc[MPW][NB];
+#pragma unroll
+  for (int i = 0; i < MPW; ++i)
+#pragma unroll
+    for (int n = 0; n < NB; ++n) acc[i][n] = f4{0.f, 0.f, 0.f, 0.f};
+  R8 ar[PF][MPW];
+  auto load = [&](int kt, R8* r) {
+#pragma unroll
+    for (int i = 0; i < MPW; ++i) r[i] = *reinterpret_cast<const R8*>(aSrc[i] + (int64_t)kt * 512);
+  };
+#pragma unroll
+  for (int d = 0; d < PF; ++d) load(min(d, KT - 1), ar[d]);
+  form(0, 0);
+  __syncthreads();
+  // one k-step: products from buffer kt & 1 with ring slot d, which is then
+  // refilled with step kt + PF (the last step again past the end); the D
+  // fragments of step kt + 1 go to the other buffer
+  auto iter = [&](int kt, int d) {
+    const int buf = kt & 1;
+    R8 bb[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) bb[n] = *reinterpret_cast<const R8*>(&bfr[buf][n][lane * 8]);
+#pragma unroll
+    for (int i = 0; i < MPW; ++i)
+#pragma unroll
+      for (int n = 0; n < NB; ++n)
+        acc[i][n] = P::mfma(__builtin_bit_cast(typename P::vec8, ar[d][i]), __builtin_bit_cast(typename P::vec8, bb[n]),
+                            acc[i][n]);
+    load(min(kt + PF, KT - 1), ar[d]);
+    if (kt + 1 < KT) form(buf ^ 1, kt + 1);
+    __syncthreads();
+  };
+  int kb = 0;
+  for (; kb + PF <= KT; kb += PF)
+#pragma unroll
+    for (int d = 0; d < PF; ++d) iter(kb + d, d);
+#pragma unroll
+  for (int d = 0; d < PF; ++d)
+    if (kb + d < KT) iter(kb + d, d);
+  const float* vec = f.vec + t * f.vec_type_stride;
+#pragma unroll
+  for (int i = 0; i < MPW; ++i) {
+    const int mt = wv + NW * i;
+    if (mt >= mtiles) break;
+    const int m0 = 16 * mt + 4 * gq;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      if (c0 + 16 * n >= n_t) continue;
+      float* out = static_cast<float*>(f.X) + (int64_t)(cb + c0 + 16 * n + r16) * f.ldx + m0;
+      float tv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tv[v] = tanh_f(acc[i][n][v] + vec[m0 + v]);
+      *reinterpret_cast<f4*>(out) = f4{tv[0], tv[1], tv[2], tv[3]};
+    }
+  }
+}
+
+// Backward.  A work-group of 4 waves owns 16 NT columns of one type; wave
+// ch takes the quarter ch of the m1 rows a of dE/dD (m-tile a = dD[a][0..15])
+// for all NT column tiles, so each weight fragment it loads serves NT
+// products.  Its dz1 fragments (the whole reduction, fw <= 256) stay in
+// registers; per m-tile it runs the fw/32 products per column tile, then
+// folds each 16 x 16 result tile into g_T at once: lane (column n, group g)
+// holds dD[a][4 g + e] in element e, so the first term sums the lane's four
+// elements against its T rows 4 g + e and the four lane groups (two
+// exchanges), and the second term accumulates dD[a][4 g + e] T[a][k] into
+// the lane's rows 4 g + e.  Rows a >= m2 are stored as they complete; rows
+// a < m2 (first term of the quarter that holds them, second term of every
+// quarter) meet in LDS and are added in quarter order.
+template <class P, int NT, int KT, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 : 2))) void k_fit1_bwd_lp(Fit1Args f) {
+  typedef typename P::store_t ST;
+  typedef typename P::raw8 R8;
+  typedef typename P::raw4 R4;
+  constexpr int CW = 16 * NT;
+  __shared__ f4 lo[CW][16];                     // first term, rows a < 16
+  __shared__ f4 part[4][CW][16];                // second term per quarter
+  const int t = blockIdx.z;
+  const int n_t = f.meta[2 * t], cb = f.meta[2 * t + 1];
+  const int c0 = blockIdx.x * CW;
+  if (c0 >= n_t) return;
+  const int tid = threadIdx.x, lane = tid & 63, ch = tid >> 6;
+  const int r16 = lane & 15, gq = lane >> 4;
+  const int m1 = f.m1;
+  // dz1 fragments of column tile n: lane elements j < 4 are
+  // dz1[32 kt + 4 g ..], j >= 4 dz1[32 kt + 16 + 4 g ..]; entries at or past
+  // fw are zero (the buffer's padding, inside its 32 KT-wide rows, may hold
+  // stale bits)
+  R8 bz[NT][KT];
+  f4 Tlo[NT][4], q[NT][4];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int64_t col = cb + c0 + 16 * n + r16;
+    const ST* src = static_cast<const ST*>(f.X) + col * f.ldx + 4 * gq;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      R4 l4 = *reinterpret_cast<const R4*>(src + 32 * kt);
+      R4 h4 = *reinterpret_cast<const R4*>(src + 32 * kt + 16);
+      const R4 z4 = {};
+      if (32 * kt + 4 * gq >= f.fw) l4 = z4;
+      if (32 * kt + 16 + 4 * gq >= f.fw) h4 = z4;
+      bz[n][kt] = join8<P>(l4, h4);
+    }
+    const float* Tc = f.T + col * m1 * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Tlo[n][e] = *reinterpret_cast<const f4*>(Tc + (4 * gq + e) * 4);
+      q[n][e] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  const int a_lo = m1 * ch / 4, a_hi = m1 * (ch + 1) / 4;
+  const ST* Afr = static_cast<const ST*>(f.Afr) + t * f.a_type_stride + (int64_t)lane * 8;
+  // T and g_T rows of the lane's column in tile 0; tile n is 16 n columns on
+  const int64_t cstride = 16 * (int64_t)m1 * 4;
+  const float* const Tcol0 = f.T + (cb + c0 + r16) * (int64_t)m1 * 4;
+  float* const gTcol0 = f.gT + (cb + c0 + r16) * (int64_t)m1 * 4;
+  // operands of m-tile a, R - 1 m-tiles ahead through a ring of R register
+  // sets: the weight fragments and the T row a of each column, requested
+  // together so that waiting for one m-tile's operands never waits for a
+  // later one's
+  R8 Ar[R][KT];
+  f4 Tar[R][NT];
+  auto load = [&](int a, R8* r, f4* ta) {
+    const int aa = min(a, a_hi - 1);
+    const ST* p = Afr + (int64_t)aa * (KT * 512);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) ta[n] = *reinterpret_cast<const f4*>(Tcol0 + n * cstride + aa * 4);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) r[kt] = *reinterpret_cast<const R8*>(p + kt * 512);
+  };
+  const bool odd = gq & 1, high = gq & 2;
+  auto tile = [&](int a, const R8* r, const f4* ta) {
+    // the column tiles' product chains interleaved
+    f4 accs[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) accs[n] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        accs[n] = P::mfma(__builtin_bit_cast(typename P::vec8, r[kt]), __builtin_bit_cast(typename P::vec8, bz[n][kt]), accs[n]);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const f4 acc = accs[n];
+      // first term: the lane's partial over its four elements, then summed
+      // over the four lane groups by halving (exchange with g ^ 1 keeps the
+      // columns k of g's parity, exchange with g ^ 2 leaves k = g)
+      float p[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float s = acc[0] * Tlo[n][0][k];
+#pragma unroll
+        for (int e = 1; e < 4; ++e) s = fmaf(acc[e], Tlo[n][e][k], s);
+        p[k] = s;
+      }
+      const float u0 = (odd ? p[1] : p[0]) + shfl_xor_f(odd ? p[0] : p[1], 16);
+      const float u1 = (odd ? p[3] : p[2]) + shfl_xor_f(odd ? p[2] : p[3], 16);
+      const float mine = (high ? u1 : u0) + shfl_xor_f(high ? u0 : u1, 32);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[n][e][k] = fmaf(acc[e], ta[n][k], q[n][e][k]);
+      const int cl = 16 * n + r16;
+      if (a >= 16) {
+        if (c0 + cl < n_t) gTcol0[n * cstride + a * 4 + gq] = mine;
+      } else {
+        reinterpret_cast<float*>(&lo[cl][a])[gq] = mine;
+      }
+    }
+  };
+#pragma unroll
+  for (int d = 0; d + 1 < R; ++d) load(a_lo + d, Ar[d], Tar[d]);
+  // m-tile a_lo + i uses slot i % R; slot (i - 1) % R, just consumed, takes
+  // m-tile a_lo + i + R - 1 (past the end the last m-tile again, unused)
+  for (int a = a_lo; a < a_hi; a += R)
+#pragma unroll
+    for (int d = 0; d < R; ++d)
+      if (a + d < a_hi) {
+        load(a + d + R - 1, Ar[(d + R - 1) % R], Tar[(d + R - 1) % R]);
+        tile(a + d, Ar[d], Tar[d]);
+      }
+  // second-term partial of this quarter: lane (n, g) holds rows 4 g + e
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[ch][16 * n + r16][4 * gq + e] = q[n][e];
+  __syncthreads();
+  for (int e = tid; e < CW * 16; e += 256) {
+    const int c2 = e >> 4, a2 = e & 15;
+    if (c0 + c2 >= n_t) continue;
+    f4 v = lo[c2][a2];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) v += part[h][c2][a2];
+    *reinterpret_cast<f4*>(f.gT + ((int64_t)(cb + c0 + c2) * m1 + a2) * 4) = v;
+  }
+}
+
 // ---------------------------------------------------------------- descriptor
 // D[a*m2 + b] = sum_k T[a][k] T[b][k], a < m1, b < m2 (m2 = 16).  One
 // work-group per column, thread a writes 16 consecutive entries.
@@ -980,7 +1303,69 @@ static GemmArgs gemm_base(dp_ctx* c, int mode) {
   return g;
 }
 
-void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) { launch_descriptor_ex(c, mode, mode != DP_FP64, s); }
+// The fused first layer (k_fit1_fwd_lp / k_fit1_bwd_lp) serves the BF16 and
+// FP16 first layers once a frame has enough atoms to give every compute unit
+// a 32-column work-group; frames of few atoms keep the split-K GEMM with the
+// separate descriptor passes.
+bool fit1_fused(const dp_ctx* c, int32_t mode) {
+  if (mode == DP_FP64 || mode == DP_FP64_TAB) return false;
+  const dp_model* m = c->model;
+  const int k1 = mix_kinds(mode).fit1;
+  if (k1 != 1 && k1 != 2) return false;
+  // the backward's reduction is 8 steps of 32 (224 < fw <= 256, as the
+  // paper's 240-wide fitting net)
+  if (m->m1 < 16 || m->m1 > kFit1MaxM1 || (m->m1 & 1) || m->fw % 16 || m->fw <= 224 || m->fw > 256) return false;
+  return (c->natoms_last + 31) / 32 >= c->ncu;
+}
+
+static Fit1Args fit1_base(dp_ctx* c, int32_t mode, bool bwd) {
+  const dp_model* m = c->model;
+  const MixKinds mk = mix_kinds(mode);
+  Fit1Args f = {};
+  f.meta = c->type_meta;
+  f.Tpart = (const float*)c->Tpart;
+  f.tstride = c->max_cols * m->m1 * 4;
+  f.ntypes = m->desc.ntypes;
+  f.T = (float*)c->T;
+  const void* frag1 = frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit1);
+  f.Afr = elem_offset(frag1, mk.fit1, bwd ? m->ffo_lp.bwd[0] : m->ffo_lp.fwd[0]);
+  f.a_type_stride = m->ffo_lp.per_type;
+  f.vec = m->fit_vec32;
+  f.vec_type_stride = m->fit_vec_per_type;
+  f.ldx = ((m->fw + 31) / 32) * 32;
+  f.gT = (float*)c->gT;
+  f.m1 = m->m1;
+  f.fw = m->fw;
+  return f;
+}
+
+// h1 = tanh(D W1 + b1) with D formed from the section partials of T (T is
+// written too; D only when write_d, for the parameter gradients)
+static void launch_fit1_fwd(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s) {
+  Fit1Args f = fit1_base(c, mode, false);
+  f.D = write_d ? c->D : nullptr;
+  f.X = c->fa[0];
+  constexpr int NB = 2, NW = 4;
+  dim3 grid((unsigned)((c->natoms_last + 16 * NB - 1) / (16 * NB)), 1, (unsigned)c->model->desc.ntypes);
+  if (mix_kinds(mode).fit1 == 1) hipLaunchKernelGGL((k_fit1_fwd_lp<PrecBF16, NB, NW, 4>), grid, dim3(64 * NW), 0, s, f);
+  else hipLaunchKernelGGL((k_fit1_fwd_lp<PrecF16, NB, NW, 4>), grid, dim3(64 * NW), 0, s, f);
+}
+
+// g_T from dz1 (the first layer's backward product with the descriptor
+// backward in its epilogue)
+static void launch_fit1_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
+  constexpr int NT = 2, RING = 2;
+  Fit1Args f = fit1_base(c, mode, true);
+  f.X = c->fa[9];
+  dim3 grid((unsigned)((c->natoms_last + 16 * NT - 1) / (16 * NT)), 1, (unsigned)c->model->desc.ntypes);
+  if (mix_kinds(mode).fit1 == 1) hipLaunchKernelGGL((k_fit1_bwd_lp<PrecBF16, NT, 8, RING>), grid, dim3(256), 0, s, f);
+  else hipLaunchKernelGGL((k_fit1_bwd_lp<PrecF16, NT, 8, RING>), grid, dim3(256), 0, s, f);
+}
+
+void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) {
+  if (fit1_fused(c, mode)) return;  // formed inside the first fitting layer
+  launch_descriptor_ex(c, mode, mode != DP_FP64, s);
+}
 
 void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s) {
   const dp_model* m = c->model;
@@ -1001,6 +1386,7 @@ void launch_descriptor_ex(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s) 
 }
 
 void launch_desc_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
+  if (fit1_fused(c, mode)) return;  // folded into the first layer's backward product
   const dp_model* m = c->model;
   const int ncols = (int)(c->natoms_last + m->desc.ntypes * kColPad);
   if (c->natoms_last <= 0) return;
@@ -1026,6 +1412,9 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
   const int64_t* off_fwd = f64 ? m->ffo.fwd : m->ffo_lp.fwd;
   const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
   // layer 1: X = D [cols][nd] (FP64: built from T inside the GEMM)
+  if (fit1_fused(c, mode)) {
+    launch_fit1_fwd(c, mode, keep_h, s);
+  } else {
   g.a_type_stride = tstride;
   g.Afr = f64 ? (const void*)((const double*)frag1 + off_fwd[0]) : elem_offset(frag1, mk.fit1, off_fwd[0]);
   g.X = c->D;
@@ -1040,6 +1429,7 @@ void launch_fit_forward(dp_ctx* c, int32_t mode, bool keep_h, hipStream_t s) {
   g.out0 = c->fa[0];
   g.ld0 = f64 ? fw : fwp;
   gemm_launch(c, g, mode, s);
+  }
   // layers 2, 3 and the output layer
   if (f64) {
     PairArgs p = {};
@@ -1128,6 +1518,22 @@ void launch_fit_backward(dp_ctx* c, int32_t mode, bool keep_dz2, hipStream_t s) 
     launch_pair_lp(c, true, mode, p, s);
   }
   // layer 1: dD = W1 dz1
+  if (fit1_fused(c, mode)) launch_fit1_bwd(c, mode, s);
+  else launch_fit1_bwd_gemm(c, mode, s);
+}
+
+// dD = W1 dz1 as a plain GEMM (FP64, FP32, few atoms; also dE/dD on request
+// where the fused form does not write it)
+void launch_fit1_bwd_gemm(dp_ctx* c, int32_t mode, hipStream_t s) {
+  const dp_model* m = c->model;
+  if (c->natoms_last <= 0) return;
+  const int fw = m->fw;
+  const int fwp = ((fw + 31) / 32) * 32;
+  const bool f64 = mode == DP_FP64;
+  const MixKinds mk = mix_kinds(mode);
+  const void* frag1 = f64 ? (const void*)m->fit_frag64 : frag_of(m->fit_frag_bf16, m->fit_frag_f16, m->fit_frag_f32, mk.fit1);
+  const int64_t* off_bwd = f64 ? m->ffo.bwd : m->ffo_lp.bwd;
+  const int64_t tstride = f64 ? m->ffo.per_type : m->ffo_lp.per_type;
   GemmArgs g = gemm_base(c, mode);
   g.a_type_stride = tstride;
   g.Afr = f64 ? (const void*)((const double*)frag1 + off_bwd[0]) : elem_offset(frag1, mk.fit1, off_bwd[0]);
@@ -1160,8 +1566,8 @@ __global__ void k_gather_cols(const int32_t* __restrict__ col_of, const void* __
 
 void launch_gather_cols(dp_ctx* c, int32_t which, int32_t mode, int32_t ntot, double* dst, hipStream_t s) {
   const dp_model* m = c->model;
-  const void* src = which == 1 ? c->T : (which == 2 ? c->D : c->dD);
-  const int width = which == 1 ? m->m1 * 4 : m->nd;
+  const void* src = which == 1 ? c->T : (which == 2 ? c->D : (which == 5 ? c->gT : c->dD));
+  const int width = which == 1 || which == 5 ? m->m1 * 4 : m->nd;
   const bool f64 = mode == DP_FP64;
   int kind_lp = 0;
   if (!f64 && which == 2 && mix_kinds(mode).fit1 != 3) kind_lp = mix_kinds(mode).fit1;

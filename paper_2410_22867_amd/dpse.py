@@ -26,7 +26,7 @@ MODES = {"fp64": DP_FP64, "bf16": DP_MIX_BF16, "fp16": DP_MIX_FP16, "mix_fp32": 
 FLAG_NOT_WRAPPED, FLAG_OVERLAP, FLAG_NONFINITE, FLAG_CAND_CAPACITY, FLAG_SEL_OVERFLOW = 1, 2, 4, 8, 16
 FLAG_BAD_INPUT, FLAG_SKIN_EXCEEDED, FLAG_TABLE_RANGE = 32, 64, 128
 
-BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD = 0, 1, 2, 3, 4
+BUF_ENV, BUF_T, BUF_D, BUF_GD, BUF_NETD, BUF_GT = 0, 1, 2, 3, 4, 5
 
 # Symbols declared in include/dp.h (checked by the CPU tests).
 EXPORTS = ("dp_model_n_params", "dp_model_create", "dp_model_set_params", "dp_model_set_params_device",
