@@ -605,7 +605,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
 // products would cost more than the multiply-adds they replace).
 // GM: group mode as in the FP64 kernels (a work-group's waves share a column).
 template <class P, int W, int WPB, bool GM>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_fwd_lp(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) void k_embed_fwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int N3 = (M1 + 15) / 16;
   constexpr int NF2 = 2048, NF3 = N3 * 1024;
@@ -629,30 +629,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
   }
   __syncthreads();
-  const float* vec = vs;
-  float w1s[8], b1s[8], b2s[4][4];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-    b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-  }
-#pragma unroll
-  for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
-
   constexpr bool MC = P::kind != 3;  // contraction on the matrix cores
-  // layer-3 biases of this lane's features, the accumulator seeds of every
-  // tile (held in registers by the 16-bit forms, re-read by the FP32 form,
-  // whose registers are taken)
-  f4 b3s[MC ? N3 : 1];
-  if constexpr (MC) {
-#pragma unroll
-    for (int o = 0; o < N3; ++o) {
-      const float b3 = vec[kV_B3F + 16 * o + r16];  // the table spans kP3 features
-      b3s[o] = f4{b3, b3, b3, b3};
-    }
-  }
   constexpr int RSTEP = GM ? 16 * WPB : 16;  // rows between a wave's tiles
   const int rfirst = GM ? 16 * wv : 0;
   for (int c_next = GM ? 0 : take();;) {
@@ -685,7 +662,21 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
       for (int v = 0; v < 4; ++v) rc_next[v] = Rs[max(min(rfirst + 4 * g + v, nn - 1), 0) * 4 + (r16 & 3)];
     }
     for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
+      // the per-net vectors are read from LDS for every tile (the opaque
+      // offset keeps the reads inside the loop): held in registers they
+      // would cost the 40 registers that a fourth wave per SIMD needs
       const int z0 = opaque_zero();
+      const float* vec = vs + z0;
+      float w1s[8], b1s[8], b2s[4][4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+      }
+#pragma unroll
+      for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
       const int row = r0 + r16;
       const float s = (float)s_next;
       s_next = env_elt(Rb, row + RSTEP, 0);
@@ -742,13 +733,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
       for (int o = 0; o < N3; ++o) {
         const int feat = 16 * o + r16;
-        f4 z;
-        if constexpr (MC) {
-          z = b3s[o];
-        } else {
-          const float b3 = vec[kV_B3F + feat];
-          z = f4{b3, b3, b3, b3};
-        }
+        const float b3 = vec[kV_B3F + feat];  // the table spans kP3 features
+        f4 z = {b3, b3, b3, b3};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
         if constexpr (MC) {
@@ -841,7 +827,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
 // transposed per column k (A of the second, built once per centre atom).
 // The FP32 form keeps the vector multiply-adds.
 template <class P, int W, int WPB, bool GM>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) void k_embed_bwd_lp(EmbArgs A) {
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) void k_embed_bwd_lp(EmbArgs A) {
   constexpr int M1 = 4 * W;
   constexpr int NFR = 2048 + 8192 + 8192 + 2048;  // F2 | F3t | B3 | B2
   constexpr bool MC = P::kind != 3;  // contractions on the matrix cores
@@ -873,13 +859,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
   }
   __syncthreads();
-  const float* vec = vs;
-  float w1s[8], b1s[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-    b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-  }
   const int gw = GM ? 0 : wv;  // this wave's g_T tile
   constexpr int RSTEP = GM ? 16 * WPB : 16;
   const int rfirst = GM ? 16 * wv : 0;
@@ -920,11 +899,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     }
     // A operands of the direct-term product, per centre atom: lane (m, g),
     // tile o, element v holds g_T[16o + 4g + v][m % 4]
-    h16x4 aD[8];
-    if constexpr (MC) {
-#pragma unroll
-      for (int o = 0; o < 8; ++o) aD[o] = __builtin_bit_cast(h16x4, gtt[gw][r16 & 3][4 * o + g]);
-    }
     const int nn = A.nnei[i * kMaxT + tj];
     const int64_t rbase = (int64_t)i * A.nm + A.sec[tj];
     const double* Rs = A.R + rbase * 4;
@@ -932,6 +906,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
     d4 R_next = env_row(Rb, rfirst + r16);  // row of the next tile is always in flight
     for (int r0 = rfirst; r0 < nn; r0 += RSTEP) {
       const int z0 = opaque_zero();
+      const float* vec = vs + z0;  // per-net vectors re-read per tile, as in the forward
+      float w1s[8], b1s[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+      }
       const int row = r0 + r16;
       const bool valid = row < nn;
       const d4 Rd = R_next;
@@ -1013,7 +994,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(3))) v
           dz3p[4 * (o & 1) + v] = dG * (1.f - t3 * t3);
           skip2[o & 3][v] += dG;
         }
-        if constexpr (MC) accD = mfma_f16k16(aD[o], pack4_f16(G4), accD);
+        // direct term: A operand lane (m, g), element v = g_T[16 o + 4 g + v][m % 4]
+        // (read for every tile: kept in registers for the atom it would take
+        // 16 of the 128 registers of four waves per SIMD)
+        if constexpr (MC) accD = mfma_f16k16(__builtin_bit_cast(h16x4, gtt[gw][r16 & 3][4 * o + g + z0]), pack4_f16(G4), accD);
         if (o & 1) bz3[o >> 1] = pack8<P>(dz3p);
       }
       float dz2[4][4], skip1[2][4];
@@ -1110,7 +1094,7 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
 }
 
 // Work-groups per net: as many as the CUs hold at once (FP64: one 8-wave
-// work-group per CU; mixed: three 4-wave work-groups), fewer when the net
+// work-group per CU; mixed: three or four 4-wave work-groups), fewer when the net
 // has fewer columns than that many waves.  Each takes a contiguous range of
 // the net's columns; the nets are ordered by net_of_row.
 static unsigned emb_groups(dp_ctx* c, int wpb, int per_cu) {
@@ -1139,15 +1123,17 @@ static void launch_embed_lp_gm(bool bwd, bool gm, dim3 grid, const EmbArgs& A, h
 }
 
 // Resident work-groups per CU: FP64 one 8-wave group; the 16-bit forms
-// three 4-wave groups; the FP32 form holds its fragments in twice the LDS:
-// the forward (55 KB) two 4-wave groups, the backward (80 KB of fragments)
-// one 8-wave group, so that two waves per SIMD share one LDS copy.
+// four 4-wave groups forward (37 KB of LDS each) and two 8-wave groups
+// backward (59 KB: the 40 KB of fragments shared by eight waves), four
+// waves per SIMD in both; the FP32 form holds its fragments in twice the
+// LDS: the forward (55 KB) two 4-wave groups, the backward (80 KB of
+// fragments) one 8-wave group, so that two waves per SIMD share one LDS copy.
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int kind = mode == DP_FP64 ? 0 : mix_kinds(mode).emb;
-  const int wpb = mode == DP_FP64 || (kind == 3 && bwd) ? 8 : kWPBlp;
+  const int wpb = mode == DP_FP64 || bwd ? 8 : kWPBlp;
   EmbArgs A = emb_args(c, mode);
-  const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : 3);
+  const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : (bwd ? 2 : 4));
   const int nnets = A.ntypes * A.ntypes;
   dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)nnets);  // row y: the y-th heaviest net
   dim3 block(64 * wpb);
@@ -1172,8 +1158,8 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
       const int64_t per = (int64_t)c->ncu * per_cu / nnets > 0 ? (int64_t)c->ncu * per_cu / nnets : 1;
       grid.x = (unsigned)(c->natoms_last < per ? c->natoms_last : per);
     }
-    if (kind == 1) launch_embed_lp_gm<PrecBF16, W, kWPBlp, kWPBlp>(bwd, gm, grid, A, s);
-    else if (kind == 2) launch_embed_lp_gm<PrecF16, W, kWPBlp, kWPBlp>(bwd, gm, grid, A, s);
+    if (kind == 1) launch_embed_lp_gm<PrecBF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
+    else if (kind == 2) launch_embed_lp_gm<PrecF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
     else launch_embed_lp_gm<PrecF32, W, kWPBlp, 8>(bwd, gm, grid, A, s);
   }
 }
