@@ -77,14 +77,17 @@ def algorithmic_flops(desc, real_rows, natoms, stored=False, tab=False):
 
 # Vector-ALU model of the FP32 elementwise work of the embedding nets (the
 # bound of the mixed forms' embedding kernels, whose products run on the
-# matrix cores): 1024 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations/s
-# for FP32 add/mul/fma, a quarter of that for the transcendental exp2 and
-# reciprocal.  A tanh costs 2 transcendentals + 3 operations (argument scale,
+# matrix cores): 1024 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-operations/s
+# for FP32 add/mul/fma (a wave64 instruction issues in 2 cycles: the FP32
+# vector peak of 157.3 TFLOP/s counts an fma as 2 flops; a throughput loop
+# of independent fmas measures 2.75 cycles per instruction with its loop
+# overhead), a quarter of that for the transcendental exp2 and reciprocal
+# (measured 8.4 cycles per wave64 instruction).  A tanh costs 2 transcendentals + 3 operations (argument scale,
 # 1 + e, the final fma); every unit of a width-keeping or width-doubling
 # layer adds its skip (1), layer 1 its input fma (1); the backward adds per
 # unit the derivative (1 - t^2) dh (2) and the skip's accumulation or, in
 # layer 1, the dot product with W1 (1), and recomputes the forward.
-ALU_OPS_PER_S = 1024 * 16 * 2.4e9
+ALU_OPS_PER_S = 1024 * 32 * 2.4e9
 ALU_TRANS_PER_S = ALU_OPS_PER_S / 4
 
 

@@ -828,9 +828,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, gq = lane >> 4;
   const int m1 = f.m1, nd = 16 * m1, KT = nd / 32;
-  // T of the work-group's columns (zero past the type's atoms), also to HBM:
-  // thread tid sums rows e = tid + NT u of the column-major [CW][m1] tile;
-  // every load of a section is issued before any is used
+  // T of the work-group's columns (zero past the type's atoms): thread tid
+  // sums rows e = tid + NT u of the column-major [CW][m1] tile; every load
+  // of a section is issued before any is used
   {
     constexpr int U = (CW * kFit1MaxM1 + NT - 1) / NT;
     const float* base = f.Tpart + (int64_t)(cb + c0) * m1 * 4;
@@ -851,10 +851,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = tid + NT * u;
-      if (e < CW * m1) {
-        Ts[e] = v[u];
-        *reinterpret_cast<f4*>(f.T + (int64_t)(cb + c0) * m1 * 4 + (int64_t)e * 4) = v[u];
-      }
+      if (e < CW * m1) Ts[e] = v[u];
     }
   }
   __syncthreads();
@@ -936,6 +933,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
   for (int d = 0; d < PF; ++d)
     if (kb + d < KT) iter(kb + d, d);
+  // T to HBM from the LDS copy (the tile's columns are contiguous there)
+  {
+    f4* const dst = reinterpret_cast<f4*>(f.T + (int64_t)(cb + c0) * m1 * 4);
+    for (int e = tid; e < CW * m1; e += NT) dst[e] = Ts[e];
+  }
   const float* vec = f.vec + t * f.vec_type_stride;
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
@@ -963,24 +965,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 // holds dD[a][4 g + e] in element e, so the first term sums the lane's four
 // elements against its T rows 4 g + e and the four lane groups (two
 // exchanges), and the second term accumulates dD[a][4 g + e] T[a][k] into
-// the lane's rows 4 g + e.  Rows a >= m2 are stored as they complete; rows
-// a < m2 (first term of the quarter that holds them, second term of every
-// quarter) meet in LDS and are added in quarter order.
-template <class P, int NT, int KT, int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 : 2))) void k_fit1_bwd_lp(Fit1Args f) {
+// the lane's rows 4 g + e.  The first terms go to an LDS copy of the
+// work-group's g_T tile (its columns are contiguous in HBM, so the tile is
+// written out at the end with whole 16-byte vectors per lane); the quarters'
+// second terms are then added into its rows a < m2 one quarter after the
+// other.
+template <class P, int NT, int NCG, int KT, int R>
+__global__ __launch_bounds__(256 * NCG) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 : 2))) void k_fit1_bwd_lp(Fit1Args f) {
   typedef typename P::store_t ST;
   typedef typename P::raw8 R8;
   typedef typename P::raw4 R4;
-  constexpr int CW = 16 * NT;
-  __shared__ f4 lo[CW][16];                     // first term, rows a < 16
-  __shared__ f4 part[4][CW][16];                // second term per quarter
+  constexpr int CW = 16 * NT * NCG;
+  __shared__ f4 gtile[CW * kFit1MaxM1];          // g_T of the work-group's columns, [CW][m1]
   const int t = blockIdx.z;
   const int n_t = f.meta[2 * t], cb = f.meta[2 * t + 1];
   const int c0 = blockIdx.x * CW;
   if (c0 >= n_t) return;
-  const int tid = threadIdx.x, lane = tid & 63, ch = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, ch = (tid >> 6) & 3;
   const int r16 = lane & 15, gq = lane >> 4;
   const int m1 = f.m1;
+  // the wave's first column: column group tid / 256 holds tiles NT cg .. NT cg + NT - 1
+  const int cw0 = 16 * NT * (tid >> 8);
   // dz1 fragments of column tile n: lane elements j < 4 are
   // dz1[32 kt + 4 g ..], j >= 4 dz1[32 kt + 16 + 4 g ..]; entries at or past
   // fw are zero (the buffer's padding, inside its 32 KT-wide rows, may hold
@@ -989,7 +994,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 :
   f4 Tlo[NT][4], q[NT][4];
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int64_t col = cb + c0 + 16 * n + r16;
+    const int64_t col = cb + c0 + cw0 + 16 * n + r16;
     const ST* src = static_cast<const ST*>(f.X) + col * f.ldx + 4 * gq;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
@@ -1009,10 +1014,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 :
   }
   const int a_lo = m1 * ch / 4, a_hi = m1 * (ch + 1) / 4;
   const ST* Afr = static_cast<const ST*>(f.Afr) + t * f.a_type_stride + (int64_t)lane * 8;
-  // T and g_T rows of the lane's column in tile 0; tile n is 16 n columns on
+  // T rows of the lane's column in tile 0; tile n is 16 n columns on
   const int64_t cstride = 16 * (int64_t)m1 * 4;
-  const float* const Tcol0 = f.T + (cb + c0 + r16) * (int64_t)m1 * 4;
-  float* const gTcol0 = f.gT + (cb + c0 + r16) * (int64_t)m1 * 4;
+  const float* const Tcol0 = f.T + (cb + c0 + cw0 + r16) * (int64_t)m1 * 4;
   // operands of m-tile a, R - 1 m-tiles ahead through a ring of R register
   // sets: the weight fragments and the T row a of each column, requested
   // together so that waiting for one m-tile's operands never waits for a
@@ -1059,12 +1063,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 :
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int k = 0; k < 4; ++k) q[n][e][k] = fmaf(acc[e], ta[n][k], q[n][e][k]);
-      const int cl = 16 * n + r16;
-      if (a >= 16) {
-        if (c0 + cl < n_t) gTcol0[n * cstride + a * 4 + gq] = mine;
-      } else {
-        reinterpret_cast<float*>(&lo[cl][a])[gq] = mine;
-      }
+      reinterpret_cast<float*>(&gtile[(cw0 + 16 * n + r16) * m1 + a])[gq] = mine;
     }
   };
 #pragma unroll
@@ -1078,20 +1077,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R > 2 ? 1 :
         load(a + d + R - 1, Ar[(d + R - 1) % R], Tar[(d + R - 1) % R]);
         tile(a + d, Ar[d], Tar[d]);
       }
-  // second-term partial of this quarter: lane (n, g) holds rows 4 g + e
+  // second-term partials, quarter by quarter: lane (n, g) holds rows 4 g + e
+  for (int h = 0; h < 4; ++h) {
+    __syncthreads();
+    if (ch == h) {
 #pragma unroll
-  for (int n = 0; n < NT; ++n)
+      for (int n = 0; n < NT; ++n)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) part[ch][16 * n + r16][4 * gq + e] = q[n][e];
-  __syncthreads();
-  for (int e = tid; e < CW * 16; e += 256) {
-    const int c2 = e >> 4, a2 = e & 15;
-    if (c0 + c2 >= n_t) continue;
-    f4 v = lo[c2][a2];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) v += part[h][c2][a2];
-    *reinterpret_cast<f4*>(f.gT + ((int64_t)(cb + c0 + c2) * m1 + a2) * 4) = v;
+        for (int e = 0; e < 4; ++e) gtile[(cw0 + 16 * n + r16) * m1 + 4 * gq + e] += q[n][e];
+    }
   }
+  __syncthreads();
+  // the real columns' rows, in order: one contiguous block of HBM
+  const int rows = min(CW, n_t - c0) * m1;
+  f4* const dst = reinterpret_cast<f4*>(f.gT + (int64_t)(cb + c0) * m1 * 4);
+  for (int e = tid; e < rows; e += 256 * NCG) dst[e] = gtile[e];
 }
 
 // ---------------------------------------------------------------- descriptor
@@ -1354,12 +1354,12 @@ static void launch_fit1_fwd(dp_ctx* c, int32_t mode, bool write_d, hipStream_t s
 // g_T from dz1 (the first layer's backward product with the descriptor
 // backward in its epilogue)
 static void launch_fit1_bwd(dp_ctx* c, int32_t mode, hipStream_t s) {
-  constexpr int NT = 2, RING = 2;
+  constexpr int NT = 2, NCG = 1, RING = 2, CW = 16 * NT * NCG;
   Fit1Args f = fit1_base(c, mode, true);
   f.X = c->fa[9];
-  dim3 grid((unsigned)((c->natoms_last + 16 * NT - 1) / (16 * NT)), 1, (unsigned)c->model->desc.ntypes);
-  if (mix_kinds(mode).fit1 == 1) hipLaunchKernelGGL((k_fit1_bwd_lp<PrecBF16, NT, 8, RING>), grid, dim3(256), 0, s, f);
-  else hipLaunchKernelGGL((k_fit1_bwd_lp<PrecF16, NT, 8, RING>), grid, dim3(256), 0, s, f);
+  dim3 grid((unsigned)((c->natoms_last + CW - 1) / CW), 1, (unsigned)c->model->desc.ntypes);
+  if (mix_kinds(mode).fit1 == 1) hipLaunchKernelGGL((k_fit1_bwd_lp<PrecBF16, NT, NCG, 8, RING>), grid, dim3(256 * NCG), 0, s, f);
+  else hipLaunchKernelGGL((k_fit1_bwd_lp<PrecF16, NT, NCG, 8, RING>), grid, dim3(256 * NCG), 0, s, f);
 }
 
 void launch_descriptor(dp_ctx* c, int32_t mode, hipStream_t s) {
