@@ -584,13 +584,13 @@ struct PairArgsLp {
 
 // PO: element type of dz1, the X operand of the first layer's backward GEMM
 // (the same as P except in the paper's MIX-fp16 recipe).
-template <class P, class PO, bool BWD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_fit_pair_lp(PairArgsLp p) {
-  constexpr int NC = 16, NW = 4, MW = 4;
+template <class P, class PO, bool BWD, int NCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCT > 1 ? 2 : 3))) void k_fit_pair_lp(PairArgsLp p) {
+  constexpr int NC = 16 * NCT, NW = 4, MW = 4;
   typedef typename P::store_t ST;
   typedef typename P::raw8 R8;
   typedef typename P::raw4 R4;
-  // forward: FP32 tile [16][fwp + 4]; backward: tile of ST [16][fwp + 8]
+  // forward: FP32 tile [NC][fwp + 4]; backward: tile of ST [NC][fwp + 8]
   extern __shared__ __attribute__((aligned(16))) float hsf[];
   ST* const hsh = reinterpret_cast<ST*>(hsf);
   const int t = blockIdx.z;
@@ -602,7 +602,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int fw = p.fw, fwp = p.fwp, KT = fwp / 32, mtiles = fw / 16;
   const int ldf = fwp + 4, ldh = fwp + 8;
   const float* vec = p.vec + t * p.vec_type_stride;
-  const int64_t col = cb + c0 + r16;
   for (int e = threadIdx.x; e < NC * fwp; e += 64 * NW) {
     const int c = e / fwp, k = e - c * fwp;
     const int64_t src = (int64_t)(cb + c0 + c) * fwp + k;
@@ -616,9 +615,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     own[j] = wv + NW * j < mtiles;
     mtj[j] = own[j] ? wv + NW * j : mtiles - 1;
   }
-  // element v of m-tile slot j: feature 16 mtj[j] + 4 gq + v of column c0 + r16
+  // element v of m-tile slot j, column tile n: feature 16 mtj[j] + 4 gq + v
+  // of column c0 + 16 n + r16
   auto feat = [&](int j, int v) { return 16 * mtj[j] + 4 * gq + v; };
-  f4 acc[MW];
+  auto colof = [&](int n) { return (int64_t)(cb + c0 + 16 * n + r16); };
+  f4 acc[MW][NCT];
   auto layer = [&](const ST* Afr) {
     R8 aA[MW], aB[MW];
     auto load = [&](int kt, R8* a) {
@@ -627,22 +628,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         a[j] = *reinterpret_cast<const R8*>(Afr + (((int64_t)mtj[j] * KT + kt) * 64 + lane) * 8);
     };
     auto step = [&](int kt, const R8* a) {
-      // B operand: features 32 kt + 4 gq + {0..3} and 32 kt + 16 + 4 gq + {0..3}
-      typename P::vec8 x;
-      if constexpr (BWD) {
-        const ST* rowp = hsh + r16 * ldh + 32 * kt + 4 * gq;
-        const R4 lo = *reinterpret_cast<const R4*>(rowp);
-        const R4 hi = *reinterpret_cast<const R4*>(rowp + 16);
-        x = __builtin_bit_cast(typename P::vec8, join8<P>(lo, hi));
-      } else {
-        const float* rowp = hsf + r16 * ldf + 32 * kt + 4 * gq;
-        const f4 lo = *reinterpret_cast<const f4*>(rowp);
-        const f4 hi = *reinterpret_cast<const f4*>(rowp + 16);
-        const float v8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-        x = pack8<P>(v8);
-      }
 #pragma unroll
-      for (int j = 0; j < MW; ++j) acc[j] = P::mfma(__builtin_bit_cast(typename P::vec8, a[j]), x, acc[j]);
+      for (int n = 0; n < NCT; ++n) {
+        // B operand: features 32 kt + 4 gq + {0..3} and 32 kt + 16 + 4 gq + {0..3}
+        const int rc = 16 * n + r16;
+        typename P::vec8 x;
+        if constexpr (BWD) {
+          const ST* rowp = hsh + rc * ldh + 32 * kt + 4 * gq;
+          const R4 lo = *reinterpret_cast<const R4*>(rowp);
+          const R4 hi = *reinterpret_cast<const R4*>(rowp + 16);
+          x = __builtin_bit_cast(typename P::vec8, join8<P>(lo, hi));
+        } else {
+          const float* rowp = hsf + rc * ldf + 32 * kt + 4 * gq;
+          const f4 lo = *reinterpret_cast<const f4*>(rowp);
+          const f4 hi = *reinterpret_cast<const f4*>(rowp + 16);
+          const float v8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          x = pack8<P>(v8);
+        }
+#pragma unroll
+        for (int j = 0; j < MW; ++j) acc[j][n] = P::mfma(__builtin_bit_cast(typename P::vec8, a[j]), x, acc[j][n]);
+      }
     };
     load(0, aA);
     int kt = 0;
@@ -662,20 +667,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int j = 0; j < MW; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[j][v] = vec[bias_off + feat(j, v)];
+        for (int n = 0; n < NCT; ++n)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[j][n][v] = vec[bias_off + feat(j, v)];
       __syncthreads();  // the tile (input or previous layer) is complete
       layer(Afr);
       __syncthreads();  // every wave has read the tile
 #pragma unroll
-      for (int j = 0; j < MW; ++j) {
+      for (int j = 0; j < MW; ++j)
+#pragma unroll
+      for (int n = 0; n < NCT; ++n) {
         if (!own[j]) continue;
         const int m0 = feat(j, 0);
-        float* hrow = hsf + r16 * ldf + m0;
+        const int64_t col = colof(n);
+        float* hrow = hsf + (16 * n + r16) * ldf + m0;
         const f4 hprev = *reinterpret_cast<const f4*>(hrow);
         float tv[4], hv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          tv[v] = tanh_f(acc[j][v]);
+          tv[v] = tanh_f(acc[j][n][v]);
           hv[v] = hprev[v] + tv[v];
         }
         *reinterpret_cast<f4*>(hrow) = f4{hv[0], hv[1], hv[2], hv[3]};
@@ -695,75 +705,94 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     fwd_layer(A1, 2 * fw, std::true_type{});
     __syncthreads();
     // E_i (summed in FP64 over the FP32 h3 w_o products): 16 threads per column
-    const int c = threadIdx.x >> 4, part = threadIdx.x & 15;
-    double e = 0.0;
-    for (int m = part; m < fw; m += 16) e += (double)(hsf[c * ldf + m] * vec[3 * fw + m]);
+    const int part = threadIdx.x & 15;
 #pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
-    if (part == 0) {
-      const int64_t cc = cb + c0 + c;
-      const int i = p.atom_at[cc];
-      if (i >= 0) {
-        const double E = e + (double)vec[4 * fw] + (double)vec[4 * fw + 1];
-        p.Ei_col[cc] = E;
-        p.Ei_atom[i] = E;
+    for (int n = 0; n < NCT; ++n) {
+      const int c = 16 * n + (threadIdx.x >> 4);
+      double e = 0.0;
+      for (int m = part; m < fw; m += 16) e += (double)(hsf[c * ldf + m] * vec[3 * fw + m]);
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o, 64);
+      if (part == 0) {
+        const int64_t cc = cb + c0 + c;
+        const int i = p.atom_at[cc];
+        if (i >= 0) {
+          const double E = e + (double)vec[4 * fw] + (double)vec[4 * fw + 1];
+          p.Ei_col[cc] = E;
+          p.Ei_atom[i] = E;
+        }
       }
     }
   } else {
-    float tp[MW][4];
+    float tp[MW][NCT][4];
     auto load_t = [&](const float* src) {
 #pragma unroll
-      for (int j = 0; j < MW; ++j) {
-        const f4 x = *reinterpret_cast<const f4*>(src + col * fwp + feat(j, 0));
+      for (int j = 0; j < MW; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) tp[j][v] = x[v];
-      }
+        for (int n = 0; n < NCT; ++n) {
+          const f4 x = *reinterpret_cast<const f4*>(src + colof(n) * fwp + feat(j, 0));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) tp[j][n][v] = x[v];
+        }
     };
     load_t(p.tprev[0]);
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[j][v] = vec[3 * fw + feat(j, v)];  // w_o
+      for (int n = 0; n < NCT; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[j][n][v] = vec[3 * fw + feat(j, v)];  // w_o
     __syncthreads();
     layer(A0);  // acc = dh2
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < MW; ++j) {
-      if (!own[j]) continue;
-      const int m0 = feat(j, 0);
-      float dz[4];
+    for (int j = 0; j < MW; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
-      store4<P>(hsh + r16 * ldh + m0, dz);
-      if (p.outlp[0]) store4<P>(reinterpret_cast<ST*>(p.outlp[0]) + col * fwp + m0, dz);
-    }
+      for (int n = 0; n < NCT; ++n) {
+        if (!own[j]) continue;
+        const int m0 = feat(j, 0);
+        float dz[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dz[v] = acc[j][n][v] * (1.f - tp[j][n][v] * tp[j][n][v]);
+        store4<P>(hsh + (16 * n + r16) * ldh + m0, dz);
+        if (p.outlp[0]) store4<P>(reinterpret_cast<ST*>(p.outlp[0]) + colof(n) * fwp + m0, dz);
+      }
     load_t(p.tprev[1]);
     __syncthreads();
     layer(A1);  // acc = dh1 = dh2 + W2 dz2
 #pragma unroll
-    for (int j = 0; j < MW; ++j) {
-      if (!own[j]) continue;
-      const int m0 = feat(j, 0);
-      float dz[4];
+    for (int j = 0; j < MW; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dz[v] = acc[j][v] * (1.f - tp[j][v] * tp[j][v]);
-      store4<PO>(reinterpret_cast<typename PO::store_t*>(p.outlp[1]) + col * fwp + m0, dz);
-    }
+      for (int n = 0; n < NCT; ++n) {
+        if (!own[j]) continue;
+        const int m0 = feat(j, 0);
+        float dz[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dz[v] = acc[j][n][v] * (1.f - tp[j][n][v] * tp[j][n][v]);
+        store4<PO>(reinterpret_cast<typename PO::store_t*>(p.outlp[1]) + colof(n) * fwp + m0, dz);
+      }
   }
 }
 
+// Column tiles per work-group of the half-precision layer pairs (each
+// weight fragment a wave loads serves that many products): one, measured
+// faster than two or four (water12k BF16 forward 57 / 62 / 82 us) — the
+// kernel gains more from the work-groups than from the weight reuse.
+constexpr int kPairNCT = 1;
+
 template <class P, class PO>
 static void launch_pair_lp_t(bool bwd, dim3 grid, size_t lds, const PairArgsLp& p, hipStream_t s) {
-  if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<P, PO, true>), grid, dim3(256), lds, s, p);
-  else hipLaunchKernelGGL((k_fit_pair_lp<P, P, false>), grid, dim3(256), lds, s, p);
+  if (bwd) hipLaunchKernelGGL((k_fit_pair_lp<P, PO, true, kPairNCT>), grid, dim3(256), lds, s, p);
+  else hipLaunchKernelGGL((k_fit_pair_lp<P, P, false, kPairNCT>), grid, dim3(256), lds, s, p);
 }
 
 static void launch_pair_lp(dp_ctx* c, bool bwd, int mode, const PairArgsLp& p, hipStream_t s) {
   const dp_model* m = c->model;
   const MixKinds mk = mix_kinds(mode);
-  dim3 grid((unsigned)((c->natoms_last + 15) / 16), 1, (unsigned)m->desc.ntypes);
+  constexpr int NC = 16 * kPairNCT;
+  dim3 grid((unsigned)((c->natoms_last + NC - 1) / NC), 1, (unsigned)m->desc.ntypes);
   const size_t esz = mk.fit23 == 3 ? 4 : 2;
-  const size_t lds = bwd ? (size_t)16 * (p.fwp + 8) * esz : (size_t)16 * (p.fwp + 4) * 4;
+  const size_t lds = bwd ? (size_t)NC * (p.fwp + 8) * esz : (size_t)NC * (p.fwp + 4) * 4;
   if (grid.x == 0) return;
   if (mk.fit23 == 1) launch_pair_lp_t<PrecBF16, PrecBF16>(bwd, grid, lds, p, s);
   else if (mk.fit23 == 2) launch_pair_lp_t<PrecF16, PrecF16>(bwd, grid, lds, p, s);
