@@ -985,10 +985,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 }
 
-// Backward.  A work-group of 4 waves owns 16 NT columns of one type; wave
-// ch takes the quarter ch of the m1 rows a of dE/dD (m-tile a = dD[a][0..15])
-// for all NT column tiles, so each weight fragment it loads serves NT
-// products.  Its dz1 fragments (the whole reduction, fw <= 256) stay in
+// Backward.  A work-group of 4 NCG waves owns 16 NT NCG columns of one
+// type: wave (cg, ch) takes the NT column tiles of column group cg and the
+// quarter ch of the m1 rows a of dE/dD (m-tile a = dD[a][0..15]), so each
+// weight fragment it loads serves NT products (the kept form: NT = 2,
+// NCG = 1).  Its dz1 fragments (the whole reduction, fw <= 256) stay in
 // registers; per m-tile it runs the fw/32 products per column tile, then
 // folds each 16 x 16 result tile into g_T at once: lane (column n, group g)
 // holds dD[a][4 g + e] in element e, so the first term sums the lane's four
