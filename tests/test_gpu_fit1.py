@@ -147,3 +147,54 @@ def test_fit1_fused_writes_d(dev):
     _say("D max err / tol", (err / tol).max())
     assert (err <= tol * 1.01).all()
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("mode,tol", [("bf16", 0.05), ("fp16", 0.01), ("mix_fp16", 0.01)])
+def test_fit1_fused_batch_param_grads(dev, mode, tol):
+    """A batch large enough for the fused first layer (12 frames, ~9,500
+    atoms): per-frame energies and forces against the oracle, and the
+    parameter gradient of the energy MSE loss against the oracle's, with
+    the mixed forms' bars (tol of the largest gradient entry)."""
+    from paper_2410_22867_amd import dpse
+    frames, targets = I.water_batch(12, seed=31, lo=230, hi=300)
+    sizes = [f.n for f in frames]
+    off = dpse.frame_offsets(sizes)
+    if not _fused_expected(int(off[-1])):
+        pytest.skip("fewer columns than 32 per compute unit on this device")
+    _say("fit1 fused batch grads", mode, int(off[-1]))
+    p = I.init_params(I.WATER, I.MODEL_SEED_WATER, I.WATER_OUTPUT_SCALE)
+    x = torch.tensor(np.concatenate([f.coords for f in frames]), device=dev)
+    t = torch.tensor(np.concatenate([f.types for f in frames]), device=dev)
+    boxes = np.stack([f.box for f in frames])
+    model = dpse.Model(I.WATER, p)
+    ctx = dpse.Context(model, int(off[-1]), max_frames=len(frames))
+    nl, ov = ctx.build_nlist_batch(x, t, boxes, off)
+    params = torch.tensor(p, device=dev, requires_grad=True)
+    E = dpse.dp_energy(params, x, t, boxes, off, ctx, nl, mode)
+    tgt = torch.tensor(targets, device=dev)
+    L = ((E - tgt) ** 2).mean()
+    L.backward()
+    r = ctx.compute_batch(x, t, boxes, off, nl, mode=mode)
+    torch.cuda.synchronize()
+    assert int(ov.item()) == 0
+    g = params.grad.cpu().numpy()
+    Em = E.detach().cpu().numpy()
+    F = r["F"].cpu().numpy()
+    B = len(frames)
+    want = np.zeros_like(g)
+    f_err, f_scale = [], []
+    for f, fr in enumerate(frames):
+        o = oracle.compute(fr.coords, fr.types, fr.box, I.WATER, p, grad_scale=2.0 * (Em[f] - targets[f]) / B)
+        want += o["grad"]
+        assert abs(Em[f] - o["E"]) / fr.n <= 5e-3
+        a0, a1 = off[f], off[f + 1]
+        f_err.append(((F[a0:a1] - o["F"]) ** 2).sum())
+        f_scale.append((o["F"] ** 2).sum())
+    f_rms = np.sqrt(sum(f_err) / (3 * off[-1]))
+    f_ref = np.sqrt(sum(f_scale) / (3 * off[-1]))
+    rel = np.abs(g - want).max() / np.abs(want).max()
+    _say(mode, "F rms err", f_rms, "of", f_ref, "param grad max error / max |grad|", rel)
+    assert f_rms <= REL_F[mode] * f_ref
+    assert np.isfinite(g).all()
+    assert rel <= tol
+    assert ctx.status() == 0
