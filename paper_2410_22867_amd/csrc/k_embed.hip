@@ -1126,12 +1126,14 @@ static void launch_embed_lp_gm(bool bwd, bool gm, dim3 grid, const EmbArgs& A, h
 // four 4-wave groups forward (37 KB of LDS each) and two 8-wave groups
 // backward (59 KB: the 40 KB of fragments shared by eight waves), four
 // waves per SIMD in both; the FP32 form holds its fragments in twice the
-// LDS: the forward (55 KB) two 4-wave groups, the backward (80 KB of
-// fragments) one 8-wave group, so that two waves per SIMD share one LDS copy.
+// LDS: the forward two 8-wave groups (72 KB each), the backward one 16-wave
+// group (80 KB of fragments and 32 KB of g_T tiles), so that four waves per
+// SIMD share the LDS copies (forward 274 -> 256 us, backward 536 -> 519 us
+// at water12k against 4- and 8-wave groups).
 template <int W>
 static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   const int kind = mode == DP_FP64 ? 0 : mix_kinds(mode).emb;
-  const int wpb = mode == DP_FP64 || bwd ? 8 : kWPBlp;
+  const int wpb = mode == DP_FP64 ? 8 : (bwd ? (kind == 3 ? 16 : 8) : (kind == 3 ? 8 : kWPBlp));
   EmbArgs A = emb_args(c, mode);
   const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : (bwd ? 2 : 4));
   const int nnets = A.ntypes * A.ntypes;
@@ -1160,7 +1162,7 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
     }
     if (kind == 1) launch_embed_lp_gm<PrecBF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
     else if (kind == 2) launch_embed_lp_gm<PrecF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
-    else launch_embed_lp_gm<PrecF32, W, kWPBlp, 8>(bwd, gm, grid, A, s);
+    else launch_embed_lp_gm<PrecF32, W, 8, 16>(bwd, gm, grid, A, s);
   }
 }
 
