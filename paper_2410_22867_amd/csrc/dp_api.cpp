@@ -124,6 +124,27 @@ int feat3(int w, int p) {
   return f < 0 ? -1 : (p >> 6) * 2 * w + f;
 }
 
+// Slot order of the half-precision kernels, whose lane group g holds slots
+// 16t + 4g + v of tile t in element v: for w <= 28 the layer-1 slots
+// 16 + 4g + 3 (g = 0..3) and their copies in the wider layers hold no
+// feature, so that element 3 of every odd tile is padding in all four lane
+// groups and the kernels skip its activation; the features fill the other
+// slots in order.
+int feat1h(int w, int p) {
+  if (w > 28) return feat1(w, p);
+  if (p >= 16 && (p & 3) == 3) return -1;
+  const int f = p < 16 ? p : 16 + 3 * ((p - 16) >> 2) + ((p - 16) & 3);
+  return f < w ? f : -1;
+}
+int feat2h(int w, int p) {
+  const int f = feat1h(w, p & 31);
+  return f < 0 ? -1 : (p >> 5) * w + f;
+}
+int feat3h(int w, int p) {
+  const int f = feat2h(w, p & 63);
+  return f < 0 ? -1 : (p >> 6) * 2 * w + f;
+}
+
 // Denser layout of the FP64 force kernels for w = 25 (the last feature of
 // each half of the width-2w layer shares one k-step; slots 26, 27 are
 // copies of features 24, 49 that feed nothing but the identity skip, and
@@ -235,30 +256,37 @@ int build_maps(dp_model* m) {
   auto I = [](int64_t k) -> int32_t { return (int32_t)k; };
   // ---- embedding vectors, slot order (plain and denser layouts)
   m->emb_vec_per_net = 384;
-  Map ev((size_t)nnets * 384, -1), evd((size_t)nnets * 384, -1);
+  Map ev((size_t)nnets * 384, -1), evd((size_t)nnets * 384, -1), evh((size_t)nnets * 384, -1);
   for (int a = 0; a < nt; ++a)
     for (int b = 0; b < nt; ++b) {
       int32_t* v = &ev[(size_t)(a * nt + b) * 384];
       int32_t* vd = &evd[(size_t)(a * nt + b) * 384];
+      int32_t* vh = &evh[(size_t)(a * nt + b) * 384];
       for (int p = 0; p < 32; ++p) {
         int f = feat1(w, p);
         if (f >= 0) { v[p] = I(L.embW[a][b][0] + f); v[32 + p] = I(L.embB[a][b][0] + f); }
         f = val1(w, p);
         if (f >= 0) { vd[p] = I(L.embW[a][b][0] + f); vd[32 + p] = I(L.embB[a][b][0] + f); }
+        f = feat1h(w, p);
+        if (f >= 0) { vh[p] = I(L.embW[a][b][0] + f); vh[32 + p] = I(L.embB[a][b][0] + f); }
       }
       for (int p = 0; p < 64; ++p) {
         int f = feat2(w, p);
         if (f >= 0) v[64 + p] = I(L.embB[a][b][1] + f);
         f = val2(w, p);
         if (f >= 0) vd[64 + p] = I(L.embB[a][b][1] + f);
+        f = feat2h(w, p);
+        if (f >= 0) vh[64 + p] = I(L.embB[a][b][1] + f);
       }
       for (int p = 0; p < 128; ++p) {
         int f = feat3(w, p);
         if (f >= 0) v[128 + p] = I(L.embB[a][b][2] + f);
         f = val3(w, p);
         if (f >= 0) vd[128 + p] = I(L.embB[a][b][2] + f);
+        f = feat3h(w, p);
+        if (f >= 0) vh[128 + p] = I(L.embB[a][b][2] + f);
       }
-      for (int f = 0; f < 4 * w; ++f) v[256 + f] = vd[256 + f] = I(L.embB[a][b][2] + f);
+      for (int f = 0; f < 4 * w; ++f) v[256 + f] = vd[256 + f] = vh[256 + f] = I(L.embB[a][b][2] + f);
     }
   // ---- embedding fragments (same element counts for both kinds)
   EmbFragOffsets& fo = m->efo;
@@ -288,6 +316,20 @@ int build_maps(dp_model* m) {
         const int fi = feat2(w, in_slot);
         return (fi < 0 || out_feat >= m1) ? -1 : I(W3 + (int64_t)fi * 4 * w + out_feat);
       };
+      // the half-precision kernels' slot order
+      auto w2h = [&](int in_slot, int out_slot) -> int32_t {
+        const int fi = feat1h(w, in_slot), fo2 = feat2h(w, out_slot);
+        return (fi < 0 || fo2 < 0) ? -1 : I(W2 + (int64_t)fi * 2 * w + fo2);
+      };
+      auto w3sh = [&](int in_slot, int out_slot) -> int32_t {
+        if (in_slot >= 64 || out_slot >= 128) return -1;
+        const int fi = feat2h(w, in_slot), fo3 = feat3h(w, out_slot);
+        return (fi < 0 || fo3 < 0) ? -1 : I(W3 + (int64_t)fi * 4 * w + fo3);
+      };
+      auto w3fh = [&](int in_slot, int out_feat) -> int32_t {
+        const int fi = feat2h(w, in_slot);
+        return (fi < 0 || out_feat >= m1) ? -1 : I(W3 + (int64_t)fi * 4 * w + out_feat);
+      };
       // the denser layout (FP64 force kernels)
       auto w2d = [&](int in_slot, int out_slot) -> int32_t {
         const int fi = wt1(w, in_slot), fo2 = val2(w, out_slot);
@@ -309,16 +351,16 @@ int build_maps(dp_model* m) {
       frag_block64(e64d, base + fo.B2, 2, 4, [&](int mi, int ko) { return w2d(mi, ko); }, true);
       // forward (A operand W^T: m = out, k = in)
       frag_block64(e64, base + fo.F2, 4, 2, [&](int mo, int ki) { return w2(ki, mo); }, true);
-      frag_block32(e32, base + fo.F2, 4, 1, [&](int mo, int ki) { return w2(ki, mo); });
+      frag_block32(e32, base + fo.F2, 4, 1, [&](int mo, int ki) { return w2h(ki, mo); });
       frag_block64(e64, base + fo.F3n, m->n3, 4, [&](int mo, int ki) { return w3f(ki, mo); }, true);
-      frag_block32(e32, base + fo.F3n, m->n3, 2, [&](int mo, int ki) { return w3f(ki, mo); });
+      frag_block32(e32, base + fo.F3n, m->n3, 2, [&](int mo, int ki) { return w3fh(ki, mo); });
       frag_block64(e64, base + fo.F3t, 8, 4, [&](int mo, int ki) { return w3s(ki, mo); }, true);
-      frag_block32(e32, base + fo.F3t, 8, 2, [&](int mo, int ki) { return w3s(ki, mo); });
+      frag_block32(e32, base + fo.F3t, 8, 2, [&](int mo, int ki) { return w3sh(ki, mo); });
       // backward (A operand W: m = in, k = out)
       frag_block64(e64, base + fo.B3, 4, 8, [&](int mi, int ko) { return w3s(mi, ko); }, true);
-      frag_block32(e32, base + fo.B3, 4, 4, [&](int mi, int ko) { return w3s(mi, ko); });
+      frag_block32(e32, base + fo.B3, 4, 4, [&](int mi, int ko) { return w3sh(mi, ko); });
       frag_block64(e64, base + fo.B2, 2, 4, [&](int mi, int ko) { return w2(mi, ko); }, true);
-      frag_block32(e32, base + fo.B2, 2, 2, [&](int mi, int ko) { return w2(mi, ko); });
+      frag_block32(e32, base + fo.B2, 2, 2, [&](int mi, int ko) { return w2h(mi, ko); });
     }
   // ---- fitting fragments
   const int fwp = ((fw + 31) / 32) * 32;
@@ -365,7 +407,7 @@ int build_maps(dp_model* m) {
   // ---- device buffers and the gathers that fill them
   struct Target { const Map* map; void** dst; int kind; size_t esize; };
   const Target tg[] = {
-      {&ev, (void**)&m->emb_vec64, 0, 8},      {&ev, (void**)&m->emb_vec32, 1, 4},
+      {&ev, (void**)&m->emb_vec64, 0, 8},      {&evh, (void**)&m->emb_vec32, 1, 4},
       {&e64, (void**)&m->emb_frag64, 0, 8},    {&evd, (void**)&m->emb_vec64d, 0, 8},
       {&e64d, (void**)&m->emb_frag64d, 0, 8},  {&e32, (void**)&m->emb_frag_bf16, 2, 2},
       {&e32, (void**)&m->emb_frag_f16, 3, 2},  {&e32, (void**)&m->emb_frag_f32, 1, 4},

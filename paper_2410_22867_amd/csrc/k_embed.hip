@@ -16,7 +16,9 @@
 // (feature f at slot f), layer 2 uses 64 (features [0, w) at slots [0, w),
 // [w, 2w) at [32, 32 + w)), layer 3 uses 128 (two copies of the layer-2
 // layout).  With that layout the identity skips of width-doubling layers,
-// h_l = [h_{l-1}, h_{l-1}] + tanh(z_l), stay inside a lane.
+// h_l = [h_{l-1}, h_{l-1}] + tanh(z_l), stay inside a lane.  The
+// half-precision kernels order the layer-1 slots so that, for w <= 28, a
+// whole register of each odd tile is padding (kpadh below).
 //
 // Forward: layer 3 is evaluated with rows along M instead (the layer-2 tile
 // is a valid A operand as it is), so the contraction T = G^T R / nm reduces
@@ -84,6 +86,24 @@ __device__ __forceinline__ int feat3_of_slot(int p) {  // -1 for padding slots
   return (p >> 6) * 2 * W + (q >> 5) * W + (q & 31);
 }
 
+// Slot order of the half-precision kernels (lane group g, element v hold
+// slot 16t + 4g + v of tile t): for w <= 28 the layer-1 slots 16 + 4g + 3
+// and their copies in the wider layers are padding, so element 3 of every
+// odd tile is padding in all four lane groups and its activation is not
+// evaluated; the features fill the other slots in order.
+template <int W>
+__device__ __forceinline__ constexpr bool kpadh(int t, int v) {
+  return W <= 28 && (t & 1) && v == 3;
+}
+template <int W>
+__device__ __forceinline__ int feat3h_of_slot(int p) {  // -1 for padding slots
+  const int q = p & 31;
+  int f = q;
+  if (W <= 28 && q >= 16) f = (q & 3) == 3 ? W : 16 + 3 * ((q - 16) >> 2) + ((q - 16) & 3);
+  if (f >= W) return -1;
+  return (p >> 6) * 2 * W + ((p >> 5) & 1) * W + f;
+}
+
 // The net that work-group row y serves: the nets in decreasing order of
 // their work, the centre type's columns times the neighbour section's row
 // tiles (ceil(sel / 16)), ties in net order.  Rows are dispatched in order,
@@ -104,9 +124,51 @@ __device__ __forceinline__ int net_of_row(const int32_t* meta, const int* sec, i
   return 0;
 }
 
+// One-row grid: every net gets one work-group and the other G - nnets are
+// split in proportion to the nets' work (as net_of_row weighs it), the nets'
+// shares laid out in decreasing order of work.  Work-group b serves the net
+// whose share holds b, as the j-th of gk work-groups.  A grid of the
+// work-groups the CUs hold at once then finishes every net in one round:
+// with one net per grid row, the light nets' work-groups would wait for the
+// heavy nets' slots and each work-group would get a few columns only, its
+// waves idling at its end for up to one column each.  Returns -1 for b past
+// the shares (none when G >= nnets and some net has work).
+__device__ __forceinline__ int net_of_group(const int32_t* meta, const int* sec, int ntypes, int G, int b, int* j,
+                                            int* gk) {
+  const int nnets = ntypes * ntypes;
+  auto wt = [&](int k) -> int64_t {
+    const int kti = k / ntypes, ktj = k - kti * ntypes;
+    return (int64_t)meta[2 * kti] * ((sec[ktj + 1] - sec[ktj] + 15) / 16);
+  };
+  int64_t total = 0;
+  for (int k = 0; k < nnets; ++k) total += wt(k);
+  const int64_t spare = G - nnets;
+  for (int k = 0; k < nnets; ++k) {
+    const int64_t wk = wt(k);
+    int rank = 0;
+    int64_t before = 0;  // work of the nets ranked before k
+    for (int q = 0; q < nnets; ++q) {
+      const int64_t wq = wt(q);
+      if (wq > wk || (wq == wk && q < k)) {
+        ++rank;
+        before += wq;
+      }
+    }
+    const int64_t lo = rank + (total > 0 ? spare * before / total : 0);
+    const int64_t hi = rank + 1 + (total > 0 ? spare * (before + wk) / total : 0);
+    if (b >= lo && b < hi) {
+      *j = (int)(b - lo);
+      *gk = (int)(hi - lo);
+      return k;
+    }
+  }
+  return -1;
+}
+
 // Common prologue of the per-net kernels: net = t_i * ntypes + t_j (centre
-// type t_i, neighbour section t_j) from net_of_row.  Work assignment: the
-// net's columns are split into gridDim.x contiguous ranges, one per
+// type t_i, neighbour section t_j) from net_of_group (one-row grid) or
+// net_of_row (one grid row per net).  Work assignment: the
+// net's columns are split into contiguous ranges, one per
 // work-group; inside its range a wavefront takes the next column from the
 // work-group's counter (a word in global memory that no other work-group
 // touches, set by the work-group itself before its first barrier; the next
@@ -117,11 +179,15 @@ __device__ __forceinline__ int net_of_row(const int32_t* meta, const int* sec, i
 // work-group end within about one column of each other, whatever the spread
 // of neighbour counts.
 #define DPSE_NET_PROLOGUE(WPB)                                            \
-  const int net = net_of_row(A.meta, A.sec, A.ntypes, blockIdx.y);        \
+  int grp = blockIdx.x, ngrp = gridDim.x;                                 \
+  const int net = gridDim.y == 1                                          \
+                      ? net_of_group(A.meta, A.sec, A.ntypes, gridDim.x, blockIdx.x, &grp, &ngrp) \
+                      : net_of_row(A.meta, A.sec, A.ntypes, blockIdx.y);  \
+  if (net < 0) return;                                                    \
   const int ti = net / A.ntypes, tj = net - ti * A.ntypes;                \
   const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];                \
-  const int c_lo = (int)((int64_t)n_t * blockIdx.x / gridDim.x);          \
-  const int c_hi = (int)((int64_t)n_t * (blockIdx.x + 1) / gridDim.x);    \
+  const int c_lo = (int)((int64_t)n_t * grp / ngrp);                      \
+  const int c_hi = (int)((int64_t)n_t * (grp + 1) / ngrp);                \
   if (c_lo >= c_hi) return;                                               \
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;              \
   const int r16 = lane & 15, g = lane >> 4;                               \
@@ -670,13 +736,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
       float w1s[8], b1s[8], b2s[4][4];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-        b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        w1s[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        b1s[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
       }
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) b2s[ot][v] = vec[kV_B2 + 16 * ot + 4 * g + v];
+        for (int v = 0; v < 4; ++v) b2s[ot][v] = kpadh<W>(ot, v) ? 0.f : vec[kV_B2 + 16 * ot + 4 * g + v];
       const int row = r0 + r16;
       const float s = (float)s_next;
       s_next = env_elt(Rb, row + RSTEP, 0);
@@ -706,7 +772,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
 
       float h1[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) h1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
+      for (int j = 0; j < 8; ++j) h1[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : tanh_f(fmaf(s, w1s[j], b1s[j]));
       const typename P::vec8 b1v = pack8<P>(h1);
       float h2[4][4];
 #pragma unroll
@@ -714,13 +780,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
         f4 z = {b2s[ot][0], b2s[ot][1], b2s[ot][2], b2s[ot][3]};
         z = P::mfma(load8<P>(fr + z0 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = h1[4 * (ot & 1) + v] + tanh_f(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpadh<W>(ot, v) ? 0.f : h1[4 * (ot & 1) + v] + tanh_f(z[v]);
       }
+      // the layer-2 tile to LDS in feature order (column f of row r16): the
+      // feature of slot 16 ot + 4g + v is linear in g, so every store is one
+      // base address plus a constant; the padding slots are left out
       wave_lds_sync();
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2s[wv][r16][16 * ot + 4 * g + v] = h2[ot][v];
+        for (int v = 0; v < 4; ++v) {
+          if (kpadh<W>(ot, v)) continue;
+          const int f1 = (ot & 1) ? 16 + (W <= 28 ? 3 : 4) * g + v : 4 * g + v;  // feature within the half
+          if ((ot & 1) == 0 || f1 < W) h2s[wv][r16][(ot >> 1) * W + f1] = h2[ot][v];
+        }
       wave_lds_sync();
       typename P::vec8 a3[2];
 #pragma unroll
@@ -741,7 +814,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
           // A operand: G of rows 4g..4g+3 of this lane's feature (0 past m1)
           float gv[4] = {0.f, 0.f, 0.f, 0.f};
           if (feat < M1) {
-            const int src = slot2_of_feat<W>(feat % (2 * W));
+            const int src = feat < 2 * W ? feat : feat - 2 * W;  // the skip partner's feature
 #pragma unroll
             for (int v = 0; v < 4; ++v) gv[v] = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
           }
@@ -749,7 +822,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
           for (int k = 0; k < 4; ++k) accT[o][k] = t4[k];
         } else if (feat < M1) {
-          const int src = slot2_of_feat<W>(feat % (2 * W));
+          const int src = feat < 2 * W ? feat : feat - 2 * W;  // the skip partner's feature
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float G = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
@@ -879,7 +952,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
       const float* gT = reinterpret_cast<const float*>(A.gT) + (int64_t)col * M1 * 4;
       if constexpr (!GM) wave_lds_sync();
       for (int p = GM ? (int)threadIdx.x : lane; p < kP3; p += GM ? 64 * WPB : 64) {
-        const int a = feat3_of_slot<W>(p);
+        const int a = feat3h_of_slot<W>(p);
         f4 x = {0.f, 0.f, 0.f, 0.f};
         if (a >= 0) x = *reinterpret_cast<const f4*>(gT + a * 4);
         if constexpr (MC) {
@@ -910,8 +983,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
       float w1s[8], b1s[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        w1s[j] = vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
-        b1s[j] = vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        w1s[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : vec[kV_W1 + 16 * (j >> 2) + 4 * g + (j & 3)];
+        b1s[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : vec[kV_B1 + 16 * (j >> 2) + 4 * g + (j & 3)];
       }
       const int row = r0 + r16;
       const bool valid = row < nn;
@@ -921,18 +994,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
       const float s = Rrow[0];
       float t1[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) t1[j] = tanh_f(fmaf(s, w1s[j], b1s[j]));
+      for (int j = 0; j < 8; ++j) t1[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : tanh_f(fmaf(s, w1s[j], b1s[j]));
       const typename P::vec8 b1v = pack8<P>(t1);
       float t2[4][4], h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
         const float* b2 = vec + kV_B2 + 16 * ot + 4 * g;
-        f4 z = {b2[0], b2[1], b2[2], b2[3]};
+        f4 z = {b2[0], b2[1], b2[2], kpadh<W>(ot, 3) ? 0.f : b2[3]};
         z = P::mfma(load8<P>(fr + z0 + oF2 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          t2[ot][v] = tanh_f(z[v]);
-          h2[ot][v] = t1[4 * (ot & 1) + v] + t2[ot][v];
+          t2[ot][v] = kpadh<W>(ot, v) ? 0.f : tanh_f(z[v]);
+          h2[ot][v] = kpadh<W>(ot, v) ? 0.f : t1[4 * (ot & 1) + v] + t2[ot][v];
         }
       }
       typename P::vec8 b2v[2];
@@ -969,7 +1042,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
         const float* b3 = vec + kV_B3S + 16 * o + 4 * g;
-        f4 z = {b3[0], b3[1], b3[2], b3[3]};
+        f4 z = {b3[0], b3[1], b3[2], kpadh<W>(o, 3) ? 0.f : b3[3]};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oF3 + ((o * 2 + kt) * 64 + lane) * 8), b2v[kt], z);
         f4 dGv;
@@ -979,6 +1052,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
         float G4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (kpadh<W>(o, v)) {  // padding slot: G = 0 and g_T = 0, no gradient
+            G4[v] = 0.f;
+            dz3p[4 * (o & 1) + v] = 0.f;
+            continue;
+          }
           const float t3 = tanh_f(z[v]);
           const float G = h2[o & 3][v] + t3;
           float dG;
@@ -1012,6 +1090,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int kt = 0; kt < 4; ++kt) z = P::mfma(load8<P>(fr + z0 + oB3 + ((i2 * 4 + kt) * 64 + lane) * 8), bz3[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (kpadh<W>(i2, v)) {
+            dz2[i2][v] = 0.f;
+            continue;
+          }
           const float dh2 = z[v];
           dz2[i2][v] = dh2 * (1.f - t2[i2][v] * t2[i2][v]);
           skip1[i2 & 1][v] += dh2;
@@ -1033,6 +1115,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(load8<P>(fr + z0 + oB2 + ((i2 * 2 + kt) * 64 + lane) * 8), bz2[kt], z);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (kpadh<W>(i2, v)) continue;
           const float dh1 = z[v];
           const float tt = t1[4 * i2 + v];
           dsp = fmaf(w1s[4 * i2 + v], dh1 * (1.f - tt * tt), dsp);
@@ -1093,14 +1176,23 @@ static EmbArgs emb_args(dp_ctx* c, int32_t mode) {
   return A;
 }
 
-// Work-groups per net: as many as the CUs hold at once (FP64: one 8-wave
-// work-group per CU; mixed: three or four 4-wave work-groups), fewer when the net
-// has fewer columns than that many waves.  Each takes a contiguous range of
-// the net's columns; the nets are ordered by net_of_row.
-static unsigned emb_groups(dp_ctx* c, int wpb, int per_cu) {
-  const int64_t need = (c->natoms_last + wpb - 1) / wpb;
+// Work-groups: one-row grid (flat) as many as the CUs hold at once (per_cu
+// per CU), fewer when the columns (one per atom and neighbour section) are
+// fewer than that many waves, at least one per net, shared out among the
+// nets by net_of_group; otherwise one row per net, each with as many
+// work-groups as the CUs hold at once (fewer when the net has fewer columns
+// than that many waves), so that the work-groups of the lighter nets take
+// over the slots of the heavier ones as they finish.
+static dim3 emb_grid(dp_ctx* c, int wpb, int per_cu, int ntypes, bool flat) {
+  const int nnets = ntypes * ntypes;
   const int64_t res = (int64_t)c->ncu * per_cu;
-  return (unsigned)(need < res ? need : res);
+  if (flat) {
+    const int64_t need = (c->natoms_last * ntypes + wpb - 1) / wpb;
+    const int64_t g = need < res ? need : res;
+    return dim3((unsigned)(g > nnets ? g : nnets), 1);
+  }
+  const int64_t need = (c->natoms_last + wpb - 1) / wpb;
+  return dim3((unsigned)(need < res ? need : res), (unsigned)nnets);
 }
 
 template <int W, bool ST, bool GM>
@@ -1137,16 +1229,20 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   EmbArgs A = emb_args(c, mode);
   const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : (bwd ? 2 : 4));
   const int nnets = A.ntypes * A.ntypes;
-  dim3 grid(emb_groups(c, wpb, per_cu), (unsigned)nnets);  // row y: the y-th heaviest net
+  // one-row grid for the FP64 forward and the FP32 form's backward (water12k:
+  // 547 -> 516 us and 504 -> 458 us); the other kernels keep one row per net
+  // (the 16-bit forward one-row: 97 -> 103 us)
+  const bool flat = mode == DP_FP64 ? !bwd : (kind == 3 && bwd);
+  dim3 grid = emb_grid(c, wpb, per_cu, A.ntypes, flat);
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
     // group mode when the columns (one per atom and neighbour section) are
     // fewer than the chip's wave slots: about one work-group per CU in all,
     // each taking whole columns with all its waves
     const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb;
-    if (gm) {
+    if (gm) {  // row y: the y-th heaviest net
       const int64_t per = c->ncu / nnets > 0 ? c->ncu / nnets : 1;
-      grid.x = (unsigned)(c->natoms_last < per ? c->natoms_last : per);
+      grid = dim3((unsigned)(c->natoms_last < per ? c->natoms_last : per), (unsigned)nnets);
       if (A.act) launch_embed_f64<W, true, true>(bwd, grid, block, A, s);
       else launch_embed_f64<W, false, true>(bwd, grid, block, A, s);
     } else {
@@ -1156,9 +1252,9 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   } else {
     // group mode on the same rule as FP64 (columns fewer than wave slots)
     const bool gm = c->natoms_last * A.ntypes < (int64_t)c->ncu * wpb * per_cu;
-    if (gm) {
+    if (gm) {  // row y: the y-th heaviest net
       const int64_t per = (int64_t)c->ncu * per_cu / nnets > 0 ? (int64_t)c->ncu * per_cu / nnets : 1;
-      grid.x = (unsigned)(c->natoms_last < per ? c->natoms_last : per);
+      grid = dim3((unsigned)(c->natoms_last < per ? c->natoms_last : per), (unsigned)nnets);
     }
     if (kind == 1) launch_embed_lp_gm<PrecBF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
     else if (kind == 2) launch_embed_lp_gm<PrecF16, W, kWPBlp, 8>(bwd, gm, grid, A, s);
