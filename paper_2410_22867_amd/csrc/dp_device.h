@@ -196,10 +196,13 @@ __device__ __forceinline__ double tanh_d(double x) {
   return __builtin_copysign(fma(2.0, q, -1.0), x);
 }
 
-__device__ __forceinline__ float tanh_f(float x) {
-  float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2/ln 2
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+constexpr float kTanhScale = 2.8853900817779268f;  // 2/ln 2
+// tanh(x) from y = x * kTanhScale, for producers that fold the scale into
+// their own multiply-add (a bias stored pre-scaled: y = fma(z, scale, b'))
+__device__ __forceinline__ float tanh_f_pre(float y) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
 }
+__device__ __forceinline__ float tanh_f(float x) { return tanh_f_pre(x * kTanhScale); }
 
 // Rows of an environment-matrix section through a buffer resource that
 // spans its nn valid rows (32 bytes each): the hardware's range check returns

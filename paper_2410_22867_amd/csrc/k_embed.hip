@@ -692,10 +692,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
   __syncthreads();
   {
     const float* vsrc = A.vec32 + net * A.vec_per_net;
-    for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
+    // 16-bit forms: the biases pre-scaled by 2/ln 2 (they enter only tanh
+    // arguments, as fma(z, 2/ln 2, b'), which saves the accumulator set-up
+    // of every product); the layer-1 weights as they are
+    for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB)
+      vs[k] = P::kind != 3 && k >= kV_B1 ? vsrc[k] * kTanhScale : vsrc[k];
   }
   __syncthreads();
   constexpr bool MC = P::kind != 3;  // contraction on the matrix cores
+  constexpr bool PS = P::kind != 3;  // biases pre-scaled (see the staging above)
+  // tanh of a product's output z plus its bias b (PS: b pre-scaled and added
+  // in the argument's multiply-add; otherwise z already holds the bias)
+  auto act = [](float z, float b) { return PS ? tanh_f_pre(fmaf(z, kTanhScale, b)) : tanh_f(z); };
   constexpr int RSTEP = GM ? 16 * WPB : 16;  // rows between a wave's tiles
   const int rfirst = GM ? 16 * wv : 0;
   for (int c_next = GM ? 0 : take();;) {
@@ -744,7 +752,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
         for (int v = 0; v < 4; ++v) b2s[ot][v] = kpadh<W>(ot, v) ? 0.f : vec[kV_B2 + 16 * ot + 4 * g + v];
       const int row = r0 + r16;
-      const float s = (float)s_next;
+      const float sK = (float)s_next * (PS ? kTanhScale : 1.f);
       s_next = env_elt(Rb, row + RSTEP, 0);
       // rows of the contraction, requested before layers 1-2 run: the vector
       // form needs all four columns of rows 4g..4g+3, the matrix form column
@@ -772,15 +780,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
 
       float h1[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) h1[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : tanh_f(fmaf(s, w1s[j], b1s[j]));
+      for (int j = 0; j < 8; ++j) {
+        const float y = fmaf(sK, w1s[j], b1s[j]);  // PS: (s w + b) 2/ln 2
+        h1[j] = kpadh<W>(j >> 2, j & 3) ? 0.f : PS ? tanh_f_pre(y) : tanh_f(y);
+      }
       const typename P::vec8 b1v = pack8<P>(h1);
       float h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
-        f4 z = {b2s[ot][0], b2s[ot][1], b2s[ot][2], b2s[ot][3]};
+        f4 z = PS ? f4{0.f, 0.f, 0.f, 0.f} : f4{b2s[ot][0], b2s[ot][1], b2s[ot][2], b2s[ot][3]};
         z = P::mfma(load8<P>(fr + z0 + (ot * 64 + lane) * 8), b1v, z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpadh<W>(ot, v) ? 0.f : h1[4 * (ot & 1) + v] + tanh_f(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpadh<W>(ot, v) ? 0.f : h1[4 * (ot & 1) + v] + act(z[v], b2s[ot][v]);
       }
       // the layer-2 tile to LDS in feature order (column f of row r16): the
       // feature of slot 16 ot + 4g + v is linear in g, so every store is one
@@ -807,7 +818,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
       for (int o = 0; o < N3; ++o) {
         const int feat = 16 * o + r16;
         const float b3 = vec[kV_B3F + feat];  // the table spans kP3 features
-        f4 z = {b3, b3, b3, b3};
+        f4 z = PS ? f4{0.f, 0.f, 0.f, 0.f} : f4{b3, b3, b3, b3};
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) z = P::mfma(a3[kt], load8<P>(fr + z0 + NF2 + ((o * 2 + kt) * 64 + lane) * 8), z);
         if constexpr (MC) {
@@ -816,7 +827,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
           if (feat < M1) {
             const int src = feat < 2 * W ? feat : feat - 2 * W;  // the skip partner's feature
 #pragma unroll
-            for (int v = 0; v < 4; ++v) gv[v] = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
+            for (int v = 0; v < 4; ++v) gv[v] = h2s[wv][4 * g + v][src] + act(z[v], b3);
           }
           const f4 t4 = mfma_f16k16(pack4_f16(gv), bR, f4{accT[o][0], accT[o][1], accT[o][2], accT[o][3]});
 #pragma unroll
@@ -825,7 +836,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(4))) v
           const int src = feat < 2 * W ? feat : feat - 2 * W;  // the skip partner's feature
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float G = h2s[wv][4 * g + v][src] + tanh_f(z[v]);
+            const float G = h2s[wv][4 * g + v][src] + act(z[v], b3);
 #pragma unroll
             for (int k = 0; k < 4; ++k) accT[o][k] = fmaf(G, Rr[v][k], accT[o][k]);
           }
