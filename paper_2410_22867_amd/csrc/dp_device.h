@@ -196,6 +196,36 @@ __device__ __forceinline__ double tanh_d(double x) {
   return __builtin_copysign(fma(2.0, q, -1.0), x);
 }
 
+// FP64 tanh with a table tab[j] = 2^(j/32), j = 0..31 (kept in LDS by the
+// caller).  As in tanh_d, t = |x| is carried as u = t/32 clamped to [0, 1];
+// with a = -2t = -64u and k = rint(a 32/ln 2), a = k ln2/32 + f with
+// |f| <= ln2/64 (ln 2/32 split in a 36-bit head, so k head is exact for
+// |k| < 2^17, and a tail), and e^a = 2^(k >> 5) tab[k & 31] e^f with e^f by
+// its Taylor polynomial of degree 6 (truncation below 4e-18 relative),
+// evaluated in w = f/64 with the coefficients 64^k/k! (exact scalings).
+// The reciprocal and the result as in tanh_d, with six FP64 operations
+// fewer than its degree-11 polynomial.
+__device__ __forceinline__ double tanh_d_tab(double x, const double* tab) {
+  const double u = __builtin_fmin(__builtin_fmax(__builtin_fabs(x) * 0.03125, 0.0), 1.0);
+  const double k = rint(u * -2954.639443740597);    // -2048/ln 2
+  double w = fma(-k, 0.0003384507717569818, -u);  // head(ln 2/32)/64
+  w = fma(-k, 8.040014444773966e-16, w);          // tail(ln 2/32)/64
+  double p = 95443717.68888889;
+  p = fma(p, w, 8947848.533333333);
+  p = fma(p, w, 699050.6666666666);
+  p = fma(p, w, 43690.666666666664);
+  p = fma(p, w, 2048.0);
+  p = fma(p, w, 64.0);
+  p = fma(p, w, 1.0);
+  const int ki = (int)k;
+  const double e = __builtin_amdgcn_ldexp(p * tab[ki & 31], ki >> 5);
+  const double d = 1.0 + e;
+  const double q0 = __builtin_amdgcn_rcp(d);
+  const double r = fma(-d, q0, 1.0);
+  const double q = fma(q0, fma(r, r, r), q0);
+  return __builtin_copysign(fma(2.0, q, -1.0), x);
+}
+
 constexpr float kTanhScale = 2.8853900817779268f;  // 2/ln 2
 // tanh(x) from y = x * kTanhScale, for producers that fold the scale into
 // their own multiply-add (a bias stored pre-scaled: y = fma(z, scale, b'))

@@ -104,6 +104,16 @@ __device__ __forceinline__ int feat3h_of_slot(int p) {  // -1 for padding slots
   return (p >> 6) * 2 * W + ((p >> 5) & 1) * W + f;
 }
 
+// 2^(j/32), j = 0..31, correctly rounded (the table of tanh_d_tab)
+__constant__ double kExp2Frac32[32] = {
+    1.0, 1.0218971486541166, 1.0442737824274138, 1.0671404006768237, 1.0905077326652577, 1.1143867425958924,
+    1.1387886347566916, 1.1637248587775775, 1.189207115002721, 1.215247359980469, 1.241857812073484,
+    1.2690509571917332, 1.2968395546510096, 1.3252366431597413, 1.3542555469368927, 1.383909881963832,
+    1.4142135623730951, 1.4451808069770467, 1.4768261459394993, 1.5091644275934228, 1.5422108254079407,
+    1.5759808451078865, 1.6104903319492543, 1.645755478153965, 1.681792830507429, 1.718619298122478,
+    1.7562521603732995, 1.7947090750031072, 1.8340080864093424, 1.8741676341103, 1.9152065613971474,
+    1.9571441241754002};
+
 // The net that work-group row y serves: the nets in decreasing order of
 // their work, the centre type's columns times the neighbour section's row
 // tiles (ceil(sel / 16)), ties in net order.  Rows are dispatched in order,
@@ -267,6 +277,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
   __shared__ double fr[NF2 + NF3];
   __shared__ double h2s[WPB][16][kP2 + 1];
   __shared__ double vs[kVecPerNet];
+  __shared__ double etab[32];  // tanh_d_tab's table
   __shared__ int col_sh;  // group mode: the work-group's column
   DPSE_NET_PROLOGUE(WPB)
   {
@@ -275,6 +286,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int k = threadIdx.x; k < NF3; k += 64 * WPB) fr[NF2 + k] = src[A.fo.F3n + k];
     const double* vsrc = A.vec64 + net * A.vec_per_net;
     for (int k = threadIdx.x; k < kVecPerNet; k += 64 * WPB) vs[k] = vsrc[k];
+    if (threadIdx.x < 32) etab[threadIdx.x] = kExp2Frac32[threadIdx.x];
   }
   __syncthreads();
   constexpr int RSTEP = GM ? 16 * WPB : 16;  // rows between a wave's tiles
@@ -329,7 +341,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          h1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
+          h1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_d_tab(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]), etab);
       double h2[4][4];
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(fr[z0 + ((ot * 2 + mt) * 4 + v) * 64 + lane], h1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : h1[ot & 1][v] + tanh_d_tab(z[v], etab);
       }
       wave_lds_sync();
 #pragma unroll
@@ -362,7 +374,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int v = 0; v < 4; ++v)
               if (!kpad2<W>(mt, v)) z = mfma_f64(fr[z0 + NF2 + ((o * 4 + mt) * 4 + v) * 64 + lane], h2[mt][v], z);
           if (g < REM) {
-            const double t3 = tanh_d(z[0]);
+            const double t3 = tanh_d_tab(z[0], etab);
             if constexpr (ST) recb[f * 16 + r16] = t3;
             const double G = h2s[wv][r16][slot2d_of_feat<W>(f % (2 * W))] + t3;
 #pragma unroll
@@ -383,7 +395,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           const int src = slot2d_of_feat<W>(feat % (2 * W));
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double t3 = tanh_d(z[v]);
+            const double t3 = tanh_d_tab(z[v], etab);
             if constexpr (ST) rec[o * 256 + 4 * v] = t3;
             const double G = h2s[wv][4 * v + g][src] + t3;
 #pragma unroll
@@ -461,10 +473,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       if (k < 2048) fr[k] = gsrc[A.fo.F2 + k];
       else if (k < 4096) fr[k] = gsrc[A.fo.B2 + k - 2048];
       else if (k < 4096 + kVecPerNet) fr[k] = vecg[k - 4096];
+      else if (k < 4096 + kVecPerNet + 32) fr[k] = kExp2Frac32[k - 4096 - kVecPerNet];  // tanh_d_tab's table
     }
     fr[8192 + k] = gsrc[A.fo.B3 + k];
   }
   __syncthreads();
+  // layers 1-2: the table form of the FP64 tanh where the store leaves LDS
+  // room for its table
+  const double* etab = fr + 4096 + kVecPerNet;
+  auto tanh_l = [&](double x) { return ST ? tanh_d_tab(x, etab) : tanh_d(x); };
   const int gw = GM ? 0 : wv;  // this wave's g_T tile
   constexpr int RSTEP = GM ? 16 * WPB : 16;
   const int rfirst = GM ? 16 * wv : 0;
@@ -542,7 +559,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          t1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_d(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
+          t1[mt][v] = kpad<W>(mt, v) ? 0.0 : tanh_l(fma(s, vec[kV_W1 + 16 * mt + 4 * v + g], vec[kV_B1 + 16 * mt + 4 * v + g]));
       double h2[4][4];  // t2 = h2 - t1 is re-derived where needed
 #pragma unroll
       for (int ot = 0; ot < 4; ++ot) {
@@ -554,7 +571,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
           for (int v = 0; v < 4; ++v)
             if (!kpad<W>(mt, v)) z = mfma_f64(F2[((ot * 2 + mt) * 4 + v) * 64 + lane], t1[mt][v], z);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_d(z[v]);
+        for (int v = 0; v < 4; ++v) h2[ot][v] = kpad2<W>(ot, v) ? 0.0 : t1[ot & 1][v] + tanh_l(z[v]);
       }
       // layer 3 per output tile o, folded immediately into dh2 = W3 dz3
       double skip2[4][4];
