@@ -426,11 +426,27 @@ __global__ __launch_bounds__(256) void k_nl_skin_build(SearchArgs A, SkinArgs S,
     bool capacity = false;
     const int ncand = gather_cells(A, L, w, lane, i, F, rl2, &capacity);
     wave_lds_sync();
-    for (int c = lane; c < ncand; c += 64) {
-      const int pk = L.r[w][c].pk;
-      int rank = 0;
-      for (int o = 0; o < ncand; ++o) rank += L.r[w][o].pk < pk;
-      S.cand[(int64_t)i * kCandCap + rank] = pk;
+    // rank of each candidate by its packed key (keys are distinct): one pass
+    // over the list serves all of a lane's candidates, each record read once
+    constexpr int M = kCandCap / 64;
+    const int mmax = (ncand + 63) / 64;  // wave-uniform
+    int pkm[M], rank[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int c = 64 * m + lane;
+      pkm[m] = c < ncand ? L.r[w][c].pk : 0x7fffffff;
+      rank[m] = 0;
+    }
+    for (int o = 0; o < ncand; ++o) {
+      const int v = L.r[w][o].pk;
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (m < mmax) rank[m] += v < pkm[m];
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int c = 64 * m + lane;
+      if (c < ncand) S.cand[(int64_t)i * kCandCap + rank[m]] = pkm[m];
     }
     if (lane < 3) S.xref[3 * i + lane] = A.x[3 * i + lane];
     if (lane == 0) {
@@ -442,23 +458,55 @@ __global__ __launch_bounds__(256) void k_nl_skin_build(SearchArgs A, SkinArgs S,
 }
 
 // Position of each candidate's reverse pair (i, -s) in j's candidate list.
-// Grid-stride over the [n, kCandCap] candidate slots.
-__global__ void k_nl_skin_crev(SkinArgs S, int ntot) {
+// One wave per atom i (atoms in a grid-stride loop over a grid of the
+// resident capacity, so that a gated launch with nothing to do is cheap);
+// lane l takes candidates l, l + 64, ... of i's list, four at a time, and
+// runs their binary searches in j's sorted candidate list in lockstep (a
+// fixed ten halvings cover the 512-entry capacity), so that four
+// dependent-load chains are in flight per lane instead of one.
+__global__ __launch_bounds__(256) void k_nl_skin_crev(SkinArgs S, int ntot) {
   if (S.gate && S.gate[0] == 0) return;
-  const int64_t total = (int64_t)ntot * kCandCap;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q / kCandCap), k = (int)(q - (int64_t)i * kCandCap);
-    if (k >= S.ncand[i]) continue;
-    const int e = S.cand[q];
-    const int j = e / 27;
-    const int target = 27 * i + (26 - (e - 27 * j));
-    const int32_t* cj = S.cand + (int64_t)j * kCandCap;
-    int lo = 0, hi = S.ncand[j];
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (cj[mid] < target) lo = mid + 1; else hi = mid;
+  const int lane = threadIdx.x & 63;
+  for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < ntot; i += gridDim.x * 4) {
+    const int nc = S.ncand[i];
+    const int32_t* ci = S.cand + (int64_t)i * kCandCap;
+    constexpr int M = kCandCap / 64, U = 4;
+    static_assert(kCandCap <= 1024, "ten halvings cover the list");
+    for (int m0 = 0; m0 < M && 64 * m0 < nc; m0 += U) {
+      int lo[U], hi[U], nj[U], tgt[U];
+      const int32_t* cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = 64 * (m0 + u) + lane;
+        lo[u] = 0;
+        hi[u] = 0;
+        nj[u] = 0;
+        tgt[u] = 0;
+        cj[u] = ci;
+        if (m0 + u < M && k < nc) {
+          const int e = ci[k];
+          const int j = e / 27;
+          tgt[u] = 27 * i + (26 - (e - 27 * j));
+          cj[u] = S.cand + (int64_t)j * kCandCap;
+          nj[u] = S.ncand[j];
+          hi[u] = nj[u];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < 10; ++it)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (lo[u] < hi[u]) {
+            const int mid = (lo[u] + hi[u]) >> 1;
+            if (cj[u][mid] < tgt[u]) lo[u] = mid + 1;
+            else hi[u] = mid;
+          }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = 64 * (m0 + u) + lane;
+        if (m0 + u < M && k < nc) S.crev[(int64_t)i * kCandCap + k] = (lo[u] < nj[u] && cj[u][lo[u]] == tgt[u]) ? lo[u] : -1;
+      }
     }
-    S.crev[q] = (lo < S.ncand[j] && cj[lo] == target) ? lo : -1;
   }
 }
 
@@ -737,7 +785,7 @@ static void skin_build_kernels(dp_ctx* c, const double* x, const int32_t* types,
   const int64_t gb = (ntot + kSearchWaves - 1) / kSearchWaves, gbmax = 5LL * c->ncu;
   hipLaunchKernelGGL(k_nl_skin_build, dim3((unsigned)(gb < gbmax ? gb : gbmax)), dim3(64 * kSearchWaves), 0, s, A, S,
                      rl * rl);
-  const int64_t gq = ((int64_t)ntot * kCandCap + 255) / 256, gqmax = 8LL * c->ncu;
+  const int64_t gq = (ntot + 3) / 4, gqmax = 8LL * c->ncu;  // a wave per atom, resident grid
   hipLaunchKernelGGL(k_nl_skin_crev, dim3((unsigned)(gq < gqmax ? gq : gqmax)), dim3(256), 0, s, S, ntot);
 }
 
