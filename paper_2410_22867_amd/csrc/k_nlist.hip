@@ -535,6 +535,97 @@ __global__ __launch_bounds__(256) void k_nl_skin_check(const double* __restrict_
   }
 }
 
+// Small frames: the skin check and, when it decides a rebuild, the cell
+// binning of the Verlet build (wrap in place, cell counts, their scan, the
+// scatter) in one work-group, so that a step with no rebuild costs one
+// launch instead of four.  Counts and fill counters stay in LDS (the global
+// ones, which the multi-work-group binning uses, stay zero).  Same gate
+// semantics as k_nl_skin_check followed by the gated binning kernels.
+constexpr int kPrepSmallAtoms = 1 << 17, kPrepSmallCells = 4096;
+__global__ __launch_bounds__(1024) void k_nl_skin_prep_small(double* __restrict__ x, const double* __restrict__ xref,
+                                                            const FrameInfo* __restrict__ fr, int ntot, int ncells,
+                                                            double half_skin2, int every, int32_t* gate,
+                                                            int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_start,
+                                                            int32_t* __restrict__ cell_atoms, int32_t* flags,
+                                                            int32_t* images) {
+  __shared__ int32_t cnt[kPrepSmallCells];  // counts, then fill counters
+  __shared__ int32_t st[kPrepSmallCells];   // cell starts
+  __shared__ int32_t part[1024];
+  __shared__ int go;
+  const int tid = threadIdx.x;
+  bool moved = false;
+  for (int i = tid; i < ntot; i += 1024) {
+    const double ex = x[3 * i] - xref[3 * i], ey = x[3 * i + 1] - xref[3 * i + 1], ez = x[3 * i + 2] - xref[3 * i + 2];
+    moved = moved || !((ex * ex + ey * ey) + ez * ez <= half_skin2);
+  }
+  for (int c = tid; c < ncells; c += 1024) cnt[c] = 0;
+  const int any = __syncthreads_or(moved);
+  if (tid == 0) {
+    const int k = gate[1] + 1;
+    gate[1] = k;
+    const int g = gate[0] | any | (every > 0 && k >= every ? 1 : 0);
+    gate[0] = g;
+    go = g;
+  }
+  __syncthreads();
+  if (go == 0) return;
+  const FrameInfo F = fr[0];
+  for (int i = tid; i < ntot; i += 1024) {
+    int cc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double xa = x[3 * i + a];
+      if (!(xa >= 0.0 && xa < F.L[a])) {
+        const double L = F.L[a];
+        const double k = floor(xa / L);
+        xa -= k * L;
+        if (xa >= L) xa -= L;  // rounding of x - k L
+        if (xa < 0.0) xa += L;
+        if (xa >= L) xa = 0.0;
+        x[3 * i + a] = xa;
+        if (images) images[3 * i + a] += (int32_t)k;
+      }
+      if (!(xa >= 0.0 && xa < F.L[a])) set_flag(flags, DP_FLAG_NOT_WRAPPED);
+      cc[a] = cell_coord(xa, F.L[a], F.ncell[a]);
+    }
+    const int cid = cc[0] + F.ncell[0] * (cc[1] + F.ncell[1] * cc[2]);
+    cell_of[i] = F.cell_off + cid;
+    atomicAdd(&cnt[cid], 1);
+  }
+  __syncthreads();
+  // exclusive scan: thread t sums its run of cells, a scan of the 1024 sums,
+  // then the run's starts
+  constexpr int kRun = kPrepSmallCells / 1024;
+  const int c0 = tid * kRun;
+  int run = 0;
+#pragma unroll
+  for (int q = 0; q < kRun; ++q) run += c0 + q < ncells ? cnt[c0 + q] : 0;
+  part[tid] = run;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int t = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += t;
+    __syncthreads();
+  }
+  int acc = part[tid] - run;
+#pragma unroll
+  for (int q = 0; q < kRun; ++q)
+    if (c0 + q < ncells) {
+      st[c0 + q] = acc;
+      cell_start[F.cell_off + c0 + q] = acc;
+      acc += cnt[c0 + q];
+      cnt[c0 + q] = 0;
+    }
+  if (tid == 1023) cell_start[F.cell_off + ncells] = part[1023];
+  __syncthreads();
+  for (int i = tid; i < ntot; i += 1024) {
+    const int cid = cell_of[i] - F.cell_off;
+    const int p = atomicAdd(&cnt[cid], 1);
+    cell_atoms[st[cid] + p] = i;
+  }
+}
+
 // Format: the sorted, truncated list on the current positions from the
 // candidates of the last build (same test and order as the cell search).
 template <int CAP>
@@ -804,14 +895,20 @@ void launch_nl_skin_update(dp_ctx* c, double* x, const int32_t* types, int32_t n
                            int32_t* rebuilds, hipStream_t s) {
   if (ntot <= 0) return;
   int32_t* gate = c->skin_gate;
-  hipLaunchKernelGGL(k_nl_skin_check, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x,
-                     (const double*)c->skin_xref, ntot, 0.25 * c->skin * c->skin, every, gate);
-  hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x, c->skin_frame, 1, ntot,
-                     c->cell_of, c->cell_count, c->flags_dev, x, images, (const int32_t*)gate);
-  hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill,
-                     c->skin_ncells, (const int32_t*)gate);
-  hipLaunchKernelGGL(k_nl_scatter, dim3((ntot + 255) / 256), dim3(256), 0, s, c->cell_of, c->cell_start,
-                     c->cell_fill, c->cell_atoms, ntot, (const int32_t*)gate);
+  if (ntot <= kPrepSmallAtoms && c->skin_ncells <= kPrepSmallCells) {
+    hipLaunchKernelGGL(k_nl_skin_prep_small, dim3(1), dim3(1024), 0, s, x, (const double*)c->skin_xref, c->skin_frame,
+                       ntot, c->skin_ncells, 0.25 * c->skin * c->skin, every, gate, c->cell_of, c->cell_start,
+                       c->cell_atoms, c->flags_dev, images);
+  } else {
+    hipLaunchKernelGGL(k_nl_skin_check, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x,
+                       (const double*)c->skin_xref, ntot, 0.25 * c->skin * c->skin, every, gate);
+    hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x, c->skin_frame, 1, ntot,
+                       c->cell_of, c->cell_count, c->flags_dev, x, images, (const int32_t*)gate);
+    hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill,
+                       c->skin_ncells, (const int32_t*)gate);
+    hipLaunchKernelGGL(k_nl_scatter, dim3((ntot + 255) / 256), dim3(256), 0, s, c->cell_of, c->cell_start,
+                       c->cell_fill, c->cell_atoms, ntot, (const int32_t*)gate);
+  }
   skin_build_kernels(c, x, types, ntot, gate, rebuilds, s);
 }
 
