@@ -535,40 +535,25 @@ __global__ __launch_bounds__(256) void k_nl_skin_check(const double* __restrict_
   }
 }
 
-// Small frames: the skin check and, when it decides a rebuild, the cell
-// binning of the Verlet build (wrap in place, cell counts, their scan, the
-// scatter) in one work-group, so that a step with no rebuild costs one
-// launch instead of four.  Counts and fill counters stay in LDS (the global
-// ones, which the multi-work-group binning uses, stay zero).  Same gate
-// semantics as k_nl_skin_check followed by the gated binning kernels.
+// Small frames: the cell binning of a gated Verlet build (wrap in place,
+// cell counts, their scan, the scatter) in one work-group, one launch
+// instead of three; a step with no rebuild returns at once.  Counts and
+// fill counters stay in LDS (the global ones, which the multi-work-group
+// binning uses, stay zero).  The skin check stays a kernel of its own: one
+// compute unit alone reads the positions several times slower.
 constexpr int kPrepSmallAtoms = 1 << 17, kPrepSmallCells = 4096;
-__global__ __launch_bounds__(1024) void k_nl_skin_prep_small(double* __restrict__ x, const double* __restrict__ xref,
-                                                            const FrameInfo* __restrict__ fr, int ntot, int ncells,
-                                                            double half_skin2, int every, int32_t* gate,
-                                                            int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_start,
-                                                            int32_t* __restrict__ cell_atoms, int32_t* flags,
-                                                            int32_t* images) {
+__global__ __launch_bounds__(1024) void k_nl_bin_small(double* __restrict__ x, const FrameInfo* __restrict__ fr,
+                                                      int ntot, int ncells, const int32_t* gate,
+                                                      int32_t* __restrict__ cell_of, int32_t* __restrict__ cell_start,
+                                                      int32_t* __restrict__ cell_atoms, int32_t* flags,
+                                                      int32_t* images) {
+  if (*gate == 0) return;
   __shared__ int32_t cnt[kPrepSmallCells];  // counts, then fill counters
   __shared__ int32_t st[kPrepSmallCells];   // cell starts
   __shared__ int32_t part[1024];
-  __shared__ int go;
   const int tid = threadIdx.x;
-  bool moved = false;
-  for (int i = tid; i < ntot; i += 1024) {
-    const double ex = x[3 * i] - xref[3 * i], ey = x[3 * i + 1] - xref[3 * i + 1], ez = x[3 * i + 2] - xref[3 * i + 2];
-    moved = moved || !((ex * ex + ey * ey) + ez * ez <= half_skin2);
-  }
   for (int c = tid; c < ncells; c += 1024) cnt[c] = 0;
-  const int any = __syncthreads_or(moved);
-  if (tid == 0) {
-    const int k = gate[1] + 1;
-    gate[1] = k;
-    const int g = gate[0] | any | (every > 0 && k >= every ? 1 : 0);
-    gate[0] = g;
-    go = g;
-  }
   __syncthreads();
-  if (go == 0) return;
   const FrameInfo F = fr[0];
   for (int i = tid; i < ntot; i += 1024) {
     int cc[3];
@@ -895,13 +880,12 @@ void launch_nl_skin_update(dp_ctx* c, double* x, const int32_t* types, int32_t n
                            int32_t* rebuilds, hipStream_t s) {
   if (ntot <= 0) return;
   int32_t* gate = c->skin_gate;
+  hipLaunchKernelGGL(k_nl_skin_check, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x,
+                     (const double*)c->skin_xref, ntot, 0.25 * c->skin * c->skin, every, gate);
   if (ntot <= kPrepSmallAtoms && c->skin_ncells <= kPrepSmallCells) {
-    hipLaunchKernelGGL(k_nl_skin_prep_small, dim3(1), dim3(1024), 0, s, x, (const double*)c->skin_xref, c->skin_frame,
-                       ntot, c->skin_ncells, 0.25 * c->skin * c->skin, every, gate, c->cell_of, c->cell_start,
-                       c->cell_atoms, c->flags_dev, images);
+    hipLaunchKernelGGL(k_nl_bin_small, dim3(1), dim3(1024), 0, s, x, c->skin_frame, ntot, c->skin_ncells,
+                       (const int32_t*)gate, c->cell_of, c->cell_start, c->cell_atoms, c->flags_dev, images);
   } else {
-    hipLaunchKernelGGL(k_nl_skin_check, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x,
-                       (const double*)c->skin_xref, ntot, 0.25 * c->skin * c->skin, every, gate);
     hipLaunchKernelGGL(k_nl_bin, dim3((ntot + 255) / 256), dim3(256), 0, s, (const double*)x, c->skin_frame, 1, ntot,
                        c->cell_of, c->cell_count, c->flags_dev, x, images, (const int32_t*)gate);
     hipLaunchKernelGGL(k_nl_scan, dim3(1), dim3(1024), 0, s, c->cell_count, c->cell_start, c->cell_fill,
