@@ -1257,10 +1257,11 @@ static void launch_embed(dp_ctx* c, int32_t mode, bool bwd, hipStream_t s) {
   EmbArgs A = emb_args(c, mode);
   const int per_cu = mode == DP_FP64 ? 1 : (kind == 3 ? (bwd ? 1 : 2) : (bwd ? 2 : 4));
   const int nnets = A.ntypes * A.ntypes;
-  // one-row grid for the FP64 forward and the FP32 form's backward (water12k:
-  // 547 -> 516 us and 504 -> 458 us); the other kernels keep one row per net
+  // one-row grid for the FP64 kernels and the FP32 form's backward (water12k:
+  // FP64 forward 547 -> 516 us, backward with stored activations 589 -> 561
+  // us, FP32 backward 504 -> 458 us); the other kernels keep one row per net
   // (the 16-bit forward one-row: 97 -> 103 us)
-  const bool flat = mode == DP_FP64 ? !bwd : (kind == 3 && bwd);
+  const bool flat = mode == DP_FP64 || (kind == 3 && bwd);
   dim3 grid = emb_grid(c, wpb, per_cu, A.ntypes, flat);
   dim3 block(64 * wpb);
   if (mode == DP_FP64) {
