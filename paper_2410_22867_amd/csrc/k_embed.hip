@@ -134,47 +134,6 @@ __device__ __forceinline__ int net_of_row(const int32_t* meta, const int* sec, i
   return 0;
 }
 
-// One-row grid: every net gets one work-group and the other G - nnets are
-// split in proportion to the nets' work (as net_of_row weighs it), the nets'
-// shares laid out in decreasing order of work.  Work-group b serves the net
-// whose share holds b, as the j-th of gk work-groups.  A grid of the
-// work-groups the CUs hold at once then finishes every net in one round:
-// with one net per grid row, the light nets' work-groups would wait for the
-// heavy nets' slots and each work-group would get a few columns only, its
-// waves idling at its end for up to one column each.  Returns -1 for b past
-// the shares (none when G >= nnets and some net has work).
-__device__ __forceinline__ int net_of_group(const int32_t* meta, const int* sec, int ntypes, int G, int b, int* j,
-                                            int* gk) {
-  const int nnets = ntypes * ntypes;
-  auto wt = [&](int k) -> int64_t {
-    const int kti = k / ntypes, ktj = k - kti * ntypes;
-    return (int64_t)meta[2 * kti] * ((sec[ktj + 1] - sec[ktj] + 15) / 16);
-  };
-  int64_t total = 0;
-  for (int k = 0; k < nnets; ++k) total += wt(k);
-  const int64_t spare = G - nnets;
-  for (int k = 0; k < nnets; ++k) {
-    const int64_t wk = wt(k);
-    int rank = 0;
-    int64_t before = 0;  // work of the nets ranked before k
-    for (int q = 0; q < nnets; ++q) {
-      const int64_t wq = wt(q);
-      if (wq > wk || (wq == wk && q < k)) {
-        ++rank;
-        before += wq;
-      }
-    }
-    const int64_t lo = rank + (total > 0 ? spare * before / total : 0);
-    const int64_t hi = rank + 1 + (total > 0 ? spare * (before + wk) / total : 0);
-    if (b >= lo && b < hi) {
-      *j = (int)(b - lo);
-      *gk = (int)(hi - lo);
-      return k;
-    }
-  }
-  return -1;
-}
-
 // Common prologue of the per-net kernels: net = t_i * ntypes + t_j (centre
 // type t_i, neighbour section t_j) from net_of_group (one-row grid) or
 // net_of_row (one grid row per net).  Work assignment: the

@@ -161,15 +161,17 @@ struct TabArgs {
 // of 16 lanes is 128 contiguous bytes and every row's sums over features
 // reduce over 16 lanes.
 #define DPSE_TAB_PROLOGUE                                                  \
-  const int net = blockIdx.y;                                             \
+  int grp = 0, ngrp = 1;                                                  \
+  const int net = net_of_group(A.meta, A.sec, A.ntypes, gridDim.x, blockIdx.x, &grp, &ngrp); \
+  if (net < 0) return;                                                    \
   const int ti = net / A.ntypes, tj = net - ti * A.ntypes;                \
   const int n_t = A.meta[2 * ti], cb = A.meta[2 * ti + 1];                \
-  const int c_lo = (int)((int64_t)n_t * blockIdx.x / gridDim.x);          \
-  const int c_hi = (int)((int64_t)n_t * (blockIdx.x + 1) / gridDim.x);    \
+  const int c_lo = (int)((int64_t)n_t * grp / ngrp);                      \
+  const int c_hi = (int)((int64_t)n_t * (grp + 1) / ngrp);                \
   if (c_lo >= c_hi) return;                                               \
   const int lane = threadIdx.x & 63;                                      \
   const int fl = lane & 15, rg = lane >> 4;                               \
-  int* const next_col = A.ctr + (net * gridDim.x + blockIdx.x) * 32;      \
+  int* const next_col = A.ctr + blockIdx.x * 32;                          \
   if (threadIdx.x == 0) atomicExch(next_col, c_lo);                       \
   __syncthreads();                                                        \
   auto take = [&]() {                                                     \
@@ -321,9 +323,12 @@ void launch_embed_tab(dp_ctx* c, bool bwd, hipStream_t s) {
   A.inv_nm = 1.0 / (double)m->nm;
   A.ctr = c->emb_ctr;
   A.flags = c->flags_dev;
-  // 4-wave work-groups, three per CU (the per-work-group counters allow three)
-  const int64_t need = (c->natoms_last + 3) / 4, res = (int64_t)c->ncu * 3;
-  dim3 grid((unsigned)(need < res ? need : res), (unsigned)(A.ntypes * A.ntypes));
+  // 4-wave work-groups, three per CU, on one grid row shared out among the
+  // nets by their work (net_of_group), all resident at once
+  const int nnets = A.ntypes * A.ntypes;
+  const int64_t need = (c->natoms_last * A.ntypes + 3) / 4, res = (int64_t)c->ncu * 3;
+  const int64_t groups = need < res ? need : res;
+  dim3 grid((unsigned)(groups > nnets ? groups : nnets), 1);
   if (m->m1 == 100) {
     if (bwd) hipLaunchKernelGGL(k_embed_bwd_tab<100>, grid, dim3(256), 0, s, A);
     else hipLaunchKernelGGL(k_embed_fwd_tab<100>, grid, dim3(256), 0, s, A);
